@@ -1,0 +1,186 @@
+/*
+ * dkss.h -- C ABI of libdkss, DKSS multiplication of large unsigned integers on one AMD
+ * Instinct MI355X (gfx950).
+ *
+ * The method is the one analysed in C. Lueders, "Fast Multiplication of Large Integers:
+ * Implementation and Analysis of the DKSS Algorithm" (arXiv 1503.04955), Chapter 3: encode both
+ * operands as polynomials over R = (Z/p^zZ)[alpha]/(alpha^m + 1) (Sec. 3.2.4), transform with a
+ * length-2M FFT whose inner 2m-point DFTs multiply by powers of alpha and whose outer stages
+ * multiply by powers of rho (Sec. 3.2.5), multiply componentwise in R (Sec. 3.2.6), transform
+ * back (Sec. 3.2.7) and recover the integer with carries (Sec. 3.2.8).
+ *
+ * Conventions for every entry point
+ *  - Integers are arrays of uint32_t limbs, least significant limb first (Sec. 2.1), with the
+ *    length passed separately.  Operands need not be normalized (high zero limbs are allowed).
+ *  - Pointers named a, b, c, x, ws are DEVICE pointers; pointers to parameter structs, length
+ *    arrays and result scalars are HOST pointers.  The caller owns all memory and keeps it
+ *    alive until the stream has finished the call.  The library never frees caller memory.
+ *  - Work is enqueued asynchronously on the given HIP stream (NULL = the null stream).  Argument
+ *    and feasibility errors are returned synchronously; device faults surface as DKSS_EHIP from
+ *    a later call or from the caller's own synchronization.
+ *  - A context is not thread-safe: use one per host thread or lock around it.
+ *  - Return value: DKSS_OK (0) or a negative DKSS_E* code; dkss_strerror() names it.
+ */
+#ifndef DKSS_H
+#define DKSS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ihipStream_t* dkss_stream_t;   /* hipStream_t */
+typedef struct dkss_ctx dkss_ctx;
+
+enum {
+    DKSS_OK = 0,
+    DKSS_EINVAL = -1,     /* null pointer, overlapping output, bad enum or struct contents */
+    DKSS_ENOSPC = -2,     /* workspace smaller than dkss_workspace_bytes() */
+    DKSS_ERANGE = -3,     /* size or parameter tuple unsupported or infeasible */
+    DKSS_EHIP = -4,       /* a HIP runtime call failed */
+    DKSS_ENOTIMPL = -5
+};
+
+/* Parameter policy of a context. */
+enum {
+    DKSS_POLICY_THESIS = 0,   /* the thesis's rule, Sec. 4.1 (with Sec. 3.2 Steps 1-2) */
+    DKSS_POLICY_TUNED = 1     /* measured plans from the context's tuning table, else THESIS */
+};
+
+/*
+ * One parameter tuple (Sec. 3.2 Steps 1-2): FFT length 2M = 2^(log2_M+1), inner degree bound
+ * m = 2^log2_m, u input bits per inner coefficient, prime p of p_bits bits (h*2^n + 1 with the
+ * smallest odd h, Sec. 4.5) and modulus p^z.  Products with min(alen, blen)*32 <= cutoff_bits
+ * use the schoolbook base case instead.  radix_log2[i] (i < n_levels) optionally fixes the FFT
+ * level split: 2M = prod 2^radix_log2[i], each radix at most 2m; n_levels = 0 lets the library
+ * choose (levels of radix 2m, then the remainder, as in the thesis's recursion, Sec. 4.2).
+ * A struct whose u is 0 asks for u = ceil(2N / Mm).
+ */
+typedef struct {
+    uint32_t log2_M;
+    uint32_t log2_m;
+    uint32_t u;
+    uint32_t p_bits;
+    uint32_t z;
+    uint32_t n_levels;
+    uint32_t radix_log2[8];
+    uint64_t cutoff_bits;
+} dkss_params;
+
+/* Derived facts of a plan (for reporting and tests). */
+typedef struct {
+    dkss_params params;
+    uint32_t L;               /* uint32 limbs per inner coefficient (ceil(bits(p^z)/32)) */
+    uint32_t q_bits;          /* bits of p^z */
+    uint32_t schoolbook;      /* 1 if the product goes to the schoolbook base case */
+    uint32_t squaring;        /* filled by dkss_plan_info only when a == b was indicated */
+    uint64_t poly_bytes;      /* S = 2M * m * L * 4, one polynomial */
+    uint64_t table_bytes;     /* device table of rho^s, s < 2M/2m */
+    uint32_t q[16];           /* p^z, L limbs */
+} dkss_plan;
+
+/* Create a context with the given policy.  cache_dir may be NULL.  Allocates nothing on the
+ * device until a parameter tuple is first prepared.  Errors: DKSS_EINVAL. */
+int dkss_ctx_create(dkss_ctx** out, int policy, const char* cache_dir);
+
+/* Release the context and the device tables it owns.  Safe on NULL. */
+void dkss_ctx_destroy(dkss_ctx* ctx);
+
+/* Parameters the context's policy picks for operands of a_bits and b_bits bits in a batch of
+ * `batch` products.  N = max(a_bits, b_bits) rounded up to whole limbs (the thesis assumes equal
+ * lengths, Sec. 3.2).  Errors: DKSS_EINVAL (null), DKSS_ERANGE (N = 0 or beyond 2^36 bits). */
+int dkss_select_params(dkss_ctx* ctx, uint64_t a_bits, uint64_t b_bits, uint32_t batch,
+                       dkss_params* out);
+
+/* Plan facts for a product of alen x blen limbs under params p (NULL = the policy). */
+int dkss_plan_info(dkss_ctx* ctx, size_t alen, size_t blen, const dkss_params* p, dkss_plan* out);
+
+/* Workspace bytes dkss_mul needs for alen x blen limbs under params p (NULL = the policy). */
+int dkss_workspace_bytes(dkss_ctx* ctx, size_t alen, size_t blen, const dkss_params* p,
+                         size_t* out);
+
+/* Build (if not yet built) and cache in ctx the device constants of params p for operands of up
+ * to alen x blen limbs: the table of rho^s (Sec. 4.2, powers below 2M/2m).  Allocates device
+ * memory and synchronizes the stream.  dkss_mul calls it itself on the first use of a tuple;
+ * calling it beforehand keeps dkss_mul free of allocations. */
+int dkss_prepare(dkss_ctx* ctx, size_t alen, size_t blen, const dkss_params* p, dkss_stream_t s);
+
+/*
+ * c[0 .. alen+blen) = a * b (Sec. 3.2, Steps 4-8).  Every limb of c is written, high zeros
+ * included.  a == b with alen == blen is a squaring (one forward transform).  alen or blen of 0
+ * gives c = 0.  c must not overlap a or b (DKSS_EINVAL).  ws must hold at least
+ * dkss_workspace_bytes() bytes of device memory, 256-byte aligned (DKSS_ENOSPC / DKSS_EINVAL).
+ * p = NULL uses the context's policy.  Errors: DKSS_EINVAL, DKSS_ENOSPC, DKSS_ERANGE (p^z below
+ * Mm 2^(2u), 2M not dividing p - 1, M < m, m < 2, capacity M*m/2*u below 32*max(alen, blen),
+ * unsupported limb count), DKSS_EHIP.
+ */
+int dkss_mul(dkss_ctx* ctx, uint32_t* c, const uint32_t* a, size_t alen, const uint32_t* b,
+             size_t blen, const dkss_params* p, void* ws, size_t ws_bytes, dkss_stream_t s);
+
+/*
+ * count independent products c[i] = a[i] * b[i] (each as in dkss_mul).  The arrays of
+ * pointers and lengths are HOST arrays of device pointers.  p is NULL (policy per product) or
+ * an array of count tuples.  Products that share a parameter tuple run together in the same
+ * kernel launches.  The workspace must hold dkss_batch_workspace_bytes().
+ */
+int dkss_mul_batch(dkss_ctx* ctx, size_t count, uint32_t* const* c, const uint32_t* const* a,
+                   const size_t* alen, const uint32_t* const* b, const size_t* blen,
+                   const dkss_params* p, void* ws, size_t ws_bytes, dkss_stream_t s);
+
+/* Workspace bytes for dkss_mul_batch with the same arguments. */
+int dkss_batch_workspace_bytes(dkss_ctx* ctx, size_t count, const size_t* alen,
+                               const size_t* blen, const dkss_params* p, size_t* out);
+
+/*
+ * Forward transform only (Steps 4-5): encode a into 2M elements of R and transform them with
+ * root rho; poly receives a(rho^i) for i < 2M in natural order, element-major (element i, inner
+ * coefficient k, limb w at ((i*m + k)*L + w)), canonical residues in [0, p^z).  poly holds
+ * poly_bytes of dkss_plan; ws holds dkss_workspace_bytes().  For checking intermediates.
+ */
+int dkss_forward(dkss_ctx* ctx, uint32_t* poly, const uint32_t* a, size_t alen, size_t blen,
+                 const dkss_params* p, void* ws, size_t ws_bytes, dkss_stream_t s);
+
+/* Residues x mod primes[j] for j < count (each prime odd, below 2^62), written to the DEVICE
+ * array out[count].  For checking products of any size by c = a*b mod q. */
+int dkss_residues(const uint32_t* x, size_t n, const uint64_t* primes_host, size_t count,
+                  uint64_t* out, dkss_stream_t s);
+
+/*
+ * Kernel timing.  With profiling on, every kernel launch a context makes is bracketed by two HIP
+ * events recorded on the launch's stream, and the launch's algorithmic work is noted: bytes that
+ * the step must move (each input read once, each output written once) and, for the products in
+ * R, 32x32-bit multiply-adds of the schoolbook product (m^2 L^2 per product in R).  The figures
+ * are summed per kernel kind.  dkss_profile_read synchronizes on the recorded events.
+ */
+enum {
+    DKSS_K_ENCODE = 0, DKSS_K_DFT, DKSS_K_TWIDDLE, DKSS_K_POINTWISE, DKSS_K_DECODE,
+    DKSS_K_CARRY_SCAN, DKSS_K_CARRY_APPLY, DKSS_K_SCHOOLBOOK, DKSS_K_TABLE, DKSS_K_UNSCRAMBLE,
+    DKSS_K_KINDS
+};
+
+typedef struct {
+    uint64_t launches;
+    double total_ms;        /* sum of event-measured launch durations */
+    double alg_bytes;       /* algorithmic bytes, summed over launches */
+    double alg_ops;         /* algorithmic 32-bit multiply-adds, summed over launches */
+} dkss_kernel_stats;
+
+/* Turn profiling on (1) or off (0).  Errors: DKSS_EINVAL. */
+int dkss_profile_enable(dkss_ctx* ctx, int on);
+/* Totals of kernel kind `kind` (DKSS_K_*) since the last reset.  Errors: DKSS_EINVAL, DKSS_EHIP. */
+int dkss_profile_read(dkss_ctx* ctx, int kind, dkss_kernel_stats* out);
+/* Clear the totals (waits for pending events first). */
+int dkss_profile_reset(dkss_ctx* ctx);
+/* Name of a kernel kind, e.g. "k_twiddle"; NULL for an unknown kind. */
+const char* dkss_kernel_name(int kind);
+
+/* Static description of an error code. */
+const char* dkss_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DKSS_H */

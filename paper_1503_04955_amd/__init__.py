@@ -1,0 +1,267 @@
+"""Python binding of libdkss (DKSS multiplication on one MI355X).
+
+Argument marshalling only: every step of the multiplication runs in the HIP kernels of
+``csrc/libdkss.so``; this module passes device pointers, lengths, parameter structs and the
+current HIP stream through the C ABI declared in ``include/dkss.h``.  PyTorch provides device
+memory and streams.  Integers are torch.int32 CUDA tensors holding uint32 limbs, least
+significant limb first.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "csrc", "libdkss.so")
+
+POLICY_THESIS = 0
+POLICY_TUNED = 1
+
+OK, EINVAL, ENOSPC, ERANGE, EHIP, ENOTIMPL = 0, -1, -2, -3, -4, -5
+
+
+class DkssError(RuntimeError):
+    def __init__(self, code, what):
+        super().__init__("%s: %s (%d)" % (what, lib().dkss_strerror(code).decode(), code))
+        self.code = code
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("log2_M", ctypes.c_uint32), ("log2_m", ctypes.c_uint32), ("u", ctypes.c_uint32),
+                ("p_bits", ctypes.c_uint32), ("z", ctypes.c_uint32),
+                ("n_levels", ctypes.c_uint32), ("radix_log2", ctypes.c_uint32 * 8),
+                ("cutoff_bits", ctypes.c_uint64)]
+
+    @classmethod
+    def make(cls, log2_M, log2_m, u=0, p_bits=128, z=1, radices=None, cutoff_bits=0):
+        p = cls()
+        p.log2_M, p.log2_m, p.u, p.p_bits, p.z = log2_M, log2_m, u, p_bits, z
+        radices = list(radices or [])
+        p.n_levels = len(radices)
+        for i, r in enumerate(radices):
+            p.radix_log2[i] = r
+        p.cutoff_bits = cutoff_bits
+        return p
+
+    def as_dict(self):
+        return {"log2_M": self.log2_M, "log2_m": self.log2_m, "u": self.u, "p_bits": self.p_bits,
+                "z": self.z, "radices": [self.radix_log2[i] for i in range(self.n_levels)],
+                "cutoff_bits": self.cutoff_bits}
+
+
+class Plan(ctypes.Structure):
+    _fields_ = [("params", Params), ("L", ctypes.c_uint32), ("q_bits", ctypes.c_uint32),
+                ("schoolbook", ctypes.c_uint32), ("squaring", ctypes.c_uint32),
+                ("poly_bytes", ctypes.c_uint64), ("table_bytes", ctypes.c_uint64),
+                ("q", ctypes.c_uint32 * 16)]
+
+    @property
+    def modulus(self):
+        return sum(int(self.q[i]) << (32 * i) for i in range(self.L))
+
+
+class KernelStats(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_uint64), ("total_ms", ctypes.c_double),
+                ("alg_bytes", ctypes.c_double), ("alg_ops", ctypes.c_double)]
+
+
+KERNEL_KINDS = 10
+
+_lib = None
+
+
+def lib():
+    """Load libdkss.so; raises if it has not been built (there is no fallback path)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libdkss.so is not built: run python -m paper_1503_04955_amd.build")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, sz, u32, u64 = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_uint32, ctypes.c_uint64
+        PP = ctypes.POINTER(Params)
+        L.dkss_ctx_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int, ctypes.c_char_p]
+        L.dkss_ctx_destroy.argtypes = [vp]
+        L.dkss_ctx_destroy.restype = None
+        L.dkss_select_params.argtypes = [vp, u64, u64, u32, PP]
+        L.dkss_plan_info.argtypes = [vp, sz, sz, PP, ctypes.POINTER(Plan)]
+        L.dkss_workspace_bytes.argtypes = [vp, sz, sz, PP, ctypes.POINTER(sz)]
+        L.dkss_prepare.argtypes = [vp, sz, sz, PP, vp]
+        L.dkss_mul.argtypes = [vp, vp, vp, sz, vp, sz, PP, vp, sz, vp]
+        L.dkss_mul_batch.argtypes = [vp, sz, ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                     ctypes.POINTER(sz), ctypes.POINTER(vp), ctypes.POINTER(sz), PP,
+                                     vp, sz, vp]
+        L.dkss_batch_workspace_bytes.argtypes = [vp, sz, ctypes.POINTER(sz), ctypes.POINTER(sz), PP,
+                                                 ctypes.POINTER(sz)]
+        L.dkss_forward.argtypes = [vp, vp, vp, sz, sz, PP, vp, sz, vp]
+        L.dkss_residues.argtypes = [vp, sz, ctypes.POINTER(u64), sz, vp, vp]
+        L.dkss_profile_enable.argtypes = [vp, ctypes.c_int]
+        L.dkss_profile_read.argtypes = [vp, ctypes.c_int, ctypes.POINTER(KernelStats)]
+        L.dkss_profile_reset.argtypes = [vp]
+        L.dkss_kernel_name.argtypes = [ctypes.c_int]
+        L.dkss_kernel_name.restype = ctypes.c_char_p
+        L.dkss_strerror.argtypes = [ctypes.c_int]
+        L.dkss_strerror.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+EXPORTED = ["dkss_ctx_create", "dkss_ctx_destroy", "dkss_select_params", "dkss_plan_info",
+            "dkss_workspace_bytes", "dkss_prepare", "dkss_mul", "dkss_mul_batch",
+            "dkss_batch_workspace_bytes", "dkss_forward", "dkss_residues", "dkss_profile_enable",
+            "dkss_profile_read", "dkss_profile_reset", "dkss_kernel_name", "dkss_strerror"]
+
+
+def _check(rc, what):
+    if rc != OK:
+        raise DkssError(rc, what)
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_ptr(stream):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None and t.numel() else ctypes.c_void_p(0)
+
+
+def _pp(params):
+    return ctypes.byref(params) if params is not None else None
+
+
+def to_device(limbs, device="cuda"):
+    """numpy uint32 limbs -> torch.int32 device tensor (same bits)."""
+    torch = _torch()
+    arr = np.ascontiguousarray(limbs, dtype=np.uint32).view(np.int32)
+    return torch.from_numpy(arr.copy()).to(device)
+
+
+def to_host(t):
+    """torch.int32 device tensor -> numpy uint32 limbs."""
+    return t.detach().cpu().numpy().view(np.uint32)
+
+
+def _alloc_ws(nbytes, device):
+    torch = _torch()
+    # torch's caching allocator returns blocks aligned to at least 512 bytes
+    return torch.empty(max(nbytes, 1), dtype=torch.uint8, device=device)
+
+
+class Context:
+    """A libdkss context: cached parameter constants and device tables."""
+
+    def __init__(self, policy=POLICY_THESIS):
+        h = ctypes.c_void_p()
+        _check(lib().dkss_ctx_create(ctypes.byref(h), policy, None), "dkss_ctx_create")
+        self._h = h
+
+    def close(self):
+        if self._h:
+            lib().dkss_ctx_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def select_params(self, a_bits, b_bits, batch=1):
+        p = Params()
+        _check(lib().dkss_select_params(self._h, a_bits, b_bits, batch, ctypes.byref(p)),
+               "dkss_select_params")
+        return p
+
+    def plan_info(self, alen, blen, params=None):
+        out = Plan()
+        _check(lib().dkss_plan_info(self._h, alen, blen, _pp(params), ctypes.byref(out)),
+               "dkss_plan_info")
+        return out
+
+    def workspace_bytes(self, alen, blen, params=None):
+        n = ctypes.c_size_t()
+        _check(lib().dkss_workspace_bytes(self._h, alen, blen, _pp(params), ctypes.byref(n)),
+               "dkss_workspace_bytes")
+        return n.value
+
+    def prepare(self, alen, blen, params=None, stream=None):
+        _check(lib().dkss_prepare(self._h, alen, blen, _pp(params), _stream_ptr(stream)),
+               "dkss_prepare")
+
+    def mul(self, a, b, out=None, params=None, ws=None, stream=None):
+        """c = a * b for int32 (uint32-limb) device tensors; returns c (alen+blen limbs)."""
+        torch = _torch()
+        alen, blen = a.numel(), b.numel()
+        if out is None:
+            out = torch.empty(alen + blen, dtype=torch.int32, device=a.device)
+        if ws is None:
+            ws = _alloc_ws(self.workspace_bytes(alen, blen, params), a.device)
+        _check(lib().dkss_mul(self._h, _ptr(out), _ptr(a), alen, _ptr(b), blen, _pp(params),
+                              _ptr(ws), ws.numel(), _stream_ptr(stream)), "dkss_mul")
+        return out
+
+    def mul_batch(self, as_, bs, outs=None, params=None, ws=None, stream=None):
+        torch = _torch()
+        n = len(as_)
+        if outs is None:
+            outs = [torch.empty(a.numel() + b.numel(), dtype=torch.int32, device=a.device)
+                    for a, b in zip(as_, bs)]
+        VP = ctypes.c_void_p * n
+        SZ = ctypes.c_size_t * n
+        al = SZ(*[a.numel() for a in as_])
+        bl = SZ(*[b.numel() for b in bs])
+        pa = None
+        if params is not None:
+            pa = (Params * n)(*params)
+        if ws is None:
+            nb = ctypes.c_size_t()
+            _check(lib().dkss_batch_workspace_bytes(self._h, n, al, bl, pa, ctypes.byref(nb)),
+                   "dkss_batch_workspace_bytes")
+            ws = _alloc_ws(nb.value, as_[0].device)
+        _check(lib().dkss_mul_batch(self._h, n, VP(*[_ptr(o) for o in outs]),
+                                    VP(*[_ptr(a) for a in as_]), al, VP(*[_ptr(b) for b in bs]),
+                                    bl, pa, _ptr(ws), ws.numel(), _stream_ptr(stream)),
+               "dkss_mul_batch")
+        return outs
+
+    def profile(self, on=True):
+        _check(lib().dkss_profile_enable(self._h, 1 if on else 0), "dkss_profile_enable")
+
+    def profile_reset(self):
+        _check(lib().dkss_profile_reset(self._h), "dkss_profile_reset")
+
+    def profile_read(self):
+        """{kernel name: KernelStats} for every kind launched since the last reset."""
+        out = {}
+        for k in range(KERNEL_KINDS):
+            st = KernelStats()
+            _check(lib().dkss_profile_read(self._h, k, ctypes.byref(st)), "dkss_profile_read")
+            if st.launches:
+                out[lib().dkss_kernel_name(k).decode()] = st
+        return out
+
+    def forward(self, a, blen, params=None, stream=None):
+        """encode + forward transform of a (operand pair a x blen limbs); natural order."""
+        torch = _torch()
+        plan = self.plan_info(a.numel(), blen, params)
+        poly = torch.empty(plan.poly_bytes // 4, dtype=torch.int32, device=a.device)
+        ws = _alloc_ws(self.workspace_bytes(a.numel(), blen, params), a.device)
+        _check(lib().dkss_forward(self._h, _ptr(poly), _ptr(a), a.numel(), blen, _pp(params),
+                                  _ptr(ws), ws.numel(), _stream_ptr(stream)), "dkss_forward")
+        return poly
+
+
+def residues(x, primes, stream=None):
+    """x mod q for each q in primes (odd, < 2^62), computed on the device."""
+    torch = _torch()
+    out = torch.empty(len(primes), dtype=torch.int64, device=x.device)
+    arr = (ctypes.c_uint64 * len(primes))(*primes)
+    _check(lib().dkss_residues(_ptr(x), x.numel(), arr, len(primes), _ptr(out),
+                               _stream_ptr(stream)), "dkss_residues")
+    return [int(v) & 0xFFFFFFFFFFFFFFFF for v in out.cpu().tolist()]

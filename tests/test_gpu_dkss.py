@@ -1,0 +1,222 @@
+"""GPU parity tests: the HIP path through the C ABI against the CPU oracle, bit-exact.
+
+Every product is exact integer arithmetic, so the bar is bit-exact equality: against the
+oracle's schoolbook product (small and mid sizes), the oracle's DKSS (2^24 bits), and residues
+modulo seeded random 61-bit primes computed by the oracle on the host (2^28 bits).  Intermediate
+parity: the GPU forward transform (natural order) against the oracle's FFT over R.
+"""
+import random
+
+import numpy as np
+import pytest
+
+import seeded_inputs as SI
+from oracle import coracle as C
+from oracle import params as OP
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    import paper_1503_04955_amd as dk
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    dk.lib()
+    return dk, torch, dk.Context()
+
+
+def _gpu_mul(env, a, b, params=None, square=False):
+    dk, torch, ctx = env
+    da = dk.to_device(a)
+    db = da if square else dk.to_device(b)
+    c = ctx.mul(da, db, params=params)
+    torch.cuda.synchronize()
+    return dk.to_host(c)
+
+
+def _primes61(seed, count):
+    rng = random.Random(seed)
+    out = []
+    while len(out) < count:
+        q = rng.getrandbits(61) | (1 << 60) | 1
+        if _isprime(q):
+            out.append(q)
+    return out
+
+
+def _isprime(n):
+    if n % 2 == 0:
+        return False
+    d, s = n - 1, 0
+    while d % 2 == 0:
+        d //= 2
+        s += 1
+    for a in (2, 3, 5, 7, 11, 13, 17, 19, 23, 29, 31, 37):
+        x = pow(a, d, n)
+        if x in (1, n - 1):
+            continue
+        for _ in range(s - 1):
+            x = x * x % n
+            if x == n - 1:
+                break
+        else:
+            return False
+    return True
+
+
+def _residue_check(a, b, c, primes):
+    for q in primes:
+        assert C.residue(c, q) == C.residue(a, q) * C.residue(b, q) % q, q
+
+
+def _params(dk, log2_M, log2_m, u=0, p_bits=128, z=1, radices=None):
+    return dk.Params.make(log2_M, log2_m, u, p_bits, z, radices=radices, cutoff_bits=0)
+
+
+# ---- intermediate: the forward transform ------------------------------------------------------
+
+FWD = [  # (log2_M, log2_m, u, p_bits, z, radices, alen)
+    (3, 2, 16, 64, 1, None, 4),              # 2M = 16 = 2m*2
+    (4, 2, 20, 64, 1, None, 8),              # 2M = 32: radices 8, 4
+    (5, 3, 24, 128, 1, None, 16),            # 2M = 64 = (2m)^2
+    (5, 2, 24, 32, 4, None, 16),             # z = 4, q = p^4 with a 32-bit p
+    (6, 2, 24, 64, 1, [1, 2, 3, 1], 24),     # forced split including radix 2
+    (9, 4, 32, 128, 1, None, 256),           # C1-like ring, 2M = 1024 = 32 * 32
+    (7, 3, 40, 192, 1, None, 64),            # L = 6
+]
+
+
+@pytest.mark.parametrize("case", FWD, ids=lambda c: "M%d_m%d_u%d_p%d_z%d_%s" % c[:6])
+def test_forward_transform_matches_oracle_fft(env, case):
+    dk, torch, ctx = env
+    log2_M, log2_m, u, p_bits, z, radices, alen = case
+    params = _params(dk, log2_M, log2_m, u, p_bits, z, radices)
+    pr = OP.Params(N=32 * alen, log2_M=log2_M, log2_m=log2_m, u=u, p_bits=p_bits, z=z)
+    S = OP.setup(pr)
+    a = SI.limbs(1000 + log2_M, alen)
+    got = dk.to_host(ctx.forward(dk.to_device(a), alen, params))
+    torch.cuda.synchronize()
+    want = C.fft(C.encode(a, pr.M, pr.m, S.L, u), 2 * pr.M, pr.m, S.L, S.q, S.rho)
+    assert np.array_equal(got, want)
+
+
+# ---- whole products, explicit parameter tuples ----------------------------------------------
+
+MUL = [  # (log2_M, log2_m, u, p_bits, z, radices)
+    (1, 1, 32, 128, 1, None),
+    (3, 2, 16, 64, 1, None),
+    (4, 3, 30, 128, 1, None),
+    (5, 2, 24, 32, 4, None),
+    (5, 3, 40, 32, 3, None),
+    (6, 2, 24, 64, 1, [1, 2, 3, 1]),
+    (8, 5, 32, 128, 1, None),               # m = 32, one level of radix 64 + ...
+    (9, 4, 57, 128, 1, None),               # the thesis's u = 57 ring
+    (7, 3, 64, 192, 1, None),
+    (6, 6, 32, 128, 1, None),               # m = 64: radix capped below 2m
+    (10, 4, 60, 256, 1, None),              # L = 8
+]
+
+
+@pytest.mark.parametrize("case", MUL, ids=lambda c: "M%d_m%d_u%d_p%d_z%d_%s" % c)
+def test_mul_parameter_tuples(env, case):
+    dk = env[0]
+    log2_M, log2_m, u, p_bits, z, radices = case
+    cap = (1 << log2_M) * (1 << log2_m) // 2 * u // 32
+    for alen, blen, seed in [(cap, cap, 1), (cap, max(1, cap // 8), 2), (max(1, cap // 3), cap, 3)]:
+        print("case", case, alen, blen, flush=True)
+        a, b = SI.operand_pair(seed + 10 * log2_M, alen, blen)
+        got = _gpu_mul(env, a, b, _params(dk, log2_M, log2_m, u, p_bits, z, radices))
+        assert np.array_equal(got, C.schoolbook(a, b))
+
+
+# ---- the thesis rule at 2^18 bits (the small configuration) and edge operands --------------
+
+def test_mul_2e18_thesis_rule(env):
+    a, b = SI.operand_pair(SI.SEED_BASE + 0, 8192, 8192)
+    assert np.array_equal(_gpu_mul(env, a, b), C.schoolbook(a, b))
+
+
+@pytest.mark.parametrize("kind", ["ones", "ones_favorable", "pow2", "square", "unbalanced",
+                                  "one_limb", "favorable_plus_one"])
+def test_mul_edge_operands(env, kind):
+    if kind == "ones":
+        a = b = SI.all_ones(8192)
+    elif kind == "ones_favorable":
+        a = b = SI.all_ones(7296)           # 3648 64-bit words: u = 57 meets the bound exactly
+    elif kind == "pow2":
+        a, b = SI.power_of_two(8192 * 32 - 1, 8192), SI.power_of_two(12345, 8192)
+    elif kind == "square":
+        a = SI.limbs(77, 8192)
+        got = _gpu_mul(env, a, a, square=True)
+        assert np.array_equal(got, C.schoolbook(a, a))
+        return
+    elif kind == "unbalanced":
+        a, b = SI.operand_pair(5, 8192, 1024)
+    elif kind == "one_limb":
+        a, b = SI.operand_pair(6, 8192, 1)
+        a[-1] = 0xFFFFFFFF
+        b[0] = 0xFFFFFFFF
+    else:
+        a, b = SI.operand_pair(8, 7297, 7297)
+    assert np.array_equal(_gpu_mul(env, a, b), C.schoolbook(a, b))
+
+
+def test_mul_zero_length_and_schoolbook_path(env):
+    dk, torch, ctx = env
+    a = SI.limbs(3, 40)
+    out = ctx.mul(dk.to_device(a), dk.to_device(np.zeros(0, np.uint32)))
+    torch.cuda.synchronize()
+    assert np.array_equal(dk.to_host(out), np.zeros(40, np.uint32))
+    for alen, blen in [(1, 1), (5, 64), (64, 64), (700, 30), (2000, 60)]:
+        a, b = SI.operand_pair(alen + blen, alen, blen)
+        assert np.array_equal(_gpu_mul(env, a, b), C.schoolbook(a, b)), (alen, blen)
+
+
+# ---- the large configurations: 2^24 and 2^28 bits --------------------------------------------
+
+def test_mul_2e24_vs_oracle_dkss(env):
+    a, b = SI.operand_pair(SI.SEED_BASE + 1, 1 << 19, 1 << 19)
+    got = _gpu_mul(env, a, b)
+    assert np.array_equal(got, C.dkss_mul(a, b))
+    _residue_check(a, b, got, _primes61(1, 8))
+
+
+@pytest.mark.parametrize("kind", ["random", "ones", "square", "unbalanced"])
+def test_mul_2e28_residues(env, kind):
+    n = 1 << 23
+    if kind == "random":
+        a, b = SI.operand_pair(SI.SEED_BASE + 2, n, n)
+    elif kind == "ones":
+        a = b = SI.all_ones(n)
+    elif kind == "square":
+        a = SI.limbs(SI.SEED_BASE + 3, n)
+        got = _gpu_mul(env, a, a, square=True)
+        _residue_check(a, a, got, _primes61(2, 8))
+        return
+    else:
+        a, b = SI.operand_pair(SI.SEED_BASE + 4, n, n // 8)
+    got = _gpu_mul(env, a, b)
+    _residue_check(a, b, got, _primes61(3, 8))
+    if kind == "ones":
+        # (2^N - 1)^2 = 2^(2N) - 2^(N+1) + 1: low limb 1, limbs 1..n-1 zero, limb n = 0xFFFFFFFE
+        assert got[0] == 1 and not got[1:n].any() and got[n] == 0xFFFFFFFE
+        assert (got[n + 1:] == 0xFFFFFFFF).all()
+
+
+def test_gpu_residues_match_oracle(env):
+    dk, torch, ctx = env
+    x = SI.limbs(99, 300001)
+    primes = _primes61(4, 5) + [3, 2 ** 61 - 1]
+    got = dk.residues(dk.to_device(x), primes)
+    assert got == [C.residue(x, q) for q in primes]
+
+
+def test_workspace_too_small(env):
+    dk, torch, ctx = env
+    a = dk.to_device(SI.limbs(1, 8192))
+    ws = torch.empty(1024, dtype=torch.uint8, device="cuda")
+    with pytest.raises(dk.DkssError) as e:
+        ctx.mul(a, a, ws=ws)
+    assert e.value.code == dk.ENOSPC

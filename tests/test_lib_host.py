@@ -1,0 +1,99 @@
+"""CPU-side checks of libdkss: exported symbols, host planning against the oracle's rule and
+prime, argument errors that are decided before any device work."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from oracle import params as OP
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def dk():
+    import paper_1503_04955_amd as dk
+    try:
+        dk.lib()
+    except RuntimeError:
+        from paper_1503_04955_amd import build
+        build.build()
+    return dk
+
+
+def test_header_symbols_exported(dk):
+    hdr = open(os.path.join(ROOT, "include", "dkss.h")).read()
+    names = set(re.findall(r"\b(dkss_[a-z_]+)\s*\(", hdr))
+    assert names == set(dk.EXPORTED)
+    L = dk.lib()
+    for n in names:
+        assert hasattr(L, n), n
+
+
+@pytest.mark.parametrize("N", [2 ** 12, 5000 * 32, 2 ** 18, 233472, 2 ** 24, 2 ** 28, 2 ** 30,
+                               2 ** 34, 64 * 1703936, 64 * 85983232])
+def test_planner_matches_oracle_rule(dk, N):
+    ctx = dk.Context()
+    p = ctx.select_params(N, N)
+    o = OP.thesis_rule(N)
+    assert (p.log2_M, p.log2_m, p.u, p.p_bits, p.z) == (o.log2_M, o.log2_m, o.u, o.p_bits, 1)
+    assert sum(p.radix_log2[i] for i in range(p.n_levels)) == o.log2_M + 1
+
+
+@pytest.mark.parametrize("N", [2 ** 12, 2 ** 18, 2 ** 24, 2 ** 28])
+def test_planner_prime_matches_oracle(dk, N):
+    ctx = dk.Context()
+    n = N // 32
+    info = ctx.plan_info(n, n, dk.Params.make(*_rule(N), cutoff_bits=0))
+    o = OP.thesis_rule(N)
+    p, h, nn = OP.proth_prime(o.p_bits, o.log2_M + 1)
+    assert info.modulus == p and info.q_bits == p.bit_length()
+    assert info.poly_bytes == (2 * o.M) * o.m * info.L * 4
+
+
+def _rule(N):
+    o = OP.thesis_rule(N)
+    return o.log2_M, o.log2_m, o.u, o.p_bits, o.z
+
+
+def test_planner_prime_power(dk):
+    """z > 1: the modulus is p^z for the 32-bit p = 3*2^30 + 1 of the oracle."""
+    ctx = dk.Context()
+    info = ctx.plan_info(48, 48, dk.Params.make(5, 2, 24, 32, 4, cutoff_bits=0))
+    assert info.modulus == (3 * 2 ** 30 + 1) ** 4
+
+
+def test_errors_before_device_work(dk):
+    ctx = dk.Context()
+    # p^z below Mm 2^(2u)
+    with pytest.raises(dk.DkssError) as e:
+        ctx.plan_info(64, 64, dk.Params.make(5, 2, 60, 64, 1, cutoff_bits=0))
+    assert e.value.code == dk.ERANGE
+    # capacity M m/2 u below the operand
+    with pytest.raises(dk.DkssError) as e:
+        ctx.plan_info(4096, 4096, dk.Params.make(5, 2, 20, 128, 1, cutoff_bits=0))
+    assert e.value.code == dk.ERANGE
+    # radices not summing to log2(2M), radix above 2m
+    with pytest.raises(dk.DkssError):
+        ctx.plan_info(64, 64, dk.Params.make(5, 2, 0, 128, 1, radices=[3, 2], cutoff_bits=0))
+    with pytest.raises(dk.DkssError):
+        ctx.plan_info(64, 64, dk.Params.make(5, 2, 0, 128, 1, radices=[4, 2], cutoff_bits=0))
+    # M < m
+    with pytest.raises(dk.DkssError):
+        ctx.plan_info(64, 64, dk.Params.make(2, 3, 0, 128, 1, cutoff_bits=0))
+    L = dk.lib()
+    assert L.dkss_mul(None, None, None, 0, None, 0, None, None, 0, None) == dk.EINVAL
+    assert L.dkss_ctx_create(None, 0, None) == dk.EINVAL
+    h = ctypes.c_void_p()
+    assert L.dkss_ctx_create(ctypes.byref(h), 7, None) == dk.EINVAL
+    assert L.dkss_strerror(dk.ENOSPC) == b"workspace too small"
+
+
+def test_workspace_and_schoolbook_routing(dk):
+    ctx = dk.Context()
+    assert ctx.workspace_bytes(0, 100) == 0
+    assert ctx.plan_info(16, 16).schoolbook == 1          # below the default cutoff
+    info = ctx.plan_info(8192, 8192)
+    assert info.schoolbook == 0
+    assert ctx.workspace_bytes(8192, 8192) >= 2 * info.poly_bytes
