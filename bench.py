@@ -87,6 +87,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--bits", type=int, default=28)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--overlap", type=int, default=1, help="transform b on a second stream")
+    ap.add_argument("--dft-lds", type=int, default=65536, help="LDS bytes per FFT-level workgroup")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -103,6 +105,8 @@ def main():
     a, b = dk.to_device(a_h, dev), dk.to_device(b_h, dev)
     c = torch.empty(2 * n, dtype=torch.int32, device=dev)
     ctx = dk.Context()
+    ctx.set_option(dk.OPT_OVERLAP, args.overlap)
+    ctx.set_option(dk.OPT_DFT_LDS, args.dft_lds)
     params = ctx.select_params(32 * n, 32 * n)
     plan = ctx.plan_info(n, n)
     ws = torch.empty(ctx.workspace_bytes(n, n), dtype=torch.uint8, device=dev)
@@ -164,7 +168,8 @@ def main():
         "data": "synthetic (seeded uniform uint32 limbs)",
         "config": {"workload": "plain DKSS, one product of two 2^%d-bit operands (%d uint32 limbs "
                                "each), thesis-rule parameters" % (args.bits, n),
-                   "params": params.as_dict(), "L": plan.L},
+                   "params": params.as_dict(), "L": plan.L, "overlap": args.overlap,
+                   "dft_lds": args.dft_lds},
         "verified": "residues mod 8 random 61-bit primes",
         "roofline": roofline, "roofline_fft": roofline_fft, "kernels": kernels,
     }

@@ -176,6 +176,17 @@ int dkss_profile_reset(dkss_ctx* ctx);
 /* Name of a kernel kind, e.g. "k_twiddle"; NULL for an unknown kind. */
 const char* dkss_kernel_name(int kind);
 
+/*
+ * Context options (tuning knobs; none changes any result bit).
+ *  DKSS_OPT_OVERLAP      1 (default): the forward transform of b runs on a second, internal
+ *                        stream of the context, forked from and joined back to the caller's
+ *                        stream with events, so it overlaps the transform of a; 0: one stream.
+ *  DKSS_OPT_DFT_LDS      LDS bytes an FFT-level workgroup may stage (default 65536; 16384 to
+ *                        163840): more columns per workgroup versus more workgroups per CU.
+ */
+enum { DKSS_OPT_OVERLAP = 0, DKSS_OPT_DFT_LDS = 1 };
+int dkss_set_option(dkss_ctx* ctx, int option, long long value);
+
 /* Static description of an error code. */
 const char* dkss_strerror(int code);
 

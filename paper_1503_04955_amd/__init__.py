@@ -99,6 +99,7 @@ def lib():
         L.dkss_profile_reset.argtypes = [vp]
         L.dkss_kernel_name.argtypes = [ctypes.c_int]
         L.dkss_kernel_name.restype = ctypes.c_char_p
+        L.dkss_set_option.argtypes = [vp, ctypes.c_int, ctypes.c_longlong]
         L.dkss_strerror.argtypes = [ctypes.c_int]
         L.dkss_strerror.restype = ctypes.c_char_p
         _lib = L
@@ -108,7 +109,10 @@ def lib():
 EXPORTED = ["dkss_ctx_create", "dkss_ctx_destroy", "dkss_select_params", "dkss_plan_info",
             "dkss_workspace_bytes", "dkss_prepare", "dkss_mul", "dkss_mul_batch",
             "dkss_batch_workspace_bytes", "dkss_forward", "dkss_residues", "dkss_profile_enable",
-            "dkss_profile_read", "dkss_profile_reset", "dkss_kernel_name", "dkss_strerror"]
+            "dkss_profile_read", "dkss_profile_reset", "dkss_kernel_name", "dkss_set_option",
+            "dkss_strerror"]
+
+OPT_OVERLAP, OPT_DFT_LDS = 0, 1
 
 
 def _check(rc, what):
@@ -229,6 +233,9 @@ class Context:
                                     bl, pa, _ptr(ws), ws.numel(), _stream_ptr(stream)),
                "dkss_mul_batch")
         return outs
+
+    def set_option(self, option, value):
+        _check(lib().dkss_set_option(self._h, option, int(value)), "dkss_set_option")
 
     def profile(self, on=True):
         _check(lib().dkss_profile_enable(self._h, 1 if on else 0), "dkss_profile_enable")

@@ -2,10 +2,10 @@
 //
 // Pipeline of one product c = a*b (thesis Sec. 3.2, Steps 4-8), all on one HIP stream:
 //   k_encode      Step 4 (Sec. 3.2.4): operand bits -> 2M elements of R, u bits per coefficient
-//   k_dft         Step 5 (Sec. 3.2.5 i/iii): one FFT level = independent radix-r DFTs with root
+//   k_level       Step 5 (Sec. 3.2.5 i/iii): one FFT level = independent radix-r DFTs with root
 //                 alpha^(2m/r) over columns of stride mu, staged in LDS; every butterfly
 //                 multiplies by a power of alpha, i.e. rotates and negates coefficients
-//   k_twiddle     Step 5 (Sec. 3.2.5 ii): the "bad multiplications" by rho^(base*l*v) between
+//                 + (Sec. 3.2.5 ii) the "bad multiplications" by rho^(base*l*v) between
 //                 levels; rho^e = alpha^(e div mu_top) rho^(e mod mu_top) (Sec. 4.2), the alpha
 //                 power folded into the product's indexing
 //   k_pointwise   Step 6 (Sec. 3.2.6): componentwise products in R, scaled by (2M)^-1
@@ -39,7 +39,7 @@ using namespace dkss;
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kTaskMax = 4;              // radix-2 butterfly tasks per thread per pass
+
 constexpr uint64_t kDefaultCutoffBits = 2048;
 constexpr size_t kSchoolbookMaxWords = 4096;   // alen + blen of the base case
 
@@ -53,291 +53,355 @@ __device__ __forceinline__ int bitrev(int x, int bits) {
 // Step 4: encode
 // ---------------------------------------------------------------------------------------------
 
-// poly: 2M elements x m coefficients x L limbs.  Coefficient k < m/2 of element i < M gets bits
+// poly: 2M elements x m coefficients x D digits.  Coefficient k < m/2 of element i < M gets bits
 // [u (i m/2 + k), u (i m/2 + k) + u) of a; all others are zero.
 template <int L>
 __global__ __launch_bounds__(kThreads) void k_encode(uint32_t* __restrict__ poly,
                                                      const uint32_t* __restrict__ a, long long alen,
                                                      long long M, int log2m, int u) {
+    constexpr int D = Dig<L>::D;
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const long long total = (2 * M) << log2m;
     if (t >= total) return;
     const int m = 1 << log2m;
     const long long i = t >> log2m;
     const int k = (int)(t & (m - 1));
-    uint32_t out[L];
+    uint32_t out[D];
 #pragma unroll
-    for (int w = 0; w < L; ++w) out[w] = 0;
+    for (int w = 0; w < D; ++w) out[w] = 0;
     if (i < M && k < m / 2) {
         const unsigned long long pos = ((unsigned long long)i * (m / 2) + k) * (unsigned)u;
 #pragma unroll
-        for (int w = 0; w < L; ++w) {
-            const int nb = u - 32 * w;
+        for (int w = 0; w < D; ++w) {
+            const int nb = u - 28 * w;
             if (nb > 0) {
-                const unsigned long long bit = pos + 32ull * w;
+                const unsigned long long bit = pos + 28ull * w;
                 const long long wi = (long long)(bit >> 5);
                 const int sh = (int)(bit & 31);
                 const uint64_t lo = wi < alen ? a[wi] : 0u;
                 const uint64_t hi = wi + 1 < alen ? a[wi + 1] : 0u;
-                uint32_t v = (uint32_t)(((hi << 32) | lo) >> sh);
-                if (nb < 32) v &= (1u << nb) - 1u;
+                uint32_t v = (uint32_t)(((hi << 32) | lo) >> sh) & kMask28;
+                if (nb < 28) v &= (1u << nb) - 1u;
                 out[w] = v;
             }
         }
     }
-    uint32_t* dst = poly + (size_t)t * L;
+    uint32_t* dst = poly + (size_t)t * D;
 #pragma unroll
-    for (int w = 0; w < L; ++w) dst[w] = out[w];
+    for (int w = 0; w < D; ++w) dst[w] = out[w];
 }
 
 // ---------------------------------------------------------------------------------------------
-// Step 5: one FFT level of radix-r DFTs with root alpha^(+-2m/r)
+// Step 5: one FFT level (radix-r DFTs with root alpha^(+-2m/r)), with the twiddle products fused
 // ---------------------------------------------------------------------------------------------
 
-// Columns: the level has 2M/n_lvl blocks of n_lvl elements; within a block, column l < mu holds
-// elements l, l + mu, ..., l + (r-1) mu.  A workgroup takes C consecutive columns, loads them
-// into LDS in bit-reversed order and runs log2 r radix-2 decimation-in-time passes; the pass that
-// merges halves of h points multiplies the odd half by alpha^((m/h) k), k < h (alpha^-... for the
-// inverse).  Output v goes to element l + v mu.
+// The level has 2M/n_lvl blocks of n_lvl elements; within a block, column l < mu holds elements
+// l, l + mu, ..., l + (r-1) mu.  A workgroup takes C = 2^log2C consecutive columns (C r
+// elements) and
+//   mode 0: loads them, runs the radix-r DFT, stores them;
+//   mode 1 (forward): loads, DFT, then multiplies output v of column l by rho^(base l v) (the bad
+//           multiplications of Sec. 3.2.5 ii) on its way back to HBM;
+//   mode 2 (inverse): loads, multiplies input v by rho^-(base l v), runs the DFT with alpha^-1,
+//           stores.
+// The DFT: inputs in bit-reversed LDS slots, log2 r radix-2 decimation-in-time passes between two
+// LDS buffers; the pass merging halves of h points multiplies the odd half by alpha^((m/h) k),
+// k < h (alpha^-((m/h) k) for the inverse).  Output v ends in slot v.  Twiddle products run in
+// rounds of 256/m elements, one output coefficient per thread: the element's digits are read in
+// place from the column buffer, the table entry rho^s (with its negation, Montgomery form) is
+// staged in the free buffer.
+struct LevelArgs {
+    long long twoM, base, mu_top;
+    int log2nl, log2mu, log2r, log2m, log2C;
+    int mode, inverse;
+    int rb_separate;              // 1: the twiddle staging area follows both column buffers
+};
+
+__device__ __forceinline__ long long level_pos(const LevelArgs& A, long long c0, int c, int j) {
+    const long long col = c0 + c;
+    const long long b = col >> A.log2mu, l = col & ((1LL << A.log2mu) - 1);
+    return (b << A.log2nl) + ((long long)j << A.log2mu) + l;
+}
+
+// Copies between the workgroup's C r elements in HBM and LDS.  Element index e: column c
+// fastest, then position j; LDS slot bitrev(j) on the way in, slot v on the way out.
 template <int L>
-__global__ __launch_bounds__(kThreads) void k_dft(uint32_t* __restrict__ poly, long long n_lvl,
-                                                  long long mu, int log2r, int log2m, int C,
-                                                  long long ncols, int inverse, QConst Q) {
-    extern __shared__ uint32_t sm[];
-    const int m = 1 << log2m, r = 1 << log2r;
-    const int EW = m * L;
-    const long long c0 = (long long)blockIdx.x * C;
-    const int ncol = (int)min((long long)C, ncols - c0);
-    const int total = ncol * r * EW;
-    for (int t = threadIdx.x; t < total; t += blockDim.x) {
-        const int wk = t % EW;
-        const int rest = t / EW;
-        const int c = rest % ncol;
-        const int j1 = rest / ncol;
-        const long long col = c0 + c;
-        const long long b = col / mu, l = col - b * mu;
-        const long long el = b * n_lvl + (long long)j1 * mu + l;
-        sm[(c * r + bitrev(j1, log2r)) * EW + wk] = poly[(size_t)el * EW + wk];
+__device__ __forceinline__ void level_copy_in(uint32_t* cur, const uint32_t* __restrict__ poly,
+                                              const LevelArgs& A, long long c0) {
+    constexpr int D = Dig<L>::D;
+    const int EW = D << A.log2m;
+    const int nel = 1 << (A.log2C + A.log2r);
+    if ((EW & 3) == 0) {
+        const int EV = EW >> 2;
+        const int total = nel * EV;
+        uint4* cv = reinterpret_cast<uint4*>(cur);
+        const uint4* gv = reinterpret_cast<const uint4*>(poly);
+#pragma unroll 4
+        for (int t = threadIdx.x; t < total; t += kThreads) {
+            const int e = ((t << 2) >> A.log2m) / D;
+            const int wk = t - e * EV;
+            const int c = e & ((1 << A.log2C) - 1), j = e >> A.log2C;
+            const long long pos = level_pos(A, c0, c, j);
+            cv[((c << A.log2r) + bitrev(j, A.log2r)) * EV + wk] = gv[(size_t)pos * EV + wk];
+        }
+    } else {
+        const int total = nel * EW;
+        for (int t = threadIdx.x; t < total; t += kThreads) {
+            const int e = (t >> A.log2m) / D;
+            const int wk = t - e * EW;
+            const int c = e & ((1 << A.log2C) - 1), j = e >> A.log2C;
+            const long long pos = level_pos(A, c0, c, j);
+            cur[((c << A.log2r) + bitrev(j, A.log2r)) * EW + wk] = poly[(size_t)pos * EW + wk];
+        }
     }
-    __syncthreads();
-    const int half_r = r >> 1;
-    const int tasks = ncol * half_r * m;
-    for (int h = 1; h < r; h <<= 1) {
-        uint32_t nx[kTaskMax][L], ny[kTaskMax][L];
-        const int mh = m / h;
+}
+
+template <int L>
+__device__ __forceinline__ void level_copy_out(uint32_t* __restrict__ poly, const uint32_t* cur,
+                                               const LevelArgs& A, long long c0) {
+    constexpr int D = Dig<L>::D;
+    const int EW = D << A.log2m;
+    const int nel = 1 << (A.log2C + A.log2r);
+    if ((EW & 3) == 0) {
+        const int EV = EW >> 2;
+        const int total = nel * EV;
+        const uint4* cv = reinterpret_cast<const uint4*>(cur);
+        uint4* gv = reinterpret_cast<uint4*>(poly);
+#pragma unroll 4
+        for (int t = threadIdx.x; t < total; t += kThreads) {
+            const int e = ((t << 2) >> A.log2m) / D;
+            const int wk = t - e * EV;
+            const int c = e & ((1 << A.log2C) - 1), v = e >> A.log2C;
+            const long long pos = level_pos(A, c0, c, v);
+            gv[(size_t)pos * EV + wk] = cv[((c << A.log2r) + v) * EV + wk];
+        }
+    } else {
+        const int total = nel * EW;
+        for (int t = threadIdx.x; t < total; t += kThreads) {
+            const int e = (t >> A.log2m) / D;
+            const int wk = t - e * EW;
+            const int c = e & ((1 << A.log2C) - 1), v = e >> A.log2C;
+            const long long pos = level_pos(A, c0, c, v);
+            poly[(size_t)pos * EW + wk] = cur[((c << A.log2r) + v) * EW + wk];
+        }
+    }
+}
+
+// Twiddle products of all C r elements of the workgroup, in rounds of 256/m elements.  The
+// element with position v in column c sits in LDS slot v (after the DFT, mode 1) or bitrev(v)
+// (before it, mode 2).  Mode 1 writes results to HBM; mode 2 writes them back into the slot once
+// the round's products (which read the slot) are done.
+template <int L>
+__device__ __forceinline__ void level_twiddle(uint32_t* cur, uint32_t* RB, uint32_t* __restrict__ poly,
+                                              const uint32_t* __restrict__ table, const LevelArgs& A,
+                                              long long c0, const QConst& Q) {
+    constexpr int D = Dig<L>::D;
+    const int m = 1 << A.log2m;
+    const int EW = D << A.log2m;
+    const int per = kThreads >> A.log2m;
+    const int g = threadIdx.x >> A.log2m, j = threadIdx.x & (m - 1);
+    const int nel = 1 << (A.log2C + A.log2r);
+    uint32_t* TP = RB + g * 2 * m * D;
+    for (int r0 = 0; r0 < nel; r0 += per) {
+        const int el = r0 + g;                          // (c, v) with v fastest
+        const bool valid = el < nel;
+        const int c = el >> A.log2r, v = el & ((1 << A.log2r) - 1);
+        const int slot = A.mode == 1 ? v : bitrev(v, A.log2r);
+        uint32_t* X = cur + ((c << A.log2r) + slot) * EW;
+        long long e = 0;
+        if (valid) {
+            const long long l = (c0 + c) & ((1LL << A.log2mu) - 1);
+            e = A.base * l * v;                         // < 2M
+            if (A.inverse && e) e = A.twoM - e;
+        }
+        int rot = 0;
+        if (e) {
+            rot = (int)(e / A.mu_top);
+            const long long s = e - (long long)rot * A.mu_top;
+            const uint32_t* ts = table + (size_t)s * 2 * m * D;
 #pragma unroll
-        for (int it = 0; it < kTaskMax; ++it) {
-            const int t = threadIdx.x + it * kThreads;
-            if (t < tasks) {
-                const int jj = t & (m - 1);
-                const int rest = t >> log2m;
-                const int bf = rest % half_r;
-                const int c = rest / half_r;
-                const int kk = bf & (h - 1);
-                const int xs = (bf - kk) * 2 + kk;
-                const int ys = xs + h;
-                int e = kk * mh;
-                if (inverse) e = (2 * m - e) & (2 * m - 1);
-                // (alpha^e y)_jj = +- y_idx, negated once per wrap past degree m-1
-                int idx = jj - e;
-                bool neg = false;
+            for (int y = 0; y < D; ++y) {
+                TP[j * D + y] = ts[j * D + y];
+                TP[(j + m) * D + y] = ts[(j + m) * D + y];
+            }
+        }
+        __syncthreads();
+        uint32_t out[D];
+        if (valid) {
+            if (e) {
+                rprod_coeff<L>(TP, X, A.log2m, j, rot, Q, out);
+            } else {
+#pragma unroll
+                for (int y = 0; y < D; ++y) out[y] = X[j * D + y];
+            }
+            if (A.mode == 1) {
+                uint32_t* dst = poly + (size_t)level_pos(A, c0, c, v) * EW + j * D;
+#pragma unroll
+                for (int y = 0; y < D; ++y) dst[y] = out[y];
+            }
+        }
+        __syncthreads();
+        if (valid && A.mode == 2 && e) {
+#pragma unroll
+            for (int y = 0; y < D; ++y) X[j * D + y] = out[y];
+        }
+    }
+    if (A.mode == 2) __syncthreads();
+}
+
+template <int L>
+__global__ __launch_bounds__(kThreads) void k_level(uint32_t* __restrict__ poly,
+                                                    const uint32_t* __restrict__ table, LevelArgs A,
+                                                    QConst Q) {
+    constexpr int D = Dig<L>::D;
+    extern __shared__ uint4 smv[];
+    const int m = 1 << A.log2m, r = 1 << A.log2r;
+    const int EW = m * D;
+    const int ncw = (1 << (A.log2C + A.log2r)) * EW;     // words of the workgroup's columns
+    uint32_t* cur = reinterpret_cast<uint32_t*>(smv);
+    uint32_t* nxt = cur + ncw;
+    uint32_t* sep = nxt + ncw;                            // separate staging area, if any
+    const long long c0 = (long long)blockIdx.x << A.log2C;
+    level_copy_in<L>(cur, poly, A, c0);
+    __syncthreads();
+    if (A.mode == 2) level_twiddle<L>(cur, A.rb_separate ? sep : nxt, poly, table, A, c0, Q);
+    const int tasks = (1 << (A.log2C + A.log2r - 1)) << A.log2m;   // butterflies x coefficients
+    for (int h = 1, lh = 0; h < r; h <<= 1, ++lh) {
+        const int mh = m >> lh;
+        for (int t = threadIdx.x; t < tasks; t += kThreads) {
+            const int jj = t & (m - 1);
+            const int rest = t >> A.log2m;
+            const int bf = rest & ((r >> 1) - 1);
+            const int c = rest >> (A.log2r - 1);
+            const int kk = bf & (h - 1);
+            const int xs = ((bf - kk) << 1) + kk;
+            const int ys = xs + h;
+            int e = kk * mh;
+            if (A.inverse) e = (2 * m - e) & (2 * m - 1);
+            // (alpha^e y)_jj = +- y_idx, negated once per wrap past degree m-1
+            int idx = jj - e;
+            bool neg = false;
+            if (idx < 0) {
+                idx += m;
+                neg = true;
                 if (idx < 0) {
                     idx += m;
-                    neg = true;
-                    if (idx < 0) {
-                        idx += m;
-                        neg = false;
-                    }
+                    neg = false;
                 }
-                const uint32_t* X = sm + (c * r + xs) * EW + jj * L;
-                const uint32_t* Y = sm + (c * r + ys) * EW + idx * L;
-                uint32_t xv[L], yv[L], s[L], d[L];
+            }
+            const int cb = (c << A.log2r) * EW;
+            const uint32_t* X = cur + cb + xs * EW + jj * D;
+            const uint32_t* Y = cur + cb + ys * EW + idx * D;
+            uint32_t xv[D], yv[D], sv[D], dv[D];
 #pragma unroll
-                for (int w = 0; w < L; ++w) {
-                    xv[w] = X[w];
-                    yv[w] = Y[w];
-                }
-                mod_add<L>(s, xv, yv, Q);
-                mod_sub<L>(d, xv, yv, Q);
+            for (int w = 0; w < D; ++w) {
+                xv[w] = X[w];
+                yv[w] = Y[w];
+            }
+            dmod_add<L>(sv, xv, yv, Q);
+            dmod_sub<L>(dv, xv, yv, Q);
+            uint32_t* NX = nxt + cb + xs * EW + jj * D;
+            uint32_t* NY = nxt + cb + ys * EW + jj * D;
 #pragma unroll
-                for (int w = 0; w < L; ++w) {
-                    nx[it][w] = neg ? d[w] : s[w];
-                    ny[it][w] = neg ? s[w] : d[w];
-                }
+            for (int w = 0; w < D; ++w) {
+                NX[w] = neg ? dv[w] : sv[w];
+                NY[w] = neg ? sv[w] : dv[w];
             }
         }
         __syncthreads();
-#pragma unroll
-        for (int it = 0; it < kTaskMax; ++it) {
-            const int t = threadIdx.x + it * kThreads;
-            if (t < tasks) {
-                const int jj = t & (m - 1);
-                const int rest = t >> log2m;
-                const int bf = rest % half_r;
-                const int c = rest / half_r;
-                const int kk = bf & (h - 1);
-                const int xs = (bf - kk) * 2 + kk;
-                const int ys = xs + h;
-                uint32_t* X = sm + (c * r + xs) * EW + jj * L;
-                uint32_t* Y = sm + (c * r + ys) * EW + jj * L;
-#pragma unroll
-                for (int w = 0; w < L; ++w) {
-                    X[w] = nx[it][w];
-                    Y[w] = ny[it][w];
-                }
-            }
-        }
-        __syncthreads();
+        uint32_t* tmp = cur;
+        cur = nxt;
+        nxt = tmp;
     }
-    for (int t = threadIdx.x; t < total; t += blockDim.x) {
-        const int wk = t % EW;
-        const int rest = t / EW;
-        const int c = rest % ncol;
-        const int v = rest / ncol;
-        const long long col = c0 + c;
-        const long long b = col / mu, l = col - b * mu;
-        const long long el = b * n_lvl + (long long)v * mu + l;
-        poly[(size_t)el * EW + wk] = sm[(c * r + v) * EW + wk];
-    }
-}
-
-// ---------------------------------------------------------------------------------------------
-// Step 5 ii: bad multiplications, element (block, v, l) *= rho^(+-base l v)
-// ---------------------------------------------------------------------------------------------
-
-// m threads per element, 256/m elements per workgroup.  LDS per element: the m digits-coefficients
-// of the table entry rho^s (Montgomery form) and the 2m of the element's negacyclic extension.
-template <int L>
-__global__ __launch_bounds__(kThreads) void k_twiddle(uint32_t* __restrict__ poly,
-                                                      const uint32_t* __restrict__ table,
-                                                      long long twoM, long long n_lvl, long long mu,
-                                                      long long base, long long mu_top, int log2m,
-                                                      int inverse, QConst Q) {
-    using G = Dig<L>;
-    extern __shared__ uint32_t sm[];
-    const int m = 1 << log2m;
-    const int per = kThreads >> log2m;
-    const int g = threadIdx.x >> log2m, j = threadIdx.x & (m - 1);
-    uint32_t* T = sm + g * 3 * m * G::D;
-    uint32_t* E = T + m * G::D;
-    const long long p = (long long)blockIdx.x * per + g;
-    long long e = 0;
-    if (p < twoM) {
-        const long long o = p % n_lvl;
-        const long long v = o / mu, l = o - v * mu;
-        e = base * l * v;                       // < base * n_lvl = 2M
-        if (inverse && e) e = twoM - e;
-    }
-    const bool active = e != 0;
-    int rot = 0;
-    if (active) {
-        rot = (int)(e / mu_top);
-        const long long s = e - (long long)rot * mu_top;
-        uint32_t x[L], nx[L];
-        const uint32_t* src = poly + ((size_t)p * m + j) * L;
-#pragma unroll
-        for (int w = 0; w < L; ++w) x[w] = src[w];
-        neg_q<L>(nx, x, Q);
-        limbs_to_digits<L>(x, E + j * G::D);
-        limbs_to_digits<L>(nx, E + (j + m) * G::D);
-        const uint32_t* ts = table + ((size_t)s * m + j) * G::D;
-#pragma unroll
-        for (int y = 0; y < G::D; ++y) T[j * G::D + y] = ts[y];
-    }
-    __syncthreads();
-    if (active) {
-        uint32_t out[L];
-        rprod_coeff<L>(T, E, log2m, j, rot, Q, out);
-        uint32_t* dst = poly + ((size_t)p * m + j) * L;
-#pragma unroll
-        for (int w = 0; w < L; ++w) dst[w] = out[w];
-    }
+    if (A.mode == 1)
+        level_twiddle<L>(cur, A.rb_separate ? sep : nxt, poly, table, A, c0, Q);
+    else
+        level_copy_out<L>(poly, cur, A, c0);
 }
 
 // ---------------------------------------------------------------------------------------------
 // Step 6: componentwise products, A[i] = A[i] * B[i] (2M)^-1
 // ---------------------------------------------------------------------------------------------
 
+// m threads per element, 256/m elements per workgroup; LDS per element: a and q - a (2m
+// residues) and b (m residues), digits.
 template <int L>
 __global__ __launch_bounds__(kThreads) void k_pointwise(uint32_t* A, const uint32_t* B,
                                                         long long count, int log2m, QConst Q) {
-    using G = Dig<L>;
+    constexpr int D = Dig<L>::D;
     extern __shared__ uint32_t sm[];
     const int m = 1 << log2m;
     const int per = kThreads >> log2m;
     const int g = threadIdx.x >> log2m, j = threadIdx.x & (m - 1);
-    uint32_t* T = sm + g * 3 * m * G::D;
-    uint32_t* E = T + m * G::D;
+    uint32_t* TP = sm + g * 3 * m * D;
+    uint32_t* X = TP + 2 * m * D;
     const long long p = (long long)blockIdx.x * per + g;
     const bool active = p < count;
     if (active) {
-        uint32_t x[L], y[L], ny[L];
-        const uint32_t* sa = A + ((size_t)p * m + j) * L;
-        const uint32_t* sb = B + ((size_t)p * m + j) * L;
+        uint32_t x[D], nx[D];
+        const uint32_t* sa = A + ((size_t)p * m + j) * D;
+        const uint32_t* sb = B + ((size_t)p * m + j) * D;
 #pragma unroll
-        for (int w = 0; w < L; ++w) {
+        for (int w = 0; w < D; ++w) {
             x[w] = sa[w];
-            y[w] = sb[w];
+            X[j * D + w] = sb[w];
         }
-        neg_q<L>(ny, y, Q);
-        limbs_to_digits<L>(x, T + j * G::D);
-        limbs_to_digits<L>(y, E + j * G::D);
-        limbs_to_digits<L>(ny, E + (j + m) * G::D);
+        dneg_q<L>(nx, x, Q);
+#pragma unroll
+        for (int w = 0; w < D; ++w) {
+            TP[j * D + w] = x[w];
+            TP[(j + m) * D + w] = nx[w];
+        }
     }
     __syncthreads();
     if (active) {
-        uint32_t c[L], out[L];
-        rprod_coeff<L>(T, E, log2m, j, 0, Q, c);     // (a*b)_j 2^-28K
-        mont_scalar<L>(c, Q.kpw, Q, out);            // * (2M)^-1 2^28K
-        uint32_t* dst = A + ((size_t)p * m + j) * L;
+        uint32_t c[D], out[D];
+        rprod_coeff<L>(TP, X, log2m, j, 0, Q, c);     // (a*b)_j 2^-28K
+        mont_scalar<L>(c, Q.kpw, Q, out);             // * (2M)^-1 2^28K
+        uint32_t* dst = A + ((size_t)p * m + j) * D;
 #pragma unroll
-        for (int w = 0; w < L; ++w) dst[w] = out[w];
+        for (int w = 0; w < D; ++w) dst[w] = out[w];
     }
 }
 
 // ---------------------------------------------------------------------------------------------
-// Table of rho^s, s < mu_top, in Montgomery form, 28-bit digits.  One launch computes
-// table[dst + j] = table[src + j] * table[mul] for j < cnt (all in Montgomery form).
+// Table of rho^s, s < mu_top, Montgomery form: entry s = m digits-residues of rho^s followed by
+// their negations.  One launch computes table[dst + j] = table[src + j] * table[mul], j < cnt.
 // ---------------------------------------------------------------------------------------------
 
 template <int L>
 __global__ __launch_bounds__(kThreads) void k_table_mul(uint32_t* table, long long src, long long mul,
                                                         long long dst, long long cnt, int log2m,
                                                         QConst Q) {
-    using G = Dig<L>;
+    constexpr int D = Dig<L>::D;
     extern __shared__ uint32_t sm[];
     const int m = 1 << log2m;
     const int per = kThreads >> log2m;
     const int g = threadIdx.x >> log2m, j = threadIdx.x & (m - 1);
-    uint32_t* T = sm + g * 3 * m * G::D;
-    uint32_t* E = T + m * G::D;
+    uint32_t* TP = sm + g * 3 * m * D;
+    uint32_t* X = TP + 2 * m * D;
     const long long jj = (long long)blockIdx.x * per + g;
     const bool active = jj < cnt;
     if (active) {
-        const uint32_t* xs = table + ((size_t)(src + jj) * m + j) * G::D;
-        const uint32_t* ts = table + ((size_t)mul * m + j) * G::D;
-        uint32_t xd[G::D + 1], x[L], nx[L];
+        const uint32_t* xs = table + (size_t)(src + jj) * 2 * m * D;
+        const uint32_t* ts = table + (size_t)mul * 2 * m * D;
 #pragma unroll
-        for (int y = 0; y < G::D; ++y) {
-            xd[y] = xs[y];
-            T[j * G::D + y] = ts[y];
+        for (int y = 0; y < D; ++y) {
+            X[j * D + y] = xs[j * D + y];
+            TP[j * D + y] = ts[j * D + y];
+            TP[(j + m) * D + y] = ts[(j + m) * D + y];
         }
-        xd[G::D] = 0;
-        digits_to_limbs<L>(xd, x);
-        neg_q<L>(nx, x, Q);
-#pragma unroll
-        for (int y = 0; y < G::D; ++y) E[j * G::D + y] = xd[y];
-        limbs_to_digits<L>(nx, E + (j + m) * G::D);
     }
     __syncthreads();
     if (active) {
-        uint32_t out[L];
-        rprod_coeff<L>(T, E, log2m, j, 0, Q, out);
-        uint32_t od[G::D];
-        limbs_to_digits<L>(out, od);
-        uint32_t* dst_p = table + ((size_t)(dst + jj) * m + j) * G::D;
+        uint32_t out[D], neg[D];
+        rprod_coeff<L>(TP, X, log2m, j, 0, Q, out);
+        dneg_q<L>(neg, out, Q);
+        uint32_t* dp = table + (size_t)(dst + jj) * 2 * m * D;
 #pragma unroll
-        for (int y = 0; y < G::D; ++y) dst_p[y] = od[y];
+        for (int y = 0; y < D; ++y) {
+            dp[j * D + y] = out[y];
+            dp[(j + m) * D + y] = neg[y];
+        }
     }
 }
 
@@ -346,13 +410,14 @@ __global__ __launch_bounds__(kThreads) void k_table_mul(uint32_t* table, long lo
 // ---------------------------------------------------------------------------------------------
 
 // Sum of the 32-bit pieces that the coefficients c_(l,k) (value sum c_(l,k) 2^(u (k + l m/2)))
-// put into output word w.  Coefficients are exact integers below 2^(32L).
+// put into output word w.  Coefficients are exact integers below q, in D digits.
 template <int L>
 __device__ __forceinline__ uint64_t word_sum(long long w, const uint32_t* __restrict__ poly,
                                              long long twoM, int log2m, int u) {
+    constexpr int D = Dig<L>::D;
     const int m = 1 << log2m;
     const int hm = m >> 1;
-    const long long lo_excl = 32 * w - 32 * L;            // piece iff u g > lo_excl
+    const long long lo_excl = 32 * w - 28 * D;            // piece iff u g > lo_excl
     const long long g_lo = lo_excl < 0 ? 0 : lo_excl / u + 1;
     const long long g_hi = (32 * w + 31) / u;
     uint64_t V = 0;
@@ -365,15 +430,17 @@ __device__ __forceinline__ uint64_t word_sum(long long w, const uint32_t* __rest
             const long long l = lmax - t;
             if (l < 0 || l >= twoM) continue;
             const int k = (int)(g - l * hm);
-            const uint32_t* T = poly + ((size_t)l * m + k) * L;
+            const uint32_t* T = poly + ((size_t)l * m + k) * D;
             uint32_t piece;
             if (off >= 0) {
-                const int li = (int)(off >> 5), bs = (int)(off & 31);
-                uint64_t v = T[li];
-                if (li + 1 < L) v |= (uint64_t)T[li + 1] << 32;
-                piece = (uint32_t)(v >> bs);
+                const int k0 = (int)(off / 28), sh = (int)(off - 28 * (off / 28));
+                uint64_t v = T[k0];
+                if (k0 + 1 < D) v |= (uint64_t)T[k0 + 1] << 28;
+                if (k0 + 2 < D) v |= (uint64_t)T[k0 + 2] << 56;
+                piece = (uint32_t)(v >> sh);
             } else {
-                piece = T[0] << (int)(-off);
+                const uint64_t v = (uint64_t)T[0] | ((uint64_t)T[1] << 28);
+                piece = (uint32_t)(v << (int)(-off));
             }
             V += piece;
         }
@@ -381,7 +448,7 @@ __device__ __forceinline__ uint64_t word_sum(long long w, const uint32_t* __rest
     return V;
 }
 
-// Per 256 output words: x_w = low(V_w) + high(V_(w-1)) < 2^32 + 2^5, so word w generates a carry
+// Per 256 output words: x_w = low(V_w) + high(V_(w-1)) < 2^32 + 2^12, so word w generates a carry
 // (x_w >= 2^32) or propagates one (low 32 bits all ones), never both.  Writes the low 32 bits
 // and the per-wavefront generate / propagate masks.
 template <int L>
@@ -420,20 +487,57 @@ __device__ __forceinline__ void wave_fn(unsigned long long G, unsigned long long
     *p = c0 || s == ~0ull;
 }
 
-// Single workgroup: carry into every wavefront.  Each thread composes the carry functions
-// c -> g | (p & c) of a contiguous run of wavefronts; thread 0 scans the 1024 compositions.
-__global__ __launch_bounds__(1024) void k_carry_scan(const unsigned long long* __restrict__ gmask,
-                                                     const unsigned long long* __restrict__ pmask,
-                                                     unsigned char* __restrict__ cin,
-                                                     long long nwaves) {
+// Carry functions c -> g | (p & c) compose as (g2, p2) o (g1, p1) = (g2 | (p2 & g1), p2 & p1).
+// Segments of 256 wavefronts (16384 words): one workgroup scans a segment's 256 functions in LDS
+// and stores, per wavefront, its carry in for a segment carry in of 0 (bit 0) and of 1 (bit 1),
+// plus the segment's composed function.
+__global__ __launch_bounds__(kThreads) void k_carry_block(const unsigned long long* __restrict__ gmask,
+                                                          const unsigned long long* __restrict__ pmask,
+                                                          unsigned char* __restrict__ cin01,
+                                                          unsigned char* __restrict__ seg_gp,
+                                                          long long nwaves) {
+    __shared__ unsigned char sg[kThreads], sp[kThreads];
+    const long long k = (long long)blockIdx.x * kThreads + threadIdx.x;
+    bool g = false, p = true;                 // identity beyond the last wavefront
+    if (k < nwaves) wave_fn(gmask[k], pmask[k], &g, &p);
+    sg[threadIdx.x] = g;
+    sp[threadIdx.x] = p;
+    __syncthreads();
+    for (int d = 1; d < kThreads; d <<= 1) {
+        bool ng = g, np = p;
+        if ((int)threadIdx.x >= d) {
+            const bool g1 = sg[threadIdx.x - d], p1 = sp[threadIdx.x - d];
+            ng = g || (p && g1);
+            np = p && p1;
+        }
+        __syncthreads();
+        sg[threadIdx.x] = ng;
+        sp[threadIdx.x] = np;
+        g = ng;
+        p = np;
+        __syncthreads();
+    }
+    // exclusive prefix = inclusive value of the previous thread
+    bool eg = false, ep = true;
+    if (threadIdx.x > 0) {
+        eg = sg[threadIdx.x - 1];
+        ep = sp[threadIdx.x - 1];
+    }
+    if (k < nwaves) cin01[k] = (unsigned char)((eg ? 1 : 0) | ((eg || ep) ? 2 : 0));
+    if (threadIdx.x == kThreads - 1) seg_gp[blockIdx.x] = (unsigned char)((g ? 1 : 0) | (p ? 2 : 0));
+}
+
+// Single workgroup: carry into every segment (each thread composes a contiguous run of segments,
+// thread 0 scans the 1024 compositions).
+__global__ __launch_bounds__(1024) void k_carry_top(const unsigned char* __restrict__ seg_gp,
+                                                    unsigned char* __restrict__ seg_cin, long long nseg) {
     __shared__ unsigned char ag[1024], ap[1024], ac[1024];
-    const long long ch = (nwaves + 1023) / 1024;
+    const long long ch = (nseg + 1023) / 1024;
     const long long s = threadIdx.x * ch;
-    const long long e = min(s + ch, nwaves);
+    const long long e = min(s + ch, nseg);
     bool fg = false, fp = true;
     for (long long k = s; k < e; ++k) {
-        bool g, p;
-        wave_fn(gmask[k], pmask[k], &g, &p);
+        const bool g = seg_gp[k] & 1, p = (seg_gp[k] >> 1) & 1;
         fg = g || (p && fg);
         fp = p && fp;
     }
@@ -450,23 +554,24 @@ __global__ __launch_bounds__(1024) void k_carry_scan(const unsigned long long* _
     __syncthreads();
     bool c = ac[threadIdx.x];
     for (long long k = s; k < e; ++k) {
-        cin[k] = c;
-        bool g, p;
-        wave_fn(gmask[k], pmask[k], &g, &p);
+        seg_cin[k] = c;
+        const bool g = seg_gp[k] & 1, p = (seg_gp[k] >> 1) & 1;
         c = g || (p && c);
     }
 }
 
-// word w += carry into w: bit (w mod 64) of ((G|P) + G + cin) ^ (G|P) ^ G
+// word w += carry into w: bit (w mod 64) of ((G|P) + G + c_in) ^ (G|P) ^ G
 __global__ __launch_bounds__(kThreads) void k_carry_apply(uint32_t* __restrict__ out, long long nw,
                                                           const unsigned long long* __restrict__ gmask,
                                                           const unsigned long long* __restrict__ pmask,
-                                                          const unsigned char* __restrict__ cin) {
+                                                          const unsigned char* __restrict__ cin01,
+                                                          const unsigned char* __restrict__ seg_cin) {
     const long long w = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (w >= nw) return;
     const long long wave = w >> 6;
+    const int c = (cin01[wave] >> (seg_cin[wave >> 8] ? 1 : 0)) & 1;
     const unsigned long long G = gmask[wave], A = G | pmask[wave];
-    const unsigned long long carries = (A + G + (unsigned long long)cin[wave]) ^ A ^ G;
+    const unsigned long long carries = (A + G + (unsigned long long)c) ^ A ^ G;
     out[w] += (uint32_t)((carries >> (w & 63)) & 1);
 }
 
@@ -512,7 +617,7 @@ __global__ void k_fill(uint32_t* __restrict__ p, long long n, uint32_t v) {
 }
 
 // ---------------------------------------------------------------------------------------------
-// Forward output in digit-reversed order -> natural order (dkss_forward only)
+// Forward output in digit-reversed order -> natural order, digits -> limbs (dkss_forward only)
 // ---------------------------------------------------------------------------------------------
 
 struct LevelIdx {
@@ -522,18 +627,27 @@ struct LevelIdx {
     int shift[8];    // log2 of the product of the radices of the earlier levels
 };
 
+// one thread per coefficient: position pos holds a(rho^f), f from the digits of pos
+template <int L>
 __global__ void k_unscramble(uint32_t* __restrict__ dst, const uint32_t* __restrict__ src,
-                             long long twoM, int EW, LevelIdx LI) {
+                             long long twoM, int log2m, LevelIdx LI) {
+    constexpr int D = Dig<L>::D;
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= twoM * EW) return;
-    const long long pos = t / EW;
-    const int wk = (int)(t - pos * EW);
+    if (t >= (twoM << log2m)) return;
+    const long long pos = t >> log2m;
+    const int k = (int)(t & ((1 << log2m) - 1));
     long long f = 0;
-    for (int k = 0; k < LI.n; ++k) {
-        const long long v = (pos >> LI.log2mu[k]) & ((1LL << LI.log2r[k]) - 1);
-        f |= v << LI.shift[k];
+    for (int i = 0; i < LI.n; ++i) {
+        const long long v = (pos >> LI.log2mu[i]) & ((1LL << LI.log2r[i]) - 1);
+        f |= v << LI.shift[i];
     }
-    dst[(size_t)f * EW + wk] = src[t];
+    uint32_t d[D], x[L];
+#pragma unroll
+    for (int w = 0; w < D; ++w) d[w] = src[(size_t)t * D + w];
+    digits_to_limbs<L>(d, x);
+    uint32_t* o = dst + (((size_t)f << log2m) + k) * L;
+#pragma unroll
+    for (int w = 0; w < L; ++w) o[w] = x[w];
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -687,9 +801,13 @@ struct Call {
     size_t alen = 0, blen = 0;
     Cached* C = nullptr;
     Prof* prof = nullptr;
+    long long dft_lds = 65536;
+    bool overlap = true;
+    hipStream_t aux = nullptr;        // second stream for the transform of b
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 };
 
-int dig_D(int L) { return (32 * L + 27) / 28; }
+int dig_D(int L) { return (32 * L + 28) / 28; }
 int dig_K(int L) { return (32 * L + 6 + 27) / 28; }
 
 }  // namespace
@@ -698,6 +816,15 @@ struct dkss_ctx {
     int policy = DKSS_POLICY_THESIS;
     std::map<std::string, std::unique_ptr<Cached>> cache;
     Prof prof;
+    bool overlap = true;
+    long long dft_lds = 65536;
+    hipStream_t aux = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    ~dkss_ctx() {
+        if (ev_fork) (void)hipEventDestroy(ev_fork);
+        if (ev_join) (void)hipEventDestroy(ev_join);
+        if (aux) (void)hipStreamDestroy(aux);
+    }
 };
 
 namespace {
@@ -765,7 +892,6 @@ int plan_constants(dkss_ctx* ctx, Call* call) {
         ModQ mq(CP.q);
         QConst& Q = c->Q;
         memset(&Q, 0, sizeof Q);
-        for (int i = 0; i < L; ++i) Q.q[i] = CP.q.limb32(i);
         auto digits = [&](const Big& x, uint32_t* d) {
             for (int k = 0; k < D; ++k) {
                 Big s = x.shr(28 * k);
@@ -787,9 +913,16 @@ int plan_constants(dkss_ctx* ctx, Call* call) {
         digits(mq.mul(inv2M, R2), Q.kpw);
         // table entries 0 (one) and 1 (rho), Montgomery form
         const int m = CP.m();
-        c->table_host01.assign((size_t)2 * m * D, 0u);
-        digits(Rm, &c->table_host01[0]);
-        for (int k = 0; k < m; ++k) digits(mq.mul(CP.rho[k], Rm), &c->table_host01[(size_t)(m + k) * D]);
+        // entry = m residues followed by their negations (q - x; q itself for x = 0)
+        c->table_host01.assign((size_t)2 * 2 * m * D, 0u);
+        auto put = [&](int entry, int k, const Big& x) {
+            digits(x, &c->table_host01[((size_t)entry * 2 * m + k) * D]);
+            digits(CP.q.sub(x), &c->table_host01[((size_t)entry * 2 * m + m + k) * D]);
+        };
+        for (int k = 0; k < m; ++k) {
+            put(0, k, k == 0 ? Rm : Big());
+            put(1, k, mq.mul(CP.rho[k], Rm));
+        }
         c->table_count = CP.mu_top();
         it = ctx->cache.emplace(key, std::move(c)).first;
     }
@@ -830,6 +963,7 @@ int dispatch_L(int L, const A&... args) {
     }
 }
 
+// LDS of the R-product kernels: kThreads coefficient slots, 3 D digits each (T, x, q - x)
 size_t rprod_lds(int L) { return (size_t)kThreads * 3 * dig_D(L) * sizeof(uint32_t); }
 
 template <int L>
@@ -862,11 +996,11 @@ int ensure_table(Cached* C, Prof* prof, hipStream_t s) {
     if (C->d_table) return DKSS_OK;
     const int m = C->plan.m();
     const size_t entries = (size_t)std::max<long long>(C->table_count, 2);
-    const size_t bytes = entries * m * C->D * sizeof(uint32_t);
+    const size_t bytes = entries * 2 * m * C->D * sizeof(uint32_t);
     uint32_t* d = nullptr;
     HIP_OK(hipMalloc(&d, bytes));
     C->d_table = d;
-    const size_t first = (size_t)std::min<long long>(C->table_count, 2) * m * C->D * sizeof(uint32_t);
+    const size_t first = (size_t)std::min<long long>(C->table_count, 2) * 2 * m * C->D * sizeof(uint32_t);
     HIP_OK(hipMemcpyAsync(d, C->table_host01.data(), first, hipMemcpyHostToDevice, s));
     int rc = dispatch_L<TableBuild>(C->plan.L, C, prof, s);
     if (rc) return rc;
@@ -879,11 +1013,15 @@ struct Workspace {
     uint32_t* B;
     unsigned long long* gmask;
     unsigned long long* pmask;
-    unsigned char* cin;
+    unsigned char* cin01;
+    unsigned char* seg_gp;
+    unsigned char* seg_cin;
     size_t bytes;
 };
 
-size_t poly_words(const Plan& P) { return ((size_t)2 << P.log2_M) * P.m() * P.L; }
+// words of one polynomial in the workspace (digits) and in limb form (dkss_forward's output)
+size_t poly_words(const Plan& P) { return ((size_t)2 << P.log2_M) * P.m() * dig_D(P.L); }
+size_t poly_limb_words(const Plan& P) { return ((size_t)2 << P.log2_M) * P.m() * P.L; }
 
 Workspace layout(const Call& c, char* base) {
     Workspace w{};
@@ -899,8 +1037,13 @@ Workspace layout(const Call& c, char* base) {
     off += align256(nwaves * 8);
     w.pmask = (unsigned long long*)(base + off);
     off += align256(nwaves * 8);
-    w.cin = (unsigned char*)(base + off);
+    const size_t nseg = (nwaves + kThreads - 1) / kThreads;
+    w.cin01 = (unsigned char*)(base + off);
     off += align256(nwaves);
+    w.seg_gp = (unsigned char*)(base + off);
+    off += align256(nseg);
+    w.seg_cin = (unsigned char*)(base + off);
+    off += align256(nseg);
     w.bytes = off;
     return w;
 }
@@ -922,43 +1065,51 @@ struct Transform {
             base[k] = twoM / n;
             n = mu[k];
         }
-        auto dft = [&](int k) -> int {
+        // one launch per level: the DFT with the following (forward) or preceding (inverse)
+        // twiddle products fused in
+        auto level = [&](int k, bool tw) -> int {
             const int log2r = P.radix_log2[k];
             const int r = 1 << log2r;
             const long long ncols = twoM >> log2r;
-            // columns per workgroup: <= kTaskMax*256 butterfly tasks, <= 64 KiB of LDS
-            int C = std::max(1, (kTaskMax * kThreads) / ((r / 2) * m));
-            const size_t colbytes = (size_t)r * m * L * 4;
-            while (C > 1 && (size_t)C * colbytes > 65536) C /= 2;
-            const unsigned blocks = (unsigned)((ncols + C - 1) / C);
-            ProfScope ps(c.prof, DKSS_K_DFT, s, 2.0 * twoM * m * L * 4, 0.0);
-            hipLaunchKernelGGL(k_dft<L>, dim3(blocks), dim3(kThreads), (size_t)C * colbytes, s, poly,
-                               n_lvl[k], mu[k], log2r, P.log2_m, C, ncols, inverse, Q);
-            return hipGetLastError() == hipSuccess ? DKSS_OK : DKSS_EHIP;
-        };
-        auto twiddle = [&](int k) -> int {
-            const int per = kThreads / m;
-            const unsigned blocks = (unsigned)((twoM + per - 1) / per);
-            // products: elements with l != 0 and v != 0 in every block
-            const double nprod = (double)(twoM / n_lvl[k]) * ((1LL << P.radix_log2[k]) - 1) * (mu[k] - 1);
-            ProfScope ps(c.prof, DKSS_K_TWIDDLE, s, 2.0 * nprod * m * L * 4,
+            constexpr int D = Dig<L>::D;
+            const size_t colbytes = (size_t)r * m * D * 4;
+            // columns per workgroup: two LDS buffers of C columns within the budget (one column
+            // when twiddles are fused), at most ncols
+            int log2C = 0;
+            while (!tw && (2 * colbytes << (log2C + 1)) <= (size_t)c.dft_lds &&
+                   (1LL << (log2C + 1)) <= ncols)
+                ++log2C;
+            LevelArgs A{};
+            A.twoM = twoM;
+            A.base = base[k];
+            A.mu_top = c.C->table_count;
+            A.log2r = log2r;
+            A.log2m = P.log2_m;
+            A.log2C = log2C;
+            while ((1LL << A.log2nl) < n_lvl[k]) ++A.log2nl;
+            while ((1LL << A.log2mu) < mu[k]) ++A.log2mu;
+            A.mode = tw ? (inverse ? 2 : 1) : 0;
+            A.inverse = inverse;
+            // twiddle staging: 256/m elements x 2m residues; in the free column buffer if it fits
+            const size_t ncw = ((size_t)r << log2C) * m * D;
+            const size_t rb_words = (size_t)kThreads * 2 * D;
+            A.rb_separate = tw && ncw < rb_words;
+            const size_t lds = 2 * ncw * 4 + (A.rb_separate ? rb_words * 4 : 0);
+            const unsigned blocks = (unsigned)(ncols >> log2C);
+            const double nprod = tw ? (double)(twoM / n_lvl[k]) * (r - 1) * (mu[k] - 1) : 0.0;
+            ProfScope ps(c.prof, tw ? DKSS_K_TWIDDLE : DKSS_K_DFT, s, 2.0 * twoM * m * L * 4,
                          nprod * (double)m * m * L * L);
-            hipLaunchKernelGGL(k_twiddle<L>, dim3(blocks), dim3(kThreads), rprod_lds(L), s, poly,
-                               (const uint32_t*)c.C->d_table, twoM, n_lvl[k], mu[k], base[k],
-                               c.C->table_count, P.log2_m, inverse, Q);
+            hipLaunchKernelGGL(k_level<L>, dim3(blocks), dim3(kThreads), lds,
+                               s, poly, (const uint32_t*)c.C->d_table, A, Q);
             return hipGetLastError() == hipSuccess ? DKSS_OK : DKSS_EHIP;
         };
         int rc;
         if (!inverse) {
-            for (int k = 0; k < nl; ++k) {
-                if ((rc = dft(k))) return rc;
-                if (k + 1 < nl && (rc = twiddle(k))) return rc;
-            }
+            for (int k = 0; k < nl; ++k)
+                if ((rc = level(k, k + 1 < nl))) return rc;
         } else {
-            for (int k = nl - 1; k >= 0; --k) {
-                if (k + 1 < nl && (rc = twiddle(k))) return rc;
-                if ((rc = dft(k))) return rc;
-            }
+            for (int k = nl - 1; k >= 0; --k)
+                if ((rc = level(k, k + 1 < nl))) return rc;
         }
         return DKSS_OK;
     }
@@ -1005,18 +1156,33 @@ struct Decode {
                                2LL << c.P.log2_M, c.P.log2_m, c.P.u, w.gmask, w.pmask);
         }
         HIP_OK(hipGetLastError());
+        const long long nseg = (nwaves + kThreads - 1) / kThreads;
         {
-            ProfScope ps(c.prof, DKSS_K_CARRY_SCAN, s, 17.0 * nwaves, 0.0);
-            hipLaunchKernelGGL(k_carry_scan, dim3(1), dim3(1024), 0, s, w.gmask, w.pmask, w.cin, nwaves);
+            ProfScope ps(c.prof, DKSS_K_CARRY_SCAN, s, 17.0 * nwaves + 3.0 * nseg, 0.0);
+            hipLaunchKernelGGL(k_carry_block, dim3((unsigned)nseg), dim3(kThreads), 0, s, w.gmask,
+                               w.pmask, w.cin01, w.seg_gp, nwaves);
+            hipLaunchKernelGGL(k_carry_top, dim3(1), dim3(1024), 0, s, w.seg_gp, w.seg_cin, nseg);
         }
         HIP_OK(hipGetLastError());
         {
             ProfScope ps(c.prof, DKSS_K_CARRY_APPLY, s, 8.0 * nw + 17.0 * nwaves, 0.0);
             hipLaunchKernelGGL(k_carry_apply, dim3(blocks), dim3(kThreads), 0, s, out, nw, w.gmask,
-                               w.pmask, w.cin);
+                               w.pmask, w.cin01, w.seg_cin);
         }
         HIP_OK(hipGetLastError());
         return DKSS_OK;
+    }
+};
+
+template <int L>
+struct Unscramble {
+    static int run(const Call& c, uint32_t* poly, const uint32_t* src, const LevelIdx& LI, hipStream_t s) {
+        const long long twoM = 2LL << c.P.log2_M;
+        const long long total = twoM << c.P.log2_m;
+        ProfScope ps(c.prof, DKSS_K_UNSCRAMBLE, s, (4.0 * L + 4.0 * Dig<L>::D) * total, 0.0);
+        hipLaunchKernelGGL(k_unscramble<L>, dim3((unsigned)((total + kThreads - 1) / kThreads)), dim3(kThreads),
+                           0, s, poly, src, twoM, c.P.log2_m, LI);
+        return hipGetLastError() == hipSuccess ? DKSS_OK : DKSS_EHIP;
     }
 };
 
@@ -1035,6 +1201,8 @@ bool overlaps(const void* x, size_t xb, const void* y, size_t yb) {
 
 int prepare_call(dkss_ctx* ctx, size_t alen, size_t blen, const dkss_params* p, Call* call) {
     call->prof = &ctx->prof;
+    call->dft_lds = ctx->dft_lds;
+    call->overlap = ctx->overlap;
     int rc = resolve_params(ctx, alen, blen, p, call);
     if (rc) return rc;
     if (alen == 0 || blen == 0 || call->schoolbook) return DKSS_OK;
@@ -1058,11 +1226,22 @@ int run_mul(const Call& call, uint32_t* c, const uint32_t* a, size_t alen, const
     const bool squaring = (a == b && alen == blen);
     const int L = call.P.L;
     int rc;
+    // the transform of b on the auxiliary stream (forked from s, joined back before the products)
+    const bool fork = !squaring && call.aux;
+    hipStream_t sb = fork ? call.aux : s;
+    if (fork) {
+        HIP_OK(hipEventRecord(call.ev_fork, s));
+        HIP_OK(hipStreamWaitEvent(sb, call.ev_fork, 0));
+    }
+    if (!squaring) {
+        if ((rc = dispatch_L<Encode>(L, call, w.B, b, blen, sb))) return rc;
+        if ((rc = dispatch_L<Transform>(L, call, w.B, 0, sb))) return rc;
+    }
     if ((rc = dispatch_L<Encode>(L, call, w.A, a, alen, s))) return rc;
     if ((rc = dispatch_L<Transform>(L, call, w.A, 0, s))) return rc;
-    if (!squaring) {
-        if ((rc = dispatch_L<Encode>(L, call, w.B, b, blen, s))) return rc;
-        if ((rc = dispatch_L<Transform>(L, call, w.B, 0, s))) return rc;
+    if (fork) {
+        HIP_OK(hipEventRecord(call.ev_join, sb));
+        HIP_OK(hipStreamWaitEvent(s, call.ev_join, 0));
     }
     if ((rc = dispatch_L<Pointwise>(L, call, w.A, squaring ? (const uint32_t*)w.A : w.B, s))) return rc;
     if ((rc = dispatch_L<Transform>(L, call, w.A, 1, s))) return rc;
@@ -1076,6 +1255,30 @@ int run_mul(const Call& call, uint32_t* c, const uint32_t* a, size_t alen, const
 // ---------------------------------------------------------------------------------------------
 
 extern "C" {
+
+static int ensure_aux(dkss_ctx* ctx) {
+    if (ctx->aux) return DKSS_OK;
+    // default priority (same as any caller stream), non-blocking with respect to the null stream
+    HIP_OK(hipStreamCreateWithFlags(&ctx->aux, hipStreamNonBlocking));
+    HIP_OK(hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming));
+    HIP_OK(hipEventCreateWithFlags(&ctx->ev_join, hipEventDisableTiming));
+    return DKSS_OK;
+}
+
+int dkss_set_option(dkss_ctx* ctx, int option, long long value) {
+    if (!ctx) return DKSS_EINVAL;
+    switch (option) {
+        case DKSS_OPT_OVERLAP:
+            ctx->overlap = value != 0;
+            return DKSS_OK;
+        case DKSS_OPT_DFT_LDS:
+            if (value < 16384 || value > 163840) return DKSS_EINVAL;
+            ctx->dft_lds = value;
+            return DKSS_OK;
+        default:
+            return DKSS_EINVAL;
+    }
+}
 
 int dkss_ctx_create(dkss_ctx** out, int policy, const char* cache_dir) {
     (void)cache_dir;
@@ -1135,8 +1338,8 @@ int dkss_plan_info(dkss_ctx* ctx, size_t alen, size_t blen, const dkss_params* p
     if (call.C) {
         out->L = (uint32_t)P.L;
         out->q_bits = (uint32_t)P.q_bits;
-        out->poly_bytes = poly_words(P) * 4;
-        out->table_bytes = (uint64_t)std::max<long long>(call.C->table_count, 2) * P.m() * call.C->D * 4;
+        out->poly_bytes = poly_limb_words(P) * 4;
+        out->table_bytes = (uint64_t)std::max<long long>(call.C->table_count, 2) * 2 * P.m() * call.C->D * 4;
         for (int i = 0; i < P.L && i < 16; ++i) out->q[i] = P.q.limb32(i);
     }
     return DKSS_OK;
@@ -1174,6 +1377,12 @@ int dkss_mul(dkss_ctx* ctx, uint32_t* c, const uint32_t* a, size_t alen, const u
     int rc = prepare_call(ctx, alen, blen, p, &call);
     if (rc) return rc;
     if (call.C && (rc = ensure_table(call.C, &ctx->prof, (hipStream_t)s))) return rc;
+    if (call.C && ctx->overlap && (rc = ensure_aux(ctx))) return rc;
+    if (call.C && ctx->overlap) {
+        call.aux = ctx->aux;
+        call.ev_fork = ctx->ev_fork;
+        call.ev_join = ctx->ev_join;
+    }
     return run_mul(call, c, a, alen, b, blen, ws, ws_bytes, (hipStream_t)s);
 }
 
@@ -1226,13 +1435,7 @@ int dkss_forward(dkss_ctx* ctx, uint32_t* poly, const uint32_t* a, size_t alen, 
         LI.shift[k] = shift;
         shift += call.P.radix_log2[k];
     }
-    const long long twoM = 2LL << call.P.log2_M;
-    const int EW = call.P.m() * call.P.L;
-    const long long total = twoM * EW;
-    ProfScope ps(call.prof, DKSS_K_UNSCRAMBLE, st, 8.0 * total, 0.0);
-    hipLaunchKernelGGL(k_unscramble, dim3((unsigned)((total + kThreads - 1) / kThreads)), dim3(kThreads),
-                       0, st, poly, (const uint32_t*)w.A, twoM, EW, LI);
-    return hipGetLastError() == hipSuccess ? DKSS_OK : DKSS_EHIP;
+    return dispatch_L<Unscramble>(call.P.L, call, poly, (const uint32_t*)w.A, LI, st);
 }
 
 int dkss_residues(const uint32_t* x, size_t n, const uint64_t* primes_host, size_t count,

@@ -335,10 +335,11 @@ std::string Plan::key() const {
 }
 
 int max_radix_log2(int log2_m, int L) {
-    // one column of 2^t elements of m residues of L limbs staged in LDS (<= 64 KiB), and at most
-    // 1024 butterfly tasks (2^(t-1) pairs x m coefficients) per radix-2 pass
+    // one column of 2^t elements of m residues of L limbs, staged twice in LDS (ping-pong
+    // buffers within kLdsBytes), and at most 1024 butterfly tasks (2^(t-1) pairs x m
+    // coefficients) per radix-2 pass
     int t = log2_m + 1;
-    while (t > 1 && (((4LL * L) << (t + log2_m)) > 65536 || ((1LL << (t - 1 + log2_m)) > 1024)))
+    while (t > 1 && ((2 * (4LL * L) << (t + log2_m)) > kLdsBytes || ((1LL << (t - 1 + log2_m)) > 1024)))
         --t;
     return t;
 }

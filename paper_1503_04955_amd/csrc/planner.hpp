@@ -9,6 +9,9 @@
 
 namespace dkss {
 
+// LDS bytes one workgroup may use for an FFT column (two buffers)
+constexpr long long kLdsBytes = 65536;
+
 // Unsigned integer of up to kWords 64-bit words, little-endian.  Sized for moduli p^z below
 // 2^512 and their double-width intermediates.
 struct Big {
