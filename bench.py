@@ -17,8 +17,14 @@ algorithmic work is counted in 32x32-bit multiply-adds of the schoolbook product
 priced against the chip's full-rate 32-bit VALU throughput (256 CUs x 64 lanes x 2.4 GHz).
 The FFT passes (k_dft) are reported against HBM bandwidth in roofline_fft.
 
+The "batch" object measures the batched configuration: 4096 independent products with operand
+lengths log-uniform in 2^12..2^22 bits and length ratios uniform in [1, 8], run (a) as 4096
+sequential plain calls (thesis rule), (b) as one dkss_mul_batch call (thesis rule) and (c) as one
+dkss_mul_batch call with the tuned policy; all three give identical bits (checked).  The "tuned"
+object times the single 2^bits product with the tuned policy.
+
 The cpu_baseline leg times the CPU oracle (plain C, one thread) on a bounded sample: one whole
-product of two 2^22-bit operands by the oracle's DKSS with the same parameter rule.
+product of two 2^24-bit operands by the oracle's DKSS with the same parameter rule.
 """
 import argparse
 import json
@@ -65,7 +71,7 @@ def primes61(seed, count):
     return out
 
 
-def cpu_baseline(bits=22):
+def cpu_baseline(bits=24):
     """Oracle (C, -O2, one thread) on one 2^bits x 2^bits product: operand bits/s."""
     import seeded_inputs as SI
     from oracle import coracle
@@ -80,6 +86,59 @@ def cpu_baseline(bits=22):
                       "single thread, %.1f s" % (bits, bits, dt)}
 
 
+def _timed(fn, reps, torch):
+    fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def batch_bench(count, reps, dk, torch, SI):
+    """4096 uneven products: plain sequential calls vs one batched call (thesis / tuned)."""
+    lens = SI.batch_lengths(SI.SEED_BASE + 2, count)
+    as_, bs = [], []
+    for i, (al, bl) in enumerate(lens):
+        a, b = SI.operand_pair(SI.SEED_BASE + 100000 + i, al, bl)
+        as_.append(dk.to_device(a))
+        bs.append(dk.to_device(b))
+    bits = 32.0 * sum(al + bl for al, bl in lens)
+    outs_p = [torch.empty(a.numel() + b.numel(), dtype=torch.int32, device="cuda") for a, b in zip(as_, bs)]
+    outs_b = [torch.empty_like(o) for o in outs_p]
+    outs_t = [torch.empty_like(o) for o in outs_p]
+    ctx = dk.Context()
+    ctx_t = dk.Context(dk.POLICY_TUNED)
+    wss = max(ctx.workspace_bytes(a.numel(), b.numel()) for a, b in zip(as_, bs))
+    ws = torch.empty(max(wss, 1), dtype=torch.uint8, device="cuda")
+
+    def plain():
+        for a, b, o in zip(as_, bs, outs_p):
+            ctx.mul(a, b, out=o, ws=ws)
+
+    def batched(c, outs):
+        return lambda: c.mul_batch(as_, bs, outs=outs)
+
+    ms_plain = _timed(plain, reps, torch)
+    ms_batch = _timed(batched(ctx, outs_b), reps, torch)
+    ms_tuned = _timed(batched(ctx_t, outs_t), reps, torch)
+    same = all(torch.equal(x, y) and torch.equal(x, z) for x, y, z in zip(outs_p, outs_b, outs_t))
+    if not same:
+        raise RuntimeError("batched products differ from the plain ones")
+    return {"workload": "%d products, operands 2^12..2^22 bits log-uniform, length ratio U[1,8]"
+                        % count,
+            "operand_bits": bits,
+            "plain_sequential": {"ms": ms_plain, "value": bits / (ms_plain / 1e3)},
+            "batched_thesis": {"ms": ms_batch, "value": bits / (ms_batch / 1e3)},
+            "batched_tuned": {"ms": ms_tuned, "value": bits / (ms_tuned / 1e3)},
+            "speedup_batched_tuned_vs_plain": ms_plain / ms_tuned,
+            "bit_identical": same}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -89,6 +148,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--overlap", type=int, default=1, help="transform b on a second stream")
     ap.add_argument("--dft-lds", type=int, default=65536, help="LDS bytes per FFT-level workgroup")
+    ap.add_argument("--batch", type=int, default=4096, help="products in the batch leg (0: skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -173,6 +233,20 @@ def main():
         "verified": "residues mod 8 random 61-bit primes",
         "roofline": roofline, "roofline_fft": roofline_fft, "kernels": kernels,
     }
+    # the same product with the tuned policy
+    ctx_t = dk.Context(dk.POLICY_TUNED)
+    ctx_t.set_option(dk.OPT_OVERLAP, args.overlap)
+    ctx_t.set_option(dk.OPT_DFT_LDS, args.dft_lds)
+    ws_t = torch.empty(ctx_t.workspace_bytes(n, n), dtype=torch.uint8, device=dev)
+    c_t = torch.empty_like(c)
+    ms_t = _timed(lambda: ctx_t.mul(a, b, out=c_t, ws=ws_t), args.steps, torch)
+    if not torch.equal(c, c_t):
+        print("tuned product differs", file=sys.stderr)
+        sys.exit(1)
+    out["tuned"] = {"ms_per_step": ms_t, "value": 2 * n * 32 / (ms_t / 1e3),
+                    "params": ctx_t.select_params(32 * n, 32 * n).as_dict()}
+    if args.batch:
+        out["batch"] = batch_bench(args.batch, 2, dk, torch, SI)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)

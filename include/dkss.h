@@ -94,6 +94,19 @@ void dkss_ctx_destroy(dkss_ctx* ctx);
 int dkss_select_params(dkss_ctx* ctx, uint64_t a_bits, uint64_t b_bits, uint32_t batch,
                        dkss_params* out);
 
+/*
+ * Candidate parameter tuples for operands of a_bits x b_bits bits (N = the longer, in whole
+ * limbs), the search space of the tuner and of the learned selector.  Candidate index
+ * c = (t_off * 6 + (log2_m - 1)), t_off in 0..2, log2_m in 1..6: Mm = 2^(t_min + t_off), where
+ * t_min is the smallest log2(Mm) whose u = ceil(2N/Mm) admits a modulus of at most 256 bits;
+ * p has the fewest whole 32-bit limbs with p^z >= Mm 2^(2u) (z = 1, Sec. 3.2.2); M = Mm/m >= m.
+ * out[c] is filled for every c < DKSS_NCAND; valid[c] = 1 where the tuple is feasible.  The
+ * radices are the library default, cutoff_bits 0.  Errors: DKSS_EINVAL, DKSS_ERANGE.
+ */
+enum { DKSS_NCAND = 18 };
+int dkss_candidates(dkss_ctx* ctx, uint64_t a_bits, uint64_t b_bits, dkss_params* out,
+                    int* valid);
+
 /* Plan facts for a product of alen x blen limbs under params p (NULL = the policy). */
 int dkss_plan_info(dkss_ctx* ctx, size_t alen, size_t blen, const dkss_params* p, dkss_plan* out);
 

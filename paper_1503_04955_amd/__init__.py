@@ -100,6 +100,7 @@ def lib():
         L.dkss_kernel_name.argtypes = [ctypes.c_int]
         L.dkss_kernel_name.restype = ctypes.c_char_p
         L.dkss_set_option.argtypes = [vp, ctypes.c_int, ctypes.c_longlong]
+        L.dkss_candidates.argtypes = [vp, u64, u64, PP, ctypes.POINTER(ctypes.c_int)]
         L.dkss_strerror.argtypes = [ctypes.c_int]
         L.dkss_strerror.restype = ctypes.c_char_p
         _lib = L
@@ -110,7 +111,10 @@ EXPORTED = ["dkss_ctx_create", "dkss_ctx_destroy", "dkss_select_params", "dkss_p
             "dkss_workspace_bytes", "dkss_prepare", "dkss_mul", "dkss_mul_batch",
             "dkss_batch_workspace_bytes", "dkss_forward", "dkss_residues", "dkss_profile_enable",
             "dkss_profile_read", "dkss_profile_reset", "dkss_kernel_name", "dkss_set_option",
-            "dkss_strerror"]
+            "dkss_candidates", "dkss_strerror"]
+
+NCAND = 18
+TUNING_DIR = os.path.join(_HERE, "tuning")
 
 OPT_OVERLAP, OPT_DFT_LDS = 0, 1
 
@@ -160,9 +164,12 @@ def _alloc_ws(nbytes, device):
 class Context:
     """A libdkss context: cached parameter constants and device tables."""
 
-    def __init__(self, policy=POLICY_THESIS):
+    def __init__(self, policy=POLICY_THESIS, tuning_dir=None):
+        """policy POLICY_THESIS (the thesis's rule) or POLICY_TUNED (the measured table in
+        tuning_dir/dkss_tuning.txt, default: the package's table, else the thesis's rule)."""
         h = ctypes.c_void_p()
-        _check(lib().dkss_ctx_create(ctypes.byref(h), policy, None), "dkss_ctx_create")
+        d = tuning_dir if tuning_dir is not None else TUNING_DIR
+        _check(lib().dkss_ctx_create(ctypes.byref(h), policy, d.encode()), "dkss_ctx_create")
         self._h = h
 
     def close(self):
@@ -181,6 +188,13 @@ class Context:
         _check(lib().dkss_select_params(self._h, a_bits, b_bits, batch, ctypes.byref(p)),
                "dkss_select_params")
         return p
+
+    def candidates(self, a_bits, b_bits):
+        """[(index, Params)] of the feasible candidate tuples for these operand sizes."""
+        arr = (Params * NCAND)()
+        valid = (ctypes.c_int * NCAND)()
+        _check(lib().dkss_candidates(self._h, a_bits, b_bits, arr, valid), "dkss_candidates")
+        return [(c, arr[c]) for c in range(NCAND) if valid[c]]
 
     def plan_info(self, alen, blen, params=None):
         out = Plan()

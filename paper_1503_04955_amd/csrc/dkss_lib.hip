@@ -22,6 +22,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -49,6 +50,25 @@ __device__ __forceinline__ int bitrev(int x, int bits) {
     return bits ? (int)(__brev((unsigned)x) >> (32 - bits)) : 0;
 }
 
+// One product of a launch: operands, result, and its u (bits per inner coefficient).  Kernels
+// that handle several products at once take the product index from blockIdx.y; their
+// polynomials sit at a fixed stride in the workspace.
+struct ProdDesc {
+    uint32_t* c;
+    const uint32_t* a;
+    const uint32_t* b;
+    long long alen, blen;
+    int u;
+    int pad;
+};
+
+// A single product by value, or a device array of many
+struct ProdArgs {
+    ProdDesc one;
+    const ProdDesc* many;
+    __device__ __forceinline__ ProdDesc get() const { return many ? many[blockIdx.y] : one; }
+};
+
 // ---------------------------------------------------------------------------------------------
 // Step 4: encode
 // ---------------------------------------------------------------------------------------------
@@ -56,10 +76,14 @@ __device__ __forceinline__ int bitrev(int x, int bits) {
 // poly: 2M elements x m coefficients x D digits.  Coefficient k < m/2 of element i < M gets bits
 // [u (i m/2 + k), u (i m/2 + k) + u) of a; all others are zero.
 template <int L>
-__global__ __launch_bounds__(kThreads) void k_encode(uint32_t* __restrict__ poly,
-                                                     const uint32_t* __restrict__ a, long long alen,
-                                                     long long M, int log2m, int u) {
+__global__ __launch_bounds__(kThreads) void k_encode(ProdArgs PA, int which, uint32_t* __restrict__ poly0,
+                                                     long long stride, long long M, int log2m) {
     constexpr int D = Dig<L>::D;
+    const ProdDesc pd = PA.get();
+    const uint32_t* __restrict__ a = which ? pd.b : pd.a;
+    const long long alen = which ? pd.blen : pd.alen;
+    const int u = pd.u;
+    uint32_t* __restrict__ poly = poly0 + (size_t)blockIdx.y * stride;
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const long long total = (2 * M) << log2m;
     if (t >= total) return;
@@ -248,11 +272,13 @@ __device__ __forceinline__ void level_twiddle(uint32_t* cur, uint32_t* RB, uint3
     if (A.mode == 2) __syncthreads();
 }
 
-template <int L>
-__global__ __launch_bounds__(kThreads) void k_level(uint32_t* __restrict__ poly,
+template <int L, int MODE>
+__global__ __launch_bounds__(kThreads) void k_level(uint32_t* __restrict__ poly0, long long stride,
                                                     const uint32_t* __restrict__ table, LevelArgs A,
                                                     QConst Q) {
     constexpr int D = Dig<L>::D;
+    A.mode = MODE;
+    uint32_t* __restrict__ poly = poly0 + (size_t)blockIdx.y * stride;
     extern __shared__ uint4 smv[];
     const int m = 1 << A.log2m, r = 1 << A.log2r;
     const int EW = m * D;
@@ -325,9 +351,11 @@ __global__ __launch_bounds__(kThreads) void k_level(uint32_t* __restrict__ poly,
 // m threads per element, 256/m elements per workgroup; LDS per element: a and q - a (2m
 // residues) and b (m residues), digits.
 template <int L>
-__global__ __launch_bounds__(kThreads) void k_pointwise(uint32_t* A, const uint32_t* B,
+__global__ __launch_bounds__(kThreads) void k_pointwise(uint32_t* A0, const uint32_t* B0, long long stride,
                                                         long long count, int log2m, QConst Q) {
     constexpr int D = Dig<L>::D;
+    uint32_t* A = A0 + (size_t)blockIdx.y * stride;
+    const uint32_t* B = B0 + (size_t)blockIdx.y * stride;
     extern __shared__ uint32_t sm[];
     const int m = 1 << log2m;
     const int per = kThreads >> log2m;
@@ -452,12 +480,19 @@ __device__ __forceinline__ uint64_t word_sum(long long w, const uint32_t* __rest
 // (x_w >= 2^32) or propagates one (low 32 bits all ones), never both.  Writes the low 32 bits
 // and the per-wavefront generate / propagate masks.
 template <int L>
-__global__ __launch_bounds__(kThreads) void k_decode(uint32_t* __restrict__ out, long long nw,
-                                                     const uint32_t* __restrict__ poly,
-                                                     long long twoM, int log2m, int u,
-                                                     unsigned long long* __restrict__ gmask,
-                                                     unsigned long long* __restrict__ pmask) {
+__global__ __launch_bounds__(kThreads) void k_decode(ProdArgs PA, const uint32_t* __restrict__ poly0,
+                                                     long long stride, long long twoM, int log2m,
+                                                     unsigned long long* __restrict__ gmask0,
+                                                     unsigned long long* __restrict__ pmask0,
+                                                     long long wstride) {
     __shared__ uint32_t hiv[kThreads + 1];
+    const ProdDesc pd = PA.get();
+    uint32_t* __restrict__ out = pd.c;
+    const long long nw = pd.alen + pd.blen;
+    const int u = pd.u;
+    const uint32_t* __restrict__ poly = poly0 + (size_t)blockIdx.y * stride;
+    unsigned long long* __restrict__ gmask = gmask0 + (size_t)blockIdx.y * wstride;
+    unsigned long long* __restrict__ pmask = pmask0 + (size_t)blockIdx.y * wstride;
     const long long w0 = (long long)blockIdx.x * kThreads;
     const long long w = w0 + threadIdx.x;
     const uint64_t V = w < nw ? word_sum<L>(w, poly, twoM, log2m, u) : 0;
@@ -491,12 +526,21 @@ __device__ __forceinline__ void wave_fn(unsigned long long G, unsigned long long
 // Segments of 256 wavefronts (16384 words): one workgroup scans a segment's 256 functions in LDS
 // and stores, per wavefront, its carry in for a segment carry in of 0 (bit 0) and of 1 (bit 1),
 // plus the segment's composed function.
-__global__ __launch_bounds__(kThreads) void k_carry_block(const unsigned long long* __restrict__ gmask,
-                                                          const unsigned long long* __restrict__ pmask,
-                                                          unsigned char* __restrict__ cin01,
-                                                          unsigned char* __restrict__ seg_gp,
-                                                          long long nwaves) {
+__global__ __launch_bounds__(kThreads) void k_carry_block(ProdArgs PA,
+                                                          const unsigned long long* __restrict__ gmask0,
+                                                          const unsigned long long* __restrict__ pmask0,
+                                                          unsigned char* __restrict__ cin010,
+                                                          unsigned char* __restrict__ seg_gp0,
+                                                          long long wstride, long long sstride) {
     __shared__ unsigned char sg[kThreads], sp[kThreads];
+    const ProdDesc pd = PA.get();
+    const long long nwaves = (pd.alen + pd.blen + 63) / 64;
+    const size_t y = blockIdx.y;
+    const unsigned long long* __restrict__ gmask = gmask0 + y * wstride;
+    const unsigned long long* __restrict__ pmask = pmask0 + y * wstride;
+    unsigned char* __restrict__ cin01 = cin010 + y * wstride;
+    unsigned char* __restrict__ seg_gp = seg_gp0 + y * sstride;
+    const long long nseg = (nwaves + kThreads - 1) / kThreads;
     const long long k = (long long)blockIdx.x * kThreads + threadIdx.x;
     bool g = false, p = true;                 // identity beyond the last wavefront
     if (k < nwaves) wave_fn(gmask[k], pmask[k], &g, &p);
@@ -524,14 +568,19 @@ __global__ __launch_bounds__(kThreads) void k_carry_block(const unsigned long lo
         ep = sp[threadIdx.x - 1];
     }
     if (k < nwaves) cin01[k] = (unsigned char)((eg ? 1 : 0) | ((eg || ep) ? 2 : 0));
-    if (threadIdx.x == kThreads - 1) seg_gp[blockIdx.x] = (unsigned char)((g ? 1 : 0) | (p ? 2 : 0));
+    if (threadIdx.x == kThreads - 1 && (long long)blockIdx.x < nseg)
+        seg_gp[blockIdx.x] = (unsigned char)((g ? 1 : 0) | (p ? 2 : 0));
 }
 
 // Single workgroup: carry into every segment (each thread composes a contiguous run of segments,
 // thread 0 scans the 1024 compositions).
-__global__ __launch_bounds__(1024) void k_carry_top(const unsigned char* __restrict__ seg_gp,
-                                                    unsigned char* __restrict__ seg_cin, long long nseg) {
+__global__ __launch_bounds__(1024) void k_carry_top(ProdArgs PA, const unsigned char* __restrict__ seg_gp0,
+                                                    unsigned char* __restrict__ seg_cin0, long long sstride) {
     __shared__ unsigned char ag[1024], ap[1024], ac[1024];
+    const ProdDesc pd = PA.get();
+    const long long nseg = ((pd.alen + pd.blen + 63) / 64 + kThreads - 1) / kThreads;
+    const unsigned char* __restrict__ seg_gp = seg_gp0 + (size_t)blockIdx.y * sstride;
+    unsigned char* __restrict__ seg_cin = seg_cin0 + (size_t)blockIdx.y * sstride;
     const long long ch = (nseg + 1023) / 1024;
     const long long s = threadIdx.x * ch;
     const long long e = min(s + ch, nseg);
@@ -541,16 +590,24 @@ __global__ __launch_bounds__(1024) void k_carry_top(const unsigned char* __restr
         fg = g || (p && fg);
         fp = p && fp;
     }
+    // inclusive scan of the 1024 run compositions (Hillis-Steele), then shift for exclusive
     ag[threadIdx.x] = fg;
     ap[threadIdx.x] = fp;
     __syncthreads();
-    if (threadIdx.x == 0) {
-        bool c = false;
-        for (int i = 0; i < 1024; ++i) {
-            ac[i] = c;
-            c = ag[i] || (ap[i] && c);
+    for (int d = 1; d < 1024; d <<= 1) {
+        bool ng = fg, np = fp;
+        if ((int)threadIdx.x >= d) {
+            ng = fg || (fp && ag[threadIdx.x - d]);
+            np = fp && ap[threadIdx.x - d];
         }
+        __syncthreads();
+        ag[threadIdx.x] = ng;
+        ap[threadIdx.x] = np;
+        fg = ng;
+        fp = np;
+        __syncthreads();
     }
+    ac[threadIdx.x] = threadIdx.x ? ag[threadIdx.x - 1] : false;   // carry in: segment cin is 0
     __syncthreads();
     bool c = ac[threadIdx.x];
     for (long long k = s; k < e; ++k) {
@@ -561,11 +618,20 @@ __global__ __launch_bounds__(1024) void k_carry_top(const unsigned char* __restr
 }
 
 // word w += carry into w: bit (w mod 64) of ((G|P) + G + c_in) ^ (G|P) ^ G
-__global__ __launch_bounds__(kThreads) void k_carry_apply(uint32_t* __restrict__ out, long long nw,
-                                                          const unsigned long long* __restrict__ gmask,
-                                                          const unsigned long long* __restrict__ pmask,
-                                                          const unsigned char* __restrict__ cin01,
-                                                          const unsigned char* __restrict__ seg_cin) {
+__global__ __launch_bounds__(kThreads) void k_carry_apply(ProdArgs PA,
+                                                          const unsigned long long* __restrict__ gmask0,
+                                                          const unsigned long long* __restrict__ pmask0,
+                                                          const unsigned char* __restrict__ cin010,
+                                                          const unsigned char* __restrict__ seg_cin0,
+                                                          long long wstride, long long sstride) {
+    const ProdDesc pd = PA.get();
+    uint32_t* __restrict__ out = pd.c;
+    const long long nw = pd.alen + pd.blen;
+    const size_t y = blockIdx.y;
+    const unsigned long long* __restrict__ gmask = gmask0 + y * wstride;
+    const unsigned long long* __restrict__ pmask = pmask0 + y * wstride;
+    const unsigned char* __restrict__ cin01 = cin010 + y * wstride;
+    const unsigned char* __restrict__ seg_cin = seg_cin0 + y * sstride;
     const long long w = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (w >= nw) return;
     const long long wave = w >> 6;
@@ -579,10 +645,13 @@ __global__ __launch_bounds__(kThreads) void k_carry_apply(uint32_t* __restrict__
 // Base case: schoolbook product (Sec. 2.3), one workgroup per product, alen + blen <= 4096
 // ---------------------------------------------------------------------------------------------
 
-__global__ __launch_bounds__(kThreads) void k_schoolbook(uint32_t* __restrict__ c,
-                                                         const uint32_t* __restrict__ a, long long alen,
-                                                         const uint32_t* __restrict__ b, long long blen) {
+__global__ __launch_bounds__(kThreads) void k_schoolbook(ProdArgs PA) {
     extern __shared__ uint32_t sv[];
+    const ProdDesc pd = PA.get();
+    uint32_t* __restrict__ c = pd.c;
+    const uint32_t* __restrict__ a = pd.a;
+    const uint32_t* __restrict__ b = pd.b;
+    const long long alen = pd.alen, blen = pd.blen;
     const long long n = alen + blen;
     for (long long w = threadIdx.x; w < n; w += blockDim.x) {
         uint64_t lo = 0, hi = 0;
@@ -614,6 +683,15 @@ __global__ __launch_bounds__(kThreads) void k_schoolbook(uint32_t* __restrict__ 
 __global__ void k_fill(uint32_t* __restrict__ p, long long n, uint32_t v) {
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = v;
+}
+
+// c = 0 for products of the launch (alen + blen words each)
+__global__ void k_zero_products(ProdArgs PA) {
+    const ProdDesc pd = PA.get();
+    const long long n = pd.alen + pd.blen;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x)
+        pd.c[i] = 0;
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -812,15 +890,31 @@ int dig_K(int L) { return (32 * L + 6 + 27) / 28; }
 
 }  // namespace
 
+// Tuned choices: for log2(N) in [lo, hi), candidate index cand (see candidate_params).
+struct TuneEntry {
+    double lo, hi;
+    int cand;
+};
+
 struct dkss_ctx {
     int policy = DKSS_POLICY_THESIS;
+    std::vector<TuneEntry> tuning;
     std::map<std::string, std::unique_ptr<Cached>> cache;
     Prof prof;
     bool overlap = true;
     long long dft_lds = 65536;
     hipStream_t aux = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    ProdDesc* hdesc = nullptr;          // pinned staging of batch descriptors
+    size_t hdesc_cap = 0;
+    hipEvent_t desc_ev = nullptr;       // recorded after the last descriptor copy
+    bool desc_pending = false;
     ~dkss_ctx() {
+        if (desc_ev) {
+            (void)hipEventSynchronize(desc_ev);
+            (void)hipEventDestroy(desc_ev);
+        }
+        if (hdesc) (void)hipHostFree(hdesc);
         if (ev_fork) (void)hipEventDestroy(ev_fork);
         if (ev_join) (void)hipEventDestroy(ev_join);
         if (aux) (void)hipStreamDestroy(aux);
@@ -834,9 +928,18 @@ namespace {
         if ((expr) != hipSuccess) return DKSS_EHIP;   \
     } while (0)
 
+// the context's policy: the tuned table's candidate for N if it has one, else the thesis rule
+bool policy_tuple(const dkss_ctx* ctx, uint64_t N, int* lM, int* lm, int* u, int* pb) {
+    if (ctx && ctx->policy == DKSS_POLICY_TUNED) {
+        const double lg = std::log2((double)N);
+        for (const TuneEntry& t : ctx->tuning)
+            if (lg >= t.lo && lg < t.hi && candidate_params(N, t.cand, lM, lm, u, pb)) return true;
+    }
+    return thesis_params(N, lM, lm, u, pb);
+}
+
 // parameters for a product, from the policy or the caller
 int resolve_params(dkss_ctx* ctx, size_t alen, size_t blen, const dkss_params* p, Call* out) {
-    (void)ctx;
     out->alen = alen;
     out->blen = blen;
     const uint64_t N = 32ull * std::max(alen, blen);
@@ -845,7 +948,7 @@ int resolve_params(dkss_ctx* ctx, size_t alen, size_t blen, const dkss_params* p
     if (N > (1ull << 36)) return DKSS_ERANGE;
     if (p == nullptr) {
         int lM, lm, u, pb;
-        if (!thesis_params(N, &lM, &lm, &u, &pb)) return DKSS_ERANGE;
+        if (!policy_tuple(ctx, N, &lM, &lm, &u, &pb)) return DKSS_ERANGE;
         P.log2_M = lM;
         P.log2_m = lm;
         P.u = u;
@@ -1008,14 +1111,18 @@ int ensure_table(Cached* C, Prof* prof, hipStream_t s) {
     return DKSS_OK;
 }
 
+// Workspace of one launch group: G products sharing a plan.  Polynomials at stride S words,
+// carry state at strides wst (wavefronts) and sst (segments) of the longest product.
 struct Workspace {
     uint32_t* A;
     uint32_t* B;
+    size_t S;                          // words per polynomial
     unsigned long long* gmask;
     unsigned long long* pmask;
     unsigned char* cin01;
     unsigned char* seg_gp;
     unsigned char* seg_cin;
+    size_t wst, sst;
     size_t bytes;
 };
 
@@ -1023,35 +1130,36 @@ struct Workspace {
 size_t poly_words(const Plan& P) { return ((size_t)2 << P.log2_M) * P.m() * dig_D(P.L); }
 size_t poly_limb_words(const Plan& P) { return ((size_t)2 << P.log2_M) * P.m() * P.L; }
 
-Workspace layout(const Call& c, char* base) {
+Workspace layout(const Plan& P, size_t G, size_t nw_max, bool need_b, char* base) {
     Workspace w{};
-    const size_t S = poly_words(c.P) * 4;
-    const size_t nw = c.alen + c.blen;
-    const size_t nwaves = (nw + 63) / 64;
+    w.S = poly_words(P);
+    const size_t nwaves = (nw_max + 63) / 64;
+    const size_t nseg = (nwaves + kThreads - 1) / kThreads;
+    w.wst = nwaves;
+    w.sst = nseg;
     size_t off = 0;
     w.A = (uint32_t*)(base + off);
-    off += align256(S);
+    off += align256(G * w.S * 4);
     w.B = (uint32_t*)(base + off);
-    off += align256(S);
+    off += need_b ? align256(G * w.S * 4) : 0;
     w.gmask = (unsigned long long*)(base + off);
-    off += align256(nwaves * 8);
+    off += align256(G * nwaves * 8);
     w.pmask = (unsigned long long*)(base + off);
-    off += align256(nwaves * 8);
-    const size_t nseg = (nwaves + kThreads - 1) / kThreads;
+    off += align256(G * nwaves * 8);
     w.cin01 = (unsigned char*)(base + off);
-    off += align256(nwaves);
+    off += align256(G * nwaves);
     w.seg_gp = (unsigned char*)(base + off);
-    off += align256(nseg);
+    off += align256(G * nseg);
     w.seg_cin = (unsigned char*)(base + off);
-    off += align256(nseg);
+    off += align256(G * nseg);
     w.bytes = off;
     return w;
 }
 
 template <int L>
 struct Transform {
-    // forward (inverse = 0) or inverse (inverse = 1) transform of poly in place
-    static int run(const Call& c, uint32_t* poly, int inverse, hipStream_t s) {
+    // forward (inverse = 0) or inverse (inverse = 1) transform of G polynomials in place
+    static int run(const Call& c, uint32_t* poly, size_t stride, unsigned G, int inverse, hipStream_t s) {
         const Plan& P = c.P;
         const long long twoM = 2LL << P.log2_M;
         const int m = P.m();
@@ -1097,10 +1205,17 @@ struct Transform {
             const size_t lds = 2 * ncw * 4 + (A.rb_separate ? rb_words * 4 : 0);
             const unsigned blocks = (unsigned)(ncols >> log2C);
             const double nprod = tw ? (double)(twoM / n_lvl[k]) * (r - 1) * (mu[k] - 1) : 0.0;
-            ProfScope ps(c.prof, tw ? DKSS_K_TWIDDLE : DKSS_K_DFT, s, 2.0 * twoM * m * L * 4,
-                         nprod * (double)m * m * L * L);
-            hipLaunchKernelGGL(k_level<L>, dim3(blocks), dim3(kThreads), lds,
-                               s, poly, (const uint32_t*)c.C->d_table, A, Q);
+            ProfScope ps(c.prof, tw ? DKSS_K_TWIDDLE : DKSS_K_DFT, s, 2.0 * G * twoM * m * L * 4,
+                         (double)G * nprod * (double)m * m * L * L);
+            if (A.mode == 0)
+                hipLaunchKernelGGL((k_level<L, 0>), dim3(blocks, G), dim3(kThreads), lds, s, poly,
+                                   (long long)stride, (const uint32_t*)c.C->d_table, A, Q);
+            else if (A.mode == 1)
+                hipLaunchKernelGGL((k_level<L, 1>), dim3(blocks, G), dim3(kThreads), lds, s, poly,
+                                   (long long)stride, (const uint32_t*)c.C->d_table, A, Q);
+            else
+                hipLaunchKernelGGL((k_level<L, 2>), dim3(blocks, G), dim3(kThreads), lds, s, poly,
+                                   (long long)stride, (const uint32_t*)c.C->d_table, A, Q);
             return hipGetLastError() == hipSuccess ? DKSS_OK : DKSS_EHIP;
         };
         int rc;
@@ -1117,57 +1232,61 @@ struct Transform {
 
 template <int L>
 struct Encode {
-    static int run(const Call& c, uint32_t* poly, const uint32_t* a, size_t alen, hipStream_t s) {
+    // operand a (which = 0) or b (which = 1) of each product into poly + y * stride
+    static int run(const Call& c, const ProdArgs& PA, unsigned G, int which, uint32_t* poly, size_t stride,
+                   double in_words, hipStream_t s) {
         const long long M = 1LL << c.P.log2_M;
         const long long total = (2 * M) << c.P.log2_m;
         const unsigned blocks = (unsigned)((total + kThreads - 1) / kThreads);
-        ProfScope ps(c.prof, DKSS_K_ENCODE, s, 4.0 * alen + 4.0 * total * L, 0.0);
-        hipLaunchKernelGGL(k_encode<L>, dim3(blocks), dim3(kThreads), 0, s, poly, a, (long long)alen, M,
-                           c.P.log2_m, c.P.u);
+        ProfScope ps(c.prof, DKSS_K_ENCODE, s, 4.0 * in_words + 4.0 * G * total * L, 0.0);
+        hipLaunchKernelGGL(k_encode<L>, dim3(blocks, G), dim3(kThreads), 0, s, PA, which, poly,
+                           (long long)stride, M, c.P.log2_m);
         return hipGetLastError() == hipSuccess ? DKSS_OK : DKSS_EHIP;
     }
 };
 
 template <int L>
 struct Pointwise {
-    static int run(const Call& c, uint32_t* A, const uint32_t* B, hipStream_t s) {
+    static int run(const Call& c, uint32_t* A, const uint32_t* B, size_t stride, unsigned G, hipStream_t s) {
         const long long count = 2LL << c.P.log2_M;
         const int per = kThreads / c.P.m();
         const unsigned blocks = (unsigned)((count + per - 1) / per);
         const int m = c.P.m();
-        ProfScope ps(c.prof, DKSS_K_POINTWISE, s, 3.0 * count * m * L * 4,
-                     (double)count * ((double)m * m * L * L + (double)m * L * L));
-        hipLaunchKernelGGL(k_pointwise<L>, dim3(blocks), dim3(kThreads), rprod_lds(L), s, A, B, count,
-                           c.P.log2_m, c.C->Q);
+        ProfScope ps(c.prof, DKSS_K_POINTWISE, s, 3.0 * G * count * m * L * 4,
+                     (double)G * count * ((double)m * m * L * L + (double)m * L * L));
+        hipLaunchKernelGGL(k_pointwise<L>, dim3(blocks, G), dim3(kThreads), rprod_lds(L), s, A, B,
+                           (long long)stride, count, c.P.log2_m, c.C->Q);
         return hipGetLastError() == hipSuccess ? DKSS_OK : DKSS_EHIP;
     }
 };
 
 template <int L>
 struct Decode {
-    static int run(const Call& c, uint32_t* out, const uint32_t* poly, const Workspace& w, hipStream_t s) {
-        const long long nw = (long long)(c.alen + c.blen);
-        const long long nwaves = (nw + 63) / 64;
-        const unsigned blocks = (unsigned)((nw + kThreads - 1) / kThreads);
-        const double S = (double)(2LL << c.P.log2_M) * c.P.m() * L * 4;
-        {
-            ProfScope ps(c.prof, DKSS_K_DECODE, s, S + 4.0 * nw + 16.0 * nwaves, 0.0);
-            hipLaunchKernelGGL(k_decode<L>, dim3(blocks), dim3(kThreads), 0, s, out, nw, poly,
-                               2LL << c.P.log2_M, c.P.log2_m, c.P.u, w.gmask, w.pmask);
-        }
-        HIP_OK(hipGetLastError());
+    static int run(const Call& c, const ProdArgs& PA, unsigned G, size_t nw_max, double out_words,
+                   const Workspace& w, hipStream_t s) {
+        const long long nwaves = ((long long)nw_max + 63) / 64;
+        const unsigned blocks = (unsigned)((nw_max + kThreads - 1) / kThreads);
+        const double S = (double)G * (2LL << c.P.log2_M) * c.P.m() * L * 4;
         const long long nseg = (nwaves + kThreads - 1) / kThreads;
         {
-            ProfScope ps(c.prof, DKSS_K_CARRY_SCAN, s, 17.0 * nwaves + 3.0 * nseg, 0.0);
-            hipLaunchKernelGGL(k_carry_block, dim3((unsigned)nseg), dim3(kThreads), 0, s, w.gmask,
-                               w.pmask, w.cin01, w.seg_gp, nwaves);
-            hipLaunchKernelGGL(k_carry_top, dim3(1), dim3(1024), 0, s, w.seg_gp, w.seg_cin, nseg);
+            ProfScope ps(c.prof, DKSS_K_DECODE, s, S + 4.0 * out_words, 0.0);
+            hipLaunchKernelGGL(k_decode<L>, dim3(blocks, G), dim3(kThreads), 0, s, PA, (const uint32_t*)w.A,
+                               (long long)w.S, 2LL << c.P.log2_M, c.P.log2_m, w.gmask, w.pmask,
+                               (long long)w.wst);
         }
         HIP_OK(hipGetLastError());
         {
-            ProfScope ps(c.prof, DKSS_K_CARRY_APPLY, s, 8.0 * nw + 17.0 * nwaves, 0.0);
-            hipLaunchKernelGGL(k_carry_apply, dim3(blocks), dim3(kThreads), 0, s, out, nw, w.gmask,
-                               w.pmask, w.cin01, w.seg_cin);
+            ProfScope ps(c.prof, DKSS_K_CARRY_SCAN, s, 17.0 * G * nwaves, 0.0);
+            hipLaunchKernelGGL(k_carry_block, dim3((unsigned)nseg, G), dim3(kThreads), 0, s, PA, w.gmask,
+                               w.pmask, w.cin01, w.seg_gp, (long long)w.wst, (long long)w.sst);
+            hipLaunchKernelGGL(k_carry_top, dim3(1, G), dim3(1024), 0, s, PA, w.seg_gp, w.seg_cin,
+                               (long long)w.sst);
+        }
+        HIP_OK(hipGetLastError());
+        {
+            ProfScope ps(c.prof, DKSS_K_CARRY_APPLY, s, 8.0 * out_words, 0.0);
+            hipLaunchKernelGGL(k_carry_apply, dim3(blocks, G), dim3(kThreads), 0, s, PA, w.gmask, w.pmask,
+                               w.cin01, w.seg_cin, (long long)w.wst, (long long)w.sst);
         }
         HIP_OK(hipGetLastError());
         return DKSS_OK;
@@ -1186,13 +1305,6 @@ struct Unscramble {
     }
 };
 
-int fill_zero(uint32_t* p, size_t n, hipStream_t s) {
-    if (n == 0) return DKSS_OK;
-    const unsigned blocks = (unsigned)((n + kThreads - 1) / kThreads);
-    hipLaunchKernelGGL(k_fill, dim3(blocks), dim3(kThreads), 0, s, p, (long long)n, 0u);
-    return hipGetLastError() == hipSuccess ? DKSS_OK : DKSS_EHIP;
-}
-
 bool overlaps(const void* x, size_t xb, const void* y, size_t yb) {
     const char* a = (const char*)x;
     const char* b = (const char*)y;
@@ -1209,21 +1321,10 @@ int prepare_call(dkss_ctx* ctx, size_t alen, size_t blen, const dkss_params* p, 
     return plan_constants(ctx, call);
 }
 
-int run_mul(const Call& call, uint32_t* c, const uint32_t* a, size_t alen, const uint32_t* b,
-            size_t blen, void* ws, size_t ws_bytes, hipStream_t s) {
-    const size_t nw = alen + blen;
-    if (alen == 0 || blen == 0) return fill_zero(c, nw, s);
-    if (call.schoolbook) {
-        ProfScope ps(call.prof, DKSS_K_SCHOOLBOOK, s, 4.0 * (alen + blen) * 2,
-                     (double)alen * (double)blen);
-        hipLaunchKernelGGL(k_schoolbook, dim3(1), dim3(kThreads), nw * 3 * sizeof(uint32_t), s, c, a,
-                           (long long)alen, b, (long long)blen);
-        return hipGetLastError() == hipSuccess ? DKSS_OK : DKSS_EHIP;
-    }
-    Workspace w = layout(call, (char*)ws);
-    if (ws == nullptr || ((uintptr_t)ws & 255)) return DKSS_EINVAL;
-    if (ws_bytes < w.bytes) return DKSS_ENOSPC;
-    const bool squaring = (a == b && alen == blen);
+// The DKSS pipeline (Steps 4-8) for G products sharing call's plan, described by PA; the
+// workspace w holds their polynomials at stride w.S.  With squaring, b is not transformed.
+int run_group(const Call& call, const ProdArgs& PA, unsigned G, size_t nw_max, double in_a, double in_b,
+              double out_w, bool squaring, const Workspace& w, hipStream_t s) {
     const int L = call.P.L;
     int rc;
     // the transform of b on the auxiliary stream (forked from s, joined back before the products)
@@ -1234,19 +1335,114 @@ int run_mul(const Call& call, uint32_t* c, const uint32_t* a, size_t alen, const
         HIP_OK(hipStreamWaitEvent(sb, call.ev_fork, 0));
     }
     if (!squaring) {
-        if ((rc = dispatch_L<Encode>(L, call, w.B, b, blen, sb))) return rc;
-        if ((rc = dispatch_L<Transform>(L, call, w.B, 0, sb))) return rc;
+        if ((rc = dispatch_L<Encode>(L, call, PA, G, 1, w.B, w.S, in_b, sb))) return rc;
+        if ((rc = dispatch_L<Transform>(L, call, w.B, w.S, G, 0, sb))) return rc;
     }
-    if ((rc = dispatch_L<Encode>(L, call, w.A, a, alen, s))) return rc;
-    if ((rc = dispatch_L<Transform>(L, call, w.A, 0, s))) return rc;
+    if ((rc = dispatch_L<Encode>(L, call, PA, G, 0, w.A, w.S, in_a, s))) return rc;
+    if ((rc = dispatch_L<Transform>(L, call, w.A, w.S, G, 0, s))) return rc;
     if (fork) {
         HIP_OK(hipEventRecord(call.ev_join, sb));
         HIP_OK(hipStreamWaitEvent(s, call.ev_join, 0));
     }
-    if ((rc = dispatch_L<Pointwise>(L, call, w.A, squaring ? (const uint32_t*)w.A : w.B, s))) return rc;
-    if ((rc = dispatch_L<Transform>(L, call, w.A, 1, s))) return rc;
-    return dispatch_L<Decode>(L, call, c, (const uint32_t*)w.A, w, s);
+    if ((rc = dispatch_L<Pointwise>(L, call, w.A, squaring ? (const uint32_t*)w.A : w.B, w.S, G, s))) return rc;
+    if ((rc = dispatch_L<Transform>(L, call, w.A, w.S, G, 1, s))) return rc;
+    return dispatch_L<Decode>(L, call, PA, G, nw_max, out_w, w, s);
 }
+
+int launch_zero(const ProdArgs& PA, unsigned G, size_t nw_max, hipStream_t s) {
+    if (nw_max == 0) return DKSS_OK;
+    const unsigned blocks = (unsigned)std::min<size_t>((nw_max + kThreads - 1) / kThreads, 4096);
+    hipLaunchKernelGGL(k_zero_products, dim3(blocks, G), dim3(kThreads), 0, s, PA);
+    return hipGetLastError() == hipSuccess ? DKSS_OK : DKSS_EHIP;
+}
+
+int launch_schoolbook(const Call& call, const ProdArgs& PA, unsigned G, size_t nw_max, double ops,
+                      hipStream_t s) {
+    ProfScope ps(call.prof, DKSS_K_SCHOOLBOOK, s, 8.0 * G * nw_max, ops);
+    hipLaunchKernelGGL(k_schoolbook, dim3(1, G), dim3(kThreads), nw_max * 3 * sizeof(uint32_t), s, PA);
+    return hipGetLastError() == hipSuccess ? DKSS_OK : DKSS_EHIP;
+}
+
+int run_mul(const Call& call, uint32_t* c, const uint32_t* a, size_t alen, const uint32_t* b,
+            size_t blen, void* ws, size_t ws_bytes, hipStream_t s) {
+    const size_t nw = alen + blen;
+    ProdArgs PA{};
+    PA.one = ProdDesc{c, a, b, (long long)alen, (long long)blen, call.P.u, 0};
+    PA.many = nullptr;
+    if (alen == 0 || blen == 0) return launch_zero(PA, 1, nw, s);
+    if (call.schoolbook) return launch_schoolbook(call, PA, 1, nw, (double)alen * (double)blen, s);
+    const bool squaring = (a == b && alen == blen);
+    if (ws == nullptr || ((uintptr_t)ws & 255)) return DKSS_EINVAL;
+    Workspace w = layout(call.P, 1, nw, !squaring, (char*)ws);
+    if (ws_bytes < w.bytes) return DKSS_ENOSPC;
+    return run_group(call, PA, 1, nw, (double)alen, (double)blen, (double)nw, squaring, w, s);
+}
+
+// A batch, planned: products grouped by plan (zero products, schoolbook products, and one group
+// per DKSS parameter tuple and level split), in the order of `order`.
+struct BatchPlan {
+    struct Grp {
+        int kind;                  // 0 zero, 1 schoolbook, 2 DKSS
+        size_t first, count;       // range in order
+        size_t nw_max;
+        double in_a, in_b, out_w, ops;
+        Call call;
+    };
+    std::vector<Grp> groups;
+    std::vector<size_t> order;
+    std::vector<Call> calls;
+    size_t desc_bytes = 0, ws_bytes = 0;
+};
+
+constexpr size_t kMaxGroup = 65535;     // gridDim.y
+
+int plan_batch(dkss_ctx* ctx, size_t count, const size_t* alen, const size_t* blen,
+               const dkss_params* p, BatchPlan* B) {
+    B->calls.assign(count, Call());
+    std::map<std::string, std::vector<size_t>> by_key;
+    for (size_t i = 0; i < count; ++i) {
+        int rc = prepare_call(ctx, alen[i], blen[i], p ? p + i : nullptr, &B->calls[i]);
+        if (rc) return rc;
+        const Call& c = B->calls[i];
+        std::string key;
+        if (alen[i] == 0 || blen[i] == 0) {
+            key = "0";
+        } else if (c.schoolbook) {
+            key = "1";
+        } else {
+            key = "2" + c.P.key() + "_r";
+            for (int r : c.P.radix_log2) key += std::to_string(r) + ".";
+        }
+        by_key[key].push_back(i);
+    }
+    B->desc_bytes = align256(count * sizeof(ProdDesc));
+    size_t ws_max = 0;
+    for (auto& kv : by_key) {
+        const std::vector<size_t>& idx = kv.second;
+        for (size_t off = 0; off < idx.size(); off += kMaxGroup) {
+            BatchPlan::Grp g{};
+            g.kind = kv.first[0] - '0';
+            g.first = B->order.size();
+            g.count = std::min(kMaxGroup, idx.size() - off);
+            g.call = B->calls[idx[off]];
+            for (size_t k = off; k < off + g.count; ++k) {
+                const size_t i = idx[k];
+                B->order.push_back(i);
+                g.nw_max = std::max(g.nw_max, alen[i] + blen[i]);
+                g.in_a += (double)alen[i];
+                g.in_b += (double)blen[i];
+                g.out_w += (double)(alen[i] + blen[i]);
+                g.ops += (double)alen[i] * (double)blen[i];
+            }
+            if (g.kind == 2)
+                ws_max = std::max(ws_max, layout(g.call.P, g.count, g.nw_max, true, nullptr).bytes);
+            B->groups.push_back(g);
+        }
+    }
+    B->ws_bytes = B->desc_bytes + ws_max;
+    return DKSS_OK;
+}
+
 
 }  // namespace
 
@@ -1255,6 +1451,24 @@ int run_mul(const Call& call, uint32_t* c, const uint32_t* a, size_t alen, const
 // ---------------------------------------------------------------------------------------------
 
 extern "C" {
+
+// pinned staging for count descriptors; waits until the previous copy out of it has run
+static int ensure_desc(dkss_ctx* ctx, size_t count) {
+    if (!ctx->desc_ev) HIP_OK(hipEventCreateWithFlags(&ctx->desc_ev, hipEventDisableTiming));
+    if (ctx->desc_pending) {
+        HIP_OK(hipEventSynchronize(ctx->desc_ev));
+        ctx->desc_pending = false;
+    }
+    if (ctx->hdesc_cap < count) {
+        if (ctx->hdesc) HIP_OK(hipHostFree(ctx->hdesc));
+        ctx->hdesc = nullptr;
+        ctx->hdesc_cap = 0;
+        const size_t cap = std::max<size_t>(count, 1024);
+        HIP_OK(hipHostMalloc((void**)&ctx->hdesc, cap * sizeof(ProdDesc), hipHostMallocDefault));
+        ctx->hdesc_cap = cap;
+    }
+    return DKSS_OK;
+}
 
 static int ensure_aux(dkss_ctx* ctx) {
     if (ctx->aux) return DKSS_OK;
@@ -1280,13 +1494,57 @@ int dkss_set_option(dkss_ctx* ctx, int option, long long value) {
     }
 }
 
+// The tuning table: text lines "lo hi cand" (log2 N range, candidate index); '#' comments.
+static void load_tuning(dkss_ctx* c, const char* dir) {
+    if (!dir) return;
+    std::string path = std::string(dir) + "/dkss_tuning.txt";
+    FILE* f = fopen(path.c_str(), "r");
+    if (!f) return;
+    char line[256];
+    while (fgets(line, sizeof line, f)) {
+        if (line[0] == '#') continue;
+        TuneEntry e{};
+        if (sscanf(line, "%lf %lf %d", &e.lo, &e.hi, &e.cand) == 3 && e.cand >= 0 &&
+            e.cand < kNumCandidates)
+            c->tuning.push_back(e);
+    }
+    fclose(f);
+}
+
 int dkss_ctx_create(dkss_ctx** out, int policy, const char* cache_dir) {
-    (void)cache_dir;
     if (!out || (policy != DKSS_POLICY_THESIS && policy != DKSS_POLICY_TUNED)) return DKSS_EINVAL;
     dkss_ctx* c = new (std::nothrow) dkss_ctx();
     if (!c) return DKSS_EINVAL;
     c->policy = policy;
+    load_tuning(c, cache_dir);
     *out = c;
+    return DKSS_OK;
+}
+
+static_assert(DKSS_NCAND == kNumCandidates, "candidate count");
+
+int dkss_candidates(dkss_ctx* ctx, uint64_t a_bits, uint64_t b_bits, dkss_params* out, int* valid) {
+    if (!ctx || !out || !valid) return DKSS_EINVAL;
+    const uint64_t N = 32 * ((std::max(a_bits, b_bits) + 31) / 32);
+    if (N == 0 || N > (1ull << 36)) return DKSS_ERANGE;
+    for (int c = 0; c < DKSS_NCAND; ++c) {
+        int lM = 0, lm = 0, u = 0, pb = 0;
+        memset(&out[c], 0, sizeof out[c]);
+        valid[c] = candidate_params(N, c, &lM, &lm, &u, &pb) ? 1 : 0;
+        if (!valid[c]) continue;
+        out[c].log2_M = (uint32_t)lM;
+        out[c].log2_m = (uint32_t)lm;
+        out[c].u = (uint32_t)u;
+        out[c].p_bits = (uint32_t)pb;
+        out[c].z = 1;
+        std::vector<int> r = default_radices(lM, lm, (pb + 31) / 32);
+        if (r.size() > 8) {           // more FFT levels than a plan holds
+            valid[c] = 0;
+            continue;
+        }
+        out[c].n_levels = (uint32_t)r.size();
+        for (size_t i = 0; i < r.size(); ++i) out[c].radix_log2[i] = (uint32_t)r[i];
+    }
     return DKSS_OK;
 }
 
@@ -1304,7 +1562,7 @@ int dkss_select_params(dkss_ctx* ctx, uint64_t a_bits, uint64_t b_bits, uint32_t
     const uint64_t N = 32 * ((std::max(a_bits, b_bits) + 31) / 32);
     if (N == 0 || N > (1ull << 36)) return DKSS_ERANGE;
     int lM, lm, u, pb;
-    if (!thesis_params(N, &lM, &lm, &u, &pb)) return DKSS_ERANGE;
+    if (!policy_tuple(ctx, N, &lM, &lm, &u, &pb)) return DKSS_ERANGE;
     memset(out, 0, sizeof *out);
     out->log2_M = (uint32_t)lM;
     out->log2_m = (uint32_t)lm;
@@ -1354,7 +1612,7 @@ int dkss_workspace_bytes(dkss_ctx* ctx, size_t alen, size_t blen, const dkss_par
         *out = 0;
         return DKSS_OK;
     }
-    *out = layout(call, nullptr).bytes;
+    *out = layout(call.P, 1, alen + blen, true, nullptr).bytes;
     return DKSS_OK;
 }
 
@@ -1389,14 +1647,10 @@ int dkss_mul(dkss_ctx* ctx, uint32_t* c, const uint32_t* a, size_t alen, const u
 int dkss_batch_workspace_bytes(dkss_ctx* ctx, size_t count, const size_t* alen, const size_t* blen,
                                const dkss_params* p, size_t* out) {
     if (!ctx || !out || (count && (!alen || !blen))) return DKSS_EINVAL;
-    size_t mx = 0;
-    for (size_t i = 0; i < count; ++i) {
-        size_t b = 0;
-        int rc = dkss_workspace_bytes(ctx, alen[i], blen[i], p ? p + i : nullptr, &b);
-        if (rc) return rc;
-        mx = std::max(mx, b);
-    }
-    *out = mx;
+    BatchPlan B;
+    int rc = plan_batch(ctx, count, alen, blen, p, &B);
+    if (rc) return rc;
+    *out = count ? B.ws_bytes : 0;
     return DKSS_OK;
 }
 
@@ -1404,8 +1658,47 @@ int dkss_mul_batch(dkss_ctx* ctx, size_t count, uint32_t* const* c, const uint32
                    const size_t* alen, const uint32_t* const* b, const size_t* blen,
                    const dkss_params* p, void* ws, size_t ws_bytes, dkss_stream_t s) {
     if (!ctx || (count && (!c || !a || !alen || !b || !blen))) return DKSS_EINVAL;
+    if (count == 0) return DKSS_OK;
     for (size_t i = 0; i < count; ++i) {
-        int rc = dkss_mul(ctx, c[i], a[i], alen[i], b[i], blen[i], p ? p + i : nullptr, ws, ws_bytes, s);
+        const size_t nw = alen[i] + blen[i];
+        if (!c[i] || (alen[i] && !a[i]) || (blen[i] && !b[i])) return DKSS_EINVAL;
+        if ((alen[i] && overlaps(c[i], nw * 4, a[i], alen[i] * 4)) ||
+            (blen[i] && overlaps(c[i], nw * 4, b[i], blen[i] * 4)))
+            return DKSS_EINVAL;
+    }
+    BatchPlan B;
+    int rc = plan_batch(ctx, count, alen, blen, p, &B);
+    if (rc) return rc;
+    if (ws == nullptr || ((uintptr_t)ws & 255)) return DKSS_EINVAL;
+    if (ws_bytes < B.ws_bytes) return DKSS_ENOSPC;
+    hipStream_t st = (hipStream_t)s;
+    for (const BatchPlan::Grp& g : B.groups)
+        if (g.kind == 2 && (rc = ensure_table(g.call.C, &ctx->prof, st))) return rc;
+    // descriptors, in group order, through the context's pinned staging buffer
+    if ((rc = ensure_desc(ctx, count))) return rc;
+    for (size_t k = 0; k < count; ++k) {
+        const size_t i = B.order[k];
+        ctx->hdesc[k] = ProdDesc{c[i], a[i], b[i], (long long)alen[i], (long long)blen[i], B.calls[i].P.u, 0};
+    }
+    ProdDesc* d_desc = (ProdDesc*)ws;
+    HIP_OK(hipMemcpyAsync(d_desc, ctx->hdesc, count * sizeof(ProdDesc), hipMemcpyHostToDevice, st));
+    HIP_OK(hipEventRecord(ctx->desc_ev, st));
+    ctx->desc_pending = true;
+    char* gws = (char*)ws + B.desc_bytes;
+    for (const BatchPlan::Grp& g : B.groups) {
+        ProdArgs PA{};
+        PA.many = d_desc + g.first;
+        const unsigned G = (unsigned)g.count;
+        if (g.kind == 0) {
+            rc = launch_zero(PA, G, g.nw_max, st);
+        } else if (g.kind == 1) {
+            rc = launch_schoolbook(g.call, PA, G, g.nw_max, g.ops, st);
+        } else {
+            Call call = g.call;
+            call.aux = nullptr;            // groups are wide enough to fill the GPU on one stream
+            Workspace w = layout(call.P, G, g.nw_max, true, gws);
+            rc = run_group(call, PA, G, g.nw_max, g.in_a, g.in_b, g.out_w, false, w, st);
+        }
         if (rc) return rc;
     }
     return DKSS_OK;
@@ -1419,12 +1712,14 @@ int dkss_forward(dkss_ctx* ctx, uint32_t* poly, const uint32_t* a, size_t alen, 
     if (rc) return rc;
     if (call.schoolbook) return DKSS_ERANGE;
     if ((rc = ensure_table(call.C, &ctx->prof, (hipStream_t)s))) return rc;
-    Workspace w = layout(call, (char*)ws);
     if (ws == nullptr || ((uintptr_t)ws & 255)) return DKSS_EINVAL;
+    Workspace w = layout(call.P, 1, alen + blen, true, (char*)ws);
     if (ws_bytes < w.bytes) return DKSS_ENOSPC;
     hipStream_t st = (hipStream_t)s;
-    if ((rc = dispatch_L<Encode>(call.P.L, call, w.A, a, alen, st))) return rc;
-    if ((rc = dispatch_L<Transform>(call.P.L, call, w.A, 0, st))) return rc;
+    ProdArgs PA{};
+    PA.one = ProdDesc{nullptr, a, a, (long long)alen, (long long)blen, call.P.u, 0};
+    if ((rc = dispatch_L<Encode>(call.P.L, call, PA, 1u, 0, w.A, w.S, (double)alen, st))) return rc;
+    if ((rc = dispatch_L<Transform>(call.P.L, call, w.A, w.S, 1u, 0, st))) return rc;
     LevelIdx LI{};
     LI.n = (int)call.P.radix_log2.size();
     int nlog = call.P.log2_M + 1, shift = 0;

@@ -178,6 +178,28 @@ bool thesis_params(uint64_t N, int* log2_M, int* log2_m, int* u, int* p_bits) {
     return true;
 }
 
+bool candidate_params(uint64_t N, int c, int* log2_M, int* log2_m, int* u, int* p_bits) {
+    if (N == 0 || N > (1ULL << 40) || c < 0 || c >= kNumCandidates) return false;
+    auto need_bits = [&](int t) -> uint64_t {       // bits of p: p - 1 >= Mm 2^(2u)
+        const uint64_t uu = ((2 * N) + (1ULL << t) - 1) >> t;
+        return (uint64_t)t + 2 * uu + 1;
+    };
+    int t = 2;
+    while (t <= 62 && need_bits(t) > 256) ++t;
+    if (t > 62) return false;
+    t += c / 6;
+    const int lm = c % 6 + 1;
+    if (lm > t - lm) return false;                   // M >= m
+    const uint64_t uu = ((2 * N) + (1ULL << t) - 1) >> t;
+    const uint64_t pb = 32 * ((need_bits(t) + 31) / 32);
+    if (pb > 256) return false;
+    *log2_m = lm;
+    *log2_M = t - lm;
+    *u = (int)uu;
+    *p_bits = (int)pb;
+    return true;
+}
+
 // ---------------------------------------------------------------------------------------------
 // Prime p (Sec. 3.2.2, Sec. 4.5) and generator (Sec. 3.2.3)
 // ---------------------------------------------------------------------------------------------

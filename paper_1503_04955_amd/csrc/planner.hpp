@@ -71,6 +71,12 @@ struct Plan {
 // tuple exists (N too large for the limits below).
 bool thesis_params(uint64_t N, int* log2_M, int* log2_m, int* u, int* p_bits);
 
+// Candidate tuple c (0 <= c < kNumCandidates) for N: Mm = 2^(t_min + c / 6), m = 2^(c % 6 + 1),
+// u = ceil(2N/Mm), p of the fewest whole 32-bit limbs with p >= 2 Mm 2^(2u).  t_min is the
+// smallest log2(Mm) for which that modulus has at most 256 bits.  False if M < m or no modulus.
+constexpr int kNumCandidates = 18;
+bool candidate_params(uint64_t N, int c, int* log2_M, int* log2_m, int* u, int* p_bits);
+
 // Smallest odd h with p = h*2^n + 1 prime, n = bits - bitlen(h), n >= min_n (Sec. 4.5).
 bool proth_prime(int bits, int min_n, Big* p, uint64_t* h, int* n);
 

@@ -220,3 +220,66 @@ def test_workspace_too_small(env):
     with pytest.raises(dk.DkssError) as e:
         ctx.mul(a, a, ws=ws)
     assert e.value.code == dk.ENOSPC
+
+
+# ---- batched products ------------------------------------------------------------------------
+
+def _batch_run(env, pairs, policy_ctx=None, params=None):
+    dk, torch, ctx = env
+    c0 = policy_ctx or ctx
+    das = [dk.to_device(a) for a, _ in pairs]
+    dbs = [dk.to_device(b) for _, b in pairs]
+    outs = c0.mul_batch(das, dbs, params=params)
+    torch.cuda.synchronize()
+    return [dk.to_host(o) for o in outs]
+
+
+def test_batch_mixed_small_vs_schoolbook(env):
+    """Zero-length, schoolbook-range and DKSS products of many parameter tuples in one batch."""
+    rng = random.Random(11)
+    lens = [(0, 5), (7, 0), (1, 1), (3, 64), (64, 64), (65, 65), (100, 13)]
+    lens += SI.batch_lengths(2024, 120, lo_bits=8, hi_bits=16)
+    pairs = [SI.operand_pair(1000 + i, al, bl) for i, (al, bl) in enumerate(lens)]
+    pairs.append((pairs[20][0], pairs[20][0]))                    # a squaring inside a batch
+    got = _batch_run(env, pairs)
+    for (a, b), g in zip(pairs, got):
+        assert np.array_equal(g, C.schoolbook(a, b)), (len(a), len(b))
+
+
+def test_batch_matches_plain_and_residues(env):
+    """A batch with the C3 length distribution (2^12..2^22 bits, ratio 1..8): every product equals
+    the plain single-product result and passes residue checks; a few against the oracle."""
+    dk, torch, ctx = env
+    lens = SI.batch_lengths(SI.SEED_BASE + 3, 256)
+    pairs = [SI.operand_pair(5000 + i, al, bl) for i, (al, bl) in enumerate(lens)]
+    got = _batch_run(env, pairs)
+    qs = _primes61(9, 4)
+    for i, ((a, b), g) in enumerate(zip(pairs, got)):
+        _residue_check(a, b, g, qs)
+        if i % 32 == 0:
+            assert np.array_equal(g, _gpu_mul(env, a, b))
+        if len(a) * len(b) < 4e6:
+            assert np.array_equal(g, C.schoolbook(a, b))
+
+
+@pytest.mark.parametrize("limbs", [128, 2048, 20000])
+def test_every_candidate_tuple_is_bit_exact(env, limbs):
+    """Parameter choices (tuner / selector search space) never change the product."""
+    dk, torch, ctx = env
+    a, b = SI.operand_pair(limbs, limbs, max(1, limbs // 3))
+    want = C.schoolbook(a, b)
+    cands = ctx.candidates(32 * limbs, 32 * limbs)
+    assert cands
+    for ci, p in cands:
+        p.cutoff_bits = 0
+        assert np.array_equal(_gpu_mul(env, a, b, p), want), ci
+
+
+def test_tuned_policy_products(env):
+    dk, torch, ctx = env
+    tctx = dk.Context(dk.POLICY_TUNED)
+    for limbs in [300, 5000, 1 << 15]:
+        a, b = SI.operand_pair(limbs + 7, limbs, limbs)
+        c = tctx.mul(dk.to_device(a), dk.to_device(b))
+        torch.cuda.synchronize()
+        assert np.array_equal(dk.to_host(c), C.schoolbook(a, b))
