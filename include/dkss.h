@@ -46,7 +46,9 @@ enum {
 /* Parameter policy of a context. */
 enum {
     DKSS_POLICY_THESIS = 0,   /* the thesis's rule, Sec. 4.1 (with Sec. 3.2 Steps 1-2) */
-    DKSS_POLICY_TUNED = 1     /* measured plans from the context's tuning table, else THESIS */
+    DKSS_POLICY_TUNED = 1,    /* measured plans from the context's tuning table, else THESIS */
+    DKSS_POLICY_LEARNED = 2   /* the learned selector's choice (dkss_set_mlp / dkss_mlp.txt),
+                               * else THESIS */
 };
 
 /*
@@ -81,8 +83,10 @@ typedef struct {
     uint32_t q[16];           /* p^z, L limbs */
 } dkss_plan;
 
-/* Create a context with the given policy.  cache_dir may be NULL.  Allocates nothing on the
- * device until a parameter tuple is first prepared.  Errors: DKSS_EINVAL. */
+/* Create a context with the given policy.  cache_dir may be NULL; a TUNED context reads
+ * cache_dir/dkss_tuning.txt and a LEARNED one cache_dir/dkss_mlp.txt (dkss_mlp_load) when they
+ * exist.  Allocates nothing on the device until a parameter tuple is first prepared or selector
+ * weights are installed.  Errors: DKSS_EINVAL. */
 int dkss_ctx_create(dkss_ctx** out, int policy, const char* cache_dir);
 
 /* Release the context and the device tables it owns.  Safe on NULL. */
@@ -90,7 +94,9 @@ void dkss_ctx_destroy(dkss_ctx* ctx);
 
 /* Parameters the context's policy picks for operands of a_bits and b_bits bits in a batch of
  * `batch` products.  N = max(a_bits, b_bits) rounded up to whole limbs (the thesis assumes equal
- * lengths, Sec. 3.2).  Errors: DKSS_EINVAL (null), DKSS_ERANGE (N = 0 or beyond 2^36 bits). */
+ * lengths, Sec. 3.2).  A LEARNED choice of a candidate sets cutoff_bits 0; its choice of the
+ * schoolbook sets cutoff_bits UINT64_MAX (with the thesis rule's tuple).  Errors: DKSS_EINVAL
+ * (null), DKSS_ERANGE (N = 0 or beyond 2^36 bits), DKSS_EHIP (learned inference). */
 int dkss_select_params(dkss_ctx* ctx, uint64_t a_bits, uint64_t b_bits, uint32_t batch,
                        dkss_params* out);
 
@@ -125,7 +131,10 @@ int dkss_prepare(dkss_ctx* ctx, size_t alen, size_t blen, const dkss_params* p, 
  * included.  a == b with alen == blen is a squaring (one forward transform).  alen or blen of 0
  * gives c = 0.  c must not overlap a or b (DKSS_EINVAL).  ws must hold at least
  * dkss_workspace_bytes() bytes of device memory, 256-byte aligned (DKSS_ENOSPC / DKSS_EINVAL).
- * p = NULL uses the context's policy.  Errors: DKSS_EINVAL, DKSS_ENOSPC, DKSS_ERANGE (p^z below
+ * p = NULL uses the context's policy; under DKSS_POLICY_LEARNED the first product of a shape
+ * waits for the selector's inference (dkss_mlp_choose, batch 1).  dkss_mul_batch asks the
+ * selector once for all new shapes of the batch, with batch = count.
+ * Errors: DKSS_EINVAL, DKSS_ENOSPC, DKSS_ERANGE (p^z below
  * Mm 2^(2u), 2M not dividing p - 1, M < m, m < 2, capacity M*m/2*u below 32*max(alen, blen),
  * unsupported limb count), DKSS_EHIP.
  */
@@ -199,6 +208,74 @@ const char* dkss_kernel_name(int kind);
  */
 enum { DKSS_OPT_OVERLAP = 0, DKSS_OPT_DFT_LDS = 1 };
 int dkss_set_option(dkss_ctx* ctx, int option, long long value);
+
+/*
+ * Learned parameter selector.  The thesis leaves the choice of parameters open beyond its
+ * asymptotic rule (Sec. 3.2 Steps 1-2, Sec. 4.1, and its outlook, Chapter 5); this selector
+ * predicts, for each candidate of dkss_candidates and for the schoolbook base case, the log of
+ * the run time per product, and the LEARNED policy takes the feasible candidate of least
+ * predicted time.  The network is an FP32 multilayer perceptron
+ *     h1 = relu(W1 x + b1), h2 = relu(W2 h1 + b2), y = W3 h2 + b3
+ * with DKSS_MLP_IN inputs, two hidden layers of DKSS_MLP_HID units and DKSS_MLP_OUT outputs:
+ * output c < DKSS_NCAND is candidate c, output DKSS_CAND_SCHOOLBOOK the schoolbook product.
+ * Parameters are one float array of DKSS_MLP_NPARAM entries in the order
+ *     W1[HID][IN], b1[HID], W2[HID][HID], b2[HID], W3[OUT][HID], b3[OUT]   (row-major).
+ * Training minimizes sum_n sum_k mask[n][k] (y[n][k] - t[n][k])^2 / mask_sum with Adam.
+ */
+enum {
+    DKSS_MLP_IN = 3,
+    DKSS_MLP_HID = 64,
+    DKSS_MLP_OUT = DKSS_NCAND + 1,
+    DKSS_CAND_SCHOOLBOOK = DKSS_NCAND,
+    DKSS_MLP_NPARAM = DKSS_MLP_HID * DKSS_MLP_IN + DKSS_MLP_HID + DKSS_MLP_HID * DKSS_MLP_HID +
+                      DKSS_MLP_HID + DKSS_MLP_OUT * DKSS_MLP_HID + DKSS_MLP_OUT
+};
+
+/* Selector inputs for a product of a_bits x b_bits bits in a batch of `batch` products (HOST
+ * out[DKSS_MLP_IN]): (log2(longer) - 21) / 9, (log2(shorter) - 21) / 9, log2(batch) / 12, with
+ * bit counts rounded up to whole limbs and at least one limb.  Errors: DKSS_EINVAL (null,
+ * batch 0). */
+int dkss_mlp_features(uint64_t a_bits, uint64_t b_bits, uint32_t batch, float* out);
+
+/* Forward pass: y[n][DKSS_MLP_OUT] from x[n][DKSS_MLP_IN] (all DEVICE pointers).  One wavefront
+ * per sample.  Errors: DKSS_EINVAL (null, n <= 0), DKSS_EHIP. */
+int dkss_mlp_forward(const float* params, const float* x, int n, float* y, dkss_stream_t s);
+
+/* Floats of the `work` buffer dkss_mlp_loss_grad needs for n samples: n * (DKSS_MLP_NPARAM + 1). */
+size_t dkss_mlp_work_floats(int n);
+
+/* Loss and its gradient (all DEVICE pointers): x[n][IN], targets t[n][OUT], mask[n][OUT]
+ * (weights, usually 0/1: which targets were measured), mask_sum > 0 the normalizer.  Writes
+ * grad[DKSS_MLP_NPARAM] and loss[1].  Per-sample gradients go to work and are summed in sample
+ * order, so the result does not depend on scheduling.  Errors: DKSS_EINVAL, DKSS_EHIP. */
+int dkss_mlp_loss_grad(const float* params, const float* x, const float* t, const float* mask, int n,
+                       float mask_sum, float* grad, float* loss, float* work, dkss_stream_t s);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8; step counts from 1) on DEVICE arrays of
+ * DKSS_MLP_NPARAM floats: m1, m2 are the moment estimates, zero before step 1.
+ * Errors: DKSS_EINVAL, DKSS_EHIP. */
+int dkss_mlp_adam(float* params, const float* grad, float* m1, float* m2, int step, float lr,
+                  dkss_stream_t s);
+
+/* Install selector weights (HOST array of DKSS_MLP_NPARAM finite floats, copied) in the
+ * context; NULL removes them.  Clears the context's cache of choices; the device copy is made at
+ * the next inference.  Errors: DKSS_EINVAL (null context, a non-finite weight). */
+int dkss_set_mlp(dkss_ctx* ctx, const float* params);
+
+/* Read weights from a text file (a header line "IN HID OUT" after '#' comments, then
+ * DKSS_MLP_NPARAM numbers) into params (HOST).  Errors: DKSS_EINVAL (unreadable or malformed). */
+int dkss_mlp_load(const char* path, float* params);
+
+/*
+ * The learned selector's choice for a product of a_bits x b_bits bits in a batch of `batch`:
+ * *cand = c < DKSS_NCAND (candidate c), DKSS_CAND_SCHOOLBOOK, or -1 when the context has no
+ * weights or no output is feasible (the thesis rule then applies).  Feasible: candidates that
+ * dkss_candidates marks valid; the schoolbook when both operands together have at most 4096
+ * limbs.  Inference runs dkss_mlp_forward on a stream private to the context and waits for it;
+ * choices are cached per (limbs of a, limbs of b, batch).  Errors: DKSS_EINVAL, DKSS_ERANGE,
+ * DKSS_EHIP.
+ */
+int dkss_mlp_choose(dkss_ctx* ctx, uint64_t a_bits, uint64_t b_bits, uint32_t batch, int* cand);
 
 /* Static description of an error code. */
 const char* dkss_strerror(int code);

@@ -16,6 +16,7 @@ LIB_PATH = os.path.join(_HERE, "csrc", "libdkss.so")
 
 POLICY_THESIS = 0
 POLICY_TUNED = 1
+POLICY_LEARNED = 2
 
 OK, EINVAL, ENOSPC, ERANGE, EHIP, ENOTIMPL = 0, -1, -2, -3, -4, -5
 
@@ -101,6 +102,16 @@ def lib():
         L.dkss_kernel_name.restype = ctypes.c_char_p
         L.dkss_set_option.argtypes = [vp, ctypes.c_int, ctypes.c_longlong]
         L.dkss_candidates.argtypes = [vp, u64, u64, PP, ctypes.POINTER(ctypes.c_int)]
+        fp = ctypes.POINTER(ctypes.c_float)
+        L.dkss_mlp_features.argtypes = [u64, u64, u32, fp]
+        L.dkss_mlp_forward.argtypes = [vp, vp, ctypes.c_int, vp, vp]
+        L.dkss_mlp_work_floats.argtypes = [ctypes.c_int]
+        L.dkss_mlp_work_floats.restype = sz
+        L.dkss_mlp_loss_grad.argtypes = [vp, vp, vp, vp, ctypes.c_int, ctypes.c_float, vp, vp, vp, vp]
+        L.dkss_mlp_adam.argtypes = [vp, vp, vp, vp, ctypes.c_int, ctypes.c_float, vp]
+        L.dkss_set_mlp.argtypes = [vp, fp]
+        L.dkss_mlp_load.argtypes = [ctypes.c_char_p, fp]
+        L.dkss_mlp_choose.argtypes = [vp, u64, u64, u32, ctypes.POINTER(ctypes.c_int)]
         L.dkss_strerror.argtypes = [ctypes.c_int]
         L.dkss_strerror.restype = ctypes.c_char_p
         _lib = L
@@ -111,9 +122,14 @@ EXPORTED = ["dkss_ctx_create", "dkss_ctx_destroy", "dkss_select_params", "dkss_p
             "dkss_workspace_bytes", "dkss_prepare", "dkss_mul", "dkss_mul_batch",
             "dkss_batch_workspace_bytes", "dkss_forward", "dkss_residues", "dkss_profile_enable",
             "dkss_profile_read", "dkss_profile_reset", "dkss_kernel_name", "dkss_set_option",
-            "dkss_candidates", "dkss_strerror"]
+            "dkss_candidates", "dkss_mlp_features", "dkss_mlp_forward", "dkss_mlp_work_floats",
+            "dkss_mlp_loss_grad", "dkss_mlp_adam", "dkss_set_mlp", "dkss_mlp_load",
+            "dkss_mlp_choose", "dkss_strerror"]
 
 NCAND = 18
+MLP_IN, MLP_HID, MLP_OUT = 3, 64, NCAND + 1
+CAND_SCHOOLBOOK = NCAND
+MLP_NPARAM = MLP_HID * MLP_IN + MLP_HID + MLP_HID * MLP_HID + MLP_HID + MLP_OUT * MLP_HID + MLP_OUT
 TUNING_DIR = os.path.join(_HERE, "tuning")
 
 OPT_OVERLAP, OPT_DFT_LDS = 0, 1
@@ -165,8 +181,10 @@ class Context:
     """A libdkss context: cached parameter constants and device tables."""
 
     def __init__(self, policy=POLICY_THESIS, tuning_dir=None):
-        """policy POLICY_THESIS (the thesis's rule) or POLICY_TUNED (the measured table in
-        tuning_dir/dkss_tuning.txt, default: the package's table, else the thesis's rule)."""
+        """policy POLICY_THESIS (the thesis's rule), POLICY_TUNED (the measured table in
+        tuning_dir/dkss_tuning.txt) or POLICY_LEARNED (the selector weights in
+        tuning_dir/dkss_mlp.txt); tuning_dir defaults to the package's tuning folder; without
+        the file the policy falls back to the thesis's rule."""
         h = ctypes.c_void_p()
         d = tuning_dir if tuning_dir is not None else TUNING_DIR
         _check(lib().dkss_ctx_create(ctypes.byref(h), policy, d.encode()), "dkss_ctx_create")
@@ -225,28 +243,27 @@ class Context:
         return out
 
     def mul_batch(self, as_, bs, outs=None, params=None, ws=None, stream=None):
-        torch = _torch()
-        n = len(as_)
-        if outs is None:
-            outs = [torch.empty(a.numel() + b.numel(), dtype=torch.int32, device=a.device)
-                    for a, b in zip(as_, bs)]
-        VP = ctypes.c_void_p * n
-        SZ = ctypes.c_size_t * n
-        al = SZ(*[a.numel() for a in as_])
-        bl = SZ(*[b.numel() for b in bs])
-        pa = None
-        if params is not None:
-            pa = (Params * n)(*params)
-        if ws is None:
-            nb = ctypes.c_size_t()
-            _check(lib().dkss_batch_workspace_bytes(self._h, n, al, bl, pa, ctypes.byref(nb)),
-                   "dkss_batch_workspace_bytes")
-            ws = _alloc_ws(nb.value, as_[0].device)
-        _check(lib().dkss_mul_batch(self._h, n, VP(*[_ptr(o) for o in outs]),
-                                    VP(*[_ptr(a) for a in as_]), al, VP(*[_ptr(b) for b in bs]),
-                                    bl, pa, _ptr(ws), ws.numel(), _stream_ptr(stream)),
-               "dkss_mul_batch")
-        return outs
+        """outs[i] = as_[i] * bs[i] in one dkss_mul_batch call; returns outs."""
+        call = BatchCall(self, as_, bs, outs, params, ws)
+        call(stream)
+        return call.outs
+
+    def set_mlp(self, weights):
+        """Install selector weights (MLP_NPARAM floats) for POLICY_LEARNED; None removes them."""
+        if weights is None:
+            _check(lib().dkss_set_mlp(self._h, None), "dkss_set_mlp")
+            return
+        w = np.ascontiguousarray(weights, dtype=np.float32)
+        assert w.size == MLP_NPARAM
+        _check(lib().dkss_set_mlp(self._h, w.ctypes.data_as(ctypes.POINTER(ctypes.c_float))),
+               "dkss_set_mlp")
+
+    def mlp_choose(self, a_bits, b_bits, batch=1):
+        """The selector's choice: a candidate index, CAND_SCHOOLBOOK, or -1 (thesis rule)."""
+        c = ctypes.c_int()
+        _check(lib().dkss_mlp_choose(self._h, a_bits, b_bits, batch, ctypes.byref(c)),
+               "dkss_mlp_choose")
+        return c.value
 
     def set_option(self, option, value):
         _check(lib().dkss_set_option(self._h, option, int(value)), "dkss_set_option")
@@ -278,6 +295,40 @@ class Context:
         return poly
 
 
+class BatchCall:
+    """A dkss_mul_batch call with its arguments marshalled once, for repeated launches over the
+    same tensors (the products are recomputed by every call)."""
+
+    def __init__(self, ctx, as_, bs, outs=None, params=None, ws=None, alloc_ws=True):
+        torch = _torch()
+        n = len(as_)
+        if outs is None:
+            outs = [torch.empty(a.numel() + b.numel(), dtype=torch.int32, device=a.device)
+                    for a, b in zip(as_, bs)]
+        self.ctx, self.as_, self.bs, self.outs, self.n = ctx, as_, bs, outs, n
+        VP = ctypes.c_void_p * n
+        SZ = ctypes.c_size_t * n
+        self.al = SZ(*[a.numel() for a in as_])
+        self.bl = SZ(*[b.numel() for b in bs])
+        self.pa = (Params * n)(*params) if params is not None else None
+        self.pc = VP(*[_ptr(o) for o in outs])
+        self.pa_ptrs = VP(*[_ptr(a) for a in as_])
+        self.pb_ptrs = VP(*[_ptr(b) for b in bs])
+        nb = ctypes.c_size_t()
+        _check(lib().dkss_batch_workspace_bytes(ctx._h, n, self.al, self.bl, self.pa,
+                                                ctypes.byref(nb)), "dkss_batch_workspace_bytes")
+        self.ws_bytes = nb.value
+        if ws is None and alloc_ws:
+            ws = _alloc_ws(nb.value, as_[0].device)
+        self.ws = ws
+
+    def __call__(self, stream=None):
+        _check(lib().dkss_mul_batch(self.ctx._h, self.n, self.pc, self.pa_ptrs, self.al,
+                                    self.pb_ptrs, self.bl, self.pa, _ptr(self.ws),
+                                    self.ws.numel(), _stream_ptr(stream)), "dkss_mul_batch")
+        return self.outs
+
+
 def residues(x, primes, stream=None):
     """x mod q for each q in primes (odd, < 2^62), computed on the device."""
     torch = _torch()
@@ -286,3 +337,71 @@ def residues(x, primes, stream=None):
     _check(lib().dkss_residues(_ptr(x), x.numel(), arr, len(primes), _ptr(out),
                                _stream_ptr(stream)), "dkss_residues")
     return [int(v) & 0xFFFFFFFFFFFFFFFF for v in out.cpu().tolist()]
+
+
+# ----- learned selector: the network's kernels ------------------------------------------------
+
+def mlp_features(a_bits, b_bits, batch=1):
+    """The selector's inputs for one product (numpy float32[MLP_IN])."""
+    out = (ctypes.c_float * MLP_IN)()
+    _check(lib().dkss_mlp_features(a_bits, b_bits, batch, out), "dkss_mlp_features")
+    return np.array(out[:], dtype=np.float32)
+
+
+def mlp_load(path):
+    """Selector weights from a text file (numpy float32[MLP_NPARAM])."""
+    w = np.zeros(MLP_NPARAM, dtype=np.float32)
+    _check(lib().dkss_mlp_load(path.encode(), w.ctypes.data_as(ctypes.POINTER(ctypes.c_float))),
+           "dkss_mlp_load")
+    return w
+
+
+def mlp_save(path, weights, comment=""):
+    """Write weights in the text form dkss_mlp_load reads."""
+    w = np.asarray(weights, dtype=np.float32).ravel()
+    assert w.size == MLP_NPARAM
+    with open(path, "w") as f:
+        for line in comment.splitlines():
+            f.write("# %s\n" % line)
+        f.write("%d %d %d\n" % (MLP_IN, MLP_HID, MLP_OUT))
+        for v in w:
+            f.write("%.9g\n" % float(v))
+
+
+def mlp_forward(params, x, y=None, stream=None):
+    """y[n][MLP_OUT] = network(x[n][MLP_IN]); float32 device tensors."""
+    torch = _torch()
+    n = x.shape[0]
+    if y is None:
+        y = torch.empty((n, MLP_OUT), dtype=torch.float32, device=x.device)
+    _check(lib().dkss_mlp_forward(_ptr(params), _ptr(x), n, _ptr(y), _stream_ptr(stream)),
+           "dkss_mlp_forward")
+    return y
+
+
+def mlp_work(n, device="cuda"):
+    """A work buffer for mlp_loss_grad over n samples."""
+    torch = _torch()
+    return torch.empty(lib().dkss_mlp_work_floats(n), dtype=torch.float32, device=device)
+
+
+def mlp_loss_grad(params, x, t, mask, mask_sum, grad=None, loss=None, work=None, stream=None):
+    """(grad[MLP_NPARAM], loss[1]) of the masked squared error; float32 device tensors."""
+    torch = _torch()
+    n = x.shape[0]
+    if grad is None:
+        grad = torch.empty(MLP_NPARAM, dtype=torch.float32, device=x.device)
+    if loss is None:
+        loss = torch.empty(1, dtype=torch.float32, device=x.device)
+    if work is None:
+        work = mlp_work(n, x.device)
+    _check(lib().dkss_mlp_loss_grad(_ptr(params), _ptr(x), _ptr(t), _ptr(mask), n,
+                                    float(mask_sum), _ptr(grad), _ptr(loss), _ptr(work),
+                                    _stream_ptr(stream)), "dkss_mlp_loss_grad")
+    return grad, loss
+
+
+def mlp_adam(params, grad, m1, m2, step, lr, stream=None):
+    """One Adam step in place on float32 device tensors (step counts from 1)."""
+    _check(lib().dkss_mlp_adam(_ptr(params), _ptr(grad), _ptr(m1), _ptr(m2), int(step), float(lr),
+                               _stream_ptr(stream)), "dkss_mlp_adam")

@@ -29,6 +29,7 @@
 #include <map>
 #include <memory>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "../../include/dkss.h"
@@ -899,6 +900,15 @@ struct TuneEntry {
 struct dkss_ctx {
     int policy = DKSS_POLICY_THESIS;
     std::vector<TuneEntry> tuning;
+    // learned selector
+    std::vector<float> mlp;             // weights (empty: none installed)
+    float* d_mlp = nullptr;             // device copy, made at the first inference
+    bool d_mlp_stale = true;
+    hipStream_t mlp_stream = nullptr;   // private stream of the selector's inference
+    float* h_io = nullptr;              // pinned features + predictions of io_cap samples
+    float* d_io = nullptr;
+    size_t io_cap = 0;
+    std::map<std::tuple<size_t, size_t, uint32_t>, int> choices;   // (alen, blen, batch) -> choice
     std::map<std::string, std::unique_ptr<Cached>> cache;
     Prof prof;
     bool overlap = true;
@@ -918,6 +928,13 @@ struct dkss_ctx {
         if (ev_fork) (void)hipEventDestroy(ev_fork);
         if (ev_join) (void)hipEventDestroy(ev_join);
         if (aux) (void)hipStreamDestroy(aux);
+        if (mlp_stream) {
+            (void)hipStreamSynchronize(mlp_stream);
+            (void)hipStreamDestroy(mlp_stream);
+        }
+        if (d_mlp) (void)hipFree(d_mlp);
+        if (d_io) (void)hipFree(d_io);
+        if (h_io) (void)hipHostFree(h_io);
     }
 };
 
@@ -938,8 +955,88 @@ bool policy_tuple(const dkss_ctx* ctx, uint64_t N, int* lM, int* lm, int* u, int
     return thesis_params(N, lM, lm, u, pb);
 }
 
-// parameters for a product, from the policy or the caller
-int resolve_params(dkss_ctx* ctx, size_t alen, size_t blen, const dkss_params* p, Call* out) {
+// ----- learned selector ------------------------------------------------------------------------
+
+// Can the selector's output c run a product of alen x blen limbs?
+bool learned_feasible(size_t alen, size_t blen, int c) {
+    if (c == DKSS_CAND_SCHOOLBOOK) return alen + blen <= kSchoolbookMaxWords;
+    int lM, lm, u, pb;
+    const uint64_t N = 32ull * std::max(alen, blen);
+    return candidate_params(N, c, &lM, &lm, &u, &pb) && default_radices(lM, lm, (pb + 31) / 32).size() <= 8;
+}
+
+int ensure_mlp_io(dkss_ctx* ctx, size_t n) {
+    if (!ctx->mlp_stream) HIP_OK(hipStreamCreateWithFlags(&ctx->mlp_stream, hipStreamNonBlocking));
+    if (!ctx->d_mlp) HIP_OK(hipMalloc((void**)&ctx->d_mlp, DKSS_MLP_NPARAM * sizeof(float)));
+    if (ctx->d_mlp_stale) {
+        HIP_OK(hipMemcpy(ctx->d_mlp, ctx->mlp.data(), DKSS_MLP_NPARAM * sizeof(float), hipMemcpyHostToDevice));
+        ctx->d_mlp_stale = false;
+    }
+    if (ctx->io_cap < n) {
+        if (ctx->d_io) HIP_OK(hipFree(ctx->d_io));
+        if (ctx->h_io) HIP_OK(hipHostFree(ctx->h_io));
+        ctx->d_io = nullptr;
+        ctx->h_io = nullptr;
+        ctx->io_cap = 0;
+        const size_t cap = std::max<size_t>(n, 256);
+        const size_t bytes = cap * (DKSS_MLP_IN + DKSS_MLP_OUT) * sizeof(float);
+        HIP_OK(hipMalloc((void**)&ctx->d_io, bytes));
+        HIP_OK(hipHostMalloc((void**)&ctx->h_io, bytes, hipHostMallocDefault));
+        ctx->io_cap = cap;
+    }
+    return DKSS_OK;
+}
+
+// The selector's choice for each product of alen[i] x blen[i] limbs in a batch of `batch`:
+// a candidate index, DKSS_CAND_SCHOOLBOOK, or -1 (no weights, nothing feasible, empty operand).
+// Shapes not seen before are evaluated together in one inference launch.
+int learned_choices(dkss_ctx* ctx, size_t count, const size_t* alen, const size_t* blen, uint32_t batch,
+                    int* out) {
+    using Key = std::tuple<size_t, size_t, uint32_t>;
+    for (size_t i = 0; i < count; ++i) out[i] = -1;
+    if (ctx->mlp.empty() || batch == 0) return DKSS_OK;
+    std::map<Key, size_t> fresh;               // unseen shape -> its row in the inference
+    std::vector<size_t> rows;                  // product index of each row
+    for (size_t i = 0; i < count; ++i) {
+        if (alen[i] == 0 || blen[i] == 0) continue;
+        const Key k{alen[i], blen[i], batch};
+        if (ctx->choices.count(k) || fresh.count(k)) continue;
+        fresh.emplace(k, rows.size());
+        rows.push_back(i);
+    }
+    if (!rows.empty()) {
+        const size_t n = rows.size();
+        int rc = ensure_mlp_io(ctx, n);
+        if (rc) return rc;
+        float* hx = ctx->h_io;
+        float* hy = ctx->h_io + n * DKSS_MLP_IN;
+        for (size_t r = 0; r < n; ++r)
+            dkss_mlp_features(32ull * alen[rows[r]], 32ull * blen[rows[r]], batch, hx + r * DKSS_MLP_IN);
+        float* dx = ctx->d_io;
+        float* dy = ctx->d_io + n * DKSS_MLP_IN;
+        hipStream_t st = ctx->mlp_stream;
+        HIP_OK(hipMemcpyAsync(dx, hx, n * DKSS_MLP_IN * sizeof(float), hipMemcpyHostToDevice, st));
+        if ((rc = dkss_mlp_forward(ctx->d_mlp, dx, (int)n, dy, (dkss_stream_t)st))) return rc;
+        HIP_OK(hipMemcpyAsync(hy, dy, n * DKSS_MLP_OUT * sizeof(float), hipMemcpyDeviceToHost, st));
+        HIP_OK(hipStreamSynchronize(st));
+        for (size_t r = 0; r < n; ++r) {
+            const size_t i = rows[r];
+            int best = -1;
+            for (int c = 0; c < DKSS_MLP_OUT; ++c)
+                if ((best < 0 || hy[r * DKSS_MLP_OUT + c] < hy[r * DKSS_MLP_OUT + best]) &&
+                    learned_feasible(alen[i], blen[i], c))
+                    best = c;
+            ctx->choices[Key{alen[i], blen[i], batch}] = best;
+        }
+    }
+    for (size_t i = 0; i < count; ++i)
+        if (alen[i] && blen[i]) out[i] = ctx->choices[Key{alen[i], blen[i], batch}];
+    return DKSS_OK;
+}
+
+// parameters for a product, from the policy or the caller.  choice: the learned selector's
+// output for the product (-1: none, use the policy's tuple).
+int resolve_params(dkss_ctx* ctx, size_t alen, size_t blen, const dkss_params* p, Call* out, int choice) {
     out->alen = alen;
     out->blen = blen;
     const uint64_t N = 32ull * std::max(alen, blen);
@@ -948,13 +1045,18 @@ int resolve_params(dkss_ctx* ctx, size_t alen, size_t blen, const dkss_params* p
     if (N > (1ull << 36)) return DKSS_ERANGE;
     if (p == nullptr) {
         int lM, lm, u, pb;
-        if (!policy_tuple(ctx, N, &lM, &lm, &u, &pb)) return DKSS_ERANGE;
+        P.cutoff_bits = kDefaultCutoffBits;
+        if (choice >= 0 && choice < kNumCandidates && candidate_params(N, choice, &lM, &lm, &u, &pb)) {
+            P.cutoff_bits = 0;
+        } else {
+            if (!policy_tuple(ctx, N, &lM, &lm, &u, &pb)) return DKSS_ERANGE;
+            if (choice == DKSS_CAND_SCHOOLBOOK) P.cutoff_bits = UINT64_MAX;
+        }
         P.log2_M = lM;
         P.log2_m = lm;
         P.u = u;
         P.p_bits = pb;
         P.z = 1;
-        P.cutoff_bits = kDefaultCutoffBits;
     } else {
         P.log2_M = (int)p->log2_M;
         P.log2_m = (int)p->log2_m;
@@ -1311,11 +1413,18 @@ bool overlaps(const void* x, size_t xb, const void* y, size_t yb) {
     return a < b + yb && b < a + xb;
 }
 
-int prepare_call(dkss_ctx* ctx, size_t alen, size_t blen, const dkss_params* p, Call* call) {
+// batch: the product's batch size, the learned selector's third input
+int prepare_call(dkss_ctx* ctx, size_t alen, size_t blen, const dkss_params* p, Call* call,
+                 uint32_t batch = 1) {
     call->prof = &ctx->prof;
     call->dft_lds = ctx->dft_lds;
     call->overlap = ctx->overlap;
-    int rc = resolve_params(ctx, alen, blen, p, call);
+    int choice = -1;
+    if (!p && ctx->policy == DKSS_POLICY_LEARNED) {
+        int rc = learned_choices(ctx, 1, &alen, &blen, batch, &choice);
+        if (rc) return rc;
+    }
+    int rc = resolve_params(ctx, alen, blen, p, call, choice);
     if (rc) return rc;
     if (alen == 0 || blen == 0 || call->schoolbook) return DKSS_OK;
     return plan_constants(ctx, call);
@@ -1400,8 +1509,14 @@ int plan_batch(dkss_ctx* ctx, size_t count, const size_t* alen, const size_t* bl
                const dkss_params* p, BatchPlan* B) {
     B->calls.assign(count, Call());
     std::map<std::string, std::vector<size_t>> by_key;
+    const uint32_t batch = (uint32_t)std::min<size_t>(count, UINT32_MAX);
+    if (!p && ctx->policy == DKSS_POLICY_LEARNED) {     // one inference for every new shape
+        std::vector<int> ch(count);
+        int rc = learned_choices(ctx, count, alen, blen, batch, ch.data());
+        if (rc) return rc;
+    }
     for (size_t i = 0; i < count; ++i) {
-        int rc = prepare_call(ctx, alen[i], blen[i], p ? p + i : nullptr, &B->calls[i]);
+        int rc = prepare_call(ctx, alen[i], blen[i], p ? p + i : nullptr, &B->calls[i], batch);
         if (rc) return rc;
         const Call& c = B->calls[i];
         std::string key;
@@ -1512,13 +1627,75 @@ static void load_tuning(dkss_ctx* c, const char* dir) {
 }
 
 int dkss_ctx_create(dkss_ctx** out, int policy, const char* cache_dir) {
-    if (!out || (policy != DKSS_POLICY_THESIS && policy != DKSS_POLICY_TUNED)) return DKSS_EINVAL;
+    if (!out || (policy != DKSS_POLICY_THESIS && policy != DKSS_POLICY_TUNED && policy != DKSS_POLICY_LEARNED))
+        return DKSS_EINVAL;
     dkss_ctx* c = new (std::nothrow) dkss_ctx();
     if (!c) return DKSS_EINVAL;
     c->policy = policy;
     load_tuning(c, cache_dir);
+    if (cache_dir && policy == DKSS_POLICY_LEARNED) {
+        std::vector<float> w(DKSS_MLP_NPARAM);
+        if (dkss_mlp_load((std::string(cache_dir) + "/dkss_mlp.txt").c_str(), w.data()) == DKSS_OK)
+            c->mlp = std::move(w);
+    }
     *out = c;
     return DKSS_OK;
+}
+
+int dkss_set_mlp(dkss_ctx* ctx, const float* params) {
+    if (!ctx) return DKSS_EINVAL;
+    if (params) {
+        for (int i = 0; i < DKSS_MLP_NPARAM; ++i)
+            if (!std::isfinite(params[i])) return DKSS_EINVAL;
+        ctx->mlp.assign(params, params + DKSS_MLP_NPARAM);
+    } else {
+        ctx->mlp.clear();
+    }
+    ctx->d_mlp_stale = true;
+    ctx->choices.clear();
+    return DKSS_OK;
+}
+
+int dkss_mlp_load(const char* path, float* params) {
+    if (!path || !params) return DKSS_EINVAL;
+    FILE* f = fopen(path, "r");
+    if (!f) return DKSS_EINVAL;
+    char line[256];
+    int in = 0, hid = 0, outn = 0, got = 0;
+    bool header = false;
+    while (fgets(line, sizeof line, f)) {
+        if (line[0] == '#' || line[0] == '\n') continue;
+        if (!header) {
+            header = sscanf(line, "%d %d %d", &in, &hid, &outn) == 3;
+            if (!header || in != DKSS_MLP_IN || hid != DKSS_MLP_HID || outn != DKSS_MLP_OUT) break;
+            continue;
+        }
+        float v;
+        if (got >= DKSS_MLP_NPARAM || sscanf(line, "%f", &v) != 1 || !std::isfinite(v)) {
+            got = -1;
+            break;
+        }
+        params[got++] = v;
+    }
+    fclose(f);
+    return header && got == DKSS_MLP_NPARAM ? DKSS_OK : DKSS_EINVAL;
+}
+
+int dkss_mlp_features(uint64_t a_bits, uint64_t b_bits, uint32_t batch, float* out) {
+    if (!out || batch == 0) return DKSS_EINVAL;
+    const double la = 32.0 * (double)std::max<uint64_t>(1, (a_bits + 31) / 32);
+    const double lb = 32.0 * (double)std::max<uint64_t>(1, (b_bits + 31) / 32);
+    out[0] = (float)((std::log2(std::max(la, lb)) - 21.0) / 9.0);
+    out[1] = (float)((std::log2(std::min(la, lb)) - 21.0) / 9.0);
+    out[2] = (float)(std::log2((double)batch) / 12.0);
+    return DKSS_OK;
+}
+
+int dkss_mlp_choose(dkss_ctx* ctx, uint64_t a_bits, uint64_t b_bits, uint32_t batch, int* cand) {
+    if (!ctx || !cand || batch == 0) return DKSS_EINVAL;
+    const size_t alen = (size_t)((a_bits + 31) / 32), blen = (size_t)((b_bits + 31) / 32);
+    if (alen == 0 || blen == 0 || 32ull * std::max(alen, blen) > (1ull << 36)) return DKSS_ERANGE;
+    return learned_choices(ctx, 1, &alen, &blen, batch, cand);
 }
 
 static_assert(DKSS_NCAND == kNumCandidates, "candidate count");
@@ -1557,19 +1734,30 @@ void dkss_ctx_destroy(dkss_ctx* ctx) {
 
 int dkss_select_params(dkss_ctx* ctx, uint64_t a_bits, uint64_t b_bits, uint32_t batch,
                        dkss_params* out) {
-    (void)batch;
     if (!ctx || !out) return DKSS_EINVAL;
     const uint64_t N = 32 * ((std::max(a_bits, b_bits) + 31) / 32);
     if (N == 0 || N > (1ull << 36)) return DKSS_ERANGE;
+    int choice = -1;
+    if (ctx->policy == DKSS_POLICY_LEARNED) {
+        const size_t alen = (size_t)((a_bits + 31) / 32), blen = (size_t)((b_bits + 31) / 32);
+        int rc = learned_choices(ctx, 1, &alen, &blen, batch ? batch : 1, &choice);
+        if (rc) return rc;
+    }
     int lM, lm, u, pb;
-    if (!policy_tuple(ctx, N, &lM, &lm, &u, &pb)) return DKSS_ERANGE;
+    uint64_t cutoff = kDefaultCutoffBits;
+    if (choice >= 0 && choice < kNumCandidates && candidate_params(N, choice, &lM, &lm, &u, &pb)) {
+        cutoff = 0;
+    } else {
+        if (!policy_tuple(ctx, N, &lM, &lm, &u, &pb)) return DKSS_ERANGE;
+        if (choice == DKSS_CAND_SCHOOLBOOK) cutoff = UINT64_MAX;
+    }
     memset(out, 0, sizeof *out);
     out->log2_M = (uint32_t)lM;
     out->log2_m = (uint32_t)lm;
     out->u = (uint32_t)u;
     out->p_bits = (uint32_t)pb;
     out->z = 1;
-    out->cutoff_bits = kDefaultCutoffBits;
+    out->cutoff_bits = cutoff;
     std::vector<int> r = default_radices(lM, lm, (pb + 31) / 32);
     out->n_levels = (uint32_t)r.size();
     for (size_t i = 0; i < r.size() && i < 8; ++i) out->radix_log2[i] = (uint32_t)r[i];

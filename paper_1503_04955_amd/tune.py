@@ -1,19 +1,30 @@
-"""Autotuner: measure every candidate parameter tuple on the GPU and write the tuned table.
+"""Autotuner: measure every candidate parameter tuple on the GPU; write the tuned table and the
+training data of the learned selector.
 
-    python -m paper_1503_04955_amd.tune [--lo 12] [--hi 30] [--step 0.5] [--ratios 1,2,4,8]
-                                        [--out DIR]
+    python -m paper_1503_04955_amd.tune [--set train|heldout] [--out DIR] [--reps 3]
 
-For each operand size N = 2^x bits (x from lo to hi in steps) and each length ratio, every
-feasible candidate tuple (dkss_candidates: Mm offset x log2 m, the smallest modulus for it) and
-the thesis's rule are timed as whole products on seeded operands (the context's tables built
-beforehand, median of a few repetitions).  Writes
-  DIR/dkss_tuning.txt   "lo hi cand" lines: the fastest candidate per size bucket (ratio 1)
-  DIR/timings.json      every measurement: the training data of the learned selector
-The table is what a DKSS_POLICY_TUNED context loads.  Choices never change result bits; each
-measured product is checked by residues on the GPU.
+A point is (x, ratio, batch): `batch` independent products of 2^x-bit by 2^x/ratio-bit operands
+(whole limbs).  At each point every feasible candidate tuple (dkss_candidates: Mm offset x
+log2 m, the smallest modulus for it), the schoolbook base case where it applies (both operands
+together at most 4096 limbs) and the thesis's rule (the context's THESIS policy) are timed:
+`reps` back-to-back calls between two HIP events after one warm call, divided by reps and by
+batch, so each figure is milliseconds per product.  batch 1 runs dkss_mul, larger batches one
+dkss_mul_batch call.  Every timed product is checked by residues on the GPU (all of a single
+product, the first and the last of a batch).
+
+Sets of points
+  train     x in 12..29.5 step 0.5, ratios 1,2,4,8, batch 1; and x in 12..22 step 1, ratios
+            1,2,4,8, batch 16, 256, 4096 while batch * 2^x <= 2^33
+  heldout   points the selector never sees in training: x = 30 and quarter points between the
+            training sizes, ratio 1 and 3, batch 1; and batch 64 and 1024 at quarter points
+
+Writes (train) DIR/dkss_tuning.txt, "lo hi cand" lines: the fastest candidate per size bucket at
+ratio 1 and batch 1 (what a DKSS_POLICY_TUNED context loads), and DIR/timings.json; (heldout)
+DIR/timings_heldout.json.  Choices never change result bits.
 """
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -25,23 +36,41 @@ if ROOT not in sys.path:
 import paper_1503_04955_amd as dk  # noqa: E402
 
 CHECK_PRIMES = [2305843009213693951, 4611686018427387847, 1152921504606846883]
+WS_LIMIT = 64 << 30          # skip a candidate whose batched workspace exceeds this
+SCHOOLBOOK = dk.CAND_SCHOOLBOOK
 
 
-def _time_product(ctx, a, b, c, ws, params, reps, torch):
-    ctx.prepare(a.numel(), b.numel(), params)
-    ctx.mul(a, b, out=c, params=params, ws=ws)          # warm
-    torch.cuda.synchronize()
-    times = []
-    for _ in range(reps):
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record()
-        ctx.mul(a, b, out=c, params=params, ws=ws)
-        e1.record()
-        torch.cuda.synchronize()
-        times.append(e0.elapsed_time(e1))
-    times.sort()
-    return times[len(times) // 2]
+def train_points():
+    pts = []
+    x = 12.0
+    while x <= 29.5 + 1e-9:
+        for r in (1, 2, 4, 8):
+            pts.append((x, r, 1))
+        x += 0.5
+    for B in (16, 256, 4096):
+        for xi in range(12, 23):
+            if B * 2.0 ** xi <= 2.0 ** 33:
+                for r in (1, 2, 4, 8):
+                    pts.append((float(xi), r, B))
+    return pts
+
+
+def heldout_points():
+    pts = [(30.0, 1, 1), (30.0, 3, 1)]
+    for x in (12.25, 13.75, 15.25, 16.75, 18.25, 19.75, 21.25, 22.75, 24.25, 25.75, 27.25, 28.75):
+        for r in (1, 3):
+            pts.append((x, r, 1))
+    for B in (64, 1024):
+        for x in (12.25, 14.75, 17.25, 19.75, 22.25):
+            if B * 2.0 ** x <= 2.0 ** 33:
+                for r in (1, 3):
+                    pts.append((x, r, B))
+    return pts
+
+
+def _lengths(x, ratio):
+    n = max(1, int(round(2.0 ** x / 32)))
+    return n, max(1, int(round(n / ratio)))
 
 
 def _check(a, b, c):
@@ -49,66 +78,137 @@ def _check(a, b, c):
     return all(z == x * y % q for x, y, z, q in zip(ra, rb, rc, CHECK_PRIMES))
 
 
-def tune(lo, hi, step, ratios, out_dir, reps=3, verbose=True):
-    import torch
-    import seeded_inputs as SI
+def _events_ms(fn, reps, torch):
+    fn()                                              # warm: tables, caches
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
 
+
+def entries(ctx, n, nb):
+    """[(label, Params)]: 'thesis', candidate indices, SCHOOLBOOK where it applies."""
+    th = ctx.select_params(32 * n, 32 * nb)
+    out = [("thesis", th)]
+    for ci, p in ctx.candidates(32 * n, 32 * nb):
+        p.cutoff_bits = 0
+        out.append((ci, p))
+    if n + nb <= 4096:
+        sb = ctx.select_params(32 * n, 32 * nb)
+        sb.cutoff_bits = (1 << 64) - 1
+        out.append((SCHOOLBOOK, sb))
+    return out
+
+
+def measure_point(ctx, x, ratio, batch, reps, torch, seed):
+    """{label: ms per product} at one point."""
+    n, nb = _lengths(x, ratio)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(seed)
+    A = torch.randint(-2 ** 31, 2 ** 31, (batch * n,), dtype=torch.int32, device="cuda", generator=g)
+    B = torch.randint(-2 ** 31, 2 ** 31, (batch * nb,), dtype=torch.int32, device="cuda", generator=g)
+    C = torch.empty(batch * (n + nb), dtype=torch.int32, device="cuda")
+    as_ = [A[i * n:(i + 1) * n] for i in range(batch)]
+    bs = [B[i * nb:(i + 1) * nb] for i in range(batch)]
+    cs = [C[i * (n + nb):(i + 1) * (n + nb)] for i in range(batch)]
+    res = {}
+    for label, p in entries(ctx, n, nb):
+        if batch == 1:
+            ws = torch.empty(max(ctx.workspace_bytes(n, nb, p), 1), dtype=torch.uint8, device="cuda")
+            ctx.prepare(n, nb, p)
+
+            def fn(p=p, ws=ws):
+                ctx.mul(as_[0], bs[0], out=cs[0], params=p, ws=ws)
+        else:
+            call = dk.BatchCall(ctx, as_, bs, cs, [p] * batch, alloc_ws=False)
+            if call.ws_bytes > WS_LIMIT:
+                continue
+            call.ws = torch.empty(max(call.ws_bytes, 1), dtype=torch.uint8, device="cuda")
+            fn = call
+        ms = _events_ms(fn, reps, torch)
+        for i in sorted({0, batch - 1}):
+            if not _check(as_[i], bs[i], cs[i]):
+                raise RuntimeError("product check failed: %s at 2^%.2f ratio %d batch %d"
+                                   % (label, x, ratio, batch))
+        res[label] = (ms / batch, p.as_dict())
+        del fn
+    del A, B, C
+    torch.cuda.empty_cache()
+    return res
+
+
+def run(points, reps, out_json, verbose=True, tuned_txt=None, merge=False):
+    """Measure the points; with merge, rows of out_json at other points are kept."""
+    import torch
     ctx = dk.Context()
     rows = []
-    best = []
-    x = lo
-    while x <= hi + 1e-9:
-        for ratio in ratios:
-            n = max(1, int(round(2.0 ** x / 32)))
-            nb = max(1, int(round(n / ratio)))
-            a_h, b_h = SI.operand_pair(int(x * 100) + ratio, n, nb)
-            a, b = dk.to_device(a_h), dk.to_device(b_h)
-            c = torch.empty(n + nb, dtype=torch.int32, device="cuda")
-            cands = [(ci, p) for ci, p in ctx.candidates(32 * n, 32 * nb)]
-            entries = [("thesis", ctx.select_params(32 * n, 32 * nb))] + cands
-            wsb = max(ctx.workspace_bytes(n, nb, p) for _, p in entries)
-            ws = torch.empty(max(wsb, 1), dtype=torch.uint8, device="cuda")
-            results = {}
-            for ci, p in entries:
-                p.cutoff_bits = 0
-                ms = _time_product(ctx, a, b, c, ws, p, reps, torch)
-                if not _check(a, b, c):
-                    raise RuntimeError("product check failed for candidate %s at 2^%.1f" % (ci, x))
-                results[ci] = ms
-                rows.append({"log2_a": x, "log2_b": x - (ratio.bit_length() - 1), "ratio": ratio,
-                             "batch": 1, "cand": ci, "ms": ms, "params": p.as_dict()})
-            win = min((k for k in results if k != "thesis"), key=lambda k: results[k])
-            if verbose:
-                print("2^%.1f ratio %d: thesis %.4f ms, best cand %d %.4f ms (%s)" % (
-                    x, ratio, results["thesis"], win, results[win],
-                    dict(entries)[win].as_dict()), flush=True)
-            if ratio == 1:
-                best.append((x, win, results[win], results["thesis"]))
-        x += step
-        torch.cuda.empty_cache()
-    os.makedirs(out_dir, exist_ok=True)
-    with open(os.path.join(out_dir, "dkss_tuning.txt"), "w") as f:
+    if merge and os.path.exists(out_json):
+        keys = {(x, r, b) for x, r, b in points}
+        with open(out_json) as f:
+            rows = [r for r in json.load(f)["rows"]
+                    if (r["log2_a"], r["ratio"], r["batch"]) not in keys]
+    t0 = time.time()
+    for k, (x, ratio, batch) in enumerate(points):
+        res = measure_point(ctx, x, ratio, batch, reps, torch, seed=int(x * 1000) * 100 + ratio * 10 + k)
+        for label, (ms, pd) in res.items():
+            rows.append({"log2_a": x, "log2_b": x - math.log2(ratio), "ratio": ratio,
+                         "batch": batch, "cand": label, "ms": ms, "params": pd})
+        if verbose:
+            win = min((c for c in res if c != "thesis"), key=lambda c: res[c][0])
+            print("[%4d/%d %6.0fs] 2^%.2f ratio %d batch %d: thesis %.5f ms, best %s %.5f ms"
+                  % (k + 1, len(points), time.time() - t0, x, ratio, batch, res["thesis"][0], win,
+                     res[win][0]), flush=True)
+    os.makedirs(os.path.dirname(out_json) or ".", exist_ok=True)
+    with open(out_json, "w") as f:
+        json.dump({"arch": "gfx950", "reps": reps, "unit": "ms per product", "rows": rows}, f)
+    if tuned_txt:
+        write_tuned_table(rows, tuned_txt)
+    return rows
+
+
+def write_tuned_table(rows, path):
+    """Fastest DKSS candidate per size at ratio 1 and batch 1, as half-open log2 N buckets."""
+    best = {}
+    for r in rows:
+        if r["ratio"] != 1 or r["batch"] != 1 or not isinstance(r["cand"], int) or r["cand"] == SCHOOLBOOK:
+            continue
+        x = r["log2_a"]
+        if x not in best or r["ms"] < best[x][1]:
+            best[x] = (r["cand"], r["ms"])
+    thesis = {r["log2_a"]: r["ms"] for r in rows
+              if r["ratio"] == 1 and r["batch"] == 1 and r["cand"] == "thesis"}
+    xs = sorted(best)
+    with open(path, "w") as f:
         f.write("# log2N_lo log2N_hi candidate   (fastest measured candidate; ms best / thesis)\n")
-        for i, (x, win, ms, ms_th) in enumerate(best):
-            lo_b = x - step / 2 if i else 0.0
-            hi_b = x + step / 2 if i + 1 < len(best) else 64.0
-            f.write("%.3f %.3f %d   # %.4f / %.4f\n" % (lo_b, hi_b, win, ms, ms_th))
-    with open(os.path.join(out_dir, "timings.json"), "w") as f:
-        json.dump({"arch": "gfx950", "reps": reps, "rows": rows}, f)
-    return best
+        for i, x in enumerate(xs):
+            lo = (xs[i - 1] + x) / 2 if i else 0.0
+            hi = (x + xs[i + 1]) / 2 if i + 1 < len(xs) else 64.0
+            f.write("%.3f %.3f %d   # %.4f / %.4f\n" % (lo, hi, best[x][0], best[x][1], thesis.get(x, 0.0)))
 
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--lo", type=float, default=12)
-    ap.add_argument("--hi", type=float, default=30)
-    ap.add_argument("--step", type=float, default=0.5)
-    ap.add_argument("--ratios", default="1,2,4,8")
+    ap.add_argument("--set", choices=["train", "heldout"], default="train")
     ap.add_argument("--reps", type=int, default=3)
     ap.add_argument("--out", default=dk.TUNING_DIR)
+    ap.add_argument("--batches", default="", help="measure only these batch sizes, e.g. 1 or 16,256")
+    ap.add_argument("--merge", action="store_true", help="keep the file's rows at other points")
     args = ap.parse_args()
+    pts = train_points() if args.set == "train" else heldout_points()
+    if args.batches:
+        keep = {int(b) for b in args.batches.split(",")}
+        pts = [p for p in pts if p[2] in keep]
     t0 = time.time()
-    tune(args.lo, args.hi, args.step, [int(r) for r in args.ratios.split(",")], args.out, args.reps)
+    if args.set == "train":
+        run(pts, args.reps, os.path.join(args.out, "timings.json"),
+            tuned_txt=os.path.join(args.out, "dkss_tuning.txt"), merge=args.merge)
+    else:
+        run(pts, args.reps, os.path.join(args.out, "timings_heldout.json"), merge=args.merge)
     print("tuning took %.1f s" % (time.time() - t0), flush=True)
 
 

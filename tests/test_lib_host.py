@@ -97,3 +97,50 @@ def test_workspace_and_schoolbook_routing(dk):
     info = ctx.plan_info(8192, 8192)
     assert info.schoolbook == 0
     assert ctx.workspace_bytes(8192, 8192) >= 2 * info.poly_bytes
+
+
+@pytest.mark.parametrize("a,b,batch", [(1, 1, 1), (2 ** 18, 2 ** 15, 16), (2 ** 30, 2 ** 30, 4096),
+                                       (100, 5000, 3), (2 ** 36, 7, 65535), (0, 40, 1)])
+def test_selector_features_match_oracle(dk, a, b, batch):
+    import numpy as np
+    import oracle.mlp as om
+    np.testing.assert_allclose(dk.mlp_features(a, b, batch), om.features(a, b, batch), rtol=1e-6,
+                               atol=1e-7)
+
+
+def test_selector_weights_io_and_errors(dk, tmp_path):
+    import numpy as np
+    w = np.random.default_rng(3).normal(0, 1, dk.MLP_NPARAM).astype(np.float32)
+    path = str(tmp_path / "w.txt")
+    dk.mlp_save(path, w, comment="test weights\nsecond line")
+    assert np.array_equal(dk.mlp_load(path), w)          # %.9g round-trips float32 exactly
+    bad = str(tmp_path / "bad.txt")
+    with open(bad, "w") as f:
+        f.write("3 64 7\n" + "0\n" * dk.MLP_NPARAM)       # wrong output count
+    with pytest.raises(dk.DkssError):
+        dk.mlp_load(bad)
+    with open(bad, "w") as f:
+        f.write("3 64 %d\n" % dk.MLP_OUT + "0\n" * (dk.MLP_NPARAM - 1))   # one weight short
+    with pytest.raises(dk.DkssError):
+        dk.mlp_load(bad)
+    ctx = dk.Context(dk.POLICY_LEARNED, tuning_dir=str(tmp_path))   # no dkss_mlp.txt there
+    assert ctx.mlp_choose(2 ** 20, 2 ** 20) == -1                     # thesis fallback, no device work
+    p = ctx.select_params(2 ** 20, 2 ** 20)
+    t = dk.Context().select_params(2 ** 20, 2 ** 20)
+    assert p.as_dict() == t.as_dict()
+    w[17] = np.nan
+    with pytest.raises(dk.DkssError):
+        ctx.set_mlp(w)
+    with pytest.raises(dk.DkssError):
+        ctx.mlp_choose(0, 5)
+    assert dk.lib().dkss_mlp_features(1, 1, 0, (ctypes.c_float * 3)()) == dk.EINVAL
+    assert dk.lib().dkss_mlp_work_floats(10) == 10 * (dk.MLP_NPARAM + 1)
+
+
+def test_committed_selector_weights_load(dk):
+    path = os.path.join(dk.TUNING_DIR, "dkss_mlp.txt")
+    if not os.path.exists(path):
+        pytest.skip("no trained selector weights in the package")
+    import numpy as np
+    w = dk.mlp_load(path)
+    assert w.shape == (dk.MLP_NPARAM,) and np.all(np.isfinite(w))
