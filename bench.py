@@ -1,6 +1,6 @@
 """Benchmark: DKSS multiplication on one MI355X, operand bits multiplied per second.
 
-python bench.py [--gpus 1] [--steps K] [--warmup W] [--bits 28] [--no-cpu]
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--bits 28] [--no-cpu] [--batch 4096]
 
 One step is one whole product c = a*b of two 2^bits-bit operands (default 2^28 bits, 8388608
 uint32 limbs each, uniform random limbs from a seeded splitmix64 stream) through every stage of
@@ -9,22 +9,25 @@ transform, decode and carries.  The parameter tuple is the thesis's rule; its co
 table of rho powers are prepared before the timed region (cached in the context).  Operands and
 workspace are resident in HBM before timing.  After timing, the product is checked by residues
 modulo 8 seeded random 61-bit primes (computed on the GPU for a, b and c and compared with
-Python integers).
+Python integers).  `value` is this plain product's throughput.
 
-The roofline object describes the dominant kernel, k_twiddle (the bad multiplications): its
-algorithmic work is counted in 32x32-bit multiply-adds of the schoolbook product in R
-(m^2 L^2 per product), timed with HIP events on the library's stream over the timed region, and
-priced against the chip's full-rate 32-bit VALU throughput (256 CUs x 64 lanes x 2.4 GHz).
-The FFT passes (k_dft) are reported against HBM bandwidth in roofline_fft.
+The roofline object describes the dominant kernel (most time over the timed region; with the
+thesis's parameters the forward FFT levels with fused rho twiddles, k_level<L, 1>), timed with
+HIP events on the library's stream.  Products in R are counted in 32x32-bit multiply-adds of the
+schoolbook product (m^2 L^2 per product in R) and priced against the chip's full-rate 32-bit VALU
+throughput (256 CUs x 64 lanes x 2.4 GHz); other kernels in algorithmic bytes against HBM
+bandwidth.  `traffic` is the HBM bytes per launch that the committed counter summary
+profiles/<kernel>_traffic.txt records, when it was taken on the current kernel sources, else
+null.  roofline_fft reports the FFT levels without twiddles (k_level<L, 0>) against HBM.
 
-The "batch" object measures the batched configuration: 4096 independent products with operand
-lengths log-uniform in 2^12..2^22 bits and length ratios uniform in [1, 8], run (a) as 4096
-sequential plain calls (thesis rule), (b) as one dkss_mul_batch call (thesis rule) and (c) as one
-dkss_mul_batch call with the tuned policy; all three give identical bits (checked).  The "tuned"
-object times the single 2^bits product with the tuned policy.
+"tuned" and "learned" time the same product under the tuned table and the learned selector.
+The "batch" object: 4096 independent products, operand lengths log-uniform in 2^12..2^22 bits,
+length ratios uniform in [1, 8], run as 4096 sequential plain calls (thesis rule), as one
+dkss_mul_batch call per policy (thesis, tuned, learned), and as the learned batch captured in a
+HIP graph and replayed; every variant's bits equal the plain calls' (checked).
 
 The cpu_baseline leg times the CPU oracle (plain C, one thread) on a bounded sample: one whole
-product of two 2^24-bit operands by the oracle's DKSS with the same parameter rule.
+product of two 2^25-bit operands by the oracle's DKSS with the same parameter rule.
 """
 import argparse
 import json
@@ -71,7 +74,7 @@ def primes61(seed, count):
     return out
 
 
-def cpu_baseline(bits=24):
+def cpu_baseline(bits=25):
     """Oracle (C, -O2, one thread) on one 2^bits x 2^bits product: operand bits/s."""
     import seeded_inputs as SI
     from oracle import coracle
@@ -100,7 +103,8 @@ def _timed(fn, reps, torch):
 
 
 def batch_bench(count, reps, dk, torch, SI):
-    """4096 uneven products: plain sequential calls vs one batched call (thesis / tuned)."""
+    """count uneven products: plain sequential calls vs one batched call per policy, and the
+    learned batch captured into a HIP graph and replayed."""
     lens = SI.batch_lengths(SI.SEED_BASE + 2, count)
     as_, bs = [], []
     for i, (al, bl) in enumerate(lens):
@@ -109,10 +113,7 @@ def batch_bench(count, reps, dk, torch, SI):
         bs.append(dk.to_device(b))
     bits = 32.0 * sum(al + bl for al, bl in lens)
     outs_p = [torch.empty(a.numel() + b.numel(), dtype=torch.int32, device="cuda") for a, b in zip(as_, bs)]
-    outs_b = [torch.empty_like(o) for o in outs_p]
-    outs_t = [torch.empty_like(o) for o in outs_p]
     ctx = dk.Context()
-    ctx_t = dk.Context(dk.POLICY_TUNED)
     wss = max(ctx.workspace_bytes(a.numel(), b.numel()) for a, b in zip(as_, bs))
     ws = torch.empty(max(wss, 1), dtype=torch.uint8, device="cuda")
 
@@ -120,23 +121,56 @@ def batch_bench(count, reps, dk, torch, SI):
         for a, b, o in zip(as_, bs, outs_p):
             ctx.mul(a, b, out=o, ws=ws)
 
-    def batched(c, outs):
-        return lambda: c.mul_batch(as_, bs, outs=outs)
-
-    ms_plain = _timed(plain, reps, torch)
-    ms_batch = _timed(batched(ctx, outs_b), reps, torch)
-    ms_tuned = _timed(batched(ctx_t, outs_t), reps, torch)
-    same = all(torch.equal(x, y) and torch.equal(x, z) for x, y, z in zip(outs_p, outs_b, outs_t))
+    res = {"workload": "%d products, operands 2^12..2^22 bits log-uniform, length ratio U[1,8]"
+                       % count, "operand_bits": bits}
+    ms = _timed(plain, reps, torch)
+    res["plain_sequential"] = {"ms": ms, "value": bits / (ms / 1e3)}
+    same = True
+    for name, policy in (("thesis", dk.POLICY_THESIS), ("tuned", dk.POLICY_TUNED),
+                         ("learned", dk.POLICY_LEARNED)):
+        call = dk.BatchCall(dk.Context(policy), as_, bs)
+        ms = _timed(call, reps, torch)
+        same = same and all(torch.equal(x, y) for x, y in zip(outs_p, call.outs))
+        res["batched_" + name] = {"ms": ms, "value": bits / (ms / 1e3)}
+        if name == "learned":
+            for o in call.outs:
+                o.zero_()
+            graph = call.graph()
+            ms = _timed(graph, reps, torch)
+            same = same and all(torch.equal(x, y) for x, y in zip(outs_p, call.outs))
+            res["graph_learned"] = {"ms": ms, "value": bits / (ms / 1e3), "kernels": graph.kernels}
+            graph.close()
+        del call
+        torch.cuda.empty_cache()
     if not same:
         raise RuntimeError("batched products differ from the plain ones")
-    return {"workload": "%d products, operands 2^12..2^22 bits log-uniform, length ratio U[1,8]"
-                        % count,
-            "operand_bits": bits,
-            "plain_sequential": {"ms": ms_plain, "value": bits / (ms_plain / 1e3)},
-            "batched_thesis": {"ms": ms_batch, "value": bits / (ms_batch / 1e3)},
-            "batched_tuned": {"ms": ms_tuned, "value": bits / (ms_tuned / 1e3)},
-            "speedup_batched_tuned_vs_plain": ms_plain / ms_tuned,
-            "bit_identical": same}
+    best = min(res[k]["ms"] for k in ("batched_tuned", "batched_learned", "graph_learned"))
+    res["speedup_best_batched_vs_plain"] = res["plain_sequential"]["ms"] / best
+    res["bit_identical"] = same
+    return res
+
+
+def traffic_record(kernel, source_files):
+    """HBM bytes per launch of `kernel` from the committed counter summary, or None when the
+    summary is missing or was taken on other kernel sources (sha256 of source_files)."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "%s_traffic.txt" % kernel)
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    h = hashlib.sha256()
+    for f in source_files:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    if kv.get("source_sha256") != h.hexdigest():
+        return None
+    return float(kv["hbm_bytes_per_launch"])
+
+
+KERNEL_SOURCES = ["paper_1503_04955_amd/csrc/dkss_lib.hip", "paper_1503_04955_amd/csrc/kernels.hpp"]
 
 
 def main():
@@ -146,9 +180,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--bits", type=int, default=28)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--overlap", type=int, default=1, help="transform b on a second stream")
-    ap.add_argument("--dft-lds", type=int, default=65536, help="LDS bytes per FFT-level workgroup")
+    ap.add_argument("--overlap", type=int, default=0, help="transform b on a second stream")
+    ap.add_argument("--dft-lds", type=int, default=32768, help="LDS bytes per FFT-level workgroup")
     ap.add_argument("--batch", type=int, default=4096, help="products in the batch leg (0: skip)")
+    ap.add_argument("--copy-calib", type=int, default=0,
+                    help="end with one device-to-device copy of this many bytes (a counter "
+                         "calibration kernel of known traffic)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -201,25 +238,42 @@ def main():
 
     ms_step = ms / args.steps
     value = args.steps * 2 * n * 32 / (ms / 1e3)
-    tw = stats.get("k_twiddle")
-    roofline = None
-    if tw and tw.launches:
-        avg_ms = tw.total_ms / tw.launches
-        ops_launch = tw.alg_ops / tw.launches
+    # dominant kernel: the kind with the most time; products in R are priced against the VALU,
+    # everything else against HBM bandwidth
+    symbols = {"k_dft": "k_level<%d, 0>", "k_twiddle": "k_level<%d, 1>",
+               "k_twiddle_inv": "k_level<%d, 2>", "k_pointwise": "k_pointwise<%d>",
+               "k_decode": "k_decode<%d>", "k_encode": "k_encode<%d>"}
+    dom = max(stats, key=lambda k: stats[k].total_ms)
+    st = stats[dom]
+    avg_ms = st.total_ms / st.launches
+    if st.alg_ops > 0:
+        ops_launch = st.alg_ops / st.launches
         achieved = ops_launch / (avg_ms / 1e3) / 1e12
-        roofline = {"kernel": "k_twiddle", "bound": "alu", "achieved": round(achieved, 3),
-                    "peak": round(PEAK_VALU_TOPS, 2), "unit": "TOP/s",
-                    "frac": round(achieved / PEAK_VALU_TOPS, 4), "traffic": None,
-                    "avg_launch_ms": round(avg_ms, 4), "ops_per_launch": ops_launch}
+        roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(PEAK_VALU_TOPS, 2),
+                    "unit": "TOP/s", "frac": round(achieved / PEAK_VALU_TOPS, 4)}
+        work = {"ops_per_launch": ops_launch}
+    else:
+        bytes_launch = st.alg_bytes / st.launches
+        achieved = bytes_launch / (avg_ms / 1e3) / 1e9
+        roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
+                    "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4)}
+        work = {"alg_bytes_per_launch": bytes_launch}
+    roofline["traffic"] = traffic_record(dom, KERNEL_SOURCES)
+    roofline.update({"kernel": dom, "symbol": symbols.get(dom, dom).replace("%d", str(plan.L))
+                     if "%d" in symbols.get(dom, "") else dom,
+                     "avg_launch_ms": round(avg_ms, 4), "launches": int(st.launches)})
+    roofline.update(work)
     dft = stats.get("k_dft")
     roofline_fft = None
     if dft and dft.launches:
         avg_ms = dft.total_ms / dft.launches
         gbs = dft.alg_bytes / dft.launches / (avg_ms / 1e3) / 1e9
-        roofline_fft = {"kernel": "k_dft", "bound": "hbm", "achieved": round(gbs, 1),
-                        "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(gbs / PEAK_HBM_GBS, 4),
-                        "avg_launch_ms": round(avg_ms, 4)}
-    kernels = {k: {"launches": int(v.launches), "ms_per_step": round(v.total_ms / args.steps, 4)}
+        roofline_fft = {"kernel": "k_dft", "symbol": "k_level<%d, 0>" % plan.L, "bound": "hbm",
+                        "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                        "frac": round(gbs / PEAK_HBM_GBS, 4), "avg_launch_ms": round(avg_ms, 4),
+                        "traffic": traffic_record("k_dft", KERNEL_SOURCES)}
+    kernels = {k: {"launches": int(v.launches), "ms_per_step": round(v.total_ms / args.steps, 4),
+                   "avg_launch_ms": round(v.total_ms / v.launches, 4)}
                for k, v in stats.items()}
     out = {
         "metric": METRIC, "value": value, "unit": "operand bits/s", "n_gpus": 1,
@@ -245,8 +299,29 @@ def main():
         sys.exit(1)
     out["tuned"] = {"ms_per_step": ms_t, "value": 2 * n * 32 / (ms_t / 1e3),
                     "params": ctx_t.select_params(32 * n, 32 * n).as_dict()}
+    del ws_t
+    # ... and with the learned selector
+    ctx_l = dk.Context(dk.POLICY_LEARNED)
+    ctx_l.set_option(dk.OPT_OVERLAP, args.overlap)
+    ctx_l.set_option(dk.OPT_DFT_LDS, args.dft_lds)
+    ws_l = torch.empty(ctx_l.workspace_bytes(n, n), dtype=torch.uint8, device=dev)
+    ms_l = _timed(lambda: ctx_l.mul(a, b, out=c_t, ws=ws_l), args.steps, torch)
+    if not torch.equal(c, c_t):
+        print("learned-policy product differs", file=sys.stderr)
+        sys.exit(1)
+    out["learned"] = {"ms_per_step": ms_l, "value": 2 * n * 32 / (ms_l / 1e3),
+                      "choice": ctx_l.mlp_choose(32 * n, 32 * n),
+                      "params": ctx_l.select_params(32 * n, 32 * n).as_dict()}
+    del ws_l, ws, c_t
+    torch.cuda.empty_cache()
     if args.batch:
-        out["batch"] = batch_bench(args.batch, 2, dk, torch, SI)
+        out["batch"] = batch_bench(args.batch, 3, dk, torch, SI)
+    if args.copy_calib:
+        src = torch.empty(args.copy_calib, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_calib_bytes"] = args.copy_calib
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)

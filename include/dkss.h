@@ -156,6 +156,30 @@ int dkss_batch_workspace_bytes(dkss_ctx* ctx, size_t count, const size_t* alen,
                                const size_t* blen, const dkss_params* p, size_t* out);
 
 /*
+ * A batch (as in dkss_mul_batch) planned once and captured into a HIP graph; every
+ * dkss_graph_launch recomputes all count products with one graph launch, reading the operands
+ * and writing the results at the same device addresses.  At creation the library plans the
+ * batch, builds the tables it needs, writes the product descriptors to the start of ws
+ * (synchronously, on a stream of its own) and captures the kernels; nothing else enters the
+ * graph.  The caller keeps ws, every operand and result buffer and the context alive and ws
+ * otherwise unused until dkss_graph_destroy; launches of one graph must not overlap in time
+ * (they share ws).  Profiling does not see graph launches.  count must be at least 1.
+ * Errors: as dkss_mul_batch, DKSS_EHIP (capture or instantiation failed).
+ */
+typedef struct dkss_graph dkss_graph;
+int dkss_batch_graph_create(dkss_ctx* ctx, size_t count, uint32_t* const* c,
+                            const uint32_t* const* a, const size_t* alen, const uint32_t* const* b,
+                            const size_t* blen, const dkss_params* p, void* ws, size_t ws_bytes,
+                            dkss_graph** out);
+/* Enqueue the graph on stream s.  Errors: DKSS_EINVAL, DKSS_EHIP. */
+int dkss_graph_launch(dkss_graph* g, dkss_stream_t s);
+/* Products in the graph and kernel nodes captured.  Errors: DKSS_EINVAL. */
+int dkss_graph_info(const dkss_graph* g, size_t* products, size_t* kernels);
+/* Release the graph (not the buffers).  Safe on NULL.  The caller makes sure no launch of it
+ * is still pending. */
+void dkss_graph_destroy(dkss_graph* g);
+
+/*
  * Forward transform only (Steps 4-5): encode a into 2M elements of R and transform them with
  * root rho; poly receives a(rho^i) for i < 2M in natural order, element-major (element i, inner
  * coefficient k, limb w at ((i*m + k)*L + w)), canonical residues in [0, p^z).  poly holds
@@ -175,11 +199,14 @@ int dkss_residues(const uint32_t* x, size_t n, const uint64_t* primes_host, size
  * the step must move (each input read once, each output written once) and, for the products in
  * R, 32x32-bit multiply-adds of the schoolbook product (m^2 L^2 per product in R).  The figures
  * are summed per kernel kind.  dkss_profile_read synchronizes on the recorded events.
+ * FFT levels: DKSS_K_DFT a level without twiddles (kernel k_level<L, 0>), DKSS_K_TWIDDLE a
+ * forward level with its rho twiddles (k_level<L, 1>), DKSS_K_TWIDDLE_INV an inverse level with
+ * its twiddles (k_level<L, 2>).
  */
 enum {
     DKSS_K_ENCODE = 0, DKSS_K_DFT, DKSS_K_TWIDDLE, DKSS_K_POINTWISE, DKSS_K_DECODE,
     DKSS_K_CARRY_SCAN, DKSS_K_CARRY_APPLY, DKSS_K_SCHOOLBOOK, DKSS_K_TABLE, DKSS_K_UNSCRAMBLE,
-    DKSS_K_KINDS
+    DKSS_K_TWIDDLE_INV, DKSS_K_KINDS
 };
 
 typedef struct {
@@ -200,10 +227,10 @@ const char* dkss_kernel_name(int kind);
 
 /*
  * Context options (tuning knobs; none changes any result bit).
- *  DKSS_OPT_OVERLAP      1 (default): the forward transform of b runs on a second, internal
- *                        stream of the context, forked from and joined back to the caller's
- *                        stream with events, so it overlaps the transform of a; 0: one stream.
- *  DKSS_OPT_DFT_LDS      LDS bytes an FFT-level workgroup may stage (default 65536; 16384 to
+ *  DKSS_OPT_OVERLAP      1: the forward transform of b runs on a second, internal stream of
+ *                        the context, forked from and joined back to the caller's stream with
+ *                        events, so it overlaps the transform of a; 0 (default): one stream.
+ *  DKSS_OPT_DFT_LDS      LDS bytes an FFT-level workgroup may stage (default 32768; 16384 to
  *                        163840): more columns per workgroup versus more workgroups per CU.
  */
 enum { DKSS_OPT_OVERLAP = 0, DKSS_OPT_DFT_LDS = 1 };
@@ -279,6 +306,14 @@ int dkss_mlp_choose(dkss_ctx* ctx, uint64_t a_bits, uint64_t b_bits, uint32_t ba
 
 /* Static description of an error code. */
 const char* dkss_strerror(int code);
+
+/* The hipError_t of the last failed HIP call made by the library on this host thread (0 if
+ * none): the detail behind a DKSS_EHIP.  Entry points that launch kernels first discard a
+ * pending error left by earlier, unrelated HIP calls of the thread, so a DKSS_EHIP names the
+ * library's own call. */
+int dkss_last_hip_error(void);
+/* HIP's description of a hipError_t code. */
+const char* dkss_hip_error_string(int code);
 
 #ifdef __cplusplus
 }

@@ -23,7 +23,11 @@ OK, EINVAL, ENOSPC, ERANGE, EHIP, ENOTIMPL = 0, -1, -2, -3, -4, -5
 
 class DkssError(RuntimeError):
     def __init__(self, code, what):
-        super().__init__("%s: %s (%d)" % (what, lib().dkss_strerror(code).decode(), code))
+        msg = "%s: %s (%d)" % (what, lib().dkss_strerror(code).decode(), code)
+        if code == EHIP:
+            h = lib().dkss_last_hip_error()
+            msg += "; HIP error %d: %s" % (h, lib().dkss_hip_error_string(h).decode())
+        super().__init__(msg)
         self.code = code
 
 
@@ -66,7 +70,7 @@ class KernelStats(ctypes.Structure):
                 ("alg_bytes", ctypes.c_double), ("alg_ops", ctypes.c_double)]
 
 
-KERNEL_KINDS = 10
+KERNEL_KINDS = 11
 
 _lib = None
 
@@ -112,6 +116,16 @@ def lib():
         L.dkss_set_mlp.argtypes = [vp, fp]
         L.dkss_mlp_load.argtypes = [ctypes.c_char_p, fp]
         L.dkss_mlp_choose.argtypes = [vp, u64, u64, u32, ctypes.POINTER(ctypes.c_int)]
+        L.dkss_batch_graph_create.argtypes = [vp, sz, ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                              ctypes.POINTER(sz), ctypes.POINTER(vp),
+                                              ctypes.POINTER(sz), PP, vp, sz, ctypes.POINTER(vp)]
+        L.dkss_graph_launch.argtypes = [vp, vp]
+        L.dkss_graph_info.argtypes = [vp, ctypes.POINTER(sz), ctypes.POINTER(sz)]
+        L.dkss_graph_destroy.argtypes = [vp]
+        L.dkss_graph_destroy.restype = None
+        L.dkss_last_hip_error.argtypes = []
+        L.dkss_hip_error_string.argtypes = [ctypes.c_int]
+        L.dkss_hip_error_string.restype = ctypes.c_char_p
         L.dkss_strerror.argtypes = [ctypes.c_int]
         L.dkss_strerror.restype = ctypes.c_char_p
         _lib = L
@@ -124,7 +138,8 @@ EXPORTED = ["dkss_ctx_create", "dkss_ctx_destroy", "dkss_select_params", "dkss_p
             "dkss_profile_read", "dkss_profile_reset", "dkss_kernel_name", "dkss_set_option",
             "dkss_candidates", "dkss_mlp_features", "dkss_mlp_forward", "dkss_mlp_work_floats",
             "dkss_mlp_loss_grad", "dkss_mlp_adam", "dkss_set_mlp", "dkss_mlp_load",
-            "dkss_mlp_choose", "dkss_strerror"]
+            "dkss_mlp_choose", "dkss_batch_graph_create", "dkss_graph_launch", "dkss_graph_info",
+            "dkss_graph_destroy", "dkss_last_hip_error", "dkss_hip_error_string", "dkss_strerror"]
 
 NCAND = 18
 MLP_IN, MLP_HID, MLP_OUT = 3, 64, NCAND + 1
@@ -327,6 +342,42 @@ class BatchCall:
                                     self.pb_ptrs, self.bl, self.pa, _ptr(self.ws),
                                     self.ws.numel(), _stream_ptr(stream)), "dkss_mul_batch")
         return self.outs
+
+    def graph(self):
+        """Capture this batch into a HIP graph (BatchGraph); it uses this call's workspace."""
+        return BatchGraph(self)
+
+
+class BatchGraph:
+    """A batch captured once (dkss_batch_graph_create) and replayed with one graph launch."""
+
+    def __init__(self, call):
+        h = ctypes.c_void_p()
+        _check(lib().dkss_batch_graph_create(call.ctx._h, call.n, call.pc, call.pa_ptrs, call.al,
+                                             call.pb_ptrs, call.bl, call.pa, _ptr(call.ws),
+                                             call.ws.numel(), ctypes.byref(h)),
+               "dkss_batch_graph_create")
+        self._h = h
+        self.call = call                     # keeps buffers and the context alive
+        n, k = ctypes.c_size_t(), ctypes.c_size_t()
+        _check(lib().dkss_graph_info(h, ctypes.byref(n), ctypes.byref(k)), "dkss_graph_info")
+        self.products, self.kernels = n.value, k.value
+
+    def __call__(self, stream=None):
+        _check(lib().dkss_graph_launch(self._h, _stream_ptr(stream)), "dkss_graph_launch")
+        return self.call.outs
+
+    def close(self):
+        if self._h:
+            _torch().cuda.synchronize()
+            lib().dkss_graph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def residues(x, primes, stream=None):

@@ -33,10 +33,19 @@
 #include <vector>
 
 #include "../../include/dkss.h"
+#include "hip_status.hpp"
 #include "kernels.hpp"
 #include "planner.hpp"
 
 using namespace dkss;
+
+static thread_local int g_last_hip = 0;
+
+int dkss::note_hip(hipError_t e) {
+    if (e == hipSuccess) return DKSS_OK;
+    g_last_hip = (int)e;
+    return DKSS_EHIP;
+}
 
 namespace {
 
@@ -46,6 +55,18 @@ constexpr uint64_t kDefaultCutoffBits = 2048;
 constexpr size_t kSchoolbookMaxWords = 4096;   // alen + blen of the base case
 
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Orders LDS accesses among the lanes of one wavefront (a wavefront's LDS operations are
+// performed in issue order; this keeps the compiler from moving them across the point).
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Words of one element's twiddle staging: rho^s and its negation, 2m residues of D digits.  (At
+// radix 2m the staging of a round fills the free column buffer exactly, so it is not padded.)
+__host__ __device__ constexpr int tw_stage_words(int m, int D) { return 2 * m * D; }
 
 __device__ __forceinline__ int bitrev(int x, int bits) {
     return bits ? (int)(__brev((unsigned)x) >> (32 - bits)) : 0;
@@ -225,7 +246,9 @@ __device__ __forceinline__ void level_twiddle(uint32_t* cur, uint32_t* RB, uint3
     const int per = kThreads >> A.log2m;
     const int g = threadIdx.x >> A.log2m, j = threadIdx.x & (m - 1);
     const int nel = 1 << (A.log2C + A.log2r);
-    uint32_t* TP = RB + g * 2 * m * D;
+    uint32_t* TP = RB + g * tw_stage_words(m, D);
+    // The m lanes of an element lie in one wavefront (m <= 64) and touch only that element's
+    // column slot and staging area, so the rounds synchronize per wavefront.
     for (int r0 = 0; r0 < nel; r0 += per) {
         const int el = r0 + g;                          // (c, v) with v fastest
         const bool valid = el < nel;
@@ -249,7 +272,7 @@ __device__ __forceinline__ void level_twiddle(uint32_t* cur, uint32_t* RB, uint3
                 TP[(j + m) * D + y] = ts[(j + m) * D + y];
             }
         }
-        __syncthreads();
+        wave_sync();
         uint32_t out[D];
         if (valid) {
             if (e) {
@@ -264,7 +287,7 @@ __device__ __forceinline__ void level_twiddle(uint32_t* cur, uint32_t* RB, uint3
                 for (int y = 0; y < D; ++y) dst[y] = out[y];
             }
         }
-        __syncthreads();
+        wave_sync();
         if (valid && A.mode == 2 && e) {
 #pragma unroll
             for (int y = 0; y < D; ++y) X[j * D + y] = out[y];
@@ -880,8 +903,8 @@ struct Call {
     size_t alen = 0, blen = 0;
     Cached* C = nullptr;
     Prof* prof = nullptr;
-    long long dft_lds = 65536;
-    bool overlap = true;
+    long long dft_lds = 32768;
+    bool overlap = false;
     hipStream_t aux = nullptr;        // second stream for the transform of b
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 };
@@ -892,9 +915,12 @@ int dig_K(int L) { return (32 * L + 6 + 27) / 28; }
 }  // namespace
 
 // Tuned choices: for log2(N) in [lo, hi), candidate index cand (see candidate_params).
+// Optionally with the FFT level split and the LDS budget of the DFT-only levels.
 struct TuneEntry {
     double lo, hi;
     int cand;
+    std::vector<int> radices;      // empty: the library default
+    long long dft_lds = 0;         // 0: the context's option
 };
 
 struct dkss_ctx {
@@ -911,8 +937,8 @@ struct dkss_ctx {
     std::map<std::tuple<size_t, size_t, uint32_t>, int> choices;   // (alen, blen, batch) -> choice
     std::map<std::string, std::unique_ptr<Cached>> cache;
     Prof prof;
-    bool overlap = true;
-    long long dft_lds = 65536;
+    bool overlap = false;
+    long long dft_lds = 32768;
     hipStream_t aux = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     ProdDesc* hdesc = nullptr;          // pinned staging of batch descriptors
@@ -940,17 +966,24 @@ struct dkss_ctx {
 
 namespace {
 
-#define HIP_OK(expr)                                  \
-    do {                                              \
-        if ((expr) != hipSuccess) return DKSS_EHIP;   \
+#define HIP_OK(expr)                                   \
+    do {                                               \
+        const hipError_t e_ = (expr);                  \
+        if (e_ != hipSuccess) return note_hip(e_);     \
     } while (0)
 
-// the context's policy: the tuned table's candidate for N if it has one, else the thesis rule
-bool policy_tuple(const dkss_ctx* ctx, uint64_t N, int* lM, int* lm, int* u, int* pb) {
+// the context's policy: the tuned table's candidate for N if it has one (its entry in *te),
+// else the thesis rule
+bool policy_tuple(const dkss_ctx* ctx, uint64_t N, int* lM, int* lm, int* u, int* pb,
+                  const TuneEntry** te = nullptr) {
+    if (te) *te = nullptr;
     if (ctx && ctx->policy == DKSS_POLICY_TUNED) {
         const double lg = std::log2((double)N);
         for (const TuneEntry& t : ctx->tuning)
-            if (lg >= t.lo && lg < t.hi && candidate_params(N, t.cand, lM, lm, u, pb)) return true;
+            if (lg >= t.lo && lg < t.hi && candidate_params(N, t.cand, lM, lm, u, pb)) {
+                if (te) *te = &t;
+                return true;
+            }
     }
     return thesis_params(N, lM, lm, u, pb);
 }
@@ -1046,11 +1079,22 @@ int resolve_params(dkss_ctx* ctx, size_t alen, size_t blen, const dkss_params* p
     if (p == nullptr) {
         int lM, lm, u, pb;
         P.cutoff_bits = kDefaultCutoffBits;
+        const TuneEntry* te = nullptr;
         if (choice >= 0 && choice < kNumCandidates && candidate_params(N, choice, &lM, &lm, &u, &pb)) {
             P.cutoff_bits = 0;
         } else {
-            if (!policy_tuple(ctx, N, &lM, &lm, &u, &pb)) return DKSS_ERANGE;
+            if (!policy_tuple(ctx, N, &lM, &lm, &u, &pb, &te)) return DKSS_ERANGE;
             if (choice == DKSS_CAND_SCHOOLBOOK) P.cutoff_bits = UINT64_MAX;
+        }
+        if (te) {                      // the tuned level split and LDS budget, where recorded
+            int sum = 0;
+            bool fits = true;
+            for (int r : te->radices) {
+                sum += r;
+                fits = fits && r <= max_radix_log2(lm, (pb + 31) / 32);
+            }
+            if (fits && sum == lM + 1) P.radix_log2 = te->radices;
+            if (te->dft_lds) out->dft_lds = te->dft_lds;
         }
         P.log2_M = lM;
         P.log2_m = lm;
@@ -1182,7 +1226,7 @@ struct TableBuild {
         ProfScope ps(prof, DKSS_K_TABLE, s, 2.0 * cnt * m * dig_D(L) * 4, (double)cnt * m * m * L * L);
         hipLaunchKernelGGL(k_table_mul<L>, dim3(blocks), dim3(kThreads), rprod_lds(L), s, C->d_table,
                            src, mul, dst, cnt, C->plan.log2_m, C->Q);
-        return hipGetLastError() == hipSuccess ? DKSS_OK : DKSS_EHIP;
+        return launch_status();
     }
     // entries 0 (one) and 1 (rho) are given; for n = 2, 4, ...: rho^n = rho^(n/2) rho^(n/2),
     // then rho^(n+j) = rho^j rho^n for 0 < j < n
@@ -1302,12 +1346,13 @@ struct Transform {
             A.inverse = inverse;
             // twiddle staging: 256/m elements x 2m residues; in the free column buffer if it fits
             const size_t ncw = ((size_t)r << log2C) * m * D;
-            const size_t rb_words = (size_t)kThreads * 2 * D;
+            const size_t rb_words = (size_t)(kThreads / m) * tw_stage_words(m, D);
             A.rb_separate = tw && ncw < rb_words;
             const size_t lds = 2 * ncw * 4 + (A.rb_separate ? rb_words * 4 : 0);
             const unsigned blocks = (unsigned)(ncols >> log2C);
             const double nprod = tw ? (double)(twoM / n_lvl[k]) * (r - 1) * (mu[k] - 1) : 0.0;
-            ProfScope ps(c.prof, tw ? DKSS_K_TWIDDLE : DKSS_K_DFT, s, 2.0 * G * twoM * m * L * 4,
+            ProfScope ps(c.prof, tw ? (inverse ? DKSS_K_TWIDDLE_INV : DKSS_K_TWIDDLE) : DKSS_K_DFT, s,
+                         2.0 * G * twoM * m * L * 4,
                          (double)G * nprod * (double)m * m * L * L);
             if (A.mode == 0)
                 hipLaunchKernelGGL((k_level<L, 0>), dim3(blocks, G), dim3(kThreads), lds, s, poly,
@@ -1318,7 +1363,7 @@ struct Transform {
             else
                 hipLaunchKernelGGL((k_level<L, 2>), dim3(blocks, G), dim3(kThreads), lds, s, poly,
                                    (long long)stride, (const uint32_t*)c.C->d_table, A, Q);
-            return hipGetLastError() == hipSuccess ? DKSS_OK : DKSS_EHIP;
+            return launch_status();
         };
         int rc;
         if (!inverse) {
@@ -1343,7 +1388,7 @@ struct Encode {
         ProfScope ps(c.prof, DKSS_K_ENCODE, s, 4.0 * in_words + 4.0 * G * total * L, 0.0);
         hipLaunchKernelGGL(k_encode<L>, dim3(blocks, G), dim3(kThreads), 0, s, PA, which, poly,
                            (long long)stride, M, c.P.log2_m);
-        return hipGetLastError() == hipSuccess ? DKSS_OK : DKSS_EHIP;
+        return launch_status();
     }
 };
 
@@ -1358,7 +1403,7 @@ struct Pointwise {
                      (double)G * count * ((double)m * m * L * L + (double)m * L * L));
         hipLaunchKernelGGL(k_pointwise<L>, dim3(blocks, G), dim3(kThreads), rprod_lds(L), s, A, B,
                            (long long)stride, count, c.P.log2_m, c.C->Q);
-        return hipGetLastError() == hipSuccess ? DKSS_OK : DKSS_EHIP;
+        return launch_status();
     }
 };
 
@@ -1376,7 +1421,7 @@ struct Decode {
                                (long long)w.S, 2LL << c.P.log2_M, c.P.log2_m, w.gmask, w.pmask,
                                (long long)w.wst);
         }
-        HIP_OK(hipGetLastError());
+        if (int rc_ = launch_status()) return rc_;
         {
             ProfScope ps(c.prof, DKSS_K_CARRY_SCAN, s, 17.0 * G * nwaves, 0.0);
             hipLaunchKernelGGL(k_carry_block, dim3((unsigned)nseg, G), dim3(kThreads), 0, s, PA, w.gmask,
@@ -1384,13 +1429,13 @@ struct Decode {
             hipLaunchKernelGGL(k_carry_top, dim3(1, G), dim3(1024), 0, s, PA, w.seg_gp, w.seg_cin,
                                (long long)w.sst);
         }
-        HIP_OK(hipGetLastError());
+        if (int rc_ = launch_status()) return rc_;
         {
             ProfScope ps(c.prof, DKSS_K_CARRY_APPLY, s, 8.0 * out_words, 0.0);
             hipLaunchKernelGGL(k_carry_apply, dim3(blocks, G), dim3(kThreads), 0, s, PA, w.gmask, w.pmask,
                                w.cin01, w.seg_cin, (long long)w.wst, (long long)w.sst);
         }
-        HIP_OK(hipGetLastError());
+        if (int rc_ = launch_status()) return rc_;
         return DKSS_OK;
     }
 };
@@ -1403,7 +1448,7 @@ struct Unscramble {
         ProfScope ps(c.prof, DKSS_K_UNSCRAMBLE, s, (4.0 * L + 4.0 * Dig<L>::D) * total, 0.0);
         hipLaunchKernelGGL(k_unscramble<L>, dim3((unsigned)((total + kThreads - 1) / kThreads)), dim3(kThreads),
                            0, s, poly, src, twoM, c.P.log2_m, LI);
-        return hipGetLastError() == hipSuccess ? DKSS_OK : DKSS_EHIP;
+        return launch_status();
     }
 };
 
@@ -1417,7 +1462,7 @@ bool overlaps(const void* x, size_t xb, const void* y, size_t yb) {
 int prepare_call(dkss_ctx* ctx, size_t alen, size_t blen, const dkss_params* p, Call* call,
                  uint32_t batch = 1) {
     call->prof = &ctx->prof;
-    call->dft_lds = ctx->dft_lds;
+    call->dft_lds = ctx->dft_lds;          // a tuned entry may override it in resolve_params
     call->overlap = ctx->overlap;
     int choice = -1;
     if (!p && ctx->policy == DKSS_POLICY_LEARNED) {
@@ -1462,14 +1507,14 @@ int launch_zero(const ProdArgs& PA, unsigned G, size_t nw_max, hipStream_t s) {
     if (nw_max == 0) return DKSS_OK;
     const unsigned blocks = (unsigned)std::min<size_t>((nw_max + kThreads - 1) / kThreads, 4096);
     hipLaunchKernelGGL(k_zero_products, dim3(blocks, G), dim3(kThreads), 0, s, PA);
-    return hipGetLastError() == hipSuccess ? DKSS_OK : DKSS_EHIP;
+    return launch_status();
 }
 
 int launch_schoolbook(const Call& call, const ProdArgs& PA, unsigned G, size_t nw_max, double ops,
                       hipStream_t s) {
     ProfScope ps(call.prof, DKSS_K_SCHOOLBOOK, s, 8.0 * G * nw_max, ops);
     hipLaunchKernelGGL(k_schoolbook, dim3(1, G), dim3(kThreads), nw_max * 3 * sizeof(uint32_t), s, PA);
-    return hipGetLastError() == hipSuccess ? DKSS_OK : DKSS_EHIP;
+    return launch_status();
 }
 
 int run_mul(const Call& call, uint32_t* c, const uint32_t* a, size_t alen, const uint32_t* b,
@@ -1615,13 +1660,29 @@ static void load_tuning(dkss_ctx* c, const char* dir) {
     std::string path = std::string(dir) + "/dkss_tuning.txt";
     FILE* f = fopen(path.c_str(), "r");
     if (!f) return;
+    // "lo hi cand [radices|-] [dft_lds]", radices as log2 values joined by '.', e.g. 5.5.5.5
     char line[256];
     while (fgets(line, sizeof line, f)) {
         if (line[0] == '#') continue;
         TuneEntry e{};
-        if (sscanf(line, "%lf %lf %d", &e.lo, &e.hi, &e.cand) == 3 && e.cand >= 0 &&
-            e.cand < kNumCandidates)
-            c->tuning.push_back(e);
+        char rad[64] = "-";
+        long long lds = 0;
+        const int n = sscanf(line, "%lf %lf %d %63s %lld", &e.lo, &e.hi, &e.cand, rad, &lds);
+        if (n < 3 || e.cand < 0 || e.cand >= kNumCandidates) continue;
+        if (n >= 4 && rad[0] != '-' && rad[0] != '#') {
+            bool ok = true;
+            for (char* t = rad; *t && ok;) {
+                char* end = nullptr;
+                const long r = strtol(t, &end, 10);
+                ok = end != t && r >= 1 && r <= 7 && e.radices.size() < 8;
+                if (ok) e.radices.push_back((int)r);
+                t = (end && *end == '.') ? end + 1 : end;
+                if (end && *end && *end != '.') ok = false;
+            }
+            if (!ok) e.radices.clear();
+        }
+        if (n >= 5 && lds >= 16384 && lds <= 163840) e.dft_lds = lds;
+        c->tuning.push_back(e);
     }
     fclose(f);
 }
@@ -1745,10 +1806,11 @@ int dkss_select_params(dkss_ctx* ctx, uint64_t a_bits, uint64_t b_bits, uint32_t
     }
     int lM, lm, u, pb;
     uint64_t cutoff = kDefaultCutoffBits;
+    const TuneEntry* te = nullptr;
     if (choice >= 0 && choice < kNumCandidates && candidate_params(N, choice, &lM, &lm, &u, &pb)) {
         cutoff = 0;
     } else {
-        if (!policy_tuple(ctx, N, &lM, &lm, &u, &pb)) return DKSS_ERANGE;
+        if (!policy_tuple(ctx, N, &lM, &lm, &u, &pb, &te)) return DKSS_ERANGE;
         if (choice == DKSS_CAND_SCHOOLBOOK) cutoff = UINT64_MAX;
     }
     memset(out, 0, sizeof *out);
@@ -1759,6 +1821,15 @@ int dkss_select_params(dkss_ctx* ctx, uint64_t a_bits, uint64_t b_bits, uint32_t
     out->z = 1;
     out->cutoff_bits = cutoff;
     std::vector<int> r = default_radices(lM, lm, (pb + 31) / 32);
+    if (te && !te->radices.empty()) {
+        int sum = 0;
+        bool fits = true;
+        for (int x : te->radices) {
+            sum += x;
+            fits = fits && x <= max_radix_log2(lm, (pb + 31) / 32);
+        }
+        if (fits && sum == lM + 1) r = te->radices;
+    }
     out->n_levels = (uint32_t)r.size();
     for (size_t i = 0; i < r.size() && i < 8; ++i) out->radix_log2[i] = (uint32_t)r[i];
     return DKSS_OK;
@@ -1805,6 +1876,7 @@ int dkss_workspace_bytes(dkss_ctx* ctx, size_t alen, size_t blen, const dkss_par
 }
 
 int dkss_prepare(dkss_ctx* ctx, size_t alen, size_t blen, const dkss_params* p, dkss_stream_t s) {
+    clear_stale_hip_error();
     if (!ctx) return DKSS_EINVAL;
     Call call;
     int rc = prepare_call(ctx, alen, blen, p, &call);
@@ -1815,6 +1887,7 @@ int dkss_prepare(dkss_ctx* ctx, size_t alen, size_t blen, const dkss_params* p, 
 
 int dkss_mul(dkss_ctx* ctx, uint32_t* c, const uint32_t* a, size_t alen, const uint32_t* b,
              size_t blen, const dkss_params* p, void* ws, size_t ws_bytes, dkss_stream_t s) {
+    clear_stale_hip_error();
     if (!ctx || !c || (alen && !a) || (blen && !b)) return DKSS_EINVAL;
     const size_t nw = alen + blen;
     if ((alen && overlaps(c, nw * 4, a, alen * 4)) || (blen && overlaps(c, nw * 4, b, blen * 4)))
@@ -1842,11 +1915,9 @@ int dkss_batch_workspace_bytes(dkss_ctx* ctx, size_t count, const size_t* alen, 
     return DKSS_OK;
 }
 
-int dkss_mul_batch(dkss_ctx* ctx, size_t count, uint32_t* const* c, const uint32_t* const* a,
-                   const size_t* alen, const uint32_t* const* b, const size_t* blen,
-                   const dkss_params* p, void* ws, size_t ws_bytes, dkss_stream_t s) {
-    if (!ctx || (count && (!c || !a || !alen || !b || !blen))) return DKSS_EINVAL;
-    if (count == 0) return DKSS_OK;
+static int check_batch_args(size_t count, uint32_t* const* c, const uint32_t* const* a, const size_t* alen,
+                            const uint32_t* const* b, const size_t* blen) {
+    if (count && (!c || !a || !alen || !b || !blen)) return DKSS_EINVAL;
     for (size_t i = 0; i < count; ++i) {
         const size_t nw = alen[i] + blen[i];
         if (!c[i] || (alen[i] && !a[i]) || (blen[i] && !b[i])) return DKSS_EINVAL;
@@ -1854,9 +1925,45 @@ int dkss_mul_batch(dkss_ctx* ctx, size_t count, uint32_t* const* c, const uint32
             (blen[i] && overlaps(c[i], nw * 4, b[i], blen[i] * 4)))
             return DKSS_EINVAL;
     }
-    BatchPlan B;
-    int rc = plan_batch(ctx, count, alen, blen, p, &B);
+    return DKSS_OK;
+}
+
+// The launches of a planned batch whose descriptors sit at the start of ws.  prof: NULL inside
+// a graph capture (no timing events there).
+static int enqueue_batch(const BatchPlan& B, void* ws, Prof* prof, hipStream_t st) {
+    ProdDesc* d_desc = (ProdDesc*)ws;
+    char* gws = (char*)ws + B.desc_bytes;
+    for (const BatchPlan::Grp& g : B.groups) {
+        ProdArgs PA{};
+        PA.many = d_desc + g.first;
+        const unsigned G = (unsigned)g.count;
+        Call call = g.call;
+        call.prof = prof;
+        call.aux = nullptr;                // groups are wide enough to fill the GPU on one stream
+        int rc;
+        if (g.kind == 0) {
+            rc = launch_zero(PA, G, g.nw_max, st);
+        } else if (g.kind == 1) {
+            rc = launch_schoolbook(call, PA, G, g.nw_max, g.ops, st);
+        } else {
+            Workspace w = layout(call.P, G, g.nw_max, true, gws);
+            rc = run_group(call, PA, G, g.nw_max, g.in_a, g.in_b, g.out_w, false, w, st);
+        }
+        if (rc) return rc;
+    }
+    return DKSS_OK;
+}
+
+int dkss_mul_batch(dkss_ctx* ctx, size_t count, uint32_t* const* c, const uint32_t* const* a,
+                   const size_t* alen, const uint32_t* const* b, const size_t* blen,
+                   const dkss_params* p, void* ws, size_t ws_bytes, dkss_stream_t s) {
+    clear_stale_hip_error();
+    if (!ctx) return DKSS_EINVAL;
+    int rc = check_batch_args(count, c, a, alen, b, blen);
     if (rc) return rc;
+    if (count == 0) return DKSS_OK;
+    BatchPlan B;
+    if ((rc = plan_batch(ctx, count, alen, blen, p, &B))) return rc;
     if (ws == nullptr || ((uintptr_t)ws & 255)) return DKSS_EINVAL;
     if (ws_bytes < B.ws_bytes) return DKSS_ENOSPC;
     hipStream_t st = (hipStream_t)s;
@@ -1868,32 +1975,98 @@ int dkss_mul_batch(dkss_ctx* ctx, size_t count, uint32_t* const* c, const uint32
         const size_t i = B.order[k];
         ctx->hdesc[k] = ProdDesc{c[i], a[i], b[i], (long long)alen[i], (long long)blen[i], B.calls[i].P.u, 0};
     }
-    ProdDesc* d_desc = (ProdDesc*)ws;
-    HIP_OK(hipMemcpyAsync(d_desc, ctx->hdesc, count * sizeof(ProdDesc), hipMemcpyHostToDevice, st));
+    HIP_OK(hipMemcpyAsync(ws, ctx->hdesc, count * sizeof(ProdDesc), hipMemcpyHostToDevice, st));
     HIP_OK(hipEventRecord(ctx->desc_ev, st));
     ctx->desc_pending = true;
-    char* gws = (char*)ws + B.desc_bytes;
-    for (const BatchPlan::Grp& g : B.groups) {
-        ProdArgs PA{};
-        PA.many = d_desc + g.first;
-        const unsigned G = (unsigned)g.count;
-        if (g.kind == 0) {
-            rc = launch_zero(PA, G, g.nw_max, st);
-        } else if (g.kind == 1) {
-            rc = launch_schoolbook(g.call, PA, G, g.nw_max, g.ops, st);
-        } else {
-            Call call = g.call;
-            call.aux = nullptr;            // groups are wide enough to fill the GPU on one stream
-            Workspace w = layout(call.P, G, g.nw_max, true, gws);
-            rc = run_group(call, PA, G, g.nw_max, g.in_a, g.in_b, g.out_w, false, w, st);
-        }
-        if (rc) return rc;
+    return enqueue_batch(B, ws, &ctx->prof, st);
+}
+
+}  // extern "C"
+
+struct dkss_graph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    size_t count = 0, launches = 0;
+    ~dkss_graph() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
     }
+};
+
+extern "C" {
+
+int dkss_batch_graph_create(dkss_ctx* ctx, size_t count, uint32_t* const* c, const uint32_t* const* a,
+                            const size_t* alen, const uint32_t* const* b, const size_t* blen,
+                            const dkss_params* p, void* ws, size_t ws_bytes, dkss_graph** out) {
+    clear_stale_hip_error();
+    if (!ctx || !out) return DKSS_EINVAL;
+    *out = nullptr;
+    int rc = check_batch_args(count, c, a, alen, b, blen);
+    if (rc) return rc;
+    if (count == 0) return DKSS_EINVAL;
+    BatchPlan B;
+    if ((rc = plan_batch(ctx, count, alen, blen, p, &B))) return rc;
+    if (ws == nullptr || ((uintptr_t)ws & 255)) return DKSS_EINVAL;
+    if (ws_bytes < B.ws_bytes) return DKSS_ENOSPC;
+    hipStream_t cs = nullptr;
+    HIP_OK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    std::unique_ptr<dkss_graph> G(new (std::nothrow) dkss_graph());
+    rc = G ? DKSS_OK : DKSS_EINVAL;
+    // tables and descriptors are written once, before the capture; the graph holds kernels only
+    for (size_t k = 0; !rc && k < B.groups.size(); ++k)
+        if (B.groups[k].kind == 2) rc = ensure_table(B.groups[k].call.C, nullptr, cs);
+    if (!rc) {
+        std::vector<ProdDesc> hd(count);
+        for (size_t k = 0; k < count; ++k) {
+            const size_t i = B.order[k];
+            hd[k] = ProdDesc{c[i], a[i], b[i], (long long)alen[i], (long long)blen[i], B.calls[i].P.u, 0};
+        }
+        if (hipMemcpyAsync(ws, hd.data(), count * sizeof(ProdDesc), hipMemcpyHostToDevice, cs) != hipSuccess ||
+            hipStreamSynchronize(cs) != hipSuccess)
+            rc = DKSS_EHIP;
+    }
+    if (!rc) {
+        if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+            rc = DKSS_EHIP;
+        } else {
+            rc = enqueue_batch(B, ws, nullptr, cs);
+            hipGraph_t graph = nullptr;      // the capture is always ended, also after an error
+            const hipError_t e = hipStreamEndCapture(cs, &graph);
+            G->graph = graph;
+            if (!rc && (e != hipSuccess || !graph)) rc = DKSS_EHIP;
+        }
+    }
+    if (!rc && hipGraphInstantiate(&G->exec, G->graph, nullptr, nullptr, 0) != hipSuccess) rc = DKSS_EHIP;
+    if (!rc) {
+        size_t nodes = 0;
+        if (hipGraphGetNodes(G->graph, nullptr, &nodes) != hipSuccess) rc = DKSS_EHIP;
+        G->launches = nodes;
+        G->count = count;
+    }
+    (void)hipStreamDestroy(cs);
+    if (rc) return rc;
+    *out = G.release();
     return DKSS_OK;
 }
 
+int dkss_graph_launch(dkss_graph* g, dkss_stream_t s) {
+    clear_stale_hip_error();
+    if (!g || !g->exec) return DKSS_EINVAL;
+    return hipGraphLaunch(g->exec, (hipStream_t)s) == hipSuccess ? DKSS_OK : DKSS_EHIP;
+}
+
+int dkss_graph_info(const dkss_graph* g, size_t* products, size_t* kernels) {
+    if (!g || !products || !kernels) return DKSS_EINVAL;
+    *products = g->count;
+    *kernels = g->launches;
+    return DKSS_OK;
+}
+
+void dkss_graph_destroy(dkss_graph* g) { delete g; }
+
 int dkss_forward(dkss_ctx* ctx, uint32_t* poly, const uint32_t* a, size_t alen, size_t blen,
                  const dkss_params* p, void* ws, size_t ws_bytes, dkss_stream_t s) {
+    clear_stale_hip_error();
     if (!ctx || !poly || !a || alen == 0 || blen == 0) return DKSS_EINVAL;
     Call call;
     int rc = prepare_call(ctx, alen, blen, p, &call);
@@ -1923,6 +2096,7 @@ int dkss_forward(dkss_ctx* ctx, uint32_t* poly, const uint32_t* a, size_t alen, 
 
 int dkss_residues(const uint32_t* x, size_t n, const uint64_t* primes_host, size_t count,
                   uint64_t* out, dkss_stream_t s) {
+    clear_stale_hip_error();
     if ((n && !x) || (count && (!primes_host || !out))) return DKSS_EINVAL;
     hipStream_t st = (hipStream_t)s;
     const long long per_block = (long long)kThreads * 64;
@@ -1957,7 +2131,7 @@ int dkss_residues(const uint32_t* x, size_t n, const uint64_t* primes_host, size
                            part + j * nb);
         hipLaunchKernelGGL(k_residue_final, dim3(1), dim3(64), 0, st, (const uint64_t*)(part + j * nb), nb, R,
                            out + j);
-        if (hipGetLastError() != hipSuccess) {
+        if (launch_status() != DKSS_OK) {
             (void)hipStreamSynchronize(st);
             (void)hipFree(part);
             return DKSS_EHIP;
@@ -1965,7 +2139,7 @@ int dkss_residues(const uint32_t* x, size_t n, const uint64_t* primes_host, size
     }
     const hipError_t e1 = hipStreamSynchronize(st);
     const hipError_t e2 = hipFree(part);
-    return (e1 == hipSuccess && e2 == hipSuccess) ? DKSS_OK : DKSS_EHIP;
+    return note_hip(e1 != hipSuccess ? e1 : e2);
 }
 
 int dkss_profile_enable(dkss_ctx* ctx, int on) {
@@ -1991,10 +2165,15 @@ int dkss_profile_reset(dkss_ctx* ctx) {
 const char* dkss_kernel_name(int kind) {
     static const char* names[DKSS_K_KINDS] = {"k_encode", "k_dft", "k_twiddle", "k_pointwise",
                                               "k_decode", "k_carry_scan", "k_carry_apply",
-                                              "k_schoolbook", "k_table_mul", "k_unscramble"};
+                                              "k_schoolbook", "k_table_mul", "k_unscramble",
+                                              "k_twiddle_inv"};
     if (kind < 0 || kind >= DKSS_K_KINDS) return nullptr;
     return names[kind];
 }
+
+int dkss_last_hip_error(void) { return g_last_hip; }
+
+const char* dkss_hip_error_string(int code) { return hipGetErrorString((hipError_t)code); }
 
 const char* dkss_strerror(int code) {
     switch (code) {

@@ -10,6 +10,7 @@
 #include <cstdint>
 
 #include "../../include/dkss.h"
+#include "hip_status.hpp"
 
 namespace {
 
@@ -159,15 +160,17 @@ size_t dkss_mlp_work_floats(int n) { return n > 0 ? (size_t)n * (kParams + 1) : 
 
 int dkss_mlp_forward(const float* params, const float* x, int n, float* y, dkss_stream_t s) {
     if (!params || !x || !y || n <= 0) return DKSS_EINVAL;
+    dkss::clear_stale_hip_error();
     hipLaunchKernelGGL(k_mlp_forward, dim3((n + kWaves - 1) / kWaves), dim3(256), 0, (hipStream_t)s, params,
                        x, n, y);
-    return hipGetLastError() == hipSuccess ? DKSS_OK : DKSS_EHIP;
+    return dkss::launch_status();
 }
 
 int dkss_mlp_loss_grad(const float* params, const float* x, const float* t, const float* mask, int n,
                        float mask_sum, float* grad, float* loss, float* work, dkss_stream_t s) {
     if (!params || !x || !t || !mask || !grad || !loss || !work || n <= 0 || !(mask_sum > 0.f))
         return DKSS_EINVAL;
+    dkss::clear_stale_hip_error();
     hipStream_t st = (hipStream_t)s;
     float* G = work;
     float* Ls = work + (size_t)n * kParams;
@@ -175,17 +178,18 @@ int dkss_mlp_loss_grad(const float* params, const float* x, const float* t, cons
                        1.f / mask_sum, G, Ls);
     hipLaunchKernelGGL(k_mlp_reduce, dim3((kParams + 255) / 256), dim3(256), 0, st, (const float*)G,
                        (const float*)Ls, n, grad, loss);
-    return hipGetLastError() == hipSuccess ? DKSS_OK : DKSS_EHIP;
+    return dkss::launch_status();
 }
 
 int dkss_mlp_adam(float* params, const float* grad, float* m1, float* m2, int step, float lr,
                   dkss_stream_t s) {
     if (!params || !grad || !m1 || !m2 || step < 1) return DKSS_EINVAL;
+    dkss::clear_stale_hip_error();
     const float b1 = 0.9f, b2 = 0.999f;
     const float c1 = 1.f / (1.f - powf(b1, (float)step)), c2 = 1.f / (1.f - powf(b2, (float)step));
     hipLaunchKernelGGL(k_mlp_adam, dim3((kParams + 255) / 256), dim3(256), 0, (hipStream_t)s, params, grad,
                        m1, m2, lr, b1, b2, c1, c2, 1e-8f);
-    return hipGetLastError() == hipSuccess ? DKSS_OK : DKSS_EHIP;
+    return dkss::launch_status();
 }
 
 }  // extern "C"

@@ -17,10 +17,14 @@ Sets of points
             1,2,4,8, batch 16, 256, 4096 while batch * 2^x <= 2^33
   heldout   points the selector never sees in training: x = 30 and quarter points between the
             training sizes, ratio 1 and 3, batch 1; and batch 64 and 1024 at quarter points
+  kernels   for each training size from 2^16 bits (ratio 1, batch 1) and its fastest candidate:
+            the FFT level split (library default, balanced, balanced with one more level) and
+            the LDS budget of the DFT-only levels (16, 32, 64 KiB); needs DIR/timings.json
 
 Writes (train) DIR/dkss_tuning.txt, "lo hi cand" lines: the fastest candidate per size bucket at
 ratio 1 and batch 1 (what a DKSS_POLICY_TUNED context loads), and DIR/timings.json; (heldout)
-DIR/timings_heldout.json.  Choices never change result bits.
+DIR/timings_heldout.json; (kernels) DIR/timings_kernels.json and DIR/dkss_tuning.txt again, its
+lines extended to "lo hi cand radices dft_lds".  Choices never change result bits.
 """
 import argparse
 import json
@@ -171,8 +175,8 @@ def run(points, reps, out_json, verbose=True, tuned_txt=None, merge=False):
     return rows
 
 
-def write_tuned_table(rows, path):
-    """Fastest DKSS candidate per size at ratio 1 and batch 1, as half-open log2 N buckets."""
+def best_candidates(rows):
+    """{x: (cand, ms)}: the fastest DKSS candidate per size at ratio 1 and batch 1."""
     best = {}
     for r in rows:
         if r["ratio"] != 1 or r["batch"] != 1 or not isinstance(r["cand"], int) or r["cand"] == SCHOOLBOOK:
@@ -180,25 +184,121 @@ def write_tuned_table(rows, path):
         x = r["log2_a"]
         if x not in best or r["ms"] < best[x][1]:
             best[x] = (r["cand"], r["ms"])
+    return best
+
+
+def write_tuned_table(rows, path, kernel_rows=None):
+    """Fastest DKSS candidate per size at ratio 1 and batch 1, as half-open log2 N buckets; with
+    kernel_rows, also the fastest level split and DFT LDS budget measured for it."""
+    best = best_candidates(rows)
     thesis = {r["log2_a"]: r["ms"] for r in rows
               if r["ratio"] == 1 and r["batch"] == 1 and r["cand"] == "thesis"}
+    kbest = {}
+    for r in kernel_rows or []:
+        x = r["log2_a"]
+        if x in best and r["cand"] == best[x][0] and (x not in kbest or r["ms"] < kbest[x]["ms"]):
+            kbest[x] = r
     xs = sorted(best)
     with open(path, "w") as f:
-        f.write("# log2N_lo log2N_hi candidate   (fastest measured candidate; ms best / thesis)\n")
+        f.write("# log2N_lo log2N_hi candidate [radices] [dft_lds]   (fastest measured; ms best / thesis)\n")
         for i, x in enumerate(xs):
             lo = (xs[i - 1] + x) / 2 if i else 0.0
             hi = (x + xs[i + 1]) / 2 if i + 1 < len(xs) else 64.0
-            f.write("%.3f %.3f %d   # %.4f / %.4f\n" % (lo, hi, best[x][0], best[x][1], thesis.get(x, 0.0)))
+            cfg, ms = "", best[x][1]
+            if x in kbest:
+                k = kbest[x]
+                cfg = " %s %d" % (".".join(str(v) for v in k["radices"]), k["dft_lds"])
+                ms = k["ms"]
+            f.write("%.3f %.3f %d%s   # %.4f / %.4f\n" % (lo, hi, best[x][0], cfg, ms, thesis.get(x, 0.0)))
+
+
+def radix_splits(total, cap):
+    """Level splits of 2^total into radices 2^r, r <= cap: the library default (full radices
+    first), the balanced split with as many levels, and the balanced split with one more."""
+    d, rem = [], total
+    while rem > cap:
+        d.append(cap)
+        rem -= cap
+    if rem:
+        d.append(rem)
+    out = [d]
+    for n in (len(d), len(d) + 1):
+        if n > 8 or n > total:
+            continue
+        q, r = divmod(total, n)
+        bal = [q + 1] * r + [q] * (n - r)
+        if max(bal) <= cap and bal not in out:
+            out.append(bal)
+    return out
+
+
+KERNEL_LDS = (16384, 32768, 65536)
+
+
+def tune_kernels(train_json, reps, out_json, tuned_txt, lo=16.0, verbose=True):
+    """For each size of the training grid (ratio 1, batch 1, 2^lo bits and up) and its fastest
+    candidate: time every level split of radix_splits and every DFT LDS budget of KERNEL_LDS."""
+    import torch
+    with open(train_json) as f:
+        rows = json.load(f)["rows"]
+    best = best_candidates(rows)
+    ctx = dk.Context()
+    krows = []
+    t0 = time.time()
+    xs = [x for x in sorted(best) if x >= lo]
+    for k, x in enumerate(xs):
+        n, nb = _lengths(x, 1)
+        cand = best[x][0]
+        p0 = dict(ctx.candidates(32 * n, 32 * nb))[cand]
+        total = p0.log2_M + 1
+        cap = max(p0.radix_log2[i] for i in range(p0.n_levels))
+        g = torch.Generator(device="cuda")
+        g.manual_seed(int(x * 1000) + 7)
+        a = torch.randint(-2 ** 31, 2 ** 31, (n,), dtype=torch.int32, device="cuda", generator=g)
+        b = torch.randint(-2 ** 31, 2 ** 31, (nb,), dtype=torch.int32, device="cuda", generator=g)
+        c = torch.empty(n + nb, dtype=torch.int32, device="cuda")
+        res = []
+        for split in radix_splits(total, cap):
+            p = dk.Params.make(p0.log2_M, p0.log2_m, p0.u, p0.p_bits, 1, split, 0)
+            ws = torch.empty(max(ctx.workspace_bytes(n, nb, p), 1), dtype=torch.uint8, device="cuda")
+            ctx.prepare(n, nb, p)
+            for lds in KERNEL_LDS:
+                ctx.set_option(dk.OPT_DFT_LDS, lds)
+                ms = _events_ms(lambda: ctx.mul(a, b, out=c, params=p, ws=ws), reps, torch)
+                if not _check(a, b, c):
+                    raise RuntimeError("product check failed: split %s lds %d at 2^%.2f" % (split, lds, x))
+                res.append((ms, split, lds))
+                krows.append({"log2_a": x, "ratio": 1, "batch": 1, "cand": cand, "radices": split,
+                              "dft_lds": lds, "ms": ms})
+            del ws
+        ctx.set_option(dk.OPT_DFT_LDS, 32768)
+        del a, b, c
+        torch.cuda.empty_cache()
+        if verbose:
+            ms, split, lds = min(res)
+            print("[%3d/%d %6.0fs] 2^%.2f cand %d: default %.4f ms, best %s lds %d %.4f ms"
+                  % (k + 1, len(xs), time.time() - t0, x, cand, best[x][1], split, lds, ms), flush=True)
+    with open(out_json, "w") as f:
+        json.dump({"arch": "gfx950", "reps": reps, "unit": "ms per product", "rows": krows}, f)
+    write_tuned_table(rows, tuned_txt, krows)
+    return krows
 
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--set", choices=["train", "heldout"], default="train")
+    ap.add_argument("--set", choices=["train", "heldout", "kernels"], default="train")
     ap.add_argument("--reps", type=int, default=3)
     ap.add_argument("--out", default=dk.TUNING_DIR)
     ap.add_argument("--batches", default="", help="measure only these batch sizes, e.g. 1 or 16,256")
     ap.add_argument("--merge", action="store_true", help="keep the file's rows at other points")
     args = ap.parse_args()
+    if args.set == "kernels":
+        t0 = time.time()
+        tune_kernels(os.path.join(args.out, "timings.json"), args.reps,
+                     os.path.join(args.out, "timings_kernels.json"),
+                     os.path.join(args.out, "dkss_tuning.txt"))
+        print("kernel tuning took %.1f s" % (time.time() - t0), flush=True)
+        return
     pts = train_points() if args.set == "train" else heldout_points()
     if args.batches:
         keep = {int(b) for b in args.batches.split(",")}

@@ -283,3 +283,37 @@ def test_tuned_policy_products(env):
         c = tctx.mul(dk.to_device(a), dk.to_device(b))
         torch.cuda.synchronize()
         assert np.array_equal(dk.to_host(c), C.schoolbook(a, b))
+
+
+def test_batch_graph_replays(env):
+    """A batch captured into a HIP graph: every replay equals the eager batch, with eager work
+    and synchronizations between replays, outputs cleared before each replay, and new operand
+    values written in place between replays (the graph reads them at the same addresses)."""
+    dk, torch, ctx = env
+    lens = [(0, 5), (3, 64), (64, 64), (100, 13)] + SI.batch_lengths(SI.SEED_BASE + 31, 150, hi_bits=18)
+    pairs = [SI.operand_pair(7000 + i, al, bl) for i, (al, bl) in enumerate(lens)]
+    as_ = [dk.to_device(a) for a, _ in pairs]
+    bs = [dk.to_device(b) for _, b in pairs]
+    call = dk.BatchCall(ctx, as_, bs)
+    graph = call.graph()
+    assert graph.products == len(pairs) and graph.kernels > 0
+    eager = dk.Context()
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(5)
+    for rep in range(3):
+        if rep == 2:                       # new operand values, same buffers
+            for t in as_ + bs:
+                if t.numel():
+                    t.copy_(torch.randint(-2 ** 31, 2 ** 31, t.shape, dtype=torch.int32,
+                                          device="cuda", generator=gen))
+        for o in call.outs:
+            o.zero_()
+        want = eager.mul_batch(as_, bs)    # eager work between the replays
+        torch.cuda.synchronize()
+        graph()
+        torch.cuda.synchronize()
+        for i, (o, w) in enumerate(zip(call.outs, want)):
+            assert torch.equal(o, w), (rep, i, lens[i])
+    a0, b0 = dk.to_host(as_[5]), dk.to_host(bs[5])
+    assert np.array_equal(dk.to_host(call.outs[5]), C.schoolbook(a0, b0))
+    graph.close()

@@ -144,3 +144,32 @@ def test_committed_selector_weights_load(dk):
     import numpy as np
     w = dk.mlp_load(path)
     assert w.shape == (dk.MLP_NPARAM,) and np.all(np.isfinite(w))
+
+
+def test_tuned_table_with_level_split(dk, tmp_path):
+    """Tuned lines may carry a level split and an LDS budget; a split that does not fit the
+    candidate's transform length or radix cap is ignored (default split)."""
+    N = 2 ** 28
+    ctx0 = dk.Context()
+    cands = dict(ctx0.candidates(N, N))
+    c = sorted(cands)[0]
+    p = cands[c]
+    total = p.log2_M + 1
+    cap = max(p.radix_log2[i] for i in range(p.n_levels))
+    split = [cap - 1] * (total // (cap - 1)) + ([total % (cap - 1)] if total % (cap - 1) else [])
+    with open(tmp_path / "dkss_tuning.txt", "w") as f:
+        f.write("# test\n")
+        f.write("0 27.5 %d %s 16384\n" % (c, ".".join(map(str, split))))
+        f.write("27.5 28.5 %d %s 16384\n" % (c, ".".join(map(str, [1] * (total - 1)))))   # sum short
+        f.write("28.5 64 %d\n" % c)
+    ctx = dk.Context(dk.POLICY_TUNED, tuning_dir=str(tmp_path))
+    q = ctx.select_params(2 ** 27, 2 ** 27)
+    q27 = dict(ctx0.candidates(2 ** 27, 2 ** 27))[c]
+    assert (q.log2_M, q.log2_m, q.p_bits) == (q27.log2_M, q27.log2_m, q27.p_bits)
+    if sum(split) == q27.log2_M + 1:
+        assert [q.radix_log2[i] for i in range(q.n_levels)] == split
+    q = ctx.select_params(N, N)
+    assert [q.radix_log2[i] for i in range(q.n_levels)] == [p.radix_log2[i] for i in range(p.n_levels)]
+    info = ctx.plan_info(N // 32, N // 32)
+    assert [info.params.radix_log2[i] for i in range(info.params.n_levels)] == \
+        [p.radix_log2[i] for i in range(p.n_levels)]
