@@ -201,7 +201,9 @@ int dkss_residues(const uint32_t* x, size_t n, const uint64_t* primes_host, size
  * are summed per kernel kind.  dkss_profile_read synchronizes on the recorded events.
  * FFT levels: DKSS_K_DFT a level without twiddles (kernel k_level<L, 0>), DKSS_K_TWIDDLE a
  * forward level with its rho twiddles (k_level<L, 1>), DKSS_K_TWIDDLE_INV an inverse level with
- * its twiddles (k_level<L, 2>).
+ * its twiddles (k_level<L, 2>).  DKSS_K_POINTWISE: the componentwise products, as k_pointwise<L>
+ * or, fused (DKSS_OPT_FUSE_PW), as k_level<L, 3> together with the bottom forward and inverse
+ * DFTs (its bytes and operations are those of the products).
  */
 enum {
     DKSS_K_ENCODE = 0, DKSS_K_DFT, DKSS_K_TWIDDLE, DKSS_K_POINTWISE, DKSS_K_DECODE,
@@ -232,8 +234,12 @@ const char* dkss_kernel_name(int kind);
  *                        events, so it overlaps the transform of a; 0 (default): one stream.
  *  DKSS_OPT_DFT_LDS      LDS bytes an FFT-level workgroup may stage (default 32768; 16384 to
  *                        163840): more columns per workgroup versus more workgroups per CU.
+ *  DKSS_OPT_FUSE_PW      1 (default): the componentwise products (Step 6) run inside the
+ *                        bottom FFT level, which then also runs the bottom level of the inverse
+ *                        transform (one launch instead of three); 0: separate launches.  Not
+ *                        fused while DKSS_OPT_OVERLAP transforms b on the second stream.
  */
-enum { DKSS_OPT_OVERLAP = 0, DKSS_OPT_DFT_LDS = 1 };
+enum { DKSS_OPT_OVERLAP = 0, DKSS_OPT_DFT_LDS = 1, DKSS_OPT_FUSE_PW = 2 };
 int dkss_set_option(dkss_ctx* ctx, int option, long long value);
 
 /*

@@ -81,6 +81,13 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError("libdkss.so is not built: run python -m paper_1503_04955_amd.build")
+        # One HIP runtime per process: torch ships its own libamdhip64 (same soname), so torch is
+        # loaded first and the library binds to that copy.  Loaded the other way round, the
+        # process would hold two runtimes and the second would find no device.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = ctypes.CDLL(LIB_PATH)
         vp, sz, u32, u64 = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_uint32, ctypes.c_uint64
         PP = ctypes.POINTER(Params)
@@ -147,7 +154,7 @@ CAND_SCHOOLBOOK = NCAND
 MLP_NPARAM = MLP_HID * MLP_IN + MLP_HID + MLP_HID * MLP_HID + MLP_HID + MLP_OUT * MLP_HID + MLP_OUT
 TUNING_DIR = os.path.join(_HERE, "tuning")
 
-OPT_OVERLAP, OPT_DFT_LDS = 0, 1
+OPT_OVERLAP, OPT_DFT_LDS, OPT_FUSE_PW = 0, 1, 2
 
 
 def _check(rc, what):

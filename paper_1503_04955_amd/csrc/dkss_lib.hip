@@ -296,24 +296,16 @@ __device__ __forceinline__ void level_twiddle(uint32_t* cur, uint32_t* RB, uint3
     if (A.mode == 2) __syncthreads();
 }
 
-template <int L, int MODE>
-__global__ __launch_bounds__(kThreads) void k_level(uint32_t* __restrict__ poly0, long long stride,
-                                                    const uint32_t* __restrict__ table, LevelArgs A,
-                                                    QConst Q) {
+// log2 r radix-2 decimation-in-time passes over the workgroup's columns, from cur into nxt and
+// back (the buffers are swapped after each pass; on return cur holds the result).  Input: the
+// element at position j of a column in slot bitrev(j); output: position v in slot v.  The pass
+// merging halves of h points multiplies the odd half by alpha^((m/h) k) (alpha^-1 if inverse).
+template <int L>
+__device__ __forceinline__ void dft_passes(uint32_t*& cur, uint32_t*& nxt, const LevelArgs& A, int inverse,
+                                           const QConst& Q) {
     constexpr int D = Dig<L>::D;
-    A.mode = MODE;
-    uint32_t* __restrict__ poly = poly0 + (size_t)blockIdx.y * stride;
-    extern __shared__ uint4 smv[];
     const int m = 1 << A.log2m, r = 1 << A.log2r;
     const int EW = m * D;
-    const int ncw = (1 << (A.log2C + A.log2r)) * EW;     // words of the workgroup's columns
-    uint32_t* cur = reinterpret_cast<uint32_t*>(smv);
-    uint32_t* nxt = cur + ncw;
-    uint32_t* sep = nxt + ncw;                            // separate staging area, if any
-    const long long c0 = (long long)blockIdx.x << A.log2C;
-    level_copy_in<L>(cur, poly, A, c0);
-    __syncthreads();
-    if (A.mode == 2) level_twiddle<L>(cur, A.rb_separate ? sep : nxt, poly, table, A, c0, Q);
     const int tasks = (1 << (A.log2C + A.log2r - 1)) << A.log2m;   // butterflies x coefficients
     for (int h = 1, lh = 0; h < r; h <<= 1, ++lh) {
         const int mh = m >> lh;
@@ -326,7 +318,7 @@ __global__ __launch_bounds__(kThreads) void k_level(uint32_t* __restrict__ poly0
             const int xs = ((bf - kk) << 1) + kk;
             const int ys = xs + h;
             int e = kk * mh;
-            if (A.inverse) e = (2 * m - e) & (2 * m - 1);
+            if (inverse) e = (2 * m - e) & (2 * m - 1);
             // (alpha^e y)_jj = +- y_idx, negated once per wrap past degree m-1
             int idx = jj - e;
             bool neg = false;
@@ -362,10 +354,107 @@ __global__ __launch_bounds__(kThreads) void k_level(uint32_t* __restrict__ poly0
         cur = nxt;
         nxt = tmp;
     }
-    if (A.mode == 1)
+}
+
+// Componentwise products of the bottom level (Step 6 fused between the last forward and the
+// first inverse level): the element at position v of each column (slot v, after the forward
+// DFT) becomes a_v * b_v * (2M)^-1, in place.  b_v is read from the transform of b at the same
+// polynomial position (or is a_v itself for a squaring) and staged with its negation, like a
+// twiddle.  Rounds of 256/m elements, synchronized per wavefront as in level_twiddle.
+template <int L>
+__device__ __forceinline__ void level_pointwise(uint32_t* cur, uint32_t* RB, const uint32_t* __restrict__ bpoly,
+                                                int squaring, const LevelArgs& A, long long c0, const QConst& Q) {
+    constexpr int D = Dig<L>::D;
+    const int m = 1 << A.log2m;
+    const int EW = D << A.log2m;
+    const int per = kThreads >> A.log2m;
+    const int g = threadIdx.x >> A.log2m, j = threadIdx.x & (m - 1);
+    const int nel = 1 << (A.log2C + A.log2r);
+    uint32_t* TP = RB + g * tw_stage_words(m, D);
+    for (int r0 = 0; r0 < nel; r0 += per) {
+        const int el = r0 + g;
+        const bool valid = el < nel;
+        const int c = el >> A.log2r, v = el & ((1 << A.log2r) - 1);
+        uint32_t* X = cur + ((c << A.log2r) + v) * EW;
+        if (valid) {
+            const uint32_t* src = squaring ? X : bpoly + (size_t)level_pos(A, c0, c, v) * EW;
+            uint32_t bv[D], nb[D];
+#pragma unroll
+            for (int y = 0; y < D; ++y) bv[y] = src[j * D + y];
+            dneg_q<L>(nb, bv, Q);
+#pragma unroll
+            for (int y = 0; y < D; ++y) {
+                TP[j * D + y] = bv[y];
+                TP[(j + m) * D + y] = nb[y];
+            }
+        }
+        wave_sync();
+        uint32_t out[D];
+        if (valid) {
+            uint32_t cv[D];
+            rprod_coeff<L>(TP, X, A.log2m, j, 0, Q, cv);    // (a*b)_j 2^-28K
+            mont_scalar<L>(cv, Q.kpw, Q, out);              // * (2M)^-1 2^28K
+        }
+        wave_sync();
+        if (valid) {
+#pragma unroll
+            for (int y = 0; y < D; ++y) X[j * D + y] = out[y];
+        }
+    }
+    __syncthreads();
+}
+
+// dst slot bitrev(v) = src slot v, every column of the workgroup
+template <int L>
+__device__ __forceinline__ void level_permute(uint32_t* dst, const uint32_t* src, const LevelArgs& A) {
+    constexpr int D = Dig<L>::D;
+    const int EW = D << A.log2m;
+    const int nel = 1 << (A.log2C + A.log2r);
+    for (int t = threadIdx.x; t < nel * EW; t += kThreads) {
+        const int e = t / EW;
+        const int w = t - e * EW;
+        const int c = e >> A.log2r, v = e & ((1 << A.log2r) - 1);
+        dst[((c << A.log2r) + bitrev(v, A.log2r)) * EW + w] = src[t];
+    }
+    __syncthreads();
+}
+
+// MODE 0: DFT only; 1: forward DFT, then twiddles on the way out; 2: twiddles, then inverse DFT;
+// 3 (bottom level, no twiddles): forward DFT, componentwise products with bpoly, inverse DFT.
+template <int L, int MODE>
+__global__ __launch_bounds__(kThreads) void k_level(uint32_t* __restrict__ poly0, long long stride,
+                                                    const uint32_t* __restrict__ table, LevelArgs A,
+                                                    QConst Q, const uint32_t* __restrict__ bpoly0,
+                                                    int squaring) {
+    constexpr int D = Dig<L>::D;
+    A.mode = MODE;
+    uint32_t* __restrict__ poly = poly0 + (size_t)blockIdx.y * stride;
+    extern __shared__ uint4 smv[];
+    const int m = 1 << A.log2m;
+    const int EW = m * D;
+    const int ncw = (1 << (A.log2C + A.log2r)) * EW;     // words of the workgroup's columns
+    uint32_t* cur = reinterpret_cast<uint32_t*>(smv);
+    uint32_t* nxt = cur + ncw;
+    uint32_t* sep = nxt + ncw;                            // separate staging area, if any
+    const long long c0 = (long long)blockIdx.x << A.log2C;
+    level_copy_in<L>(cur, poly, A, c0);
+    __syncthreads();
+    if (MODE == 2) level_twiddle<L>(cur, A.rb_separate ? sep : nxt, poly, table, A, c0, Q);
+    dft_passes<L>(cur, nxt, A, MODE == 3 ? 0 : A.inverse, Q);
+    if (MODE == 1) {
         level_twiddle<L>(cur, A.rb_separate ? sep : nxt, poly, table, A, c0, Q);
-    else
+    } else if (MODE == 3) {
+        const uint32_t* bpoly = bpoly0 ? bpoly0 + (size_t)blockIdx.y * stride : nullptr;
+        level_pointwise<L>(cur, A.rb_separate ? sep : nxt, bpoly, squaring, A, c0, Q);
+        level_permute<L>(nxt, cur, A);
+        uint32_t* tmp = cur;
+        cur = nxt;
+        nxt = tmp;
+        dft_passes<L>(cur, nxt, A, 1, Q);
         level_copy_out<L>(poly, cur, A, c0);
+    } else {
+        level_copy_out<L>(poly, cur, A, c0);
+    }
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -905,6 +994,7 @@ struct Call {
     Prof* prof = nullptr;
     long long dft_lds = 32768;
     bool overlap = false;
+    bool fuse_pw = true;              // componentwise products fused into the bottom level
     hipStream_t aux = nullptr;        // second stream for the transform of b
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 };
@@ -938,6 +1028,7 @@ struct dkss_ctx {
     std::map<std::string, std::unique_ptr<Cached>> cache;
     Prof prof;
     bool overlap = false;
+    bool fuse_pw = true;
     long long dft_lds = 32768;
     hipStream_t aux = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
@@ -1304,8 +1395,12 @@ Workspace layout(const Plan& P, size_t G, size_t nw_max, bool need_b, char* base
 
 template <int L>
 struct Transform {
-    // forward (inverse = 0) or inverse (inverse = 1) transform of G polynomials in place
-    static int run(const Call& c, uint32_t* poly, size_t stride, unsigned G, int inverse, hipStream_t s) {
+    // Forward (inverse = 0) or inverse (inverse = 1) transform of G polynomials in place.
+    // fused (forward): the bottom level also multiplies componentwise by bpoly (poly itself if
+    // squaring, (2M)^-1 included) and runs the bottom inverse level, so the inverse transform
+    // that follows starts one level up (fused = 1 there too).
+    static int run(const Call& c, uint32_t* poly, size_t stride, unsigned G, int inverse, hipStream_t s,
+                   int fused = 0, const uint32_t* bpoly = nullptr, int squaring = 0) {
         const Plan& P = c.P;
         const long long twoM = 2LL << P.log2_M;
         const int m = P.m();
@@ -1342,27 +1437,39 @@ struct Transform {
             A.log2C = log2C;
             while ((1LL << A.log2nl) < n_lvl[k]) ++A.log2nl;
             while ((1LL << A.log2mu) < mu[k]) ++A.log2mu;
-            A.mode = tw ? (inverse ? 2 : 1) : 0;
+            const bool pw = fused && !inverse && k == nl - 1;     // fused componentwise products
+            A.mode = pw ? 3 : tw ? (inverse ? 2 : 1) : 0;
             A.inverse = inverse;
-            // twiddle staging: 256/m elements x 2m residues; in the free column buffer if it fits
+            // staging of twiddles or of b: 256/m elements x 2m residues; in the free column
+            // buffer if it fits
             const size_t ncw = ((size_t)r << log2C) * m * D;
             const size_t rb_words = (size_t)(kThreads / m) * tw_stage_words(m, D);
-            A.rb_separate = tw && ncw < rb_words;
+            A.rb_separate = (tw || pw) && ncw < rb_words;
             const size_t lds = 2 * ncw * 4 + (A.rb_separate ? rb_words * 4 : 0);
             const unsigned blocks = (unsigned)(ncols >> log2C);
             const double nprod = tw ? (double)(twoM / n_lvl[k]) * (r - 1) * (mu[k] - 1) : 0.0;
+            const uint32_t* tab = (const uint32_t*)c.C->d_table;
+            if (pw) {
+                // algorithmic work: a and b read, the product written; 2M products in R and
+                // 2M m scalar products for the (2M)^-1
+                ProfScope ps(c.prof, DKSS_K_POINTWISE, s, 3.0 * G * twoM * m * L * 4,
+                             (double)G * twoM * ((double)m * m * L * L + (double)m * L * L));
+                hipLaunchKernelGGL((k_level<L, 3>), dim3(blocks, G), dim3(kThreads), lds, s, poly,
+                                   (long long)stride, tab, A, Q, bpoly, squaring);
+                return launch_status();
+            }
             ProfScope ps(c.prof, tw ? (inverse ? DKSS_K_TWIDDLE_INV : DKSS_K_TWIDDLE) : DKSS_K_DFT, s,
                          2.0 * G * twoM * m * L * 4,
                          (double)G * nprod * (double)m * m * L * L);
             if (A.mode == 0)
                 hipLaunchKernelGGL((k_level<L, 0>), dim3(blocks, G), dim3(kThreads), lds, s, poly,
-                                   (long long)stride, (const uint32_t*)c.C->d_table, A, Q);
+                                   (long long)stride, tab, A, Q, (const uint32_t*)nullptr, 0);
             else if (A.mode == 1)
                 hipLaunchKernelGGL((k_level<L, 1>), dim3(blocks, G), dim3(kThreads), lds, s, poly,
-                                   (long long)stride, (const uint32_t*)c.C->d_table, A, Q);
+                                   (long long)stride, tab, A, Q, (const uint32_t*)nullptr, 0);
             else
                 hipLaunchKernelGGL((k_level<L, 2>), dim3(blocks, G), dim3(kThreads), lds, s, poly,
-                                   (long long)stride, (const uint32_t*)c.C->d_table, A, Q);
+                                   (long long)stride, tab, A, Q, (const uint32_t*)nullptr, 0);
             return launch_status();
         };
         int rc;
@@ -1370,7 +1477,7 @@ struct Transform {
             for (int k = 0; k < nl; ++k)
                 if ((rc = level(k, k + 1 < nl))) return rc;
         } else {
-            for (int k = nl - 1; k >= 0; --k)
+            for (int k = nl - 1 - (fused ? 1 : 0); k >= 0; --k)
                 if ((rc = level(k, k + 1 < nl))) return rc;
         }
         return DKSS_OK;
@@ -1464,6 +1571,7 @@ int prepare_call(dkss_ctx* ctx, size_t alen, size_t blen, const dkss_params* p, 
     call->prof = &ctx->prof;
     call->dft_lds = ctx->dft_lds;          // a tuned entry may override it in resolve_params
     call->overlap = ctx->overlap;
+    call->fuse_pw = ctx->fuse_pw;
     int choice = -1;
     if (!p && ctx->policy == DKSS_POLICY_LEARNED) {
         int rc = learned_choices(ctx, 1, &alen, &blen, batch, &choice);
@@ -1492,14 +1600,21 @@ int run_group(const Call& call, const ProdArgs& PA, unsigned G, size_t nw_max, d
         if ((rc = dispatch_L<Encode>(L, call, PA, G, 1, w.B, w.S, in_b, sb))) return rc;
         if ((rc = dispatch_L<Transform>(L, call, w.B, w.S, G, 0, sb))) return rc;
     }
+    // the componentwise products run inside the bottom level of a's transform (one launch for
+    // the last forward level, the products and the first inverse level) unless b is still being
+    // transformed on the other stream
+    const int fz = (call.fuse_pw && !fork) ? 1 : 0;
+    const uint32_t* bp = squaring ? (const uint32_t*)w.A : w.B;
     if ((rc = dispatch_L<Encode>(L, call, PA, G, 0, w.A, w.S, in_a, s))) return rc;
-    if ((rc = dispatch_L<Transform>(L, call, w.A, w.S, G, 0, s))) return rc;
+    if ((rc = dispatch_L<Transform>(L, call, w.A, w.S, G, 0, s, fz, squaring ? nullptr : bp,
+                                    squaring ? 1 : 0)))
+        return rc;
     if (fork) {
         HIP_OK(hipEventRecord(call.ev_join, sb));
         HIP_OK(hipStreamWaitEvent(s, call.ev_join, 0));
     }
-    if ((rc = dispatch_L<Pointwise>(L, call, w.A, squaring ? (const uint32_t*)w.A : w.B, w.S, G, s))) return rc;
-    if ((rc = dispatch_L<Transform>(L, call, w.A, w.S, G, 1, s))) return rc;
+    if (!fz && (rc = dispatch_L<Pointwise>(L, call, w.A, bp, w.S, G, s))) return rc;
+    if ((rc = dispatch_L<Transform>(L, call, w.A, w.S, G, 1, s, fz))) return rc;
     return dispatch_L<Decode>(L, call, PA, G, nw_max, out_w, w, s);
 }
 
@@ -1644,6 +1759,9 @@ int dkss_set_option(dkss_ctx* ctx, int option, long long value) {
     switch (option) {
         case DKSS_OPT_OVERLAP:
             ctx->overlap = value != 0;
+            return DKSS_OK;
+        case DKSS_OPT_FUSE_PW:
+            ctx->fuse_pw = value != 0;
             return DKSS_OK;
         case DKSS_OPT_DFT_LDS:
             if (value < 16384 || value > 163840) return DKSS_EINVAL;

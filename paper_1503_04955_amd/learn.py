@@ -129,7 +129,6 @@ def summary(regs, field):
 
 
 def main():
-    dk.lib()                                  # load the library before the device is set up
     ap = argparse.ArgumentParser()
     ap.add_argument("--timings", default=os.path.join(dk.TUNING_DIR, "timings.json"))
     ap.add_argument("--out", default=os.path.join(dk.TUNING_DIR, "dkss_mlp.txt"))

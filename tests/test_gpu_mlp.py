@@ -214,3 +214,21 @@ def test_learned_beats_thesis_on_heldout_sizes(env):
         torch.cuda.empty_cache()
     print("\n".join(lines))
     assert tot_l < tot_t, lines
+
+
+def test_library_loaded_before_torch_in_a_fresh_process(env):
+    """The binding loads torch's HIP runtime before the library, whatever the caller imports
+    first, so a process never holds two runtimes (the second one would see no device)."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    code = ("import sys; sys.path.insert(0, %r)\n"
+            "import paper_1503_04955_amd as dk\n"
+            "f = dk.mlp_features(1 << 20, 1 << 18, 4)\n"
+            "import torch, numpy as np\n"
+            "w = torch.zeros(dk.MLP_NPARAM, device='cuda')\n"
+            "y = dk.mlp_forward(w, torch.from_numpy(f[None, :]).cuda())\n"
+            "assert float(y.abs().sum()) == 0.0\n"
+            "print('ok')\n" % root)
+    res = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=240)
+    assert res.returncode == 0 and "ok" in res.stdout, res.stderr[-2000:]
