@@ -552,20 +552,30 @@ __global__ __launch_bounds__(kThreads) void k_table_mul(uint32_t* table, long lo
 
 // Sum of the 32-bit pieces that the coefficients c_(l,k) (value sum c_(l,k) 2^(u (k + l m/2)))
 // put into output word w.  Coefficients are exact integers below q, in D digits.
+// floor(x / u) for 0 <= x < 2^40 and 1 <= u < 2^20: a double-precision estimate, corrected by
+// one step either way (the estimate is within 1 of the quotient)
+__device__ __forceinline__ long long div_u(long long x, int u, double inv_u) {
+    long long q = (long long)((double)x * inv_u);
+    if (q * u > x) --q;
+    else if ((q + 1) * u <= x) ++q;
+    return q;
+}
+
 template <int L>
 __device__ __forceinline__ uint64_t word_sum(long long w, const uint32_t* __restrict__ poly,
                                              long long twoM, int log2m, int u) {
     constexpr int D = Dig<L>::D;
     const int m = 1 << log2m;
     const int hm = m >> 1;
+    const double inv_u = 1.0 / (double)u;
     const long long lo_excl = 32 * w - 28 * D;            // piece iff u g > lo_excl
-    const long long g_lo = lo_excl < 0 ? 0 : lo_excl / u + 1;
-    const long long g_hi = (32 * w + 31) / u;
+    const long long g_lo = lo_excl < 0 ? 0 : div_u(lo_excl, u, inv_u) + 1;
+    const long long g_hi = div_u(32 * w + 31, u, inv_u);
     uint64_t V = 0;
     for (long long g = g_lo; g <= g_hi; ++g) {
         const long long P = (long long)u * g;
         const long long off = 32 * w - P;                  // bit of the term at word w's bit 0
-        const long long lmax = g / hm;
+        const long long lmax = g >> (log2m - 1);          // g / (m/2)
 #pragma unroll
         for (int t = 0; t < 2; ++t) {
             const long long l = lmax - t;
@@ -574,7 +584,8 @@ __device__ __forceinline__ uint64_t word_sum(long long w, const uint32_t* __rest
             const uint32_t* T = poly + ((size_t)l * m + k) * D;
             uint32_t piece;
             if (off >= 0) {
-                const int k0 = (int)(off / 28), sh = (int)(off - 28 * (off / 28));
+                const int o = (int)off;                 // below 28 D
+                const int k0 = o / 28, sh = o - 28 * k0;
                 uint64_t v = T[k0];
                 if (k0 + 1 < D) v |= (uint64_t)T[k0 + 1] << 28;
                 if (k0 + 2 < D) v |= (uint64_t)T[k0 + 2] << 56;
