@@ -157,6 +157,7 @@ __global__ __launch_bounds__(kThreads) void k_encode(ProdArgs PA, int which, uin
 // staged in the free buffer.
 struct LevelArgs {
     long long twoM, base, mu_top;
+    int log2mut;                  // log2 mu_top
     int log2nl, log2mu, log2r, log2m, log2C;
     int mode, inverse;
     int rb_separate;              // 1: the twiddle staging area follows both column buffers
@@ -232,12 +233,49 @@ __device__ __forceinline__ void level_copy_out(uint32_t* __restrict__ poly, cons
     }
 }
 
+// A thread's operand for one round of products, fetched from HBM a round ahead (the load is
+// issued before the preceding work and waited for at first use): coefficient j of the table
+// entry rho^s and of its negation (twiddles), or coefficient j of b (componentwise products).
+template <int L>
+struct Ahead {
+    uint32_t v[2 * Dig<L>::D];
+    int rot;                      // the twiddle's power of alpha
+    bool nz;                      // the element gets a product
+};
+
+// Twiddle of the element that this thread serves in the round starting at element r0.
+template <int L>
+__device__ __forceinline__ void tw_fetch(Ahead<L>& f, int r0, const uint32_t* __restrict__ table,
+                                         const LevelArgs& A, long long c0) {
+    constexpr int D = Dig<L>::D;
+    const int m = 1 << A.log2m;
+    const int g = threadIdx.x >> A.log2m, j = threadIdx.x & (m - 1);
+    const int el = r0 + g;
+    f.nz = false;
+    f.rot = 0;
+    if (el >= (1 << (A.log2C + A.log2r))) return;
+    const int c = el >> A.log2r, v = el & ((1 << A.log2r) - 1);
+    const long long l = (c0 + c) & ((1LL << A.log2mu) - 1);
+    long long e = A.base * l * v;                       // < 2M
+    if (A.inverse && e) e = A.twoM - e;
+    if (!e) return;
+    f.nz = true;
+    f.rot = (int)(e >> A.log2mut);
+    const long long s = e & ((1LL << A.log2mut) - 1);
+    const uint32_t* ts = table + (size_t)s * 2 * m * D;
+#pragma unroll
+    for (int y = 0; y < D; ++y) {
+        f.v[y] = ts[j * D + y];
+        f.v[D + y] = ts[(j + m) * D + y];
+    }
+}
+
 // Twiddle products of all C r elements of the workgroup, in rounds of 256/m elements.  The
 // element with position v in column c sits in LDS slot v (after the DFT, mode 1) or bitrev(v)
 // (before it, mode 2).  Mode 1 writes results to HBM; mode 2 writes them back into the slot once
-// the round's products (which read the slot) are done.
+// the round's products (which read the slot) are done.  f holds round 0's twiddle on entry.
 template <int L>
-__device__ __forceinline__ void level_twiddle(uint32_t* cur, uint32_t* RB, uint32_t* __restrict__ poly,
+__device__ __forceinline__ void level_twiddle(Ahead<L>& f, uint32_t* cur, uint32_t* RB, uint32_t* __restrict__ poly,
                                               const uint32_t* __restrict__ table, const LevelArgs& A,
                                               long long c0, const QConst& Q) {
     constexpr int D = Dig<L>::D;
@@ -255,27 +293,20 @@ __device__ __forceinline__ void level_twiddle(uint32_t* cur, uint32_t* RB, uint3
         const int c = el >> A.log2r, v = el & ((1 << A.log2r) - 1);
         const int slot = A.mode == 1 ? v : bitrev(v, A.log2r);
         uint32_t* X = cur + ((c << A.log2r) + slot) * EW;
-        long long e = 0;
-        if (valid) {
-            const long long l = (c0 + c) & ((1LL << A.log2mu) - 1);
-            e = A.base * l * v;                         // < 2M
-            if (A.inverse && e) e = A.twoM - e;
-        }
-        int rot = 0;
-        if (e) {
-            rot = (int)(e / A.mu_top);
-            const long long s = e - (long long)rot * A.mu_top;
-            const uint32_t* ts = table + (size_t)s * 2 * m * D;
+        const bool nz = f.nz;
+        const int rot = f.rot;
+        if (nz) {
 #pragma unroll
             for (int y = 0; y < D; ++y) {
-                TP[j * D + y] = ts[j * D + y];
-                TP[(j + m) * D + y] = ts[(j + m) * D + y];
+                TP[j * D + y] = f.v[y];
+                TP[(j + m) * D + y] = f.v[D + y];
             }
         }
+        if (r0 + per < nel) tw_fetch<L>(f, r0 + per, table, A, c0);     // next round's twiddle
         wave_sync();
         uint32_t out[D];
         if (valid) {
-            if (e) {
+            if (nz) {
                 rprod_coeff<L>(TP, X, A.log2m, j, rot, Q, out);
             } else {
 #pragma unroll
@@ -288,7 +319,7 @@ __device__ __forceinline__ void level_twiddle(uint32_t* cur, uint32_t* RB, uint3
             }
         }
         wave_sync();
-        if (valid && A.mode == 2 && e) {
+        if (valid && A.mode == 2 && nz) {
 #pragma unroll
             for (int y = 0; y < D; ++y) X[j * D + y] = out[y];
         }
@@ -356,14 +387,31 @@ __device__ __forceinline__ void dft_passes(uint32_t*& cur, uint32_t*& nxt, const
     }
 }
 
+// Coefficient j of b for the element that this thread serves in the round starting at r0.
+template <int L>
+__device__ __forceinline__ void pw_fetch(Ahead<L>& f, int r0, const uint32_t* __restrict__ bpoly,
+                                         const LevelArgs& A, long long c0) {
+    constexpr int D = Dig<L>::D;
+    const int g = threadIdx.x >> A.log2m, j = threadIdx.x & ((1 << A.log2m) - 1);
+    const int el = r0 + g;
+    f.nz = el < (1 << (A.log2C + A.log2r));
+    if (!f.nz || !bpoly) return;
+    const int c = el >> A.log2r, v = el & ((1 << A.log2r) - 1);
+    const uint32_t* src = bpoly + (size_t)level_pos(A, c0, c, v) * (D << A.log2m) + j * D;
+#pragma unroll
+    for (int y = 0; y < D; ++y) f.v[y] = src[y];
+}
+
 // Componentwise products of the bottom level (Step 6 fused between the last forward and the
 // first inverse level): the element at position v of each column (slot v, after the forward
 // DFT) becomes a_v * b_v * (2M)^-1, in place.  b_v is read from the transform of b at the same
-// polynomial position (or is a_v itself for a squaring) and staged with its negation, like a
-// twiddle.  Rounds of 256/m elements, synchronized per wavefront as in level_twiddle.
+// polynomial position (bpoly; f holds round 0's on entry), or is a_v itself for a squaring
+// (bpoly NULL), and is staged with its negation, like a twiddle.  Rounds of 256/m elements,
+// synchronized per wavefront as in level_twiddle.
 template <int L>
-__device__ __forceinline__ void level_pointwise(uint32_t* cur, uint32_t* RB, const uint32_t* __restrict__ bpoly,
-                                                int squaring, const LevelArgs& A, long long c0, const QConst& Q) {
+__device__ __forceinline__ void level_pointwise(Ahead<L>& f, uint32_t* cur, uint32_t* RB,
+                                                const uint32_t* __restrict__ bpoly, const LevelArgs& A,
+                                                long long c0, const QConst& Q) {
     constexpr int D = Dig<L>::D;
     const int m = 1 << A.log2m;
     const int EW = D << A.log2m;
@@ -377,10 +425,9 @@ __device__ __forceinline__ void level_pointwise(uint32_t* cur, uint32_t* RB, con
         const int c = el >> A.log2r, v = el & ((1 << A.log2r) - 1);
         uint32_t* X = cur + ((c << A.log2r) + v) * EW;
         if (valid) {
-            const uint32_t* src = squaring ? X : bpoly + (size_t)level_pos(A, c0, c, v) * EW;
             uint32_t bv[D], nb[D];
 #pragma unroll
-            for (int y = 0; y < D; ++y) bv[y] = src[j * D + y];
+            for (int y = 0; y < D; ++y) bv[y] = bpoly ? f.v[y] : X[j * D + y];
             dneg_q<L>(nb, bv, Q);
 #pragma unroll
             for (int y = 0; y < D; ++y) {
@@ -388,6 +435,7 @@ __device__ __forceinline__ void level_pointwise(uint32_t* cur, uint32_t* RB, con
                 TP[(j + m) * D + y] = nb[y];
             }
         }
+        if (r0 + per < nel) pw_fetch<L>(f, r0 + per, bpoly, A, c0);     // next round's b
         wave_sync();
         uint32_t out[D];
         if (valid) {
@@ -437,15 +485,21 @@ __global__ __launch_bounds__(kThreads) void k_level(uint32_t* __restrict__ poly0
     uint32_t* nxt = cur + ncw;
     uint32_t* sep = nxt + ncw;                            // separate staging area, if any
     const long long c0 = (long long)blockIdx.x << A.log2C;
+    const uint32_t* bpoly = (MODE == 3 && !squaring) ? bpoly0 + (size_t)blockIdx.y * stride : nullptr;
+    Ahead<L> f;
+    // round 0's operand: before the column loads (mode 2, needed first) or after them, so that
+    // its latency hides behind the DFT (modes 1 and 3)
+    if (MODE == 2) tw_fetch<L>(f, 0, table, A, c0);
     level_copy_in<L>(cur, poly, A, c0);
+    if (MODE == 1) tw_fetch<L>(f, 0, table, A, c0);
+    if (MODE == 3) pw_fetch<L>(f, 0, bpoly, A, c0);
     __syncthreads();
-    if (MODE == 2) level_twiddle<L>(cur, A.rb_separate ? sep : nxt, poly, table, A, c0, Q);
+    if (MODE == 2) level_twiddle<L>(f, cur, A.rb_separate ? sep : nxt, poly, table, A, c0, Q);
     dft_passes<L>(cur, nxt, A, MODE == 3 ? 0 : A.inverse, Q);
     if (MODE == 1) {
-        level_twiddle<L>(cur, A.rb_separate ? sep : nxt, poly, table, A, c0, Q);
+        level_twiddle<L>(f, cur, A.rb_separate ? sep : nxt, poly, table, A, c0, Q);
     } else if (MODE == 3) {
-        const uint32_t* bpoly = bpoly0 ? bpoly0 + (size_t)blockIdx.y * stride : nullptr;
-        level_pointwise<L>(cur, A.rb_separate ? sep : nxt, bpoly, squaring, A, c0, Q);
+        level_pointwise<L>(f, cur, A.rb_separate ? sep : nxt, bpoly, A, c0, Q);
         level_permute<L>(nxt, cur, A);
         uint32_t* tmp = cur;
         cur = nxt;
@@ -1443,6 +1497,7 @@ struct Transform {
             A.twoM = twoM;
             A.base = base[k];
             A.mu_top = c.C->table_count;
+            while ((1LL << A.log2mut) < A.mu_top) ++A.log2mut;
             A.log2r = log2r;
             A.log2m = P.log2_m;
             A.log2C = log2C;
