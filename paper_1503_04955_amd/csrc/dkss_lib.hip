@@ -95,8 +95,35 @@ struct ProdArgs {
 // Step 4: encode
 // ---------------------------------------------------------------------------------------------
 
-// poly: 2M elements x m coefficients x D digits.  Coefficient k < m/2 of element i < M gets bits
-// [u (i m/2 + k), u (i m/2 + k) + u) of a; all others are zero.
+// Digits of coefficient k of element i: bits [u (i m/2 + k), u (i m/2 + k) + u) of a for
+// k < m/2 and i < M; zero otherwise.
+template <int L>
+__device__ __forceinline__ void encode_digits(const uint32_t* __restrict__ a, long long alen, int u, long long i,
+                                              int k, long long M, int log2m, uint32_t* out) {
+    constexpr int D = Dig<L>::D;
+    const int hm = 1 << (log2m - 1);
+#pragma unroll
+    for (int w = 0; w < D; ++w) out[w] = 0;
+    if (i < M && k < hm) {
+        const unsigned long long pos = ((unsigned long long)i * hm + k) * (unsigned)u;
+#pragma unroll
+        for (int w = 0; w < D; ++w) {
+            const int nb = u - 28 * w;
+            if (nb > 0) {
+                const unsigned long long bit = pos + 28ull * w;
+                const long long wi = (long long)(bit >> 5);
+                const int sh = (int)(bit & 31);
+                const uint64_t lo = wi < alen ? a[wi] : 0u;
+                const uint64_t hi = wi + 1 < alen ? a[wi + 1] : 0u;
+                uint32_t v = (uint32_t)(((hi << 32) | lo) >> sh) & kMask28;
+                if (nb < 28) v &= (1u << nb) - 1u;
+                out[w] = v;
+            }
+        }
+    }
+}
+
+// poly: 2M elements x m coefficients x D digits (encode_digits).
 template <int L>
 __global__ __launch_bounds__(kThreads) void k_encode(ProdArgs PA, int which, uint32_t* __restrict__ poly0,
                                                      long long stride, long long M, int log2m) {
@@ -113,25 +140,7 @@ __global__ __launch_bounds__(kThreads) void k_encode(ProdArgs PA, int which, uin
     const long long i = t >> log2m;
     const int k = (int)(t & (m - 1));
     uint32_t out[D];
-#pragma unroll
-    for (int w = 0; w < D; ++w) out[w] = 0;
-    if (i < M && k < m / 2) {
-        const unsigned long long pos = ((unsigned long long)i * (m / 2) + k) * (unsigned)u;
-#pragma unroll
-        for (int w = 0; w < D; ++w) {
-            const int nb = u - 28 * w;
-            if (nb > 0) {
-                const unsigned long long bit = pos + 28ull * w;
-                const long long wi = (long long)(bit >> 5);
-                const int sh = (int)(bit & 31);
-                const uint64_t lo = wi < alen ? a[wi] : 0u;
-                const uint64_t hi = wi + 1 < alen ? a[wi + 1] : 0u;
-                uint32_t v = (uint32_t)(((hi << 32) | lo) >> sh) & kMask28;
-                if (nb < 28) v &= (1u << nb) - 1u;
-                out[w] = v;
-            }
-        }
-    }
+    encode_digits<L>(a, alen, u, i, k, M, log2m, out);
     uint32_t* dst = poly + (size_t)t * D;
 #pragma unroll
     for (int w = 0; w < D; ++w) dst[w] = out[w];
@@ -199,6 +208,25 @@ __device__ __forceinline__ void level_copy_in(uint32_t* cur, const uint32_t* __r
             const long long pos = level_pos(A, c0, c, j);
             cur[((c << A.log2r) + bitrev(j, A.log2r)) * EW + wk] = poly[(size_t)pos * EW + wk];
         }
+    }
+}
+
+// The top forward level's columns straight from the operand (Step 4 fused into the first level):
+// element at position j of a column into slot bitrev(j), as level_copy_in would load it.
+template <int L>
+__device__ __forceinline__ void level_encode_in(uint32_t* cur, const uint32_t* __restrict__ a, long long alen,
+                                                int u, long long M, const LevelArgs& A, long long c0) {
+    constexpr int D = Dig<L>::D;
+    const int EW = D << A.log2m;
+    const int nel = 1 << (A.log2C + A.log2r);
+    for (int t = threadIdx.x; t < (nel << A.log2m); t += kThreads) {
+        const int e = t >> A.log2m, k = t & ((1 << A.log2m) - 1);
+        const int c = e & ((1 << A.log2C) - 1), j = e >> A.log2C;
+        uint32_t out[D];
+        encode_digits<L>(a, alen, u, level_pos(A, c0, c, j), k, M, A.log2m, out);
+        uint32_t* dst = cur + ((c << A.log2r) + bitrev(j, A.log2r)) * EW + k * D;
+#pragma unroll
+        for (int w = 0; w < D; ++w) dst[w] = out[w];
     }
 }
 
@@ -469,11 +497,13 @@ __device__ __forceinline__ void level_permute(uint32_t* dst, const uint32_t* src
 
 // MODE 0: DFT only; 1: forward DFT, then twiddles on the way out; 2: twiddles, then inverse DFT;
 // 3 (bottom level, no twiddles): forward DFT, componentwise products with bpoly, inverse DFT.
-template <int L, int MODE>
+// ENC (top forward level): the columns are encoded from operand `which` of PA's product instead
+// of being read from poly.
+template <int L, int MODE, bool ENC>
 __global__ __launch_bounds__(kThreads) void k_level(uint32_t* __restrict__ poly0, long long stride,
                                                     const uint32_t* __restrict__ table, LevelArgs A,
                                                     QConst Q, const uint32_t* __restrict__ bpoly0,
-                                                    int squaring) {
+                                                    int squaring, ProdArgs PA, int which, long long M) {
     constexpr int D = Dig<L>::D;
     A.mode = MODE;
     uint32_t* __restrict__ poly = poly0 + (size_t)blockIdx.y * stride;
@@ -490,7 +520,12 @@ __global__ __launch_bounds__(kThreads) void k_level(uint32_t* __restrict__ poly0
     // round 0's operand: before the column loads (mode 2, needed first) or after them, so that
     // its latency hides behind the DFT (modes 1 and 3)
     if (MODE == 2) tw_fetch<L>(f, 0, table, A, c0);
-    level_copy_in<L>(cur, poly, A, c0);
+    if (ENC) {
+        const ProdDesc pd = PA.get();
+        level_encode_in<L>(cur, which ? pd.b : pd.a, which ? pd.blen : pd.alen, pd.u, M, A, c0);
+    } else {
+        level_copy_in<L>(cur, poly, A, c0);
+    }
     if (MODE == 1) tw_fetch<L>(f, 0, table, A, c0);
     if (MODE == 3) pw_fetch<L>(f, 0, bpoly, A, c0);
     __syncthreads();
@@ -1464,8 +1499,11 @@ struct Transform {
     // fused (forward): the bottom level also multiplies componentwise by bpoly (poly itself if
     // squaring, (2M)^-1 included) and runs the bottom inverse level, so the inverse transform
     // that follows starts one level up (fused = 1 there too).
+    // enc (forward): the top level encodes operand `which` of the products in *enc itself (Step 4
+    // fused in; in_words: operand limbs read, for the byte count).
     static int run(const Call& c, uint32_t* poly, size_t stride, unsigned G, int inverse, hipStream_t s,
-                   int fused = 0, const uint32_t* bpoly = nullptr, int squaring = 0) {
+                   int fused = 0, const uint32_t* bpoly = nullptr, int squaring = 0,
+                   const ProdArgs* enc = nullptr, int which = 0, double in_words = 0.0) {
         const Plan& P = c.P;
         const long long twoM = 2LL << P.log2_M;
         const int m = P.m();
@@ -1515,27 +1553,37 @@ struct Transform {
             const unsigned blocks = (unsigned)(ncols >> log2C);
             const double nprod = tw ? (double)(twoM / n_lvl[k]) * (r - 1) * (mu[k] - 1) : 0.0;
             const uint32_t* tab = (const uint32_t*)c.C->d_table;
+            const bool ec = enc && !inverse && k == 0;         // encode fused into the top level
+            const ProdArgs PA = ec ? *enc : ProdArgs{};
+            const long long M = twoM / 2;
+            const double Sb = (double)G * twoM * m * L * 4;   // one polynomial set, limb form
+            const double in_b = ec ? Sb + 4.0 * in_words : 2.0 * Sb;   // bytes: read + write
+            const uint32_t* bp = pw ? bpoly : nullptr;
+            const int sq = pw ? squaring : 0;
+#define DKSS_LEVEL(MD, EC)                                                                          \
+    hipLaunchKernelGGL((k_level<L, MD, EC>), dim3(blocks, G), dim3(kThreads), lds, s, poly, (long long)stride, \
+                       tab, A, Q, bp, sq, PA, which, M)
             if (pw) {
                 // algorithmic work: a and b read, the product written; 2M products in R and
                 // 2M m scalar products for the (2M)^-1
-                ProfScope ps(c.prof, DKSS_K_POINTWISE, s, 3.0 * G * twoM * m * L * 4,
+                ProfScope ps(c.prof, DKSS_K_POINTWISE, s, ec ? Sb + 4.0 * in_words + Sb : 3.0 * Sb,
                              (double)G * twoM * ((double)m * m * L * L + (double)m * L * L));
-                hipLaunchKernelGGL((k_level<L, 3>), dim3(blocks, G), dim3(kThreads), lds, s, poly,
-                                   (long long)stride, tab, A, Q, bpoly, squaring);
+                if (ec) DKSS_LEVEL(3, true);
+                else DKSS_LEVEL(3, false);
                 return launch_status();
             }
-            ProfScope ps(c.prof, tw ? (inverse ? DKSS_K_TWIDDLE_INV : DKSS_K_TWIDDLE) : DKSS_K_DFT, s,
-                         2.0 * G * twoM * m * L * 4,
+            ProfScope ps(c.prof, tw ? (inverse ? DKSS_K_TWIDDLE_INV : DKSS_K_TWIDDLE) : DKSS_K_DFT, s, in_b,
                          (double)G * nprod * (double)m * m * L * L);
-            if (A.mode == 0)
-                hipLaunchKernelGGL((k_level<L, 0>), dim3(blocks, G), dim3(kThreads), lds, s, poly,
-                                   (long long)stride, tab, A, Q, (const uint32_t*)nullptr, 0);
-            else if (A.mode == 1)
-                hipLaunchKernelGGL((k_level<L, 1>), dim3(blocks, G), dim3(kThreads), lds, s, poly,
-                                   (long long)stride, tab, A, Q, (const uint32_t*)nullptr, 0);
-            else
-                hipLaunchKernelGGL((k_level<L, 2>), dim3(blocks, G), dim3(kThreads), lds, s, poly,
-                                   (long long)stride, tab, A, Q, (const uint32_t*)nullptr, 0);
+            if (A.mode == 0) {
+                if (ec) DKSS_LEVEL(0, true);
+                else DKSS_LEVEL(0, false);
+            } else if (A.mode == 1) {
+                if (ec) DKSS_LEVEL(1, true);
+                else DKSS_LEVEL(1, false);
+            } else {
+                DKSS_LEVEL(2, false);
+            }
+#undef DKSS_LEVEL
             return launch_status();
         };
         int rc;
@@ -1662,18 +1710,16 @@ int run_group(const Call& call, const ProdArgs& PA, unsigned G, size_t nw_max, d
         HIP_OK(hipEventRecord(call.ev_fork, s));
         HIP_OK(hipStreamWaitEvent(sb, call.ev_fork, 0));
     }
-    if (!squaring) {
-        if ((rc = dispatch_L<Encode>(L, call, PA, G, 1, w.B, w.S, in_b, sb))) return rc;
-        if ((rc = dispatch_L<Transform>(L, call, w.B, w.S, G, 0, sb))) return rc;
-    }
+    // the encoding of each operand runs inside the top level of its transform
+    if (!squaring && (rc = dispatch_L<Transform>(L, call, w.B, w.S, G, 0, sb, 0, nullptr, 0, &PA, 1, in_b)))
+        return rc;
     // the componentwise products run inside the bottom level of a's transform (one launch for
     // the last forward level, the products and the first inverse level) unless b is still being
     // transformed on the other stream
     const int fz = (call.fuse_pw && !fork) ? 1 : 0;
     const uint32_t* bp = squaring ? (const uint32_t*)w.A : w.B;
-    if ((rc = dispatch_L<Encode>(L, call, PA, G, 0, w.A, w.S, in_a, s))) return rc;
     if ((rc = dispatch_L<Transform>(L, call, w.A, w.S, G, 0, s, fz, squaring ? nullptr : bp,
-                                    squaring ? 1 : 0)))
+                                    squaring ? 1 : 0, &PA, 0, in_a)))
         return rc;
     if (fork) {
         HIP_OK(hipEventRecord(call.ev_join, sb));
