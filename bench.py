@@ -150,11 +150,12 @@ def batch_bench(count, reps, dk, torch, SI):
     return res
 
 
-def traffic_record(kernel, source_files):
-    """HBM bytes per launch of `kernel` from the committed counter summary, or None when the
-    summary is missing or was taken on other kernel sources (sha256 of source_files)."""
+def traffic_record(kernel, bits, source_files):
+    """HBM bytes per launch of `kernel` in the 2^bits product from the committed counter summary,
+    or None when the summary is missing or was taken on other kernel sources (sha256 of
+    source_files)."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "%s_traffic.txt" % kernel)
+    path = os.path.join(ROOT, "profiles", "%s_dkss_mul_2p%d_traffic.txt" % (kernel, bits))
     if not os.path.exists(path):
         return None
     kv = {}
@@ -258,7 +259,7 @@ def main():
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
                     "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4)}
         work = {"alg_bytes_per_launch": bytes_launch}
-    roofline["traffic"] = traffic_record(dom, KERNEL_SOURCES)
+    roofline["traffic"] = traffic_record(dom, args.bits, KERNEL_SOURCES)
     roofline.update({"kernel": dom, "symbol": symbols.get(dom, dom).replace("%d", str(plan.L))
                      if "%d" in symbols.get(dom, "") else dom,
                      "avg_launch_ms": round(avg_ms, 4), "launches": int(st.launches)})
@@ -271,7 +272,7 @@ def main():
         roofline_fft = {"kernel": "k_dft", "symbol": "k_level<%d, 0>" % plan.L, "bound": "hbm",
                         "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                         "frac": round(gbs / PEAK_HBM_GBS, 4), "avg_launch_ms": round(avg_ms, 4),
-                        "traffic": traffic_record("k_dft", KERNEL_SOURCES)}
+                        "traffic": traffic_record("k_dft", args.bits, KERNEL_SOURCES)}
     kernels = {k: {"launches": int(v.launches), "ms_per_step": round(v.total_ms / args.steps, 4),
                    "avg_launch_ms": round(v.total_ms / v.launches, 4)}
                for k, v in stats.items()}

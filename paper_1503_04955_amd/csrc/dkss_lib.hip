@@ -400,12 +400,13 @@ __device__ __forceinline__ void dft_passes(uint32_t*& cur, uint32_t*& nxt, const
             }
             dmod_add<L>(sv, xv, yv, Q);
             dmod_sub<L>(dv, xv, yv, Q);
-            uint32_t* NX = nxt + cb + xs * EW + jj * D;
-            uint32_t* NY = nxt + cb + ys * EW + jj * D;
+            // a negated y swaps the two outputs: chosen by address, not per digit
+            uint32_t* PS = nxt + cb + (neg ? ys : xs) * EW + jj * D;
+            uint32_t* PD = nxt + cb + (neg ? xs : ys) * EW + jj * D;
 #pragma unroll
             for (int w = 0; w < D; ++w) {
-                NX[w] = neg ? dv[w] : sv[w];
-                NY[w] = neg ? sv[w] : dv[w];
+                PS[w] = sv[w];
+                PD[w] = dv[w];
             }
         }
         __syncthreads();
@@ -1344,6 +1345,13 @@ int plan_constants(dkss_ctx* ctx, Call* call) {
         uint32_t inv = q0;
         for (int i = 0; i < 5; ++i) inv *= 2u - q0 * inv;
         Q.qinv28 = (0u - inv) & kMask28;
+        // sparse form: q = 1 + (digits T and up), T >= 2
+        Q.sparse = 0;
+        if (Q.qd[0] == 1) {
+            int T = 1;
+            while (T < D && Q.qd[T] == 0) ++T;
+            if (T >= 2 && T < D) Q.sparse = T;
+        }
         // R' = 2^(28K) mod q, R'^2 mod q, (2M)^-1 mod q
         Big Rm = mq.reduce(Big::of(1));
         for (int i = 0; i < 28 * K; ++i) Rm = mq.add(Rm, Rm);

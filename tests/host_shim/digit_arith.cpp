@@ -1,0 +1,65 @@
+// Host build of the library's device arithmetic (kernels.hpp is __host__ __device__), so that
+// CPU tests can compare it with Python integers.  Not part of the library.
+#include <cstdint>
+#include <cstring>
+
+#include "../../paper_1503_04955_amd/csrc/kernels.hpp"
+
+using namespace dkss;
+
+namespace {
+
+template <int L>
+void run(int op, const uint32_t* qd, uint32_t qinv, int sparse, const uint32_t* a, const uint32_t* b, int log2m,
+         int j, int r, uint32_t* out) {
+    QConst Q;
+    memset(&Q, 0, sizeof Q);
+    memcpy(Q.qd, qd, sizeof(uint32_t) * Dig<L>::D);
+    Q.qinv28 = qinv;
+    Q.sparse = sparse;
+    switch (op) {
+        case 0: dmod_add<L>(out, a, b, Q); break;
+        case 1: dmod_sub<L>(out, a, b, Q); break;
+        case 2: dneg_q<L>(out, a, Q); break;
+        case 3: rprod_coeff<L>(a, b, log2m, j, r, Q, out); break;
+        case 4: mont_scalar<L>(a, b, Q, out); break;
+        case 5: digits_to_limbs<L>(a, out); break;
+        default: break;
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+int da_D(int L) {
+    switch (L) {
+        case 1: return Dig<1>::D; case 2: return Dig<2>::D; case 3: return Dig<3>::D; case 4: return Dig<4>::D;
+        case 5: return Dig<5>::D; case 6: return Dig<6>::D; case 7: return Dig<7>::D; case 8: return Dig<8>::D;
+    }
+    return -1;
+}
+
+int da_K(int L) {
+    switch (L) {
+        case 1: return Dig<1>::K; case 2: return Dig<2>::K; case 3: return Dig<3>::K; case 4: return Dig<4>::K;
+        case 5: return Dig<5>::K; case 6: return Dig<6>::K; case 7: return Dig<7>::K; case 8: return Dig<8>::K;
+    }
+    return -1;
+}
+
+void da_run(int L, int op, const uint32_t* qd, uint32_t qinv, int sparse, const uint32_t* a, const uint32_t* b,
+            int log2m, int j, int r, uint32_t* out) {
+    switch (L) {
+        case 1: run<1>(op, qd, qinv, sparse, a, b, log2m, j, r, out); break;
+        case 2: run<2>(op, qd, qinv, sparse, a, b, log2m, j, r, out); break;
+        case 3: run<3>(op, qd, qinv, sparse, a, b, log2m, j, r, out); break;
+        case 4: run<4>(op, qd, qinv, sparse, a, b, log2m, j, r, out); break;
+        case 5: run<5>(op, qd, qinv, sparse, a, b, log2m, j, r, out); break;
+        case 6: run<6>(op, qd, qinv, sparse, a, b, log2m, j, r, out); break;
+        case 7: run<7>(op, qd, qinv, sparse, a, b, log2m, j, r, out); break;
+        case 8: run<8>(op, qd, qinv, sparse, a, b, log2m, j, r, out); break;
+    }
+}
+
+}  // extern "C"
