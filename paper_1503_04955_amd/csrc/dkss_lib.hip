@@ -651,8 +651,9 @@ __device__ __forceinline__ long long div_u(long long x, int u, double inv_u) {
     return q;
 }
 
+// poly holds the elements from lbase on (the whole polynomial: lbase 0).
 template <int L>
-__device__ __forceinline__ uint64_t word_sum(long long w, const uint32_t* __restrict__ poly,
+__device__ __forceinline__ uint64_t word_sum(long long w, const uint32_t* __restrict__ poly, long long lbase,
                                              long long twoM, int log2m, int u) {
     constexpr int D = Dig<L>::D;
     const int m = 1 << log2m;
@@ -671,7 +672,7 @@ __device__ __forceinline__ uint64_t word_sum(long long w, const uint32_t* __rest
             const long long l = lmax - t;
             if (l < 0 || l >= twoM) continue;
             const int k = (int)(g - l * hm);
-            const uint32_t* T = poly + ((size_t)l * m + k) * D;
+            const uint32_t* T = poly + ((size_t)(l - lbase) * m + k) * D;
             uint32_t piece;
             if (off >= 0) {
                 const int o = (int)off;                 // below 28 D
@@ -692,14 +693,18 @@ __device__ __forceinline__ uint64_t word_sum(long long w, const uint32_t* __rest
 
 // Per 256 output words: x_w = low(V_w) + high(V_(w-1)) < 2^32 + 2^12, so word w generates a carry
 // (x_w >= 2^32) or propagates one (low 32 bits all ones), never both.  Writes the low 32 bits
-// and the per-wavefront generate / propagate masks.
-template <int L>
+// and the per-wavefront generate / propagate masks.  TILED: the workgroup first copies the
+// elements its words draw on (one contiguous range) into LDS; the host picks it when that range
+// fits (decode_tile_words).
+template <int L, bool TILED>
 __global__ __launch_bounds__(kThreads) void k_decode(ProdArgs PA, const uint32_t* __restrict__ poly0,
                                                      long long stride, long long twoM, int log2m,
                                                      unsigned long long* __restrict__ gmask0,
                                                      unsigned long long* __restrict__ pmask0,
                                                      long long wstride) {
+    constexpr int D = Dig<L>::D;
     __shared__ uint32_t hiv[kThreads + 1];
+    extern __shared__ uint4 dsmv[];
     const ProdDesc pd = PA.get();
     uint32_t* __restrict__ out = pd.c;
     const long long nw = pd.alen + pd.blen;
@@ -709,10 +714,37 @@ __global__ __launch_bounds__(kThreads) void k_decode(ProdArgs PA, const uint32_t
     unsigned long long* __restrict__ pmask = pmask0 + (size_t)blockIdx.y * wstride;
     const long long w0 = (long long)blockIdx.x * kThreads;
     const long long w = w0 + threadIdx.x;
-    const uint64_t V = w < nw ? word_sum<L>(w, poly, twoM, log2m, u) : 0;
+    const uint32_t* src = poly;
+    long long lbase = 0;
+    if (TILED && w0 < nw) {
+        // elements holding the pieces of words w0 - 1 .. min(w0 + 255, nw - 1)
+        const int m = 1 << log2m;
+        const double inv_u = 1.0 / (double)u;
+        const long long wlo = w0 > 0 ? w0 - 1 : 0;
+        const long long whi = (w0 + kThreads - 1 < nw ? w0 + kThreads : nw) - 1;
+        const long long lo_excl = 32 * wlo - 28 * D;
+        const long long g_min = lo_excl < 0 ? 0 : div_u(lo_excl, u, inv_u) + 1;
+        const long long g_max = div_u(32 * whi + 31, u, inv_u);
+        const long long l_min = (g_min >> (log2m - 1)) > 0 ? (g_min >> (log2m - 1)) - 1 : 0;
+        const long long l_top = g_max >> (log2m - 1);
+        const long long l_max = l_top < twoM - 1 ? l_top : twoM - 1;
+        uint32_t* dsm = reinterpret_cast<uint32_t*>(dsmv);
+        const int nwords = (int)((l_max - l_min + 1) * m * D);
+        const uint32_t* g0 = poly + (size_t)l_min * m * D;
+        if (((m * D) & 3) == 0) {
+            const uint4* gv = reinterpret_cast<const uint4*>(g0);
+            for (int t = threadIdx.x; t < (nwords >> 2); t += kThreads) dsmv[t] = gv[t];
+        } else {
+            for (int t = threadIdx.x; t < nwords; t += kThreads) dsm[t] = g0[t];
+        }
+        src = dsm;
+        lbase = l_min;
+    }
+    if (TILED) __syncthreads();
+    const uint64_t V = w < nw ? word_sum<L>(w, src, lbase, twoM, log2m, u) : 0;
     hiv[threadIdx.x + 1] = (uint32_t)(V >> 32);
     if (threadIdx.x == 0)
-        hiv[0] = w0 > 0 ? (uint32_t)(word_sum<L>(w0 - 1, poly, twoM, log2m, u) >> 32) : 0u;
+        hiv[0] = (w0 > 0 && w0 < nw) ? (uint32_t)(word_sum<L>(w0 - 1, src, lbase, twoM, log2m, u) >> 32) : 0u;
     __syncthreads();
     const uint64_t x = (uint64_t)(uint32_t)V + hiv[threadIdx.x];
     const uint32_t y = (uint32_t)x;
@@ -1345,13 +1377,6 @@ int plan_constants(dkss_ctx* ctx, Call* call) {
         uint32_t inv = q0;
         for (int i = 0; i < 5; ++i) inv *= 2u - q0 * inv;
         Q.qinv28 = (0u - inv) & kMask28;
-        // sparse form: q = 1 + (digits T and up), T >= 2
-        Q.sparse = 0;
-        if (Q.qd[0] == 1) {
-            int T = 1;
-            while (T < D && Q.qd[T] == 0) ++T;
-            if (T >= 2 && T < D) Q.sparse = T;
-        }
         // R' = 2^(28K) mod q, R'^2 mod q, (2M)^-1 mod q
         Big Rm = mq.reduce(Big::of(1));
         for (int i = 0; i < 28 * K; ++i) Rm = mq.add(Rm, Rm);
@@ -1638,17 +1663,28 @@ struct Pointwise {
 
 template <int L>
 struct Decode {
+    // u_min: the smallest u of the products (it bounds the elements one workgroup reads)
     static int run(const Call& c, const ProdArgs& PA, unsigned G, size_t nw_max, double out_words,
-                   const Workspace& w, hipStream_t s) {
+                   const Workspace& w, hipStream_t s, int u_min) {
         const long long nwaves = ((long long)nw_max + 63) / 64;
         const unsigned blocks = (unsigned)((nw_max + kThreads - 1) / kThreads);
         const double S = (double)G * (2LL << c.P.log2_M) * c.P.m() * L * 4;
         const long long nseg = (nwaves + kThreads - 1) / kThreads;
         {
             ProfScope ps(c.prof, DKSS_K_DECODE, s, S + 4.0 * out_words, 0.0);
-            hipLaunchKernelGGL(k_decode<L>, dim3(blocks, G), dim3(kThreads), 0, s, PA, (const uint32_t*)w.A,
-                               (long long)w.S, 2LL << c.P.log2_M, c.P.log2_m, w.gmask, w.pmask,
-                               (long long)w.wst);
+            // elements per workgroup: pieces of 257 words span (32*257 + 28D + 31)/u + 2 values of
+            // g, each element m/2 of them, plus one element on either side
+            const int m = c.P.m(), D = Dig<L>::D;
+            const long long gspan = (32LL * (kThreads + 1) + 28 * D + 31) / std::max(u_min, 1) + 2;
+            const long long tile_words = (gspan / (m / 2) + 3) * m * D;
+            if (u_min >= 1 && tile_words * 4 <= 32768)
+                hipLaunchKernelGGL((k_decode<L, true>), dim3(blocks, G), dim3(kThreads), tile_words * 4, s, PA,
+                                   (const uint32_t*)w.A, (long long)w.S, 2LL << c.P.log2_M, c.P.log2_m,
+                                   w.gmask, w.pmask, (long long)w.wst);
+            else
+                hipLaunchKernelGGL((k_decode<L, false>), dim3(blocks, G), dim3(kThreads), 0, s, PA,
+                                   (const uint32_t*)w.A, (long long)w.S, 2LL << c.P.log2_M, c.P.log2_m,
+                                   w.gmask, w.pmask, (long long)w.wst);
         }
         if (int rc_ = launch_status()) return rc_;
         {
@@ -1708,7 +1744,7 @@ int prepare_call(dkss_ctx* ctx, size_t alen, size_t blen, const dkss_params* p, 
 // The DKSS pipeline (Steps 4-8) for G products sharing call's plan, described by PA; the
 // workspace w holds their polynomials at stride w.S.  With squaring, b is not transformed.
 int run_group(const Call& call, const ProdArgs& PA, unsigned G, size_t nw_max, double in_a, double in_b,
-              double out_w, bool squaring, const Workspace& w, hipStream_t s) {
+              double out_w, bool squaring, const Workspace& w, hipStream_t s, int u_min) {
     const int L = call.P.L;
     int rc;
     // the transform of b on the auxiliary stream (forked from s, joined back before the products)
@@ -1735,7 +1771,7 @@ int run_group(const Call& call, const ProdArgs& PA, unsigned G, size_t nw_max, d
     }
     if (!fz && (rc = dispatch_L<Pointwise>(L, call, w.A, bp, w.S, G, s))) return rc;
     if ((rc = dispatch_L<Transform>(L, call, w.A, w.S, G, 1, s, fz))) return rc;
-    return dispatch_L<Decode>(L, call, PA, G, nw_max, out_w, w, s);
+    return dispatch_L<Decode>(L, call, PA, G, nw_max, out_w, w, s, u_min);
 }
 
 int launch_zero(const ProdArgs& PA, unsigned G, size_t nw_max, hipStream_t s) {
@@ -1764,7 +1800,7 @@ int run_mul(const Call& call, uint32_t* c, const uint32_t* a, size_t alen, const
     if (ws == nullptr || ((uintptr_t)ws & 255)) return DKSS_EINVAL;
     Workspace w = layout(call.P, 1, nw, !squaring, (char*)ws);
     if (ws_bytes < w.bytes) return DKSS_ENOSPC;
-    return run_group(call, PA, 1, nw, (double)alen, (double)blen, (double)nw, squaring, w, s);
+    return run_group(call, PA, 1, nw, (double)alen, (double)blen, (double)nw, squaring, w, s, call.P.u);
 }
 
 // A batch, planned: products grouped by plan (zero products, schoolbook products, and one group
@@ -1774,6 +1810,7 @@ struct BatchPlan {
         int kind;                  // 0 zero, 1 schoolbook, 2 DKSS
         size_t first, count;       // range in order
         size_t nw_max;
+        int u_min = 0;             // smallest u of the group's products
         double in_a, in_b, out_w, ops;
         Call call;
     };
@@ -1824,6 +1861,8 @@ int plan_batch(dkss_ctx* ctx, size_t count, const size_t* alen, const size_t* bl
                 const size_t i = idx[k];
                 B->order.push_back(i);
                 g.nw_max = std::max(g.nw_max, alen[i] + blen[i]);
+                const int ui = B->calls[i].P.u;
+                g.u_min = g.u_min ? std::min(g.u_min, ui) : ui;
                 g.in_a += (double)alen[i];
                 g.in_b += (double)blen[i];
                 g.out_w += (double)(alen[i] + blen[i]);
@@ -2185,7 +2224,7 @@ static int enqueue_batch(const BatchPlan& B, void* ws, Prof* prof, hipStream_t s
             rc = launch_schoolbook(call, PA, G, g.nw_max, g.ops, st);
         } else {
             Workspace w = layout(call.P, G, g.nw_max, true, gws);
-            rc = run_group(call, PA, G, g.nw_max, g.in_a, g.in_b, g.out_w, false, w, st);
+            rc = run_group(call, PA, G, g.nw_max, g.in_a, g.in_b, g.out_w, false, w, st, g.u_min);
         }
         if (rc) return rc;
     }

@@ -25,8 +25,6 @@ struct QConst {
     uint32_t qd[kMaxD + 2];  // q in 28-bit digits
     uint32_t qinv28;         // -q^-1 mod 2^28
     uint32_t kpw[kMaxD + 2]; // digits of (2M)^-1 R'^2 mod q: rescales a pointwise product
-    int sparse;              // T >= 2 if q = 1 + (digits T.. only), as for p = h 2^n + 1 with a
-                             // small h and z = 1; else 0
 };
 
 template <int L>
@@ -148,27 +146,13 @@ __host__ __device__ __forceinline__ void digits_to_limbs(const uint32_t* d, uint
 template <int L>
 __host__ __device__ __forceinline__ void redc_cols(uint64_t* col, const QConst& Q, uint32_t* x) {
     using G = Dig<L>;
-    if (Q.sparse) {
-        // q = 1 + sum_{y >= T} q_y 2^(28y): then -q^-1 = -1 mod 2^28, and the digits 1 .. T-1
-        // of q add nothing
 #pragma unroll
-        for (int i = 0; i < G::K; ++i) {
-            const uint32_t u = (0u - (uint32_t)col[i]) & kMask28;
-            col[i] += u;
+    for (int i = 0; i < G::K; ++i) {
+        uint32_t s = (uint32_t)col[i] & kMask28;
+        uint32_t u = (s * Q.qinv28) & kMask28;
 #pragma unroll
-            for (int y = 1; y < G::D; ++y)
-                if (y >= Q.sparse) col[i + y] += (uint64_t)u * Q.qd[y];
-            col[i + 1] += col[i] >> 28;
-        }
-    } else {
-#pragma unroll
-        for (int i = 0; i < G::K; ++i) {
-            uint32_t s = (uint32_t)col[i] & kMask28;
-            uint32_t u = (s * Q.qinv28) & kMask28;
-#pragma unroll
-            for (int y = 0; y < G::D; ++y) col[i + y] += (uint64_t)u * Q.qd[y];
-            col[i + 1] += col[i] >> 28;
-        }
+        for (int y = 0; y < G::D; ++y) col[i + y] += (uint64_t)u * Q.qd[y];
+        col[i + 1] += col[i] >> 28;
     }
     // the result (< 2q < 2^(28D)) sits in columns K .. K+D-1
     uint64_t carry = 0;

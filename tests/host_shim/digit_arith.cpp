@@ -10,13 +10,12 @@ using namespace dkss;
 namespace {
 
 template <int L>
-void run(int op, const uint32_t* qd, uint32_t qinv, int sparse, const uint32_t* a, const uint32_t* b, int log2m,
+void run(int op, const uint32_t* qd, uint32_t qinv, const uint32_t* a, const uint32_t* b, int log2m,
          int j, int r, uint32_t* out) {
     QConst Q;
     memset(&Q, 0, sizeof Q);
     memcpy(Q.qd, qd, sizeof(uint32_t) * Dig<L>::D);
     Q.qinv28 = qinv;
-    Q.sparse = sparse;
     switch (op) {
         case 0: dmod_add<L>(out, a, b, Q); break;
         case 1: dmod_sub<L>(out, a, b, Q); break;
@@ -48,17 +47,17 @@ int da_K(int L) {
     return -1;
 }
 
-void da_run(int L, int op, const uint32_t* qd, uint32_t qinv, int sparse, const uint32_t* a, const uint32_t* b,
+void da_run(int L, int op, const uint32_t* qd, uint32_t qinv, const uint32_t* a, const uint32_t* b,
             int log2m, int j, int r, uint32_t* out) {
     switch (L) {
-        case 1: run<1>(op, qd, qinv, sparse, a, b, log2m, j, r, out); break;
-        case 2: run<2>(op, qd, qinv, sparse, a, b, log2m, j, r, out); break;
-        case 3: run<3>(op, qd, qinv, sparse, a, b, log2m, j, r, out); break;
-        case 4: run<4>(op, qd, qinv, sparse, a, b, log2m, j, r, out); break;
-        case 5: run<5>(op, qd, qinv, sparse, a, b, log2m, j, r, out); break;
-        case 6: run<6>(op, qd, qinv, sparse, a, b, log2m, j, r, out); break;
-        case 7: run<7>(op, qd, qinv, sparse, a, b, log2m, j, r, out); break;
-        case 8: run<8>(op, qd, qinv, sparse, a, b, log2m, j, r, out); break;
+        case 1: run<1>(op, qd, qinv, a, b, log2m, j, r, out); break;
+        case 2: run<2>(op, qd, qinv, a, b, log2m, j, r, out); break;
+        case 3: run<3>(op, qd, qinv, a, b, log2m, j, r, out); break;
+        case 4: run<4>(op, qd, qinv, a, b, log2m, j, r, out); break;
+        case 5: run<5>(op, qd, qinv, a, b, log2m, j, r, out); break;
+        case 6: run<6>(op, qd, qinv, a, b, log2m, j, r, out); break;
+        case 7: run<7>(op, qd, qinv, a, b, log2m, j, r, out); break;
+        case 8: run<8>(op, qd, qinv, a, b, log2m, j, r, out); break;
     }
 }
 

@@ -1,7 +1,7 @@
 """The library's digit arithmetic (paper_1503_04955_amd/csrc/kernels.hpp, compiled for the host)
 against Python integers: modular add/sub/negation, one coefficient of a product in R with a
 rotation by alpha^r (Sec. 3.2.5, the bad multiplications with the power trick of Sec. 4.2),
-Montgomery scaling, limb conversion; generic and sparse (p = h 2^n + 1) moduli."""
+Montgomery scaling, limb conversion; random odd moduli and moduli p = h 2^n + 1."""
 import ctypes
 import os
 import random
@@ -24,7 +24,7 @@ def da(tmp_path_factory):
     assert res.returncode == 0, res.stderr[-3000:]
     lib = ctypes.CDLL(out)
     P = ctypes.POINTER(ctypes.c_uint32)
-    lib.da_run.argtypes = [ctypes.c_int, ctypes.c_int, P, ctypes.c_uint32, ctypes.c_int, P, P,
+    lib.da_run.argtypes = [ctypes.c_int, ctypes.c_int, P, ctypes.c_uint32, P, P,
                            ctypes.c_int, ctypes.c_int, ctypes.c_int, P]
     return lib
 
@@ -46,25 +46,23 @@ def arr(vals, n=None):
 
 
 def moduli(L, rng):
-    """(q, sparse T) pairs with ceil(bits(q)/32) = L: a random odd one and, where it fits,
-    p = h 2^n + 1 with a small h."""
+    """Moduli q with ceil(bits(q)/32) = L: a random odd one and, where it fits, p = h 2^n + 1
+    with a small h (mostly zero 28-bit digits)."""
     bits = 32 * L
-    out = [(rng.getrandbits(bits) | (1 << (bits - 1)) | 1, 0)]
+    out = [rng.getrandbits(bits) | (1 << (bits - 1)) | 1]
     if bits >= 64:
         for h in (13, 27, 81):
             n = bits - h.bit_length()
             if n >= 56:
-                q = h * (1 << n) + 1
-                T = n // 28
-                out.append((q, T if T >= 2 else 0))
+                out.append(h * (1 << n) + 1)
     return out
 
 
-def call(da, L, op, q, sparse, a, b, D, log2m=1, j=0, r=0, n_out=None):
+def call(da, L, op, q, a, b, D, log2m=1, j=0, r=0, n_out=None):
     K = da.da_K(L)
     qinv = (-pow(q, -1, 1 << 28)) % (1 << 28)
     out = (ctypes.c_uint32 * (n_out or D))()
-    da.da_run(L, op, arr(digits(q, D)), qinv, sparse, a, b, log2m, j, r, out)
+    da.da_run(L, op, arr(digits(q, D)), qinv, a, b, log2m, j, r, out)
     return out, K
 
 
@@ -73,14 +71,14 @@ def test_add_sub_neg(da, L):
     rng = random.Random(100 + L)
     D = da.da_D(L)
     assert (1 << (28 * D)) > 2 * (1 << (32 * L))
-    for q, sp in moduli(L, rng):
+    for q in moduli(L, rng):
         for _ in range(40):
             x, y = rng.randrange(q), rng.randrange(q)
-            o, _ = call(da, L, 0, q, sp, arr(digits(x, D)), arr(digits(y, D)), D)
+            o, _ = call(da, L, 0, q, arr(digits(x, D)), arr(digits(y, D)), D)
             assert value(o) == (x + y) % q
-            o, _ = call(da, L, 1, q, sp, arr(digits(x, D)), arr(digits(y, D)), D)
+            o, _ = call(da, L, 1, q, arr(digits(x, D)), arr(digits(y, D)), D)
             assert value(o) == (x - y) % q
-            o, _ = call(da, L, 2, q, sp, arr(digits(x, D)), arr(digits(0, D)), D)
+            o, _ = call(da, L, 2, q, arr(digits(x, D)), arr(digits(0, D)), D)
             assert value(o) == q - x
 
 
@@ -92,7 +90,7 @@ def test_ring_product_coefficient(da, L, log2m):
     rng = random.Random(1000 * L + log2m)
     D = da.da_D(L)
     m = 1 << log2m
-    for q, sp in moduli(L, rng):
+    for q in moduli(L, rng):
         K = da.da_K(L)
         Rinv = pow(1 << (28 * K), -1, q)
         for _ in range(6):
@@ -112,7 +110,7 @@ def test_ring_product_coefficient(da, L, log2m):
                 ax[k % m] = (ax[k % m] + sgn * x[i]) % q
             for j in range(m):
                 want = sum(t[i] * ax[(j - i) % m] * (1 if j >= i else -1) for i in range(m)) % q
-                o, _ = call(da, L, 3, q, sp, arr(TP), arr(X), D, log2m, j, r)
+                o, _ = call(da, L, 3, q, arr(TP), arr(X), D, log2m, j, r)
                 assert value(o) == want * Rinv % q, (q, j, r)
 
 
@@ -120,20 +118,12 @@ def test_ring_product_coefficient(da, L, log2m):
 def test_montgomery_scalar_and_limbs(da, L):
     rng = random.Random(7 + L)
     D = da.da_D(L)
-    for q, sp in moduli(L, rng):
+    for q in moduli(L, rng):
         K = da.da_K(L)
         Rinv = pow(1 << (28 * K), -1, q)
         for _ in range(30):
             x, k = rng.randrange(q), rng.randrange(q)
-            o, _ = call(da, L, 4, q, sp, arr(digits(x, D)), arr(digits(k, D)), D)
+            o, _ = call(da, L, 4, q, arr(digits(x, D)), arr(digits(k, D)), D)
             assert value(o) == x * k * Rinv % q
-            o, _ = call(da, L, 5, q, sp, arr(digits(x, D)), arr(digits(0, D)), D, n_out=L)
+            o, _ = call(da, L, 5, q, arr(digits(x, D)), arr(digits(0, D)), D, n_out=L)
             assert sum(int(o[w]) << (32 * w) for w in range(L)) == x
-
-
-def test_sparse_moduli_are_recognized_by_form():
-    """The sparse path needs q = 1 mod 2^28 with zero digits 1 .. T-1; the thesis's primes
-    (Sec. 4.5) at 128 and 192 bits have that form."""
-    for q in (81 * 2 ** 121 + 1, 13 * 2 ** 188 + 1):
-        ds = digits(q, (q.bit_length() + 28) // 28 + 1)
-        assert ds[0] == 1 and all(v == 0 for v in ds[1:2])
