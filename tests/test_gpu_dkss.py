@@ -116,6 +116,8 @@ MUL = [  # (log2_M, log2_m, u, p_bits, z, radices)
     (7, 3, 64, 192, 1, None),
     (6, 6, 32, 128, 1, None),               # m = 64: radix capped below 2m
     (10, 4, 60, 256, 1, None),              # L = 8
+    (8, 2, 2, 64, 1, None),                 # u = 2: the decode's elements exceed an LDS tile
+    (11, 1, 5, 64, 1, None),                # m = 2, u = 5
 ]
 
 
@@ -317,3 +319,31 @@ def test_batch_graph_replays(env):
     a0, b0 = dk.to_host(as_[5]), dk.to_host(bs[5])
     assert np.array_equal(dk.to_host(call.outs[5]), C.schoolbook(a0, b0))
     graph.close()
+
+
+@pytest.mark.parametrize("opts", [{"fuse": 0}, {"overlap": 1}, {"overlap": 1, "fuse": 0},
+                                  {"lds": 16384}, {"lds": 65536}, {"lds": 163840}])
+def test_context_options_keep_the_bits(env, opts):
+    """The unfused componentwise products (separate k_pointwise, k_encode), the second stream for
+    b and other LDS budgets give the same product, single and batched."""
+    dk, torch, ctx0 = env
+    ctx = dk.Context()
+    names = {"fuse": dk.OPT_FUSE_PW, "overlap": dk.OPT_OVERLAP, "lds": dk.OPT_DFT_LDS}
+    for k, v in opts.items():
+        ctx.set_option(names[k], v)
+    for alen, blen in [(8192, 8192), (30000, 4000), (131072, 131072)]:
+        a, b = SI.operand_pair(alen + 3 * blen, alen, blen)
+        da, db = dk.to_device(a), dk.to_device(b)
+        got = ctx.mul(da, db)
+        want = ctx0.mul(da, db)
+        assert torch.equal(got, want), (opts, alen, blen)
+        sq = ctx.mul(da, da)
+        assert torch.equal(sq, ctx0.mul(da, da)), (opts, alen)
+        if alen * blen < 1e8:
+            assert np.array_equal(dk.to_host(got), C.schoolbook(a, b))
+    lens = SI.batch_lengths(SI.SEED_BASE + 5, 64, hi_bits=18)
+    pairs = [SI.operand_pair(300 + i, al, bl) for i, (al, bl) in enumerate(lens)]
+    as_ = [dk.to_device(x) for x, _ in pairs]
+    bs = [dk.to_device(y) for _, y in pairs]
+    for x, y in zip(ctx.mul_batch(as_, bs), ctx0.mul_batch(as_, bs)):
+        assert torch.equal(x, y), opts
