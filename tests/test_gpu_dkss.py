@@ -347,3 +347,42 @@ def test_context_options_keep_the_bits(env, opts):
     bs = [dk.to_device(y) for _, y in pairs]
     for x, y in zip(ctx.mul_batch(as_, bs), ctx0.mul_batch(as_, bs)):
         assert torch.equal(x, y), opts
+
+
+def test_mul_2e34_thesis_learned_and_square(env):
+    """The largest single product: two 2^34-bit operands (2 GiB each, seeded uniform limbs made
+    on the device) under the thesis rule and under the learned selector, and the squaring of a:
+    residues mod 16 seeded 61-bit primes (a, b and c reduced on the GPU, compared in Python
+    integers); both policies give identical limbs."""
+    dk, torch, _ = env
+    import time
+    n = (1 << 34) // 32
+    g = torch.Generator(device="cuda")
+    g.manual_seed(SI.SEED_BASE + 34)
+    a = torch.randint(-2 ** 31, 2 ** 31, (n,), dtype=torch.int32, device="cuda", generator=g)
+    b = torch.randint(-2 ** 31, 2 ** 31, (n,), dtype=torch.int32, device="cuda", generator=g)
+    qs = _primes61(34, 16)
+    ra, rb = dk.residues(a, qs), dk.residues(b, qs)
+    outs = {}
+    for name, policy in (("thesis", dk.POLICY_THESIS), ("learned", dk.POLICY_LEARNED)):
+        ctx = dk.Context(policy)
+        ws = torch.empty(ctx.workspace_bytes(n, n), dtype=torch.uint8, device="cuda")
+        c = torch.empty(2 * n, dtype=torch.int32, device="cuda")
+        ctx.prepare(n, n)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.mul(a, b, out=c, ws=ws)
+        torch.cuda.synchronize()
+        print("2^34 x 2^34 %s: %.1f ms, params %s" % (name, 1e3 * (time.perf_counter() - t0),
+                                                      ctx.select_params(1 << 34, 1 << 34).as_dict()), flush=True)
+        rc = dk.residues(c, qs)
+        assert all(z == x * y % q for x, y, z, q in zip(ra, rb, rc, qs)), name
+        outs[name] = c
+        if name == "thesis":
+            sq = ctx.mul(a, a, ws=ws)
+            rs = dk.residues(sq, qs)
+            assert all(z == x * x % q for x, z, q in zip(ra, rs, qs))
+            del sq
+        del ws
+        torch.cuda.empty_cache()
+    assert torch.equal(outs["thesis"], outs["learned"])
