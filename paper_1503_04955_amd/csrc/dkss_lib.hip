@@ -364,10 +364,9 @@ __device__ __forceinline__ void dft_passes(uint32_t*& cur, uint32_t*& nxt, const
                                            const QConst& Q) {
     constexpr int D = Dig<L>::D;
     const int m = 1 << A.log2m, r = 1 << A.log2r;
-    const int EW = m * D;
     const int tasks = (1 << (A.log2C + A.log2r - 1)) << A.log2m;   // butterflies x coefficients
     for (int h = 1, lh = 0; h < r; h <<= 1, ++lh) {
-        const int mh = m >> lh;
+        const int lmh = A.log2m - lh;                   // log2(m/h)
         for (int t = threadIdx.x; t < tasks; t += kThreads) {
             const int jj = t & (m - 1);
             const int rest = t >> A.log2m;
@@ -376,7 +375,7 @@ __device__ __forceinline__ void dft_passes(uint32_t*& cur, uint32_t*& nxt, const
             const int kk = bf & (h - 1);
             const int xs = ((bf - kk) << 1) + kk;
             const int ys = xs + h;
-            int e = kk * mh;
+            int e = kk << lmh;
             if (inverse) e = (2 * m - e) & (2 * m - 1);
             // (alpha^e y)_jj = +- y_idx, negated once per wrap past degree m-1
             int idx = jj - e;
@@ -389,9 +388,11 @@ __device__ __forceinline__ void dft_passes(uint32_t*& cur, uint32_t*& nxt, const
                     neg = false;
                 }
             }
-            const int cb = (c << A.log2r) * EW;
-            const uint32_t* X = cur + cb + xs * EW + jj * D;
-            const uint32_t* Y = cur + cb + ys * EW + idx * D;
+            // coefficient slots (element * m + coefficient), D words each; 24-bit products
+            const int ex = ((c << A.log2r) + xs) << A.log2m;
+            const int ey = ((c << A.log2r) + ys) << A.log2m;
+            const uint32_t* X = cur + __umul24(ex + jj, D);
+            const uint32_t* Y = cur + __umul24(ey + idx, D);
             uint32_t xv[D], yv[D], sv[D], dv[D];
 #pragma unroll
             for (int w = 0; w < D; ++w) {
@@ -401,13 +402,12 @@ __device__ __forceinline__ void dft_passes(uint32_t*& cur, uint32_t*& nxt, const
             dmod_add<L>(sv, xv, yv, Q);
             dmod_sub<L>(dv, xv, yv, Q);
             // a negated y swaps the two outputs: chosen by address, not per digit
-            uint32_t* PS = nxt + cb + (neg ? ys : xs) * EW + jj * D;
-            uint32_t* PD = nxt + cb + (neg ? xs : ys) * EW + jj * D;
+            uint32_t* PS = nxt + __umul24((neg ? ey : ex) + jj, D);
+            uint32_t* PD = nxt + __umul24((neg ? ex : ey) + jj, D);
 #pragma unroll
-            for (int w = 0; w < D; ++w) {
-                PS[w] = sv[w];
-                PD[w] = dv[w];
-            }
+            for (int w = 0; w < D; ++w) PS[w] = sv[w];
+#pragma unroll
+            for (int w = 0; w < D; ++w) PD[w] = dv[w];
         }
         __syncthreads();
         uint32_t* tmp = cur;
