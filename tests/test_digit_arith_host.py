@@ -127,3 +127,24 @@ def test_montgomery_scalar_and_limbs(da, L):
             assert value(o) == x * k * Rinv % q
             o, _ = call(da, L, 5, q, arr(digits(x, D)), arr(digits(0, D)), D, n_out=L)
             assert sum(int(o[w]) << (32 * w) for w in range(L)) == x
+
+
+@pytest.mark.parametrize("L,log2m", [(1, 6), (2, 6), (5, 5), (6, 4), (6, 5), (6, 6), (7, 6), (8, 6)])
+def test_ring_product_coefficient_extreme_digits(da, L, log2m):
+    """Largest canonical digits: q = 2^(32L) - 1 (every 28-bit digit of q - 1 at or near its
+    maximum) and t_i = x_i = q - 1 for every i, with no wrap (j = m - 1, r = 0), so that every
+    column receives the most and the largest digit products; for degrees m up to 64."""
+    D = da.da_D(L)
+    m = 1 << log2m
+    q = (1 << (32 * L)) - 1
+    K = da.da_K(L)
+    Rinv = pow(1 << (28 * K), -1, q)
+    v = q - 1
+    TP = digits(v, D) * m + digits(1, D) * m
+    X = digits(v, D) * m
+    o, _ = call(da, L, 3, q, arr(TP), arr(X), D, log2m, m - 1, 0)
+    assert value(o) == m * v * v % q * Rinv % q
+    # and with every term wrapped (negated): r = m gives x_(j-i-m) = -x_(j-i)
+    TPn = digits(1, D) * m + digits(v, D) * m
+    o, _ = call(da, L, 3, q, arr(TPn), arr(X), D, log2m, m - 1, m)
+    assert value(o) == m * v * v % q * Rinv % q
