@@ -180,107 +180,32 @@ __host__ __device__ __forceinline__ void normalize_cols(uint64_t* col) {
 // (alpha^r x)_(j-i) = +- x_((j-i-r) mod m), negative when (j-i-r) mod 2m >= m; the sign is moved
 // onto t: TP holds t_0..t_(m-1) followed by q-t_0..q-t_(m-1).  X holds x_0..x_(m-1).
 // Returns c_j 2^(-28K) mod q in digits.
-//
-// Each digit product t_i x_(.) is split once in Karatsuba's way: with the digits cut at D0,
-// t = t0 + t1 B, x = x0 + x1 B (B = 2^(28 D0)), the column sums of t0 x0, t1 x1 and
-// (t0 + t1)(x0 + x1) (digit-wise sums, no carries) are accumulated over i in three arrays, and
-// t x = P0 + (Pm - P0 - P1) B + P1 B^2 is formed once at the end: D0^2 + D1^2 + D0^2 multiply-adds
-// per term instead of D^2.  Column by column Pm - P0 - P1 is a sum of products, hence never
-// negative; the combination is done in signed 64-bit columns and normalized.
-template <int L>
-struct Kara {
-    static constexpr int D = Dig<L>::D;
-    static constexpr int D0 = (D + 1) / 2, D1 = D - D0;
-    static constexpr int N0 = 2 * D0, N1 = 2 * D1 > 0 ? 2 * D1 : 1;     // columns incl. one for carries
-    // terms per normalization: D0 products of at most (2^29 - 2)^2 per column and term, on top of
-    // a normalized column (< 2^28), below 2^64
-    static constexpr uint64_t kMaxSum = ((~0ull) - (1ull << 28)) / ((uint64_t)D0 * ((1ull << 29) - 2) * ((1ull << 29) - 2));
-    static constexpr int NI = (int)kMaxSum;
-};
-
-template <int N>
-__host__ __device__ __forceinline__ void normalize_n(uint64_t* col) {
-#pragma unroll
-    for (int k = 0; k + 1 < N; ++k) {
-        col[k + 1] += col[k] >> 28;
-        col[k] &= kMask28;
-    }
-}
-
 template <int L>
 __host__ __device__ __forceinline__ void rprod_coeff(const uint32_t* TP, const uint32_t* X, int log2m, int j,
                                             int r, const QConst& Q, uint32_t* out) {
     using G = Dig<L>;
-    using KA = Kara<L>;
-    constexpr int D = G::D, D0 = KA::D0, D1 = KA::D1;
     const int m = 1 << log2m;
     const int mask2 = 2 * m - 1;
-    uint64_t c0[KA::N0], c1[KA::N1], cm[KA::N0];
+    uint64_t col[G::NC];
 #pragma unroll
-    for (int k = 0; k < KA::N0; ++k) c0[k] = cm[k] = 0;
-#pragma unroll
-    for (int k = 0; k < KA::N1; ++k) c1[k] = 0;
+    for (int k = 0; k < G::NC; ++k) col[k] = 0;
     int idx = (j - r) & mask2;
     for (int i = 0; i < m; ++i) {
         const int ti = i + (idx & m);               // the wrap's sign selects t or q - t
         const int xi = idx & (m - 1);
-        uint32_t tv[D], xv[D], ts[D0], xs[D0];
+        uint32_t tv[G::D], xv[G::D];
 #pragma unroll
-        for (int x = 0; x < D; ++x) {
-            tv[x] = TP[ti * D + x];
-            xv[x] = X[xi * D + x];
+        for (int x = 0; x < G::D; ++x) {
+            tv[x] = TP[ti * G::D + x];
+            xv[x] = X[xi * G::D + x];
         }
 #pragma unroll
-        for (int x = 0; x < D0; ++x) {
-            ts[x] = tv[x] + (x < D1 ? tv[D0 + x] : 0u);
-            xs[x] = xv[x] + (x < D1 ? xv[D0 + x] : 0u);
-        }
+        for (int x = 0; x < G::D; ++x)
 #pragma unroll
-        for (int x = 0; x < D0; ++x)
-#pragma unroll
-            for (int y = 0; y < D0; ++y) {
-                c0[x + y] += (uint64_t)tv[x] * xv[y];
-                cm[x + y] += (uint64_t)ts[x] * xs[y];
-            }
-#pragma unroll
-        for (int x = 0; x < D1; ++x)
-#pragma unroll
-            for (int y = 0; y < D1; ++y) c1[x + y] += (uint64_t)tv[D0 + x] * xv[D0 + y];
+            for (int y = 0; y < G::D; ++y) col[x + y] += (uint64_t)tv[x] * xv[y];
         idx = (idx - 1) & mask2;
-        if ((i + 1) % KA::NI == 0 && i + 1 < m) {        // the last batch is normalized below
-            normalize_n<KA::N0>(c0);
-            normalize_n<KA::N0>(cm);
-            normalize_n<KA::N1>(c1);
-        }
+        if ((i + 1) % G::NI == 0) normalize_cols<L>(col);
     }
-    // t x = P0 + (Pm - P0 - P1) B + P1 B^2, in signed columns (each array normalized first, so
-    // that every column is far below 2^63), then normalized
-    normalize_n<KA::N0>(c0);
-    normalize_n<KA::N0>(cm);
-    normalize_n<KA::N1>(c1);
-    int64_t sc[G::NC];
-#pragma unroll
-    for (int k = 0; k < G::NC; ++k) sc[k] = 0;
-#pragma unroll
-    for (int k = 0; k < KA::N0; ++k) {
-        sc[k] += (int64_t)c0[k];
-        sc[k + D0] += (int64_t)cm[k] - (int64_t)c0[k];
-    }
-#pragma unroll
-    for (int k = 0; k < KA::N1; ++k) {
-        if (D1 == 0) break;
-        sc[k + D0] -= (int64_t)c1[k];
-        sc[k + 2 * D0] += (int64_t)c1[k];
-    }
-    uint64_t col[G::NC];
-    int64_t carry = 0;
-#pragma unroll
-    for (int k = 0; k < G::NC; ++k) {
-        const int64_t v = sc[k] + carry;
-        col[k] = (uint64_t)(v & (int64_t)kMask28);
-        carry = v >> 28;                            // arithmetic: floor division
-    }
-    col[G::NC - 1] += (uint64_t)carry << 28;        // the value is below 2^(28 NC); carry is 0
     redc_cols<L>(col, Q, out);
 }
 
