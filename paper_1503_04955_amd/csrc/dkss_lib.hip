@@ -158,18 +158,20 @@ __global__ __launch_bounds__(kThreads) void k_encode(ProdArgs PA, int which, uin
 //           multiplications of Sec. 3.2.5 ii) on its way back to HBM;
 //   mode 2 (inverse): loads, multiplies input v by rho^-(base l v), runs the DFT with alpha^-1,
 //           stores.
-// The DFT: inputs in bit-reversed LDS slots, log2 r radix-2 decimation-in-time passes between two
-// LDS buffers; the pass merging halves of h points multiplies the odd half by alpha^((m/h) k),
-// k < h (alpha^-((m/h) k) for the inverse).  Output v ends in slot v.  Twiddle products run in
-// rounds of 256/m elements, one output coefficient per thread: the element's digits are read in
-// place from the column buffer, the table entry rho^s (with its negation, Montgomery form) is
-// staged in the free buffer.
+// The DFT works on 32-bit limbs (additions with the hardware carry): inputs in bit-reversed LDS
+// slots, log2 r radix-2 decimation-in-time passes between the two halves of the workgroup's LDS;
+// the pass merging halves of h points multiplies the odd half by alpha^((m/h) k), k < h
+// (alpha^-((m/h) k) for the inverse).  Output v ends in slot v.  Products in R work on 28-bit
+// digits (HBM holds digits): the columns are converted in LDS between the two forms.  Twiddle
+// products run in rounds of 256/m elements, one output coefficient per thread: the element's
+// digits are read in place, the table entry rho^s (with its negation, Montgomery form) is staged
+// in the other half.
 struct LevelArgs {
     long long twoM, base, mu_top;
     int log2mut;                  // log2 mu_top
     int log2nl, log2mu, log2r, log2m, log2C;
     int mode, inverse;
-    int rb_separate;              // 1: the twiddle staging area follows both column buffers
+    int half;                     // words of each of the two LDS halves
 };
 
 __device__ __forceinline__ long long level_pos(const LevelArgs& A, long long c0, int c, int j) {
@@ -178,11 +180,13 @@ __device__ __forceinline__ long long level_pos(const LevelArgs& A, long long c0,
     return (b << A.log2nl) + ((long long)j << A.log2mu) + l;
 }
 
-// Copies between the workgroup's C r elements in HBM and LDS.  Element index e: column c
+// Copies between the workgroup's C r elements in HBM (digits) and LDS.  Element index e: column c
 // fastest, then position j; LDS slot bitrev(j) on the way in, slot v on the way out.
+
+// digits into LDS, digit layout (the twiddles of an inverse level come first)
 template <int L>
-__device__ __forceinline__ void level_copy_in(uint32_t* cur, const uint32_t* __restrict__ poly,
-                                              const LevelArgs& A, long long c0) {
+__device__ __forceinline__ void level_load_digits(uint32_t* cur, const uint32_t* __restrict__ poly,
+                                                  const LevelArgs& A, long long c0) {
     constexpr int D = Dig<L>::D;
     const int EW = D << A.log2m;
     const int nel = 1 << (A.log2C + A.log2r);
@@ -211,54 +215,128 @@ __device__ __forceinline__ void level_copy_in(uint32_t* cur, const uint32_t* __r
     }
 }
 
-// The top forward level's columns straight from the operand (Step 4 fused into the first level):
-// element at position j of a column into slot bitrev(j), as level_copy_in would load it.
+// digits into LDS as limbs (one coefficient per thread and step)
 template <int L>
-__device__ __forceinline__ void level_encode_in(uint32_t* cur, const uint32_t* __restrict__ a, long long alen,
-                                                int u, long long M, const LevelArgs& A, long long c0) {
+__device__ __forceinline__ void level_load_limbs(uint32_t* cur, const uint32_t* __restrict__ poly,
+                                                 const LevelArgs& A, long long c0) {
     constexpr int D = Dig<L>::D;
-    const int EW = D << A.log2m;
     const int nel = 1 << (A.log2C + A.log2r);
     for (int t = threadIdx.x; t < (nel << A.log2m); t += kThreads) {
         const int e = t >> A.log2m, k = t & ((1 << A.log2m) - 1);
         const int c = e & ((1 << A.log2C) - 1), j = e >> A.log2C;
-        uint32_t out[D];
-        encode_digits<L>(a, alen, u, level_pos(A, c0, c, j), k, M, A.log2m, out);
-        uint32_t* dst = cur + ((c << A.log2r) + bitrev(j, A.log2r)) * EW + k * D;
+        const uint32_t* src = poly + ((size_t)level_pos(A, c0, c, j) << A.log2m) * D + k * D;
+        uint32_t dv[D], x[L];
 #pragma unroll
-        for (int w = 0; w < D; ++w) dst[w] = out[w];
+        for (int w = 0; w < D; ++w) dv[w] = src[w];
+        digits_to_limbs<L>(dv, x);
+        uint32_t* dst = cur + ((((c << A.log2r) + bitrev(j, A.log2r)) << A.log2m) + k) * L;
+#pragma unroll
+        for (int w = 0; w < L; ++w) dst[w] = x[w];
     }
 }
 
+// Coefficient k of element i as limbs: bits [u (i m/2 + k), u (i m/2 + k) + u) of a for k < m/2
+// and i < M; zero otherwise (encode_digits in limb form).
 template <int L>
-__device__ __forceinline__ void level_copy_out(uint32_t* __restrict__ poly, const uint32_t* cur,
-                                               const LevelArgs& A, long long c0) {
-    constexpr int D = Dig<L>::D;
-    const int EW = D << A.log2m;
-    const int nel = 1 << (A.log2C + A.log2r);
-    if ((EW & 3) == 0) {
-        const int EV = EW >> 2;
-        const int total = nel * EV;
-        const uint4* cv = reinterpret_cast<const uint4*>(cur);
-        uint4* gv = reinterpret_cast<uint4*>(poly);
-#pragma unroll 4
-        for (int t = threadIdx.x; t < total; t += kThreads) {
-            const int e = ((t << 2) >> A.log2m) / D;
-            const int wk = t - e * EV;
-            const int c = e & ((1 << A.log2C) - 1), v = e >> A.log2C;
-            const long long pos = level_pos(A, c0, c, v);
-            gv[(size_t)pos * EV + wk] = cv[((c << A.log2r) + v) * EV + wk];
-        }
-    } else {
-        const int total = nel * EW;
-        for (int t = threadIdx.x; t < total; t += kThreads) {
-            const int e = (t >> A.log2m) / D;
-            const int wk = t - e * EW;
-            const int c = e & ((1 << A.log2C) - 1), v = e >> A.log2C;
-            const long long pos = level_pos(A, c0, c, v);
-            poly[(size_t)pos * EW + wk] = cur[((c << A.log2r) + v) * EW + wk];
+__device__ __forceinline__ void encode_limbs(const uint32_t* __restrict__ a, long long alen, int u, long long i,
+                                             int k, long long M, int log2m, uint32_t* out) {
+    const int hm = 1 << (log2m - 1);
+#pragma unroll
+    for (int w = 0; w < L; ++w) out[w] = 0;
+    if (i < M && k < hm) {
+        const unsigned long long pos = ((unsigned long long)i * hm + k) * (unsigned)u;
+#pragma unroll
+        for (int w = 0; w < L; ++w) {
+            const int nb = u - 32 * w;
+            if (nb > 0) {
+                const unsigned long long bit = pos + 32ull * w;
+                const long long wi = (long long)(bit >> 5);
+                const int sh = (int)(bit & 31);
+                const uint64_t lo = wi < alen ? a[wi] : 0u;
+                const uint64_t hi = wi + 1 < alen ? a[wi + 1] : 0u;
+                uint32_t v = (uint32_t)(((hi << 32) | lo) >> sh);
+                if (nb < 32) v &= (1u << nb) - 1u;
+                out[w] = v;
+            }
         }
     }
+}
+
+// The top forward level's columns straight from the operand (Step 4 fused into the first level):
+// element at position j of a column into slot bitrev(j), as limbs.
+template <int L>
+__device__ __forceinline__ void level_encode_in(uint32_t* cur, const uint32_t* __restrict__ a, long long alen,
+                                                int u, long long M, const LevelArgs& A, long long c0) {
+    const int nel = 1 << (A.log2C + A.log2r);
+    for (int t = threadIdx.x; t < (nel << A.log2m); t += kThreads) {
+        const int e = t >> A.log2m, k = t & ((1 << A.log2m) - 1);
+        const int c = e & ((1 << A.log2C) - 1), j = e >> A.log2C;
+        uint32_t out[L];
+        encode_limbs<L>(a, alen, u, level_pos(A, c0, c, j), k, M, A.log2m, out);
+        uint32_t* dst = cur + ((((c << A.log2r) + bitrev(j, A.log2r)) << A.log2m) + k) * L;
+#pragma unroll
+        for (int w = 0; w < L; ++w) dst[w] = out[w];
+    }
+}
+
+// LDS limbs (slot v) out to HBM digits (position v)
+template <int L>
+__device__ __forceinline__ void level_store_limbs(uint32_t* __restrict__ poly, const uint32_t* cur,
+                                                  const LevelArgs& A, long long c0) {
+    constexpr int D = Dig<L>::D;
+    const int nel = 1 << (A.log2C + A.log2r);
+    for (int t = threadIdx.x; t < (nel << A.log2m); t += kThreads) {
+        const int e = t >> A.log2m, k = t & ((1 << A.log2m) - 1);
+        const int c = e & ((1 << A.log2C) - 1), v = e >> A.log2C;
+        const uint32_t* src = cur + ((((c << A.log2r) + v) << A.log2m) + k) * L;
+        uint32_t x[L], dv[D];
+#pragma unroll
+        for (int w = 0; w < L; ++w) x[w] = src[w];
+        limbs_to_digits<L>(x, dv);
+        uint32_t* dst = poly + ((size_t)level_pos(A, c0, c, v) << A.log2m) * D + k * D;
+#pragma unroll
+        for (int w = 0; w < D; ++w) dst[w] = dv[w];
+    }
+}
+
+// Within LDS: every coefficient from limbs to digits, same slot (then a barrier)
+template <int L>
+__device__ __forceinline__ void lds_to_digits(uint32_t* dg, const uint32_t* lb, const LevelArgs& A) {
+    constexpr int D = Dig<L>::D;
+    const int n = 1 << (A.log2C + A.log2r + A.log2m);
+    for (int t = threadIdx.x; t < n; t += kThreads) {
+        uint32_t x[L], dv[D];
+#pragma unroll
+        for (int w = 0; w < L; ++w) x[w] = lb[t * L + w];
+        limbs_to_digits<L>(x, dv);
+#pragma unroll
+        for (int w = 0; w < D; ++w) dg[t * D + w] = dv[w];
+    }
+    __syncthreads();
+}
+
+// Within LDS: every coefficient from digits to limbs; the element in slot s of its column moves
+// to slot bitrev(s) if perm (then a barrier)
+template <int L>
+__device__ __forceinline__ void lds_to_limbs(uint32_t* lb, const uint32_t* dg, const LevelArgs& A, bool perm) {
+    constexpr int D = Dig<L>::D;
+    const int n = 1 << (A.log2C + A.log2r + A.log2m);
+    for (int t = threadIdx.x; t < n; t += kThreads) {
+        uint32_t dv[D], x[L];
+#pragma unroll
+        for (int w = 0; w < D; ++w) dv[w] = dg[t * D + w];
+        digits_to_limbs<L>(dv, x);
+        int to = t;
+        if (perm) {
+            const int k = t & ((1 << A.log2m) - 1);
+            const int e = t >> A.log2m;
+            const int c = e >> A.log2r, sl = e & ((1 << A.log2r) - 1);
+            to = ((((c << A.log2r) + bitrev(sl, A.log2r))) << A.log2m) + k;
+        }
+#pragma unroll
+        for (int w = 0; w < L; ++w) lb[to * L + w] = x[w];
+    }
+    __syncthreads();
 }
 
 // A thread's operand for one round of products, fetched from HBM a round ahead (the load is
@@ -355,14 +433,14 @@ __device__ __forceinline__ void level_twiddle(Ahead<L>& f, uint32_t* cur, uint32
     if (A.mode == 2) __syncthreads();
 }
 
-// log2 r radix-2 decimation-in-time passes over the workgroup's columns, from cur into nxt and
-// back (the buffers are swapped after each pass; on return cur holds the result).  Input: the
-// element at position j of a column in slot bitrev(j); output: position v in slot v.  The pass
-// merging halves of h points multiplies the odd half by alpha^((m/h) k) (alpha^-1 if inverse).
+// log2 r radix-2 decimation-in-time passes over the workgroup's columns (limbs, L words per
+// coefficient), from cur into nxt and back (the buffers are swapped after each pass; on return
+// cur holds the result).  Input: the element at position j of a column in slot bitrev(j);
+// output: position v in slot v.  The pass merging halves of h points multiplies the odd half by
+// alpha^((m/h) k) (alpha^-1 if inverse).
 template <int L>
 __device__ __forceinline__ void dft_passes(uint32_t*& cur, uint32_t*& nxt, const LevelArgs& A, int inverse,
                                            const QConst& Q) {
-    constexpr int D = Dig<L>::D;
     const int m = 1 << A.log2m, r = 1 << A.log2r;
     const int tasks = (1 << (A.log2C + A.log2r - 1)) << A.log2m;   // butterflies x coefficients
     for (int h = 1, lh = 0; h < r; h <<= 1, ++lh) {
@@ -388,26 +466,26 @@ __device__ __forceinline__ void dft_passes(uint32_t*& cur, uint32_t*& nxt, const
                     neg = false;
                 }
             }
-            // coefficient slots (element * m + coefficient), D words each; 24-bit products
+            // coefficient slots (element * m + coefficient), L words each
             const int ex = ((c << A.log2r) + xs) << A.log2m;
             const int ey = ((c << A.log2r) + ys) << A.log2m;
-            const uint32_t* X = cur + __umul24(ex + jj, D);
-            const uint32_t* Y = cur + __umul24(ey + idx, D);
-            uint32_t xv[D], yv[D], sv[D], dv[D];
+            const uint32_t* X = cur + (ex + jj) * L;
+            const uint32_t* Y = cur + (ey + idx) * L;
+            uint32_t xv[L], yv[L], sv[L], dv[L];
 #pragma unroll
-            for (int w = 0; w < D; ++w) {
+            for (int w = 0; w < L; ++w) {
                 xv[w] = X[w];
                 yv[w] = Y[w];
             }
-            dmod_add<L>(sv, xv, yv, Q);
-            dmod_sub<L>(dv, xv, yv, Q);
-            // a negated y swaps the two outputs: chosen by address, not per digit
-            uint32_t* PS = nxt + __umul24((neg ? ey : ex) + jj, D);
-            uint32_t* PD = nxt + __umul24((neg ? ex : ey) + jj, D);
+            lmod_add<L>(sv, xv, yv, Q);
+            lmod_sub<L>(dv, xv, yv, Q);
+            // a negated y swaps the two outputs: chosen by address, not per limb
+            uint32_t* PS = nxt + ((neg ? ey : ex) + jj) * L;
+            uint32_t* PD = nxt + ((neg ? ex : ey) + jj) * L;
 #pragma unroll
-            for (int w = 0; w < D; ++w) PS[w] = sv[w];
+            for (int w = 0; w < L; ++w) PS[w] = sv[w];
 #pragma unroll
-            for (int w = 0; w < D; ++w) PD[w] = dv[w];
+            for (int w = 0; w < L; ++w) PD[w] = dv[w];
         }
         __syncthreads();
         uint32_t* tmp = cur;
@@ -481,69 +559,65 @@ __device__ __forceinline__ void level_pointwise(Ahead<L>& f, uint32_t* cur, uint
     __syncthreads();
 }
 
-// dst slot bitrev(v) = src slot v, every column of the workgroup
-template <int L>
-__device__ __forceinline__ void level_permute(uint32_t* dst, const uint32_t* src, const LevelArgs& A) {
-    constexpr int D = Dig<L>::D;
-    const int EW = D << A.log2m;
-    const int nel = 1 << (A.log2C + A.log2r);
-    for (int t = threadIdx.x; t < nel * EW; t += kThreads) {
-        const int e = t / EW;
-        const int w = t - e * EW;
-        const int c = e >> A.log2r, v = e & ((1 << A.log2r) - 1);
-        dst[((c << A.log2r) + bitrev(v, A.log2r)) * EW + w] = src[t];
-    }
-    __syncthreads();
-}
-
 // MODE 0: DFT only; 1: forward DFT, then twiddles on the way out; 2: twiddles, then inverse DFT;
 // 3 (bottom level, no twiddles): forward DFT, componentwise products with bpoly, inverse DFT.
 // ENC (top forward level): the columns are encoded from operand `which` of PA's product instead
-// of being read from poly.
+// of being read from poly.  LDS: two halves of A.half words; a DFT runs between them on limbs,
+// products run on digits in one half with their operands staged in the other.
 template <int L, int MODE, bool ENC>
 __global__ __launch_bounds__(kThreads) void k_level(uint32_t* __restrict__ poly0, long long stride,
                                                     const uint32_t* __restrict__ table, LevelArgs A,
                                                     QConst Q, const uint32_t* __restrict__ bpoly0,
                                                     int squaring, ProdArgs PA, int which, long long M) {
-    constexpr int D = Dig<L>::D;
     A.mode = MODE;
     uint32_t* __restrict__ poly = poly0 + (size_t)blockIdx.y * stride;
     extern __shared__ uint4 smv[];
-    const int m = 1 << A.log2m;
-    const int EW = m * D;
-    const int ncw = (1 << (A.log2C + A.log2r)) * EW;     // words of the workgroup's columns
-    uint32_t* cur = reinterpret_cast<uint32_t*>(smv);
-    uint32_t* nxt = cur + ncw;
-    uint32_t* sep = nxt + ncw;                            // separate staging area, if any
+    uint32_t* const H0 = reinterpret_cast<uint32_t*>(smv);
+    uint32_t* const H1 = H0 + A.half;
     const long long c0 = (long long)blockIdx.x << A.log2C;
     const uint32_t* bpoly = (MODE == 3 && !squaring) ? bpoly0 + (size_t)blockIdx.y * stride : nullptr;
     Ahead<L> f;
-    // round 0's operand: before the column loads (mode 2, needed first) or after them, so that
-    // its latency hides behind the DFT (modes 1 and 3)
-    if (MODE == 2) tw_fetch<L>(f, 0, table, A, c0);
+    if (MODE == 2) {
+        // twiddles on digits in H0 (operands staged in H1), then limbs in H1 for the DFT
+        tw_fetch<L>(f, 0, table, A, c0);
+        level_load_digits<L>(H0, poly, A, c0);
+        __syncthreads();
+        level_twiddle<L>(f, H0, H1, poly, table, A, c0, Q);
+        lds_to_limbs<L>(H1, H0, A, false);
+        uint32_t* cur = H1;
+        uint32_t* nxt = H0;
+        dft_passes<L>(cur, nxt, A, 1, Q);
+        level_store_limbs<L>(poly, cur, A, c0);
+        return;
+    }
     if (ENC) {
         const ProdDesc pd = PA.get();
-        level_encode_in<L>(cur, which ? pd.b : pd.a, which ? pd.blen : pd.alen, pd.u, M, A, c0);
+        level_encode_in<L>(H0, which ? pd.b : pd.a, which ? pd.blen : pd.alen, pd.u, M, A, c0);
     } else {
-        level_copy_in<L>(cur, poly, A, c0);
+        level_load_limbs<L>(H0, poly, A, c0);
     }
+    // round 0's operand after the column loads, so that its latency hides behind the DFT
     if (MODE == 1) tw_fetch<L>(f, 0, table, A, c0);
     if (MODE == 3) pw_fetch<L>(f, 0, bpoly, A, c0);
     __syncthreads();
-    if (MODE == 2) level_twiddle<L>(f, cur, A.rb_separate ? sep : nxt, poly, table, A, c0, Q);
+    uint32_t* cur = H0;
+    uint32_t* nxt = H1;
     dft_passes<L>(cur, nxt, A, MODE == 3 ? 0 : A.inverse, Q);
+    if (MODE == 0) {
+        level_store_limbs<L>(poly, cur, A, c0);
+        return;
+    }
+    // digits for the products in the other half; the staging takes the DFT's half
+    uint32_t* dg = nxt;
+    lds_to_digits<L>(dg, cur, A);
     if (MODE == 1) {
-        level_twiddle<L>(f, cur, A.rb_separate ? sep : nxt, poly, table, A, c0, Q);
-    } else if (MODE == 3) {
-        level_pointwise<L>(f, cur, A.rb_separate ? sep : nxt, bpoly, A, c0, Q);
-        level_permute<L>(nxt, cur, A);
-        uint32_t* tmp = cur;
-        cur = nxt;
-        nxt = tmp;
-        dft_passes<L>(cur, nxt, A, 1, Q);
-        level_copy_out<L>(poly, cur, A, c0);
+        level_twiddle<L>(f, dg, cur, poly, table, A, c0, Q);
     } else {
-        level_copy_out<L>(poly, cur, A, c0);
+        level_pointwise<L>(f, dg, cur, bpoly, A, c0, Q);
+        lds_to_limbs<L>(cur, dg, A, true);          // slot v -> bitrev(v): the inverse DFT's input
+        nxt = dg;
+        dft_passes<L>(cur, nxt, A, 1, Q);
+        level_store_limbs<L>(poly, cur, A, c0);
     }
 }
 
@@ -1372,6 +1446,7 @@ int plan_constants(dkss_ctx* ctx, Call* call) {
             }
         };
         digits(CP.q, Q.qd);
+        for (int k = 0; k < L; ++k) Q.ql[k] = (uint32_t)(CP.q.w[k / 2] >> (32 * (k % 2)));
         // -q^-1 mod 2^28 by Newton iteration on the low word
         uint32_t q0 = (uint32_t)CP.q.w[0];
         uint32_t inv = q0;
@@ -1557,11 +1632,12 @@ struct Transform {
             const int r = 1 << log2r;
             const long long ncols = twoM >> log2r;
             constexpr int D = Dig<L>::D;
-            const size_t colbytes = (size_t)r * m * D * 4;
-            // columns per workgroup: two LDS buffers of C columns within the budget (one column
-            // when twiddles are fused), at most ncols
+            const bool pw = fused && !inverse && k == nl - 1;     // fused componentwise products
+            const size_t colbytes = (size_t)r * m * L * 4;        // one column in limbs
+            // columns per workgroup: two LDS halves of C columns within the budget (one column
+            // when products are fused), at most ncols
             int log2C = 0;
-            while (!tw && (2 * colbytes << (log2C + 1)) <= (size_t)c.dft_lds &&
+            while (!tw && !pw && (2 * colbytes << (log2C + 1)) <= (size_t)c.dft_lds &&
                    (1LL << (log2C + 1)) <= ncols)
                 ++log2C;
             LevelArgs A{};
@@ -1574,15 +1650,18 @@ struct Transform {
             A.log2C = log2C;
             while ((1LL << A.log2nl) < n_lvl[k]) ++A.log2nl;
             while ((1LL << A.log2mu) < mu[k]) ++A.log2mu;
-            const bool pw = fused && !inverse && k == nl - 1;     // fused componentwise products
             A.mode = pw ? 3 : tw ? (inverse ? 2 : 1) : 0;
             A.inverse = inverse;
-            // staging of twiddles or of b: 256/m elements x 2m residues; in the free column
-            // buffer if it fits
-            const size_t ncw = ((size_t)r << log2C) * m * D;
+            // two halves: each holds the columns in limbs (DFT) and, where products run, the
+            // columns in digits and the staging of 256/m operands of 2m residues
+            const size_t ncl = ((size_t)r << log2C) * m * L;
+            const size_t ncd = ((size_t)r << log2C) * m * D;
             const size_t rb_words = (size_t)(kThreads / m) * tw_stage_words(m, D);
-            A.rb_separate = (tw || pw) && ncw < rb_words;
-            const size_t lds = 2 * ncw * 4 + (A.rb_separate ? rb_words * 4 : 0);
+            size_t half = ncl;
+            if (tw || pw) half = std::max(half, std::max(ncd, rb_words));
+            half = (half + 3) & ~(size_t)3;                       // 16-byte aligned halves
+            A.half = (int)half;
+            const size_t lds = 2 * half * 4;
             const unsigned blocks = (unsigned)(ncols >> log2C);
             const double nprod = tw ? (double)(twoM / n_lvl[k]) * (r - 1) * (mu[k] - 1) : 0.0;
             const uint32_t* tab = (const uint32_t*)c.C->d_table;

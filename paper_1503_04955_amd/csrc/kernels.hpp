@@ -25,6 +25,7 @@ struct QConst {
     uint32_t qd[kMaxD + 2];  // q in 28-bit digits
     uint32_t qinv28;         // -q^-1 mod 2^28
     uint32_t kpw[kMaxD + 2]; // digits of (2M)^-1 R'^2 mod q: rescales a pointwise product
+    uint32_t ql[kMaxL];      // q in 32-bit limbs
 };
 
 template <int L>
@@ -137,6 +138,52 @@ __host__ __device__ __forceinline__ void digits_to_limbs(const uint32_t* d, uint
         if (k + 2 < D) v |= (uint64_t)d[k + 2] << 56;
         x[w] = (uint32_t)(v >> s);
     }
+}
+
+// 28-bit digits of a residue given in 32-bit limbs
+template <int L>
+__host__ __device__ __forceinline__ void limbs_to_digits(const uint32_t* x, uint32_t* d) {
+    constexpr int D = Dig<L>::D;
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        const int bit = 28 * k;
+        const int w = bit >> 5, s = bit & 31;
+        uint64_t v = w < L ? x[w] : 0u;
+        if (w + 1 < L) v |= (uint64_t)x[w + 1] << 32;
+        d[k] = (uint32_t)(v >> s) & kMask28;
+    }
+}
+
+// ----- arithmetic mod q on 32-bit limbs (the FFT passes) ----------------------------------------
+// A residue in L limbs, canonical in [0, q); additions use the hardware carry (add/sub with carry
+// chains): 2q < 2^(32L + 1), the carry out of the top limb is the extra bit.
+
+// r = x + y mod q
+template <int L>
+__host__ __device__ __forceinline__ void lmod_add(uint32_t* r, const uint32_t* x, const uint32_t* y,
+                                                  const QConst& Q) {
+    uint32_t s[L], d[L];
+    unsigned int c = 0, b = 0;
+#pragma unroll
+    for (int k = 0; k < L; ++k) s[k] = __builtin_addc(x[k], y[k], c, &c);
+#pragma unroll
+    for (int k = 0; k < L; ++k) d[k] = __builtin_subc(s[k], Q.ql[k], b, &b);
+    const bool ge = c || !b;                 // x + y >= q
+#pragma unroll
+    for (int k = 0; k < L; ++k) r[k] = ge ? d[k] : s[k];
+}
+
+// r = x - y mod q
+template <int L>
+__host__ __device__ __forceinline__ void lmod_sub(uint32_t* r, const uint32_t* x, const uint32_t* y,
+                                                  const QConst& Q) {
+    uint32_t d[L];
+    unsigned int b = 0, c = 0;
+#pragma unroll
+    for (int k = 0; k < L; ++k) d[k] = __builtin_subc(x[k], y[k], b, &b);
+    const uint32_t mask = 0u - b;            // add q back if x < y
+#pragma unroll
+    for (int k = 0; k < L; ++k) r[k] = __builtin_addc(d[k], Q.ql[k] & mask, c, &c);
 }
 
 // ----- Montgomery reduction of a column sum ---------------------------------------------------

@@ -148,3 +148,29 @@ def test_ring_product_coefficient_extreme_digits(da, L, log2m):
     TPn = digits(1, D) * m + digits(v, D) * m
     o, _ = call(da, L, 3, q, arr(TPn), arr(X), D, log2m, m - 1, m)
     assert value(o) == m * v * v % q * Rinv % q
+
+
+
+def limbs(x, L):
+    return [(x >> (32 * k)) & 0xFFFFFFFF for k in range(L)]
+
+
+@pytest.mark.parametrize("L", [1, 2, 3, 4, 5, 6, 7, 8])
+def test_limb_add_sub_and_conversions(da, L):
+    """The FFT passes' arithmetic on 32-bit limbs (add/sub with carry chains) and the conversions
+    between limbs and 28-bit digits; moduli up to 32L bits, including q = 2^(32L) - 1 where the
+    sum of two residues carries out of the top limb."""
+    rng = random.Random(300 + L)
+    D = da.da_D(L)
+    qs = moduli(L, rng) + [(1 << (32 * L)) - 1]
+    for q in qs:
+        for _ in range(60):
+            x, y = rng.randrange(q), rng.randrange(q)
+            if rng.random() < 0.2:
+                x, y = q - 1, q - 1 - rng.randrange(3)
+            o, _ = call(da, L, 6, q, arr(limbs(x, L)), arr(limbs(y, L)), D, n_out=L)
+            assert sum(int(o[w]) << (32 * w) for w in range(L)) == (x + y) % q
+            o, _ = call(da, L, 7, q, arr(limbs(x, L)), arr(limbs(y, L)), D, n_out=L)
+            assert sum(int(o[w]) << (32 * w) for w in range(L)) == (x - y) % q
+            o, _ = call(da, L, 8, q, arr(limbs(x, L)), arr(limbs(0, L)), D, n_out=D)
+            assert [o[k] for k in range(D)] == digits(x, D)
