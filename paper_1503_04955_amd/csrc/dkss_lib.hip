@@ -56,6 +56,9 @@ constexpr size_t kSchoolbookMaxWords = 4096;   // alen + blen of the base case
 
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// A dispatch's work-items per grid dimension must fit in 32 bits.
+inline bool grid_ok(size_t blocks, size_t threads = 256) { return blocks * threads < (1ull << 32); }
+
 // Orders LDS accesses among the lanes of one wavefront (a wavefront's LDS operations are
 // performed in issue order; this keeps the compiler from moving them across the point).
 __device__ __forceinline__ void wave_sync() {
@@ -1633,11 +1636,11 @@ struct Transform {
             const long long ncols = twoM >> log2r;
             constexpr int D = Dig<L>::D;
             const bool pw = fused && !inverse && k == nl - 1;     // fused componentwise products
-            const size_t colbytes = (size_t)r * m * L * 4;        // one column in limbs
-            // columns per workgroup: two LDS halves of C columns within the budget (one column
-            // when products are fused), at most ncols
+            // columns per workgroup: two LDS halves of C columns (limbs; digits too where the
+            // products run) within the budget, at most ncols; one column on twiddle levels
+            const size_t colbytes = (size_t)r * m * (pw ? Dig<L>::D : L) * 4;
             int log2C = 0;
-            while (!tw && !pw && (2 * colbytes << (log2C + 1)) <= (size_t)c.dft_lds &&
+            while (!tw && (2 * colbytes << (log2C + 1)) <= (size_t)c.dft_lds &&
                    (1LL << (log2C + 1)) <= ncols)
                 ++log2C;
             LevelArgs A{};
@@ -1662,6 +1665,7 @@ struct Transform {
             half = (half + 3) & ~(size_t)3;                       // 16-byte aligned halves
             A.half = (int)half;
             const size_t lds = 2 * half * 4;
+            if (!grid_ok((size_t)(ncols >> log2C))) return DKSS_ERANGE;
             const unsigned blocks = (unsigned)(ncols >> log2C);
             const double nprod = tw ? (double)(twoM / n_lvl[k]) * (r - 1) * (mu[k] - 1) : 0.0;
             const uint32_t* tab = (const uint32_t*)c.C->d_table;
@@ -1717,6 +1721,7 @@ struct Encode {
                    double in_words, hipStream_t s) {
         const long long M = 1LL << c.P.log2_M;
         const long long total = (2 * M) << c.P.log2_m;
+        if (!grid_ok((size_t)((total + kThreads - 1) / kThreads))) return DKSS_ERANGE;
         const unsigned blocks = (unsigned)((total + kThreads - 1) / kThreads);
         ProfScope ps(c.prof, DKSS_K_ENCODE, s, 4.0 * in_words + 4.0 * G * total * L, 0.0);
         hipLaunchKernelGGL(k_encode<L>, dim3(blocks, G), dim3(kThreads), 0, s, PA, which, poly,
@@ -1730,6 +1735,7 @@ struct Pointwise {
     static int run(const Call& c, uint32_t* A, const uint32_t* B, size_t stride, unsigned G, hipStream_t s) {
         const long long count = 2LL << c.P.log2_M;
         const int per = kThreads / c.P.m();
+        if (!grid_ok((size_t)((count + per - 1) / per))) return DKSS_ERANGE;
         const unsigned blocks = (unsigned)((count + per - 1) / per);
         const int m = c.P.m();
         ProfScope ps(c.prof, DKSS_K_POINTWISE, s, 3.0 * G * count * m * L * 4,
@@ -1746,6 +1752,7 @@ struct Decode {
     static int run(const Call& c, const ProdArgs& PA, unsigned G, size_t nw_max, double out_words,
                    const Workspace& w, hipStream_t s, int u_min) {
         const long long nwaves = ((long long)nw_max + 63) / 64;
+        if (!grid_ok((size_t)((nw_max + kThreads - 1) / kThreads))) return DKSS_ERANGE;
         const unsigned blocks = (unsigned)((nw_max + kThreads - 1) / kThreads);
         const double S = (double)G * (2LL << c.P.log2_M) * c.P.m() * L * 4;
         const long long nseg = (nwaves + kThreads - 1) / kThreads;
