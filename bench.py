@@ -20,7 +20,10 @@ bandwidth.  `traffic` is the HBM bytes per launch that the committed counter sum
 profiles/<kernel>_traffic.txt records, when it was taken on the current kernel sources, else
 null.  roofline_fft reports the FFT levels without twiddles (k_level<L, 0>) against HBM.
 
-"tuned" and "learned" time the same product under the tuned table and the learned selector.
+"tuned" and "learned" time the same product under the tuned table and the learned selector;
+"sizes" times single products of 2^18 and 2^24 bits (thesis rule, learned selector, and the
+thesis-rule product replayed as a one-product HIP graph, which removes the host launch cost of
+the launch-bound small case).
 The "batch" object: 4096 independent products, operand lengths log-uniform in 2^12..2^22 bits,
 length ratios uniform in [1, 8], run as 4096 sequential plain calls (thesis rule), as one
 dkss_mul_batch call per policy (thesis, tuned, learned), and as the learned batch captured in a
@@ -150,6 +153,40 @@ def batch_bench(count, reps, dk, torch, SI):
     return res
 
 
+def sizes_bench(bits_list, reps, dk, torch, SI):
+    """Single products at other sizes (the 2^18-bit case is launch-bound): thesis rule and learned
+    selector as plain calls, and the thesis-rule product captured as a one-product HIP graph;
+    every variant bit-identical to the first."""
+    out = {}
+    for bits in bits_list:
+        n = (1 << bits) // 32
+        a_h, b_h = SI.operand_pair(SI.SEED_BASE + 3 + bits, n, n)
+        a, b = dk.to_device(a_h), dk.to_device(b_h)
+        res = {"limbs": n}
+        ref = None
+        for name, policy in (("thesis", dk.POLICY_THESIS), ("learned", dk.POLICY_LEARNED)):
+            ctx = dk.Context(policy)
+            c = torch.empty(2 * n, dtype=torch.int32, device="cuda")
+            ws = torch.empty(max(ctx.workspace_bytes(n, n), 1), dtype=torch.uint8, device="cuda")
+            ms = _timed(lambda: ctx.mul(a, b, out=c, ws=ws), reps, torch)
+            if ref is None:
+                ref = c
+            elif not torch.equal(ref, c):
+                raise RuntimeError("2^%d product differs between policies" % bits)
+            res[name] = {"ms": ms, "value": 2 * n * 32 / (ms / 1e3)}
+            if name == "thesis":
+                call = dk.BatchCall(ctx, [a], [b])
+                graph = call.graph()
+                ms = _timed(graph, reps, torch)
+                if not torch.equal(ref, call.outs[0]):
+                    raise RuntimeError("2^%d graph product differs" % bits)
+                res["thesis_graph"] = {"ms": ms, "value": 2 * n * 32 / (ms / 1e3),
+                                       "kernels": graph.kernels}
+                graph.close()
+        out["2^%d" % bits] = res
+    return out
+
+
 def traffic_record(kernel, bits, source_files):
     """HBM bytes per launch of `kernel` in the 2^bits product from the committed counter summary,
     or None when the summary is missing or was taken on other kernel sources (sha256 of
@@ -184,6 +221,7 @@ def main():
     ap.add_argument("--overlap", type=int, default=0, help="transform b on a second stream")
     ap.add_argument("--dft-lds", type=int, default=32768, help="LDS bytes per FFT-level workgroup")
     ap.add_argument("--batch", type=int, default=4096, help="products in the batch leg (0: skip)")
+    ap.add_argument("--sizes", default="18,24", help="other single-product sizes, log2 bits ('' to skip)")
     ap.add_argument("--copy-calib", type=int, default=0,
                     help="end with one device-to-device copy of this many bytes (a counter "
                          "calibration kernel of known traffic)")
@@ -317,6 +355,8 @@ def main():
     torch.cuda.empty_cache()
     if args.batch:
         out["batch"] = batch_bench(args.batch, 3, dk, torch, SI)
+    if args.sizes:
+        out["sizes"] = sizes_bench([int(x) for x in args.sizes.split(",")], 20, dk, torch, SI)
     if args.copy_calib:
         src = torch.empty(args.copy_calib, dtype=torch.uint8, device=dev)
         dst = torch.empty_like(src)
