@@ -69,7 +69,7 @@ __device__ __forceinline__ void wave_sync() {
 
 // Words of one element's twiddle staging: rho^s and its negation, 2m residues of D digits.  (At
 // radix 2m the staging of a round fills the free column buffer exactly, so it is not padded.)
-__host__ __device__ constexpr int tw_stage_words(int m, int D) { return 2 * m * D; }
+__host__ __device__ constexpr int tw_stage_words(int m, int DS) { return 2 * m * DS; }
 
 __device__ __forceinline__ int bitrev(int x, int bits) {
     return bits ? (int)(__brev((unsigned)x) >> (32 - bits)) : 0;
@@ -219,7 +219,7 @@ __device__ __forceinline__ void level_load_digits(uint32_t* cur, const uint32_t*
 }
 
 // digits into LDS as limbs (one coefficient per thread and step)
-template <int L>
+template <int L, int LS>
 __device__ __forceinline__ void level_load_limbs(uint32_t* cur, const uint32_t* __restrict__ poly,
                                                  const LevelArgs& A, long long c0) {
     constexpr int D = Dig<L>::D;
@@ -232,7 +232,7 @@ __device__ __forceinline__ void level_load_limbs(uint32_t* cur, const uint32_t* 
 #pragma unroll
         for (int w = 0; w < D; ++w) dv[w] = src[w];
         digits_to_limbs<L>(dv, x);
-        uint32_t* dst = cur + ((((c << A.log2r) + bitrev(j, A.log2r)) << A.log2m) + k) * L;
+        uint32_t* dst = cur + ((((c << A.log2r) + bitrev(j, A.log2r)) << A.log2m) + k) * LS;
 #pragma unroll
         for (int w = 0; w < L; ++w) dst[w] = x[w];
     }
@@ -267,7 +267,7 @@ __device__ __forceinline__ void encode_limbs(const uint32_t* __restrict__ a, lon
 
 // The top forward level's columns straight from the operand (Step 4 fused into the first level):
 // element at position j of a column into slot bitrev(j), as limbs.
-template <int L>
+template <int L, int LS>
 __device__ __forceinline__ void level_encode_in(uint32_t* cur, const uint32_t* __restrict__ a, long long alen,
                                                 int u, long long M, const LevelArgs& A, long long c0) {
     const int nel = 1 << (A.log2C + A.log2r);
@@ -276,14 +276,14 @@ __device__ __forceinline__ void level_encode_in(uint32_t* cur, const uint32_t* _
         const int c = e & ((1 << A.log2C) - 1), j = e >> A.log2C;
         uint32_t out[L];
         encode_limbs<L>(a, alen, u, level_pos(A, c0, c, j), k, M, A.log2m, out);
-        uint32_t* dst = cur + ((((c << A.log2r) + bitrev(j, A.log2r)) << A.log2m) + k) * L;
+        uint32_t* dst = cur + ((((c << A.log2r) + bitrev(j, A.log2r)) << A.log2m) + k) * LS;
 #pragma unroll
         for (int w = 0; w < L; ++w) dst[w] = out[w];
     }
 }
 
 // LDS limbs (slot v) out to HBM digits (position v)
-template <int L>
+template <int L, int LS>
 __device__ __forceinline__ void level_store_limbs(uint32_t* __restrict__ poly, const uint32_t* cur,
                                                   const LevelArgs& A, long long c0) {
     constexpr int D = Dig<L>::D;
@@ -291,7 +291,7 @@ __device__ __forceinline__ void level_store_limbs(uint32_t* __restrict__ poly, c
     for (int t = threadIdx.x; t < (nel << A.log2m); t += kThreads) {
         const int e = t >> A.log2m, k = t & ((1 << A.log2m) - 1);
         const int c = e & ((1 << A.log2C) - 1), v = e >> A.log2C;
-        const uint32_t* src = cur + ((((c << A.log2r) + v) << A.log2m) + k) * L;
+        const uint32_t* src = cur + ((((c << A.log2r) + v) << A.log2m) + k) * LS;
         uint32_t x[L], dv[D];
 #pragma unroll
         for (int w = 0; w < L; ++w) x[w] = src[w];
@@ -303,14 +303,14 @@ __device__ __forceinline__ void level_store_limbs(uint32_t* __restrict__ poly, c
 }
 
 // Within LDS: every coefficient from limbs to digits, same slot (then a barrier)
-template <int L>
+template <int L, int LS>
 __device__ __forceinline__ void lds_to_digits(uint32_t* dg, const uint32_t* lb, const LevelArgs& A) {
     constexpr int D = Dig<L>::D;
     const int n = 1 << (A.log2C + A.log2r + A.log2m);
     for (int t = threadIdx.x; t < n; t += kThreads) {
         uint32_t x[L], dv[D];
 #pragma unroll
-        for (int w = 0; w < L; ++w) x[w] = lb[t * L + w];
+        for (int w = 0; w < L; ++w) x[w] = lb[t * LS + w];
         limbs_to_digits<L>(x, dv);
 #pragma unroll
         for (int w = 0; w < D; ++w) dg[t * D + w] = dv[w];
@@ -320,7 +320,7 @@ __device__ __forceinline__ void lds_to_digits(uint32_t* dg, const uint32_t* lb, 
 
 // Within LDS: every coefficient from digits to limbs; the element in slot s of its column moves
 // to slot bitrev(s) if perm (then a barrier)
-template <int L>
+template <int L, int LS>
 __device__ __forceinline__ void lds_to_limbs(uint32_t* lb, const uint32_t* dg, const LevelArgs& A, bool perm) {
     constexpr int D = Dig<L>::D;
     const int n = 1 << (A.log2C + A.log2r + A.log2m);
@@ -337,7 +337,7 @@ __device__ __forceinline__ void lds_to_limbs(uint32_t* lb, const uint32_t* dg, c
             to = ((((c << A.log2r) + bitrev(sl, A.log2r))) << A.log2m) + k;
         }
 #pragma unroll
-        for (int w = 0; w < L; ++w) lb[to * L + w] = x[w];
+        for (int w = 0; w < L; ++w) lb[to * LS + w] = x[w];
     }
     __syncthreads();
 }
@@ -393,7 +393,7 @@ __device__ __forceinline__ void level_twiddle(Ahead<L>& f, uint32_t* cur, uint32
     const int per = kThreads >> A.log2m;
     const int g = threadIdx.x >> A.log2m, j = threadIdx.x & (m - 1);
     const int nel = 1 << (A.log2C + A.log2r);
-    uint32_t* TP = RB + g * tw_stage_words(m, D);
+    uint32_t* TP = RB + g * tw_stage_words(m, Dig<L>::DS);
     // The m lanes of an element lie in one wavefront (m <= 64) and touch only that element's
     // column slot and staging area, so the rounds synchronize per wavefront.
     for (int r0 = 0; r0 < nel; r0 += per) {
@@ -407,8 +407,8 @@ __device__ __forceinline__ void level_twiddle(Ahead<L>& f, uint32_t* cur, uint32
         if (nz) {
 #pragma unroll
             for (int y = 0; y < D; ++y) {
-                TP[j * D + y] = f.v[y];
-                TP[(j + m) * D + y] = f.v[D + y];
+                TP[j * Dig<L>::DS + y] = f.v[y];
+                TP[(j + m) * Dig<L>::DS + y] = f.v[D + y];
             }
         }
         if (r0 + per < nel) tw_fetch<L>(f, r0 + per, table, A, c0);     // next round's twiddle
@@ -441,7 +441,7 @@ __device__ __forceinline__ void level_twiddle(Ahead<L>& f, uint32_t* cur, uint32
 // cur holds the result).  Input: the element at position j of a column in slot bitrev(j);
 // output: position v in slot v.  The pass merging halves of h points multiplies the odd half by
 // alpha^((m/h) k) (alpha^-1 if inverse).
-template <int L>
+template <int L, int LS>
 __device__ __forceinline__ void dft_passes(uint32_t*& cur, uint32_t*& nxt, const LevelArgs& A, int inverse,
                                            const QConst& Q) {
     const int m = 1 << A.log2m, r = 1 << A.log2r;
@@ -472,8 +472,8 @@ __device__ __forceinline__ void dft_passes(uint32_t*& cur, uint32_t*& nxt, const
             // coefficient slots (element * m + coefficient), L words each
             const int ex = ((c << A.log2r) + xs) << A.log2m;
             const int ey = ((c << A.log2r) + ys) << A.log2m;
-            const uint32_t* X = cur + (ex + jj) * L;
-            const uint32_t* Y = cur + (ey + idx) * L;
+            const uint32_t* X = cur + (ex + jj) * LS;
+            const uint32_t* Y = cur + (ey + idx) * LS;
             uint32_t xv[L], yv[L], sv[L], dv[L];
 #pragma unroll
             for (int w = 0; w < L; ++w) {
@@ -483,8 +483,8 @@ __device__ __forceinline__ void dft_passes(uint32_t*& cur, uint32_t*& nxt, const
             lmod_add<L>(sv, xv, yv, Q);
             lmod_sub<L>(dv, xv, yv, Q);
             // a negated y swaps the two outputs: chosen by address, not per limb
-            uint32_t* PS = nxt + ((neg ? ey : ex) + jj) * L;
-            uint32_t* PD = nxt + ((neg ? ex : ey) + jj) * L;
+            uint32_t* PS = nxt + ((neg ? ey : ex) + jj) * LS;
+            uint32_t* PD = nxt + ((neg ? ex : ey) + jj) * LS;
 #pragma unroll
             for (int w = 0; w < L; ++w) PS[w] = sv[w];
 #pragma unroll
@@ -528,7 +528,7 @@ __device__ __forceinline__ void level_pointwise(Ahead<L>& f, uint32_t* cur, uint
     const int per = kThreads >> A.log2m;
     const int g = threadIdx.x >> A.log2m, j = threadIdx.x & (m - 1);
     const int nel = 1 << (A.log2C + A.log2r);
-    uint32_t* TP = RB + g * tw_stage_words(m, D);
+    uint32_t* TP = RB + g * tw_stage_words(m, Dig<L>::DS);
     for (int r0 = 0; r0 < nel; r0 += per) {
         const int el = r0 + g;
         const bool valid = el < nel;
@@ -541,8 +541,8 @@ __device__ __forceinline__ void level_pointwise(Ahead<L>& f, uint32_t* cur, uint
             dneg_q<L>(nb, bv, Q);
 #pragma unroll
             for (int y = 0; y < D; ++y) {
-                TP[j * D + y] = bv[y];
-                TP[(j + m) * D + y] = nb[y];
+                TP[j * Dig<L>::DS + y] = bv[y];
+                TP[(j + m) * Dig<L>::DS + y] = nb[y];
             }
         }
         if (r0 + per < nel) pw_fetch<L>(f, r0 + per, bpoly, A, c0);     // next round's b
@@ -573,6 +573,9 @@ __global__ __launch_bounds__(kThreads) void k_level(uint32_t* __restrict__ poly0
                                                     QConst Q, const uint32_t* __restrict__ bpoly0,
                                                     int squaring, ProdArgs PA, int which, long long M) {
     A.mode = MODE;
+    // words per limb-form residue in LDS: padded to an odd count where products follow (bank
+    // conflicts cost more there than the LDS), dense on DFT-only levels (occupancy counts more)
+    constexpr int LS = MODE == 0 ? L : Dig<L>::LS;
     uint32_t* __restrict__ poly = poly0 + (size_t)blockIdx.y * stride;
     extern __shared__ uint4 smv[];
     uint32_t* const H0 = reinterpret_cast<uint32_t*>(smv);
@@ -586,18 +589,18 @@ __global__ __launch_bounds__(kThreads) void k_level(uint32_t* __restrict__ poly0
         level_load_digits<L>(H0, poly, A, c0);
         __syncthreads();
         level_twiddle<L>(f, H0, H1, poly, table, A, c0, Q);
-        lds_to_limbs<L>(H1, H0, A, false);
+        lds_to_limbs<L, LS>(H1, H0, A, false);
         uint32_t* cur = H1;
         uint32_t* nxt = H0;
-        dft_passes<L>(cur, nxt, A, 1, Q);
-        level_store_limbs<L>(poly, cur, A, c0);
+        dft_passes<L, LS>(cur, nxt, A, 1, Q);
+        level_store_limbs<L, LS>(poly, cur, A, c0);
         return;
     }
     if (ENC) {
         const ProdDesc pd = PA.get();
-        level_encode_in<L>(H0, which ? pd.b : pd.a, which ? pd.blen : pd.alen, pd.u, M, A, c0);
+        level_encode_in<L, LS>(H0, which ? pd.b : pd.a, which ? pd.blen : pd.alen, pd.u, M, A, c0);
     } else {
-        level_load_limbs<L>(H0, poly, A, c0);
+        level_load_limbs<L, LS>(H0, poly, A, c0);
     }
     // round 0's operand after the column loads, so that its latency hides behind the DFT
     if (MODE == 1) tw_fetch<L>(f, 0, table, A, c0);
@@ -605,22 +608,22 @@ __global__ __launch_bounds__(kThreads) void k_level(uint32_t* __restrict__ poly0
     __syncthreads();
     uint32_t* cur = H0;
     uint32_t* nxt = H1;
-    dft_passes<L>(cur, nxt, A, MODE == 3 ? 0 : A.inverse, Q);
+    dft_passes<L, LS>(cur, nxt, A, MODE == 3 ? 0 : A.inverse, Q);
     if (MODE == 0) {
-        level_store_limbs<L>(poly, cur, A, c0);
+        level_store_limbs<L, LS>(poly, cur, A, c0);
         return;
     }
     // digits for the products in the other half; the staging takes the DFT's half
     uint32_t* dg = nxt;
-    lds_to_digits<L>(dg, cur, A);
+    lds_to_digits<L, LS>(dg, cur, A);
     if (MODE == 1) {
         level_twiddle<L>(f, dg, cur, poly, table, A, c0, Q);
     } else {
         level_pointwise<L>(f, dg, cur, bpoly, A, c0, Q);
-        lds_to_limbs<L>(cur, dg, A, true);          // slot v -> bitrev(v): the inverse DFT's input
+        lds_to_limbs<L, LS>(cur, dg, A, true);          // slot v -> bitrev(v): the inverse DFT's input
         nxt = dg;
-        dft_passes<L>(cur, nxt, A, 1, Q);
-        level_store_limbs<L>(poly, cur, A, c0);
+        dft_passes<L, LS>(cur, nxt, A, 1, Q);
+        level_store_limbs<L, LS>(poly, cur, A, c0);
     }
 }
 
@@ -640,8 +643,9 @@ __global__ __launch_bounds__(kThreads) void k_pointwise(uint32_t* A0, const uint
     const int m = 1 << log2m;
     const int per = kThreads >> log2m;
     const int g = threadIdx.x >> log2m, j = threadIdx.x & (m - 1);
-    uint32_t* TP = sm + g * 3 * m * D;
-    uint32_t* X = TP + 2 * m * D;
+    constexpr int DS = Dig<L>::DS;
+    uint32_t* TP = sm + g * m * (2 * DS + D);
+    uint32_t* X = TP + 2 * m * DS;
     const long long p = (long long)blockIdx.x * per + g;
     const bool active = p < count;
     if (active) {
@@ -656,8 +660,8 @@ __global__ __launch_bounds__(kThreads) void k_pointwise(uint32_t* A0, const uint
         dneg_q<L>(nx, x, Q);
 #pragma unroll
         for (int w = 0; w < D; ++w) {
-            TP[j * D + w] = x[w];
-            TP[(j + m) * D + w] = nx[w];
+            TP[j * DS + w] = x[w];
+            TP[(j + m) * DS + w] = nx[w];
         }
     }
     __syncthreads();
@@ -685,8 +689,9 @@ __global__ __launch_bounds__(kThreads) void k_table_mul(uint32_t* table, long lo
     const int m = 1 << log2m;
     const int per = kThreads >> log2m;
     const int g = threadIdx.x >> log2m, j = threadIdx.x & (m - 1);
-    uint32_t* TP = sm + g * 3 * m * D;
-    uint32_t* X = TP + 2 * m * D;
+    constexpr int DS = Dig<L>::DS;
+    uint32_t* TP = sm + g * m * (2 * DS + D);
+    uint32_t* X = TP + 2 * m * DS;
     const long long jj = (long long)blockIdx.x * per + g;
     const bool active = jj < cnt;
     if (active) {
@@ -695,8 +700,8 @@ __global__ __launch_bounds__(kThreads) void k_table_mul(uint32_t* table, long lo
 #pragma unroll
         for (int y = 0; y < D; ++y) {
             X[j * D + y] = xs[j * D + y];
-            TP[j * D + y] = ts[j * D + y];
-            TP[(j + m) * D + y] = ts[(j + m) * D + y];
+            TP[j * DS + y] = ts[j * D + y];
+            TP[(j + m) * DS + y] = ts[(j + m) * D + y];
         }
     }
     __syncthreads();
@@ -1515,7 +1520,7 @@ int dispatch_L(int L, const A&... args) {
 }
 
 // LDS of the R-product kernels: kThreads coefficient slots, 3 D digits each (T, x, q - x)
-size_t rprod_lds(int L) { return (size_t)kThreads * 3 * dig_D(L) * sizeof(uint32_t); }
+size_t rprod_lds(int L) { return (size_t)kThreads * (2 * (dig_D(L) | 1) + dig_D(L)) * sizeof(uint32_t); }
 
 template <int L>
 struct TableBuild {
@@ -1657,9 +1662,9 @@ struct Transform {
             A.inverse = inverse;
             // two halves: each holds the columns in limbs (DFT) and, where products run, the
             // columns in digits and the staging of 256/m operands of 2m residues
-            const size_t ncl = ((size_t)r << log2C) * m * L;
+            const size_t ncl = ((size_t)r << log2C) * m * (tw || pw ? Dig<L>::LS : L);
             const size_t ncd = ((size_t)r << log2C) * m * D;
-            const size_t rb_words = (size_t)(kThreads / m) * tw_stage_words(m, D);
+            const size_t rb_words = (size_t)(kThreads / m) * tw_stage_words(m, Dig<L>::DS);
             size_t half = ncl;
             if (tw || pw) half = std::max(half, std::max(ncd, rb_words));
             half = (half + 3) & ~(size_t)3;                       // 16-byte aligned halves

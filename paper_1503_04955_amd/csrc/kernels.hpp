@@ -34,6 +34,11 @@ struct Dig {
     static constexpr int K = (32 * L + 6 + 27) / 28;      // Montgomery steps: 2^(28K) > 64 q
     static constexpr int NC = K + D + 1;                  // 64-bit columns of a product sum
     static constexpr int NI = (253 - K) / D;              // products per column between carries
+    // LDS strides: a staged ring element's residues (and the limb-form residues of levels that
+    // also multiply) are laid out at an odd number of words, so that lanes reading consecutive
+    // residues hit distinct banks
+    static constexpr int DS = D | 1;                      // words per staged residue (digits)
+    static constexpr int LS = L | 1;                      // words per residue in limbs
 };
 
 // ----- digit arithmetic mod q -----------------------------------------------------------------
@@ -222,10 +227,13 @@ __host__ __device__ __forceinline__ void normalize_cols(uint64_t* col) {
     }
 }
 
-// One output coefficient j of t * alpha^r * x in R, reduced by Montgomery:
-//   c_j = sum_{i<m} t_i (alpha^r x)_(j-i)  with alpha^m = -1.
-// (alpha^r x)_(j-i) = +- x_((j-i-r) mod m), negative when (j-i-r) mod 2m >= m; the sign is moved
-// onto t: TP holds t_0..t_(m-1) followed by q-t_0..q-t_(m-1).  X holds x_0..x_(m-1).
+// One output coefficient j of t * alpha^r * x in R, reduced by Montgomery.  With alpha^m = -1
+// (so alpha^(2m) = 1), the term t_i x_k lands on coefficient j with sign + when
+// i + k + r = j (mod 2m) and with sign - when i + k + r = j + m (mod 2m); for each k exactly one
+// i < m does one of the two, hence
+//   c_j = sum_{k<m} x_k T_((j - r - k) mod 2m),  T_w = t_w (w < m),  T_w = q - t_(w-m) (w >= m).
+// TP holds T_0..T_(2m-1) at a stride of DS words, X holds x_0..x_(m-1) at D words.  The lanes
+// of one element read the same x_k (one LDS address) and consecutive T entries (odd stride).
 // Returns c_j 2^(-28K) mod q in digits.
 template <int L>
 __host__ __device__ __forceinline__ void rprod_coeff(const uint32_t* TP, const uint32_t* X, int log2m, int j,
@@ -236,22 +244,22 @@ __host__ __device__ __forceinline__ void rprod_coeff(const uint32_t* TP, const u
     uint64_t col[G::NC];
 #pragma unroll
     for (int k = 0; k < G::NC; ++k) col[k] = 0;
-    int idx = (j - r) & mask2;
-    for (int i = 0; i < m; ++i) {
-        const int ti = i + (idx & m);               // the wrap's sign selects t or q - t
-        const int xi = idx & (m - 1);
+    int w = (j - r) & mask2;
+    for (int k = 0; k < m; ++k) {
+        const uint32_t* tp = TP + w * G::DS;
+        const uint32_t* xp = X + k * G::D;
         uint32_t tv[G::D], xv[G::D];
 #pragma unroll
         for (int x = 0; x < G::D; ++x) {
-            tv[x] = TP[ti * G::D + x];
-            xv[x] = X[xi * G::D + x];
+            tv[x] = tp[x];
+            xv[x] = xp[x];
         }
 #pragma unroll
         for (int x = 0; x < G::D; ++x)
 #pragma unroll
             for (int y = 0; y < G::D; ++y) col[x + y] += (uint64_t)tv[x] * xv[y];
-        idx = (idx - 1) & mask2;
-        if ((i + 1) % G::NI == 0) normalize_cols<L>(col);
+        w = (w - 1) & mask2;
+        if ((k + 1) % G::NI == 0) normalize_cols<L>(col);
     }
     redc_cols<L>(col, Q, out);
 }

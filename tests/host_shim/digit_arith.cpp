@@ -43,6 +43,14 @@ int da_D(int L) {
     return -1;
 }
 
+int da_DS(int L) {
+    switch (L) {
+        case 1: return Dig<1>::DS; case 2: return Dig<2>::DS; case 3: return Dig<3>::DS; case 4: return Dig<4>::DS;
+        case 5: return Dig<5>::DS; case 6: return Dig<6>::DS; case 7: return Dig<7>::DS; case 8: return Dig<8>::DS;
+    }
+    return -1;
+}
+
 int da_K(int L) {
     switch (L) {
         case 1: return Dig<1>::K; case 2: return Dig<2>::K; case 3: return Dig<3>::K; case 4: return Dig<4>::K;

@@ -58,6 +58,15 @@ def moduli(L, rng):
     return out
 
 
+def staged(vals, D, DS):
+    """Residues at the staging stride DS (>= D words); the padding words hold a value that would
+    spoil any product that read them."""
+    out = []
+    for v in vals:
+        out += digits(v, D) + [0x0FFFFFFF] * (DS - D)
+    return out
+
+
 def call(da, L, op, q, a, b, D, log2m=1, j=0, r=0, n_out=None):
     K = da.da_K(L)
     qinv = (-pow(q, -1, 1 << 28)) % (1 << 28)
@@ -86,7 +95,7 @@ def test_add_sub_neg(da, L):
 @pytest.mark.parametrize("log2m", [1, 3, 4])
 def test_ring_product_coefficient(da, L, log2m):
     """Coefficient j of t * alpha^r * x in R = (Z/q)[alpha]/(alpha^m + 1), times 2^(-28K), with t
-    given as its negacyclic extension (t, q - t) and x as m residues."""
+    given as its negacyclic extension (t, q - t) at the staging stride and x as m residues."""
     rng = random.Random(1000 * L + log2m)
     D = da.da_D(L)
     m = 1 << log2m
@@ -99,7 +108,7 @@ def test_ring_product_coefficient(da, L, log2m):
             if rng.random() < 0.3:
                 t[rng.randrange(m)] = 0
                 x[rng.randrange(m)] = q - 1
-            TP = [d for v in t for d in digits(v, D)] + [d for v in t for d in digits((q - v) if v else q, D)]
+            TP = staged(t + [(q - v) if v else q for v in t], D, da.da_DS(L))
             X = [d for v in x for d in digits(v, D)]
             r = rng.randrange(2 * m)
             # alpha^r x, negacyclic
@@ -140,12 +149,13 @@ def test_ring_product_coefficient_extreme_digits(da, L, log2m):
     K = da.da_K(L)
     Rinv = pow(1 << (28 * K), -1, q)
     v = q - 1
-    TP = digits(v, D) * m + digits(1, D) * m
+    DS = da.da_DS(L)
+    TP = staged([v] * m + [1] * m, D, DS)
     X = digits(v, D) * m
     o, _ = call(da, L, 3, q, arr(TP), arr(X), D, log2m, m - 1, 0)
     assert value(o) == m * v * v % q * Rinv % q
     # and with every term wrapped (negated): r = m gives x_(j-i-m) = -x_(j-i)
-    TPn = digits(1, D) * m + digits(v, D) * m
+    TPn = staged([1] * m + [v] * m, D, DS)
     o, _ = call(da, L, 3, q, arr(TPn), arr(X), D, log2m, m - 1, m)
     assert value(o) == m * v * v % q * Rinv % q
 
