@@ -973,39 +973,74 @@ __global__ __launch_bounds__(kThreads) void k_carry_apply(ProdArgs PA,
 // Base case: schoolbook product (Sec. 2.3), one workgroup per product, alen + blen <= 4096
 // ---------------------------------------------------------------------------------------------
 
+// LDS: a and b (alen + blen words, at least 64), then the three 32-bit parts of every output
+// column's sum; once the columns are summed, the first 256 bytes hold one carry function per
+// thread.  Thread t sums columns t, t + 256, ...; each column total sum_i a_i b_(w-i) < 2^76 is
+// kept as 64 + 32 bits (a carry count beside a 64-bit accumulator).
+// The words x_w = col_w[0] + col_(w-1)[1] + col_(w-2)[2] < 3 2^32 then take carries of 0, 1 or 2:
+// thread t owns the chunk of K consecutive words starting at t K, its carry out as a function of
+// its carry in (three values of {0, 1, 2}) is composed across threads by a prefix scan, and each
+// chunk is finished with its carry in.
+__device__ __forceinline__ uint32_t chunk_carry(const uint32_t* col, long long w0, long long w1, uint32_t cin,
+                                                uint32_t* __restrict__ out) {
+    uint64_t carry = cin;
+    for (long long w = w0; w < w1; ++w) {
+        uint64_t x = carry + col[3 * w];
+        if (w >= 1) x += col[3 * (w - 1) + 1];
+        if (w >= 2) x += col[3 * (w - 2) + 2];
+        if (out) out[w] = (uint32_t)x;
+        carry = x >> 32;
+    }
+    return (uint32_t)carry;
+}
+
 __global__ __launch_bounds__(kThreads) void k_schoolbook(ProdArgs PA) {
     extern __shared__ uint32_t sv[];
     const ProdDesc pd = PA.get();
-    uint32_t* __restrict__ c = pd.c;
-    const uint32_t* __restrict__ a = pd.a;
-    const uint32_t* __restrict__ b = pd.b;
     const long long alen = pd.alen, blen = pd.blen;
     const long long n = alen + blen;
-    for (long long w = threadIdx.x; w < n; w += blockDim.x) {
-        uint64_t lo = 0, hi = 0;
+    uint32_t* const A = sv;
+    uint32_t* const B = sv + alen;
+    uint32_t* const col = sv + (n > 64 ? n : 64);
+    unsigned char* const fn = reinterpret_cast<unsigned char*>(sv);     // after the columns
+    for (long long i = threadIdx.x; i < alen; i += kThreads) A[i] = pd.a[i];
+    for (long long i = threadIdx.x; i < blen; i += kThreads) B[i] = pd.b[i];
+    __syncthreads();
+    for (long long w = threadIdx.x; w < n; w += kThreads) {
+        uint64_t acc = 0;
+        uint32_t top = 0;
         const long long i0 = w - blen + 1 > 0 ? w - blen + 1 : 0;
         const long long i1 = w < alen - 1 ? w : alen - 1;
         for (long long i = i0; i <= i1; ++i) {
-            const uint64_t p = (uint64_t)a[i] * b[w - i];
-            lo += (uint32_t)p;
-            hi += p >> 32;
+            const uint64_t s2 = (uint64_t)A[i] * B[w - i] + acc;
+            top += s2 < acc;
+            acc = s2;
         }
-        const uint64_t t = hi + (lo >> 32);
-        sv[3 * w] = (uint32_t)lo;
-        sv[3 * w + 1] = (uint32_t)t;
-        sv[3 * w + 2] = (uint32_t)(t >> 32);
+        col[3 * w] = (uint32_t)acc;
+        col[3 * w + 1] = (uint32_t)(acc >> 32);
+        col[3 * w + 2] = top;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        uint64_t carry = 0;
-        for (long long w = 0; w < n; ++w) {
-            uint64_t s = carry + sv[3 * w];
-            if (w >= 1) s += sv[3 * (w - 1) + 1];
-            if (w >= 2) s += sv[3 * (w - 2) + 2];
-            c[w] = (uint32_t)s;
-            carry = s >> 32;
-        }
+    // carries: chunk t covers words [t K, min(n, (t+1) K))
+    const long long K = (n + kThreads - 1) / kThreads;
+    const long long w0 = threadIdx.x * K < n ? threadIdx.x * K : n;
+    const long long w1 = w0 + K < n ? w0 + K : n;
+    uint32_t f = 0;                                   // bits 2c..2c+1: carry out for carry in c
+    for (uint32_t c = 0; c < 3; ++c) f |= chunk_carry(col, w0, w1, c, nullptr) << (2 * c);
+    fn[threadIdx.x] = (unsigned char)f;
+    __syncthreads();
+    // inclusive scan of the carry functions: g = f_t o f_(t-1) o ... o f_0
+    for (int d = 1; d < kThreads; d <<= 1) {
+        const uint32_t mine = fn[threadIdx.x];
+        const uint32_t prev = threadIdx.x >= d ? fn[threadIdx.x - d] : 0x24u;   // 0x24: identity
+        __syncthreads();
+        uint32_t comp = 0;
+        for (uint32_t c = 0; c < 3; ++c) comp |= ((mine >> (2 * ((prev >> (2 * c)) & 3))) & 3) << (2 * c);
+        fn[threadIdx.x] = (unsigned char)comp;
+        __syncthreads();
     }
+    const uint32_t cin = threadIdx.x ? fn[threadIdx.x - 1] & 3 : 0;
+    chunk_carry(col, w0, w1, cin, pd.c);
 }
 
 __global__ void k_fill(uint32_t* __restrict__ p, long long n, uint32_t v) {
@@ -1875,7 +1910,8 @@ int launch_zero(const ProdArgs& PA, unsigned G, size_t nw_max, hipStream_t s) {
 int launch_schoolbook(const Call& call, const ProdArgs& PA, unsigned G, size_t nw_max, double ops,
                       hipStream_t s) {
     ProfScope ps(call.prof, DKSS_K_SCHOOLBOOK, s, 8.0 * G * nw_max, ops);
-    hipLaunchKernelGGL(k_schoolbook, dim3(1, G), dim3(kThreads), nw_max * 3 * sizeof(uint32_t), s, PA);
+    const size_t lds = (std::max<size_t>(nw_max, 64) + 3 * nw_max) * sizeof(uint32_t);   // <= 64 KiB
+    hipLaunchKernelGGL(k_schoolbook, dim3(1, G), dim3(kThreads), lds, s, PA);
     return launch_status();
 }
 
