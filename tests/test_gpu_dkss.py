@@ -176,6 +176,23 @@ def test_mul_zero_length_and_schoolbook_path(env):
         assert np.array_equal(_gpu_mul(env, a, b), C.schoolbook(a, b)), (alen, blen)
 
 
+@pytest.mark.parametrize("alen,blen,ones", [(2048, 2048, True), (2048, 2048, False), (4095, 1, True),
+                                             (2, 2, True), (31, 32, True), (1000, 3000, False)])
+def test_schoolbook_base_case_up_to_its_limit(env, alen, blen, ones):
+    """The base case forced (cutoff above both operands) up to alen + blen = 4096 words, with
+    all-ones operands (every column at its largest sum, carries through whole chunks of the
+    carry scan) and random ones."""
+    dk, torch, ctx = env
+    if ones:
+        a, b = SI.all_ones(alen), SI.all_ones(blen)
+    else:
+        a, b = SI.operand_pair(SI.SEED_BASE + 31 + alen, alen, blen)
+    p = ctx.select_params(32 * alen, 32 * blen)
+    p.cutoff_bits = 2 ** 64 - 1
+    assert ctx.plan_info(alen, blen, p).schoolbook
+    assert np.array_equal(_gpu_mul(env, a, b, params=p), C.schoolbook(a, b)), (alen, blen)
+
+
 # ---- the large configurations: 2^24 and 2^28 bits --------------------------------------------
 
 def test_mul_2e24_vs_oracle_dkss(env):
