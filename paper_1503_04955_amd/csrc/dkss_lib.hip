@@ -1495,6 +1495,14 @@ int plan_constants(dkss_ctx* ctx, Call* call) {
         uint32_t inv = q0;
         for (int i = 0; i < 5; ++i) inv *= 2u - q0 * inv;
         Q.qinv28 = (0u - inv) & kMask28;
+        // q = 1 + qd[e] 2^(28e) + qd[e+1] 2^(28(e+1)): the reduction's sparse steps
+        if (Q.qd[0] == 1) {
+            int e = 1;
+            while (e < D && Q.qd[e] == 0) ++e;
+            bool sparse = e < D;
+            for (int k = e + 2; k < D; ++k) sparse = sparse && Q.qd[k] == 0;
+            Q.se = sparse ? e : 0;
+        }
         // R' = 2^(28K) mod q, R'^2 mod q, (2M)^-1 mod q
         Big Rm = mq.reduce(Big::of(1));
         for (int i = 0; i < 28 * K; ++i) Rm = mq.add(Rm, Rm);

@@ -26,6 +26,7 @@ struct QConst {
     uint32_t qinv28;         // -q^-1 mod 2^28
     uint32_t kpw[kMaxD + 2]; // digits of (2M)^-1 R'^2 mod q: rescales a pointwise product
     uint32_t ql[kMaxL];      // q in 32-bit limbs
+    int se;                  // e >= 1 when q = 1 + qd[e] 2^(28e) + qd[e+1] 2^(28(e+1)), else 0
 };
 
 template <int L>
@@ -193,18 +194,37 @@ __host__ __device__ __forceinline__ void lmod_sub(uint32_t* r, const uint32_t* x
 
 // ----- Montgomery reduction of a column sum ---------------------------------------------------
 
+// The K Montgomery steps for a modulus q = 1 + qd[E] 2^(28E) + qd[E+1] 2^(28(E+1)) (a prime
+// h 2^n + 1 with n >= 28, the thesis's kind of prime, Sec. 4.5): -q^-1 = -1 mod 2^28, and of the
+// D digit products of a step only two are not zero.
+template <int L, int E>
+__host__ __device__ __forceinline__ void redc_steps_sparse(uint64_t* col, const QConst& Q) {
+    using G = Dig<L>;
+#pragma unroll
+    for (int i = 0; i < G::K; ++i) {
+        const uint32_t u = (0u - (uint32_t)col[i]) & kMask28;
+        col[i + 1] += (col[i] + u) >> 28;
+        col[i + E] += (uint64_t)u * Q.qd[E];
+        if (E + 1 < G::D) col[i + E + 1] += (uint64_t)u * Q.qd[E + 1];
+    }
+}
+
 // col holds S = sum_k col[k] 2^(28k) with S < 64 q^2 (any split into 64-bit columns whose
 // running totals stay below 2^64).  Writes S 2^(-28K) mod q, canonical, in digits to x.
 template <int L>
 __host__ __device__ __forceinline__ void redc_cols(uint64_t* col, const QConst& Q, uint32_t* x) {
     using G = Dig<L>;
+    if (Q.se == (32 * L - 1) / 28) {
+        redc_steps_sparse<L, (32 * L - 1) / 28>(col, Q);
+    } else {
 #pragma unroll
-    for (int i = 0; i < G::K; ++i) {
-        uint32_t s = (uint32_t)col[i] & kMask28;
-        uint32_t u = (s * Q.qinv28) & kMask28;
+        for (int i = 0; i < G::K; ++i) {
+            uint32_t s = (uint32_t)col[i] & kMask28;
+            uint32_t u = (s * Q.qinv28) & kMask28;
 #pragma unroll
-        for (int y = 0; y < G::D; ++y) col[i + y] += (uint64_t)u * Q.qd[y];
-        col[i + 1] += col[i] >> 28;
+            for (int y = 0; y < G::D; ++y) col[i + y] += (uint64_t)u * Q.qd[y];
+            col[i + 1] += col[i] >> 28;
+        }
     }
     // the result (< 2q < 2^(28D)) sits in columns K .. K+D-1
     uint64_t carry = 0;

@@ -9,6 +9,18 @@ using namespace dkss;
 
 namespace {
 
+// e >= 1 when q = 1 + qd[e] 2^(28e) + qd[e+1] 2^(28(e+1)) (the library's rule for its sparse
+// Montgomery steps), else 0
+int sparse_e(int D, const uint32_t* qd) {
+    if (qd[0] != 1) return 0;
+    int e = 1;
+    while (e < D && qd[e] == 0) ++e;
+    if (e >= D) return 0;
+    for (int k = e + 2; k < D; ++k)
+        if (qd[k] != 0) return 0;
+    return e;
+}
+
 template <int L>
 void run(int op, const uint32_t* qd, uint32_t qinv, const uint32_t* a, const uint32_t* b, int log2m,
          int j, int r, uint32_t* out) {
@@ -17,6 +29,7 @@ void run(int op, const uint32_t* qd, uint32_t qinv, const uint32_t* a, const uin
     memcpy(Q.qd, qd, sizeof(uint32_t) * Dig<L>::D);
     digits_to_limbs<L>(qd, Q.ql);
     Q.qinv28 = qinv;
+    Q.se = sparse_e(Dig<L>::D, qd);
     switch (op) {
         case 0: dmod_add<L>(out, a, b, Q); break;
         case 1: dmod_sub<L>(out, a, b, Q); break;
@@ -49,6 +62,21 @@ int da_DS(int L) {
         case 5: return Dig<5>::DS; case 6: return Dig<6>::DS; case 7: return Dig<7>::DS; case 8: return Dig<8>::DS;
     }
     return -1;
+}
+
+// 1 when the Montgomery reduction for modulus digits qd takes its sparse steps
+int da_sparse(int L, const uint32_t* qd) {
+    switch (L) {
+        case 1: return sparse_e(Dig<1>::D, qd) == (32 * 1 - 1) / 28;
+        case 2: return sparse_e(Dig<2>::D, qd) == (32 * 2 - 1) / 28;
+        case 3: return sparse_e(Dig<3>::D, qd) == (32 * 3 - 1) / 28;
+        case 4: return sparse_e(Dig<4>::D, qd) == (32 * 4 - 1) / 28;
+        case 5: return sparse_e(Dig<5>::D, qd) == (32 * 5 - 1) / 28;
+        case 6: return sparse_e(Dig<6>::D, qd) == (32 * 6 - 1) / 28;
+        case 7: return sparse_e(Dig<7>::D, qd) == (32 * 7 - 1) / 28;
+        case 8: return sparse_e(Dig<8>::D, qd) == (32 * 8 - 1) / 28;
+    }
+    return 0;
 }
 
 int da_K(int L) {

@@ -46,15 +46,15 @@ def arr(vals, n=None):
 
 
 def moduli(L, rng):
-    """Moduli q with ceil(bits(q)/32) = L: a random odd one and, where it fits, p = h 2^n + 1
-    with a small h (mostly zero 28-bit digits)."""
+    """Moduli q with ceil(bits(q)/32) = L: a random odd one and, where n >= 28, p = h 2^n + 1
+    with a small h (mostly zero 28-bit digits: the reduction's sparse steps when the high digit
+    sits where the library expects it, its general steps otherwise)."""
     bits = 32 * L
     out = [rng.getrandbits(bits) | (1 << (bits - 1)) | 1]
-    if bits >= 64:
-        for h in (13, 27, 81):
-            n = bits - h.bit_length()
-            if n >= 56:
-                out.append(h * (1 << n) + 1)
+    for h in (3, 13, 27, 81):
+        n = bits - h.bit_length()
+        if n >= 28:
+            out.append(h * (1 << n) + 1)
     return out
 
 
@@ -121,6 +121,20 @@ def test_ring_product_coefficient(da, L, log2m):
                 want = sum(t[i] * ax[(j - i) % m] * (1 if j >= i else -1) for i in range(m)) % q
                 o, _ = call(da, L, 3, q, arr(TP), arr(X), D, log2m, j, r)
                 assert value(o) == want * Rinv % q, (q, j, r)
+
+
+@pytest.mark.parametrize("L", [1, 2, 3, 4, 5, 6, 7, 8])
+def test_sparse_reduction_is_exercised(da, L):
+    """The thesis's kind of prime, p = h 2^n + 1 with n >= 28 and a small h, takes the sparse
+    Montgomery steps (two digit products per step) at every L, and a random odd modulus the
+    general ones; the products above check both against Python integers."""
+    D = da.da_D(L)
+    bits = 32 * L
+    h = 13 if L != 1 else 3
+    p = h * (1 << (bits - h.bit_length())) + 1
+    assert da.da_sparse(L, arr(digits(p, D))) == 1
+    q = random.Random(L).getrandbits(bits) | (1 << (bits - 1)) | 1
+    assert da.da_sparse(L, arr(digits(q, D))) == 0
 
 
 @pytest.mark.parametrize("L", [2, 5, 6, 8])
