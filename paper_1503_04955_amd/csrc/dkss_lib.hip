@@ -773,18 +773,88 @@ __device__ __forceinline__ uint64_t word_sum(long long w, const uint32_t* __rest
     return V;
 }
 
+// Words of a position's aligned value: V_g < 2^(28D + 1) shifted left by up to 31 bits.
+template <int L>
+__host__ __device__ constexpr int pos_words() { return (28 * Dig<L>::D + 1 + 31 + 31) / 32; }
+
+// Position g = l m/2 + k (k < m/2) of the product's coefficient sequence: the value
+// V_g = c_(l,k) + c_(l-1,k+m/2) (the upper half of element l-1 overlaps the lower half of element l,
+// Sec. 3.2.8) starts at bit u g.  Writes V_g shifted left by (u g) mod 32 as pos_words() words,
+// so that word i of it is bits [32 (W_g + i), 32 (W_g + i + 1)) of its contribution, W_g = u g div 32.
+template <int L>
+__device__ __forceinline__ void position_value(const uint32_t* __restrict__ poly, long long g, long long twoM,
+                                               int log2m, int u, uint32_t* out) {
+    constexpr int D = Dig<L>::D, NW = pos_words<L>();
+    const int m = 1 << log2m, hm = m >> 1;
+    const long long l = g >> (log2m - 1);
+    const int k = (int)(g & (hm - 1));
+    const bool has1 = l < twoM, has2 = l >= 1 && l - 1 < twoM;
+    const size_t o1 = has1 ? ((size_t)l * m + k) * D : 0;
+    const size_t o2 = has2 ? ((size_t)(l - 1) * m + k + hm) * D : 0;
+    uint32_t v[D + 1];
+    uint32_t carry = 0;
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+        const uint32_t x = has1 ? poly[o1 + i] : 0u;
+        const uint32_t y = has2 ? poly[o2 + i] : 0u;
+        const uint32_t t = x + y + carry;                 // < 2^29 + 1
+        v[i] = t & kMask28;
+        carry = t >> 28;
+    }
+    v[D] = carry;
+    // 32-bit limbs of V (28 (D + 1) bits), then the shift by sh = u g mod 32
+    constexpr int NL = (28 * (D + 1) + 31) / 32;
+    uint32_t lv[NL + 1];
+#pragma unroll
+    for (int w = 0; w < NL; ++w) {
+        const int bit = 32 * w;
+        const int d = bit / 28, s0 = bit % 28;
+        uint64_t x = v[d];
+        if (d + 1 <= D) x |= (uint64_t)v[d + 1] << 28;
+        if (d + 2 <= D) x |= (uint64_t)v[d + 2] << 56;
+        lv[w] = (uint32_t)(x >> s0);
+    }
+    lv[NL] = 0;
+    const int sh = (int)(((unsigned)u * (unsigned)g) & 31u);
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+        const uint32_t lo = w >= 1 && w - 1 <= NL ? lv[w - 1] : 0u;
+        const uint32_t hi = w <= NL ? lv[w] : 0u;
+        out[w] = (uint32_t)(((((uint64_t)hi << 32) | lo) << sh) >> 32);
+    }
+}
+
+// Sum of word w's 32-bit pieces from the positions in LDS (positions g_min .. g_max of the
+// workgroup, pos_words() words each).
+template <int L>
+__device__ __forceinline__ uint64_t word_sum_tiled(long long w, const uint32_t* pv, long long g_min, long long g_max,
+                                                   int u, double inv_u) {
+    constexpr int D = Dig<L>::D, NW = pos_words<L>();
+    const long long lo_excl = 32 * w - (28 * D + 1);      // V_g reaches word w iff u g > lo_excl
+    long long g = lo_excl < 0 ? 0 : div_u(lo_excl, u, inv_u) + 1;
+    long long g_hi = div_u(32 * w + 31, u, inv_u);
+    if (g < g_min) g = g_min;
+    if (g_hi > g_max) g_hi = g_max;
+    uint64_t V = 0;
+    for (; g <= g_hi; ++g) {
+        const long long W = ((long long)u * g) >> 5;
+        V += pv[(g - g_min) * NW + (w - W)];
+    }
+    return V;
+}
+
 // Per 256 output words: x_w = low(V_w) + high(V_(w-1)) < 2^32 + 2^12, so word w generates a carry
 // (x_w >= 2^32) or propagates one (low 32 bits all ones), never both.  Writes the low 32 bits
-// and the per-wavefront generate / propagate masks.  TILED: the workgroup first copies the
-// elements its words draw on (one contiguous range) into LDS; the host picks it when that range
-// fits (decode_tile_words).
+// and the per-wavefront generate / propagate masks.  TILED: the workgroup first writes the
+// aligned values of the positions its words draw on into LDS (one position per thread and step),
+// then sums each word from them; the host picks it when those positions fit.
 template <int L, bool TILED>
 __global__ __launch_bounds__(kThreads) void k_decode(ProdArgs PA, const uint32_t* __restrict__ poly0,
                                                      long long stride, long long twoM, int log2m,
                                                      unsigned long long* __restrict__ gmask0,
                                                      unsigned long long* __restrict__ pmask0,
                                                      long long wstride) {
-    constexpr int D = Dig<L>::D;
+    constexpr int D = Dig<L>::D, NW = pos_words<L>();
     __shared__ uint32_t hiv[kThreads + 1];
     extern __shared__ uint4 dsmv[];
     const ProdDesc pd = PA.get();
@@ -796,37 +866,30 @@ __global__ __launch_bounds__(kThreads) void k_decode(ProdArgs PA, const uint32_t
     unsigned long long* __restrict__ pmask = pmask0 + (size_t)blockIdx.y * wstride;
     const long long w0 = (long long)blockIdx.x * kThreads;
     const long long w = w0 + threadIdx.x;
-    const uint32_t* src = poly;
-    long long lbase = 0;
-    if (TILED && w0 < nw) {
-        // elements holding the pieces of words w0 - 1 .. min(w0 + 255, nw - 1)
-        const int m = 1 << log2m;
+    uint64_t V = 0, Vprev = 0;
+    if (TILED) {
+        // positions reaching words w0 - 1 .. min(w0 + 255, nw - 1)
+        uint32_t* pv = reinterpret_cast<uint32_t*>(dsmv);
         const double inv_u = 1.0 / (double)u;
-        const long long wlo = w0 > 0 ? w0 - 1 : 0;
-        const long long whi = (w0 + kThreads - 1 < nw ? w0 + kThreads : nw) - 1;
-        const long long lo_excl = 32 * wlo - 28 * D;
-        const long long g_min = lo_excl < 0 ? 0 : div_u(lo_excl, u, inv_u) + 1;
-        const long long g_max = div_u(32 * whi + 31, u, inv_u);
-        const long long l_min = (g_min >> (log2m - 1)) > 0 ? (g_min >> (log2m - 1)) - 1 : 0;
-        const long long l_top = g_max >> (log2m - 1);
-        const long long l_max = l_top < twoM - 1 ? l_top : twoM - 1;
-        uint32_t* dsm = reinterpret_cast<uint32_t*>(dsmv);
-        const int nwords = (int)((l_max - l_min + 1) * m * D);
-        const uint32_t* g0 = poly + (size_t)l_min * m * D;
-        if (((m * D) & 3) == 0) {
-            const uint4* gv = reinterpret_cast<const uint4*>(g0);
-            for (int t = threadIdx.x; t < (nwords >> 2); t += kThreads) dsmv[t] = gv[t];
-        } else {
-            for (int t = threadIdx.x; t < nwords; t += kThreads) dsm[t] = g0[t];
+        long long g_min = 0, g_max = -1;
+        if (w0 < nw) {
+            const long long wlo = w0 > 0 ? w0 - 1 : 0;
+            const long long whi = (w0 + kThreads - 1 < nw ? w0 + kThreads : nw) - 1;
+            const long long lo_excl = 32 * wlo - (28 * D + 1);
+            g_min = lo_excl < 0 ? 0 : div_u(lo_excl, u, inv_u) + 1;
+            g_max = div_u(32 * whi + 31, u, inv_u);
         }
-        src = dsm;
-        lbase = l_min;
+        for (long long g = g_min + threadIdx.x; g <= g_max; g += kThreads)
+            position_value<L>(poly, g, twoM, log2m, u, pv + (g - g_min) * NW);
+        __syncthreads();
+        if (w < nw) V = word_sum_tiled<L>(w, pv, g_min, g_max, u, inv_u);
+        if (threadIdx.x == 0 && w0 > 0 && w0 < nw) Vprev = word_sum_tiled<L>(w0 - 1, pv, g_min, g_max, u, inv_u);
+    } else {
+        if (w < nw) V = word_sum<L>(w, poly, 0, twoM, log2m, u);
+        if (threadIdx.x == 0 && w0 > 0 && w0 < nw) Vprev = word_sum<L>(w0 - 1, poly, 0, twoM, log2m, u);
     }
-    if (TILED) __syncthreads();
-    const uint64_t V = w < nw ? word_sum<L>(w, src, lbase, twoM, log2m, u) : 0;
     hiv[threadIdx.x + 1] = (uint32_t)(V >> 32);
-    if (threadIdx.x == 0)
-        hiv[0] = (w0 > 0 && w0 < nw) ? (uint32_t)(word_sum<L>(w0 - 1, src, lbase, twoM, log2m, u) >> 32) : 0u;
+    if (threadIdx.x == 0) hiv[0] = (uint32_t)(Vprev >> 32);
     __syncthreads();
     const uint64_t x = (uint64_t)(uint32_t)V + hiv[threadIdx.x];
     const uint32_t y = (uint32_t)x;
@@ -1806,11 +1869,11 @@ struct Decode {
         const long long nseg = (nwaves + kThreads - 1) / kThreads;
         {
             ProfScope ps(c.prof, DKSS_K_DECODE, s, S + 4.0 * out_words, 0.0);
-            // elements per workgroup: pieces of 257 words span (32*257 + 28D + 31)/u + 2 values of
-            // g, each element m/2 of them, plus one element on either side
-            const int m = c.P.m(), D = Dig<L>::D;
-            const long long gspan = (32LL * (kThreads + 1) + 28 * D + 31) / std::max(u_min, 1) + 2;
-            const long long tile_words = (gspan / (m / 2) + 3) * m * D;
+            // positions per workgroup: the values reaching 257 words start within
+            // 32*257 + 28D + 1 bits, (32*257 + 28D + 1)/u + 2 positions of pos_words() words each
+            const int D = Dig<L>::D;
+            const long long gspan = (32LL * (kThreads + 1) + 28 * D + 1) / std::max(u_min, 1) + 2;
+            const long long tile_words = gspan * pos_words<L>();
             if (u_min >= 1 && tile_words * 4 <= 32768)
                 hipLaunchKernelGGL((k_decode<L, true>), dim3(blocks, G), dim3(kThreads), tile_words * 4, s, PA,
                                    (const uint32_t*)w.A, (long long)w.S, 2LL << c.P.log2_M, c.P.log2_m,
