@@ -13,8 +13,8 @@ dkss_mul_batch call.  Every timed product is checked by residues on the GPU (all
 product, the first and the last of a batch).
 
 Sets of points
-  train     x in 12..29.5 step 0.5, ratios 1,2,4,8, batch 1; and x in 12..22 step 1, ratios
-            1,2,4,8, batch 16, 256, 4096 while batch * 2^x <= 2^33
+  train     x in 12..29.5 step 0.5, ratios 1,2,4,8, batch 1; x in 12..22 step 0.5 for batch 16
+            and 256 and step 1 for batch 4096, ratios 1,2,4,8, while batch * 2^x <= 2^33
   heldout   points the selector never sees in training: x = 30 and quarter points between the
             training sizes, ratio 1 and 3, batch 1; and batch 64 and 1024 at quarter points
   kernels   for each training size from 2^16 bits (ratio 1, batch 1) and its fastest candidate:
@@ -51,11 +51,16 @@ def train_points():
         for r in (1, 2, 4, 8):
             pts.append((x, r, 1))
         x += 0.5
+    # batches: every half-integer size for 16 and 256 products, whole sizes for 4096 (their
+    # points are the costly ones)
     for B in (16, 256, 4096):
-        for xi in range(12, 23):
-            if B * 2.0 ** xi <= 2.0 ** 33:
+        step = 1.0 if B == 4096 else 0.5
+        x = 12.0
+        while x <= 22.0 + 1e-9:
+            if B * 2.0 ** x <= 2.0 ** 33:
                 for r in (1, 2, 4, 8):
-                    pts.append((float(xi), r, B))
+                    pts.append((x, r, B))
+            x += step
     return pts
 
 
