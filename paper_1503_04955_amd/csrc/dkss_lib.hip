@@ -265,20 +265,30 @@ __device__ __forceinline__ void encode_limbs(const uint32_t* __restrict__ a, lon
     }
 }
 
-// The top forward level's columns straight from the operand (Step 4 fused into the first level):
-// element at position j of a column into slot bitrev(j), as limbs.
+// The top forward level's columns straight from the operand (Step 4 fused into the first level),
+// with the DFT's first pass done on the way in.  At the top level position j of a column is
+// element j mu + l, which is zero padding for j >= r/2 (elements M..2M-1, Sec. 3.2.4); the first
+// decimation-in-time pass pairs slots 2k and 2k+1, holding positions bitrev(2k) < r/2 and
+// bitrev(2k) + r/2, without rotation, so it leaves the element of position bitrev(2k) in both.
+// Each element at j < r/2 is therefore written, as limbs, to slots bitrev(j) and bitrev(j) + 1,
+// and the DFT starts at its second pass.
 template <int L, int LS>
 __device__ __forceinline__ void level_encode_in(uint32_t* cur, const uint32_t* __restrict__ a, long long alen,
                                                 int u, long long M, const LevelArgs& A, long long c0) {
-    const int nel = 1 << (A.log2C + A.log2r);
+    const int nel = 1 << (A.log2C + A.log2r - 1);        // the elements at j < r/2
     for (int t = threadIdx.x; t < (nel << A.log2m); t += kThreads) {
         const int e = t >> A.log2m, k = t & ((1 << A.log2m) - 1);
         const int c = e & ((1 << A.log2C) - 1), j = e >> A.log2C;
         uint32_t out[L];
         encode_limbs<L>(a, alen, u, level_pos(A, c0, c, j), k, M, A.log2m, out);
-        uint32_t* dst = cur + ((((c << A.log2r) + bitrev(j, A.log2r)) << A.log2m) + k) * LS;
+        const int slot = (c << A.log2r) + bitrev(j, A.log2r);
+        uint32_t* d0 = cur + ((slot << A.log2m) + k) * LS;
+        uint32_t* d1 = cur + (((slot + 1) << A.log2m) + k) * LS;
 #pragma unroll
-        for (int w = 0; w < L; ++w) dst[w] = out[w];
+        for (int w = 0; w < L; ++w) {
+            d0[w] = out[w];
+            d1[w] = out[w];
+        }
     }
 }
 
@@ -436,17 +446,17 @@ __device__ __forceinline__ void level_twiddle(Ahead<L>& f, uint32_t* cur, uint32
     if (A.mode == 2) __syncthreads();
 }
 
-// log2 r radix-2 decimation-in-time passes over the workgroup's columns (limbs, L words per
+// log2 r radix-2 decimation-in-time passes over the workgroup's columns (limbs, LS words per
 // coefficient), from cur into nxt and back (the buffers are swapped after each pass; on return
 // cur holds the result).  Input: the element at position j of a column in slot bitrev(j);
 // output: position v in slot v.  The pass merging halves of h points multiplies the odd half by
-// alpha^((m/h) k) (alpha^-1 if inverse).
+// alpha^((m/h) k) (alpha^-1 if inverse).  Passes before first_pass are taken as done.
 template <int L, int LS>
 __device__ __forceinline__ void dft_passes(uint32_t*& cur, uint32_t*& nxt, const LevelArgs& A, int inverse,
-                                           const QConst& Q) {
+                                           const QConst& Q, int first_pass = 0) {
     const int m = 1 << A.log2m, r = 1 << A.log2r;
     const int tasks = (1 << (A.log2C + A.log2r - 1)) << A.log2m;   // butterflies x coefficients
-    for (int h = 1, lh = 0; h < r; h <<= 1, ++lh) {
+    for (int h = 1 << first_pass, lh = first_pass; h < r; h <<= 1, ++lh) {
         const int lmh = A.log2m - lh;                   // log2(m/h)
         for (int t = threadIdx.x; t < tasks; t += kThreads) {
             const int jj = t & (m - 1);
@@ -608,7 +618,7 @@ __global__ __launch_bounds__(kThreads) void k_level(uint32_t* __restrict__ poly0
     __syncthreads();
     uint32_t* cur = H0;
     uint32_t* nxt = H1;
-    dft_passes<L, LS>(cur, nxt, A, MODE == 3 ? 0 : A.inverse, Q);
+    dft_passes<L, LS>(cur, nxt, A, MODE == 3 ? 0 : A.inverse, Q, ENC ? 1 : 0);   // ENC: pass 0 done
     if (MODE == 0) {
         level_store_limbs<L, LS>(poly, cur, A, c0);
         return;
