@@ -54,7 +54,7 @@ enum {
 /*
  * One parameter tuple (Sec. 3.2 Steps 1-2): FFT length 2M = 2^(log2_M+1), inner degree bound
  * m = 2^log2_m, u input bits per inner coefficient, prime p of p_bits bits (h*2^n + 1 with the
- * smallest odd h, Sec. 4.5) and modulus p^z.  Products with min(alen, blen)*32 <= cutoff_bits
+ * smallest odd h, Sec. 4.6) and modulus p^z.  Products with min(alen, blen)*32 <= cutoff_bits
  * use the schoolbook base case instead.  radix_log2[i] (i < n_levels) optionally fixes the FFT
  * level split: 2M = prod 2^radix_log2[i], each radix at most 2m; n_levels = 0 lets the library
  * choose (levels of radix 2m, then the remainder, as in the thesis's recursion, Sec. 4.2).

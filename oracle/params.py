@@ -6,7 +6,7 @@ leg may use this module.  Every function cites the thesis passage it follows
 
 Contents
   thesis_rule       Sec. 4.1 (Parameter Selection) with Sec. 3.2 Steps 1-2
-  proth_prime       Sec. 3.2.2 and Sec. 4.5 (table of primes h*2^n+1, smallest odd h)
+  proth_prime       Sec. 3.2.2 and Sec. 4.6 (table of primes h*2^n+1, smallest odd h)
   generator         Sec. 3.2.3 (generator zeta of F_p^*)
   hensel_lift       Sec. 3.2.3, Hensel lifting theorem
   principal_root    Sec. 3.2.3 (omega = zeta_z^h)
@@ -90,7 +90,7 @@ def thesis_rule(N, p_bits=None, z=1):
 
 
 # ----------------------------------------------------------------------------------------------
-# Sec. 3.2.2 Finding the prime p; Sec. 4.5 (table of primes h*2^n + 1 with the smallest odd h)
+# Sec. 3.2.2 Finding the prime p; Sec. 4.6 (table of primes h*2^n + 1 with the smallest odd h)
 # ----------------------------------------------------------------------------------------------
 
 def _small_factors(h):
@@ -131,7 +131,7 @@ def is_prime_proth(h, n):
 
 def proth_prime(bits, min_two_power=1):
     """Prime p = h*2^n + 1 with exactly ``bits`` bits, the smallest odd h, n = bits - bitlen(h)
-    (Sec. 4.5: one prime per bit length with the smallest odd h), and 2^min_two_power | p - 1
+    (Sec. 4.6: one prime per bit length with the smallest odd h), and 2^min_two_power | p - 1
     (Sec. 3.2.2: 2M | p - 1).  Returns (p, h, n)."""
     h = 1
     while True:

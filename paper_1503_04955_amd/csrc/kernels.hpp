@@ -194,9 +194,9 @@ __host__ __device__ __forceinline__ void lmod_sub(uint32_t* r, const uint32_t* x
 
 // ----- Montgomery reduction of a column sum ---------------------------------------------------
 
-// The K Montgomery steps for a modulus q = 1 + qd[E] 2^(28E) + qd[E+1] 2^(28(E+1)) (a prime
-// h 2^n + 1 with n >= 28, the thesis's kind of prime, Sec. 4.5): -q^-1 = -1 mod 2^28, and of the
-// D digit products of a step only two are not zero.
+// The K Montgomery steps for a modulus q = 1 + qd[E] 2^(28E) + qd[E+1] 2^(28(E+1)), such as a
+// prime h 2^n + 1 with n >= 28 (the thesis's kind of prime, Sec. 3.2.2 and Sec. 4.6):
+// -q^-1 = -1 mod 2^28, and of the D digit products of a step only two are not zero.
 template <int L, int E>
 __host__ __device__ __forceinline__ void redc_steps_sparse(uint64_t* col, const QConst& Q) {
     using G = Dig<L>;

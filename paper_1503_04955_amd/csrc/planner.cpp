@@ -201,7 +201,7 @@ bool candidate_params(uint64_t N, int c, int* log2_M, int* log2_m, int* u, int* 
 }
 
 // ---------------------------------------------------------------------------------------------
-// Prime p (Sec. 3.2.2, Sec. 4.5) and generator (Sec. 3.2.3)
+// Prime p (Sec. 3.2.2, Sec. 4.6) and generator (Sec. 3.2.3)
 // ---------------------------------------------------------------------------------------------
 
 // Proth's theorem for p = h 2^n + 1, h < 2^n: p is prime iff a^((p-1)/2) = -1 for some a; a

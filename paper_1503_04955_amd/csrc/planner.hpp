@@ -77,7 +77,7 @@ bool thesis_params(uint64_t N, int* log2_M, int* log2_m, int* u, int* p_bits);
 constexpr int kNumCandidates = 18;
 bool candidate_params(uint64_t N, int c, int* log2_M, int* log2_m, int* u, int* p_bits);
 
-// Smallest odd h with p = h*2^n + 1 prime, n = bits - bitlen(h), n >= min_n (Sec. 4.5).
+// Smallest odd h with p = h*2^n + 1 prime, n = bits - bitlen(h), n >= min_n (Sec. 4.6).
 bool proth_prime(int bits, int min_n, Big* p, uint64_t* h, int* n);
 
 // Fill p, q, zeta, omega, rho of a plan whose parameters are set.  Returns false if the tuple

@@ -35,7 +35,7 @@ def _mr_probable_prime(n, bases=(2, 3, 5, 7, 11, 13, 17, 19, 23, 29, 31, 37)):
 
 
 def _memory_model(pr):
-    """DKSS_MUL memory as the thesis's allocation pattern implies (Sec. 4.2 listing, Sec. 4.6):
+    """DKSS_MUL memory as the thesis's allocation pattern implies (Sec. 4.2 listing, Sec. 4.5):
     two polynomials of 2M elements, the mu precomputed rho powers, per recursion level of the
     FFT a temporary of (2M' + 2m + 1) elements, the base case's one element, plus one element."""
     E = pr.m * pr.p_bits // 8
@@ -75,7 +75,7 @@ def test_rule_is_feasible(N):
 
 
 def test_rule_stair_step():
-    """One limb past a favorable length needs about twice the coefficients (Sec. 4.6)."""
+    """One limb past a favorable length needs about twice the coefficients (Sec. 4.5)."""
     a = P.thesis_rule(64 * 3648)
     b = P.thesis_rule(64 * 3648 + 32)
     assert (b.M * b.m) == 2 * (a.M * a.m) or b.u > a.u
