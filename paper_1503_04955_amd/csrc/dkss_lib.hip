@@ -373,7 +373,11 @@ __device__ __forceinline__ void tw_fetch(Ahead<L>& f, int r0, const uint32_t* __
     f.nz = false;
     f.rot = 0;
     if (el >= (1 << (A.log2C + A.log2r))) return;
-    const int c = el >> A.log2r, v = el & ((1 << A.log2r) - 1);
+    // the round's elements go by LDS slot (consecutive slots: their residues fall on distinct
+    // banks); a slot holds its own position after a DFT (mode 1), the bit-reversed one before
+    // a DFT (mode 2)
+    const int c = el >> A.log2r, slot = el & ((1 << A.log2r) - 1);
+    const int v = A.mode == 2 ? bitrev(slot, A.log2r) : slot;
     const long long l = (c0 + c) & ((1LL << A.log2mu) - 1);
     long long e = A.base * l * v;                       // < 2M
     if (A.inverse && e) e = A.twoM - e;
@@ -407,10 +411,10 @@ __device__ __forceinline__ void level_twiddle(Ahead<L>& f, uint32_t* cur, uint32
     // The m lanes of an element lie in one wavefront (m <= 64) and touch only that element's
     // column slot and staging area, so the rounds synchronize per wavefront.
     for (int r0 = 0; r0 < nel; r0 += per) {
-        const int el = r0 + g;                          // (c, v) with v fastest
+        const int el = r0 + g;                          // (c, slot) with slot fastest
         const bool valid = el < nel;
-        const int c = el >> A.log2r, v = el & ((1 << A.log2r) - 1);
-        const int slot = A.mode == 1 ? v : bitrev(v, A.log2r);
+        const int c = el >> A.log2r, slot = el & ((1 << A.log2r) - 1);
+        const int v = A.mode == 2 ? bitrev(slot, A.log2r) : slot;        // its position
         uint32_t* X = cur + ((c << A.log2r) + slot) * EW;
         const bool nz = f.nz;
         const int rot = f.rot;
