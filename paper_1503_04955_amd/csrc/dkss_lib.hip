@@ -460,6 +460,11 @@ __device__ __forceinline__ void dft_passes(uint32_t*& cur, uint32_t*& nxt, const
                                            const QConst& Q, int first_pass = 0) {
     const int m = 1 << A.log2m, r = 1 << A.log2r;
     const int tasks = (1 << (A.log2C + A.log2r - 1)) << A.log2m;   // butterflies x coefficients
+    // q's limbs in vector registers for all passes: an add or subtract with carry already reads
+    // its carry from scalar registers and may read only one scalar operand
+    uint32_t qv[L];
+#pragma unroll
+    for (int w = 0; w < L; ++w) asm volatile("v_mov_b32 %0, %1" : "=v"(qv[w]) : "s"(Q.ql[w]));
     for (int h = 1 << first_pass, lh = first_pass; h < r; h <<= 1, ++lh) {
         const int lmh = A.log2m - lh;                   // log2(m/h)
         for (int t = threadIdx.x; t < tasks; t += kThreads) {
@@ -468,24 +473,16 @@ __device__ __forceinline__ void dft_passes(uint32_t*& cur, uint32_t*& nxt, const
             const int bf = rest & ((r >> 1) - 1);
             const int c = rest >> (A.log2r - 1);
             const int kk = bf & (h - 1);
-            const int xs = ((bf - kk) << 1) + kk;
-            const int ys = xs + h;
-            int e = kk << lmh;
-            if (inverse) e = (2 * m - e) & (2 * m - 1);
-            // (alpha^e y)_jj = +- y_idx, negated once per wrap past degree m-1
-            int idx = jj - e;
-            bool neg = false;
-            if (idx < 0) {
-                idx += m;
-                neg = true;
-                if (idx < 0) {
-                    idx += m;
-                    neg = false;
-                }
-            }
-            // coefficient slots (element * m + coefficient), L words each
+            const int xs = (bf << 1) - kk;
+            const int e = kk << lmh;                    // alpha^e, alpha^-e if inverse
+            // (alpha^(+-e) y)_jj = y_w for w = jj -+ e mod 2m below m, -y_(w-m) otherwise
+            // (alpha^m = -1, alpha^2m = 1)
+            const int w2 = (inverse ? jj + e : jj - e) & (2 * m - 1);
+            const bool neg = (w2 & m) != 0;
+            const int idx = w2 & (m - 1);
+            // coefficient slots (element * m + coefficient), LS words each
             const int ex = ((c << A.log2r) + xs) << A.log2m;
-            const int ey = ((c << A.log2r) + ys) << A.log2m;
+            const int ey = ex + (h << A.log2m);
             const uint32_t* X = cur + (ex + jj) * LS;
             const uint32_t* Y = cur + (ey + idx) * LS;
             uint32_t xv[L], yv[L], sv[L], dv[L];
@@ -494,8 +491,8 @@ __device__ __forceinline__ void dft_passes(uint32_t*& cur, uint32_t*& nxt, const
                 xv[w] = X[w];
                 yv[w] = Y[w];
             }
-            lmod_add<L>(sv, xv, yv, Q);
-            lmod_sub<L>(dv, xv, yv, Q);
+            lmod_add<L>(sv, xv, yv, qv);
+            lmod_sub<L>(dv, xv, yv, qv);
             // a negated y swaps the two outputs: chosen by address, not per limb
             uint32_t* PS = nxt + ((neg ? ey : ex) + jj) * LS;
             uint32_t* PD = nxt + ((neg ? ex : ey) + jj) * LS;

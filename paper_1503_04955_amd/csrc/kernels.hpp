@@ -164,32 +164,32 @@ __host__ __device__ __forceinline__ void limbs_to_digits(const uint32_t* x, uint
 // A residue in L limbs, canonical in [0, q); additions use the hardware carry (add/sub with carry
 // chains): 2q < 2^(32L + 1), the carry out of the top limb is the extra bit.
 
-// r = x + y mod q
+// r = x + y mod q, q given by its limbs ql
 template <int L>
 __host__ __device__ __forceinline__ void lmod_add(uint32_t* r, const uint32_t* x, const uint32_t* y,
-                                                  const QConst& Q) {
+                                                  const uint32_t* ql) {
     uint32_t s[L], d[L];
     unsigned int c = 0, b = 0;
 #pragma unroll
     for (int k = 0; k < L; ++k) s[k] = __builtin_addc(x[k], y[k], c, &c);
 #pragma unroll
-    for (int k = 0; k < L; ++k) d[k] = __builtin_subc(s[k], Q.ql[k], b, &b);
+    for (int k = 0; k < L; ++k) d[k] = __builtin_subc(s[k], ql[k], b, &b);
     const bool ge = c || !b;                 // x + y >= q
 #pragma unroll
     for (int k = 0; k < L; ++k) r[k] = ge ? d[k] : s[k];
 }
 
-// r = x - y mod q
+// r = x - y mod q, q given by its limbs ql
 template <int L>
 __host__ __device__ __forceinline__ void lmod_sub(uint32_t* r, const uint32_t* x, const uint32_t* y,
-                                                  const QConst& Q) {
+                                                  const uint32_t* ql) {
     uint32_t d[L];
     unsigned int b = 0, c = 0;
 #pragma unroll
     for (int k = 0; k < L; ++k) d[k] = __builtin_subc(x[k], y[k], b, &b);
     const uint32_t mask = 0u - b;            // add q back if x < y
 #pragma unroll
-    for (int k = 0; k < L; ++k) r[k] = __builtin_addc(d[k], Q.ql[k] & mask, c, &c);
+    for (int k = 0; k < L; ++k) r[k] = __builtin_addc(d[k], ql[k] & mask, c, &c);
 }
 
 // ----- Montgomery reduction of a column sum ---------------------------------------------------

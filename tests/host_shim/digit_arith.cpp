@@ -37,8 +37,8 @@ void run(int op, const uint32_t* qd, uint32_t qinv, const uint32_t* a, const uin
         case 3: rprod_coeff<L>(a, b, log2m, j, r, Q, out); break;
         case 4: mont_scalar<L>(a, b, Q, out); break;
         case 5: digits_to_limbs<L>(a, out); break;
-        case 6: lmod_add<L>(out, a, b, Q); break;      // a, b, out in limbs
-        case 7: lmod_sub<L>(out, a, b, Q); break;
+        case 6: lmod_add<L>(out, a, b, Q.ql); break;   // a, b, out in limbs
+        case 7: lmod_sub<L>(out, a, b, Q.ql); break;
         case 8: limbs_to_digits<L>(a, out); break;
         default: break;
     }
