@@ -177,10 +177,11 @@ struct LevelArgs {
     int half;                     // words of each of the two LDS halves
 };
 
+// Position of element j of column c0 + c in the polynomial (positions stay below 2M < 2^32)
 __device__ __forceinline__ long long level_pos(const LevelArgs& A, long long c0, int c, int j) {
-    const long long col = c0 + c;
-    const long long b = col >> A.log2mu, l = col & ((1LL << A.log2mu) - 1);
-    return (b << A.log2nl) + ((long long)j << A.log2mu) + l;
+    const uint32_t col = (uint32_t)c0 + (uint32_t)c;
+    const uint32_t b = col >> A.log2mu, l = col & ((1u << A.log2mu) - 1u);
+    return (long long)((b << A.log2nl) + ((uint32_t)j << A.log2mu) + l);
 }
 
 // Copies between the workgroup's C r elements in HBM (digits) and LDS.  Element index e: column c
@@ -378,13 +379,13 @@ __device__ __forceinline__ void tw_fetch(Ahead<L>& f, int r0, const uint32_t* __
     // a DFT (mode 2)
     const int c = el >> A.log2r, slot = el & ((1 << A.log2r) - 1);
     const int v = A.mode == 2 ? bitrev(slot, A.log2r) : slot;
-    const long long l = (c0 + c) & ((1LL << A.log2mu) - 1);
-    long long e = A.base * l * v;                       // < 2M
-    if (A.inverse && e) e = A.twoM - e;
+    const uint32_t l = ((uint32_t)c0 + (uint32_t)c) & ((1u << A.log2mu) - 1u);
+    uint32_t e = (uint32_t)A.base * l * (uint32_t)v;    // < 2M < 2^32
+    if (A.inverse && e) e = (uint32_t)A.twoM - e;
     if (!e) return;
     f.nz = true;
     f.rot = (int)(e >> A.log2mut);
-    const long long s = e & ((1LL << A.log2mut) - 1);
+    const uint32_t s = e & ((1u << A.log2mut) - 1u);
     const uint32_t* ts = table + (size_t)s * 2 * m * D;
 #pragma unroll
     for (int y = 0; y < D; ++y) {
@@ -1739,6 +1740,7 @@ struct Transform {
                    const ProdArgs* enc = nullptr, int which = 0, double in_words = 0.0) {
         const Plan& P = c.P;
         const long long twoM = 2LL << P.log2_M;
+        if (twoM > (1LL << 31)) return DKSS_ERANGE;     // the kernels index positions in 32 bits
         const int m = P.m();
         const int nl = (int)P.radix_log2.size();
         const QConst& Q = c.C->Q;

@@ -255,6 +255,22 @@ __host__ __device__ __forceinline__ void normalize_cols(uint64_t* col) {
 // TP holds T_0..T_(2m-1) at a stride of DS words, X holds x_0..x_(m-1) at D words.  The lanes
 // of one element read the same x_k (one LDS address) and consecutive T entries (odd stride).
 // Returns c_j 2^(-28K) mod q in digits.
+// col[x + y] += t_x x_y over the D x D digit pairs of one term
+template <int L>
+__host__ __device__ __forceinline__ void rprod_term(uint64_t* col, const uint32_t* tp, const uint32_t* xp) {
+    using G = Dig<L>;
+    uint32_t tv[G::D], xv[G::D];
+#pragma unroll
+    for (int x = 0; x < G::D; ++x) {
+        tv[x] = tp[x];
+        xv[x] = xp[x];
+    }
+#pragma unroll
+    for (int x = 0; x < G::D; ++x)
+#pragma unroll
+        for (int y = 0; y < G::D; ++y) col[x + y] += (uint64_t)tv[x] * xv[y];
+}
+
 template <int L>
 __host__ __device__ __forceinline__ void rprod_coeff(const uint32_t* TP, const uint32_t* X, int log2m, int j,
                                             int r, const QConst& Q, uint32_t* out) {
@@ -265,20 +281,10 @@ __host__ __device__ __forceinline__ void rprod_coeff(const uint32_t* TP, const u
 #pragma unroll
     for (int k = 0; k < G::NC; ++k) col[k] = 0;
     int w = (j - r) & mask2;
-    for (int k = 0; k < m; ++k) {
-        const uint32_t* tp = TP + w * G::DS;
-        const uint32_t* xp = X + k * G::D;
-        uint32_t tv[G::D], xv[G::D];
-#pragma unroll
-        for (int x = 0; x < G::D; ++x) {
-            tv[x] = tp[x];
-            xv[x] = xp[x];
-        }
-#pragma unroll
-        for (int x = 0; x < G::D; ++x)
-#pragma unroll
-            for (int y = 0; y < G::D; ++y) col[x + y] += (uint64_t)tv[x] * xv[y];
+    rprod_term<L>(col, TP + w * G::DS, X);      // k = 0 ahead of the loop: the columns start from it
+    for (int k = 1; k < m; ++k) {
         w = (w - 1) & mask2;
+        rprod_term<L>(col, TP + w * G::DS, X + k * G::D);
         if ((k + 1) % G::NI == 0) normalize_cols<L>(col);
     }
     redc_cols<L>(col, Q, out);
