@@ -136,8 +136,9 @@ int dkss_prepare(dkss_ctx* ctx, size_t alen, size_t blen, const dkss_params* p, 
  * selector once for all new shapes of the batch, with batch = count.
  * Errors: DKSS_EINVAL, DKSS_ENOSPC, DKSS_ERANGE (p^z below
  * Mm 2^(2u), 2M not dividing p - 1, M < m, m < 2, capacity M*m/2*u below 32*max(alen, blen),
- * unsupported limb count, a kernel grid of 2^32 work-items or more: operands beyond about 2^35
- * bits, or a level split with very small radices), DKSS_EHIP.
+ * unsupported limb count, a transform length 2M above 2^31, a kernel grid of 2^32 work-items
+ * or more: operands beyond about 2^35 bits, or a level split with very small radices),
+ * DKSS_EHIP.
  */
 int dkss_mul(dkss_ctx* ctx, uint32_t* c, const uint32_t* a, size_t alen, const uint32_t* b,
              size_t blen, const dkss_params* p, void* ws, size_t ws_bytes, dkss_stream_t s);
