@@ -8,8 +8,11 @@ network kernels (dkss_mlp_loss_grad, dkss_mlp_adam), and evaluate its regret.
 Data: one sample per measured point (operand sizes, batch) of the tuner; input the selector's
 features (dkss_mlp_features), target the natural log of milliseconds per product for each
 output (DKSS candidate c, or the schoolbook), masked where the output was not measured
-(infeasible at that size).  Loss: masked mean squared error; Adam with a cosine-decayed step
-size; weights initialised from a seeded normal (He scaling), output biases at the mean target.
+(infeasible at that size).  Loss: weighted mean squared error, each measured output weighted
+by max(exp(-(ln t - ln t_best) / 0.3), 0.1), t_best the point's fastest output, so that the fit
+is closest where it decides the argmin (an output three times slower than the best still
+counts a tenth); Adam with a cosine-decayed step size; weights initialised from a seeded normal
+(He scaling), output biases at the mean target.
 
 Regret of a choice at a point = t(choice) / t(fastest measured output) - 1.
 """
@@ -59,6 +62,13 @@ def dataset(points):
                 T[i, label] = math.log(ms)
                 Mk[i, label] = 1.0
     return X, T, Mk, keys
+
+
+def decision_weights(T, Mk, tau=0.3, floor=0.1):
+    """Per-output loss weights: max(exp(-(ln t - ln t_best) / tau), floor) where measured, else 0."""
+    best = np.where(Mk > 0, T, np.inf).min(axis=1, keepdims=True)
+    best = np.where(np.isfinite(best), best, 0.0)
+    return np.where(Mk > 0, np.maximum(np.exp(-(T - best) / tau), floor), 0.0).astype(np.float32)
 
 
 def init_params(seed, mean_target):
@@ -151,12 +161,13 @@ def main():
         return
     pts = load_points(args.timings)
     X, T, Mk, keys = dataset(pts)
-    w, curve = train(X, T, Mk, args.steps, args.lr, args.seed)
+    w, curve = train(X, T, decision_weights(T, Mk), args.steps, args.lr, args.seed)
     regs = regrets(pts, predict(w, X), keys)
     fit = summary(regs, "learned")
     dk.mlp_save(args.out, w, comment=(
         "learned parameter selector, trained on %s (%d points, %d targets)\n"
-        "Adam, %d steps, lr %g cosine, seed %d; final loss %.5f; training-set regret mean %.4f"
+        "Adam, %d steps, lr %g cosine, seed %d; final weighted loss %.5f; training-set regret "
+        "mean %.4f"
         % (os.path.basename(args.timings), X.shape[0], int(Mk.sum()), args.steps, args.lr,
            args.seed, curve[-1][1], fit["mean"])))
     with open(os.path.splitext(args.out)[0] + "_train.json", "w") as f:
