@@ -207,3 +207,45 @@ def test_dkss_mul_other_moduli(log2_M, log2_m, u, p_bits, z):
     a, b = SI.operand_pair(u, cap, max(1, cap // 3))
     c = C.dkss_mul(a, b, S)
     assert C.from_limbs(c) == C.from_limbs(a) * C.from_limbs(b)
+
+
+def _planted_setup(good, p_bits):
+    """Steps 2-3 of Sec. 3.2 for good's M, m, u but a prime of p_bits bits, without the check
+    p^z >= Mm 2^(2u): the mistake a wrong parameter tuple would make."""
+    prm = P.Params(N=good.N, log2_M=good.log2_M, log2_m=good.log2_m, u=good.u, p_bits=p_bits, z=1)
+    p, h, n = P.proth_prime(p_bits, prm.log2_M + 1)
+    zeta = P.generator(p, h, n)
+    omega = P.principal_root(P.hensel_lift(zeta, p, 1), p, 1, prm.log2_M)
+    rho = P.rho_lagrange(omega, prm.m, prm.mu, p)
+    return P.Setup(params=prm, p=p, h=h, n=n, q=p, zeta=zeta, zeta_z=zeta, omega=omega, rho=rho)
+
+
+def test_residue_check_catches_planted_mistakes():
+    """The verifier's check (residues modulo 61-bit primes, as dkss_residues computes them on the
+    GPU) accepts the exact product and rejects: the product of a DKSS run whose modulus is below
+    the bound of Sec. 3.2.2 (coefficient sums wrap), and single-limb corruptions of the exact
+    product."""
+    alen = blen = 256
+    a, b = SI.all_ones(alen), SI.all_ones(blen)
+    exact = C.schoolbook(a, b)
+    rng = random.Random(77)
+    primes = []
+    while len(primes) < 8:
+        q = rng.getrandbits(61) | (1 << 60) | 1
+        if all(pow(w, q - 1, q) == 1 for w in (2, 3, 5, 7, 11, 13)):
+            primes.append(q)
+
+    def passes(c):
+        return all(C.residue(c, q) == C.residue(a, q) * C.residue(b, q) % q for q in primes)
+
+    assert passes(exact)
+    good = P.thesis_rule(32 * alen)
+    bad = _planted_setup(good, good.p_bits // 2)
+    assert bad.q < 1 << (good.log2_M + good.log2_m + 2 * good.u)
+    wrong = C.dkss_mul(a, b, setup=bad)
+    assert not np.array_equal(wrong, exact) and not passes(wrong)
+    for _ in range(20):
+        c = exact.copy()
+        i = rng.randrange(len(c))
+        c[i] ^= np.uint32(1 << rng.randrange(32))
+        assert not passes(c), i
