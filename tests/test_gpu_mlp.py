@@ -65,6 +65,22 @@ def test_loss_and_gradient_match_oracle(env, n):
     assert np.all(err[big] <= 2e-4 * np.abs(go[big]) + 1e-6 * scale)
 
 
+def test_weighted_loss_and_gradient_match_oracle(env):
+    """Real-valued per-output weights (as the trainer's decision weights) in place of the 0/1
+    mask: the same kernels, the oracle's weighted definition."""
+    dk, torch = env
+    from paper_1503_04955_amd import learn
+    th, X, T, Mk = _case(60, 300)
+    W = learn.decision_weights(T, Mk)
+    ws = float(W.sum())
+    g, loss = dk.mlp_loss_grad(_dev(torch, th), _dev(torch, X), _dev(torch, T), _dev(torch, W), ws)
+    lo, go = om.loss_grad(th.astype(np.float64), X.astype(np.float64), T.astype(np.float64),
+                          W.astype(np.float64), ws, OUT)
+    assert abs(float(loss.item()) - lo) <= 1e-5 * abs(lo)
+    scale = np.max(np.abs(go))
+    assert np.max(np.abs(g.cpu().numpy() - go)) <= 1e-4 * scale
+
+
 def test_gradient_is_deterministic(env):
     dk, torch = env
     th, X, T, Mk = _case(31, 999)
