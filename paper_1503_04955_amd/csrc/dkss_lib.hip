@@ -98,39 +98,37 @@ struct ProdArgs {
 // Step 4: encode
 // ---------------------------------------------------------------------------------------------
 
-// Digits of coefficient k of element i: bits [u (i m/2 + k), u (i m/2 + k) + u) of a for
-// k < m/2 and i < M; zero otherwise.
+// Coefficient k of element i as limbs: bits [u (i m/2 + k), u (i m/2 + k) + u) of a for k < m/2
+// and i < M; zero otherwise.
 template <int L>
-__device__ __forceinline__ void encode_digits(const uint32_t* __restrict__ a, long long alen, int u, long long i,
-                                              int k, long long M, int log2m, uint32_t* out) {
-    constexpr int D = Dig<L>::D;
+__device__ __forceinline__ void encode_limbs(const uint32_t* __restrict__ a, long long alen, int u, long long i,
+                                             int k, long long M, int log2m, uint32_t* out) {
     const int hm = 1 << (log2m - 1);
 #pragma unroll
-    for (int w = 0; w < D; ++w) out[w] = 0;
+    for (int w = 0; w < L; ++w) out[w] = 0;
     if (i < M && k < hm) {
         const unsigned long long pos = ((unsigned long long)i * hm + k) * (unsigned)u;
 #pragma unroll
-        for (int w = 0; w < D; ++w) {
-            const int nb = u - 28 * w;
+        for (int w = 0; w < L; ++w) {
+            const int nb = u - 32 * w;
             if (nb > 0) {
-                const unsigned long long bit = pos + 28ull * w;
+                const unsigned long long bit = pos + 32ull * w;
                 const long long wi = (long long)(bit >> 5);
                 const int sh = (int)(bit & 31);
                 const uint64_t lo = wi < alen ? a[wi] : 0u;
                 const uint64_t hi = wi + 1 < alen ? a[wi + 1] : 0u;
-                uint32_t v = (uint32_t)(((hi << 32) | lo) >> sh) & kMask28;
-                if (nb < 28) v &= (1u << nb) - 1u;
+                uint32_t v = (uint32_t)(((hi << 32) | lo) >> sh);
+                if (nb < 32) v &= (1u << nb) - 1u;
                 out[w] = v;
             }
         }
     }
 }
 
-// poly: 2M elements x m coefficients x D digits (encode_digits).
+// poly: 2M elements x m coefficients x L limbs.
 template <int L>
 __global__ __launch_bounds__(kThreads) void k_encode(ProdArgs PA, int which, uint32_t* __restrict__ poly0,
                                                      long long stride, long long M, int log2m) {
-    constexpr int D = Dig<L>::D;
     const ProdDesc pd = PA.get();
     const uint32_t* __restrict__ a = which ? pd.b : pd.a;
     const long long alen = which ? pd.blen : pd.alen;
@@ -142,11 +140,11 @@ __global__ __launch_bounds__(kThreads) void k_encode(ProdArgs PA, int which, uin
     const int m = 1 << log2m;
     const long long i = t >> log2m;
     const int k = (int)(t & (m - 1));
-    uint32_t out[D];
-    encode_digits<L>(a, alen, u, i, k, M, log2m, out);
-    uint32_t* dst = poly + (size_t)t * D;
+    uint32_t out[L];
+    encode_limbs<L>(a, alen, u, i, k, M, log2m, out);
+    uint32_t* dst = poly + (size_t)t * L;
 #pragma unroll
-    for (int w = 0; w < D; ++w) dst[w] = out[w];
+    for (int w = 0; w < L; ++w) dst[w] = out[w];
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -184,85 +182,42 @@ __device__ __forceinline__ long long level_pos(const LevelArgs& A, long long c0,
     return (long long)((b << A.log2nl) + ((uint32_t)j << A.log2mu) + l);
 }
 
-// Copies between the workgroup's C r elements in HBM (digits) and LDS.  Element index e: column c
-// fastest, then position j; LDS slot bitrev(j) on the way in, slot v on the way out.
+// Copies between the workgroup's C r elements in HBM (L limbs per residue) and LDS.  Element
+// index e: column c fastest, then position j; LDS slot bitrev(j) on the way in, slot v on the
+// way out.
 
-// digits into LDS, digit layout (the twiddles of an inverse level come first)
+// HBM limbs into LDS as digits, D words per residue (an inverse level's twiddles come first)
 template <int L>
 __device__ __forceinline__ void level_load_digits(uint32_t* cur, const uint32_t* __restrict__ poly,
                                                   const LevelArgs& A, long long c0) {
-    constexpr int D = Dig<L>::D;
-    const int EW = D << A.log2m;
-    const int nel = 1 << (A.log2C + A.log2r);
-    if ((EW & 3) == 0) {
-        const int EV = EW >> 2;
-        const int total = nel * EV;
-        uint4* cv = reinterpret_cast<uint4*>(cur);
-        const uint4* gv = reinterpret_cast<const uint4*>(poly);
-#pragma unroll 4
-        for (int t = threadIdx.x; t < total; t += kThreads) {
-            const int e = ((t << 2) >> A.log2m) / D;
-            const int wk = t - e * EV;
-            const int c = e & ((1 << A.log2C) - 1), j = e >> A.log2C;
-            const long long pos = level_pos(A, c0, c, j);
-            cv[((c << A.log2r) + bitrev(j, A.log2r)) * EV + wk] = gv[(size_t)pos * EV + wk];
-        }
-    } else {
-        const int total = nel * EW;
-        for (int t = threadIdx.x; t < total; t += kThreads) {
-            const int e = (t >> A.log2m) / D;
-            const int wk = t - e * EW;
-            const int c = e & ((1 << A.log2C) - 1), j = e >> A.log2C;
-            const long long pos = level_pos(A, c0, c, j);
-            cur[((c << A.log2r) + bitrev(j, A.log2r)) * EW + wk] = poly[(size_t)pos * EW + wk];
-        }
-    }
-}
-
-// digits into LDS as limbs (one coefficient per thread and step)
-template <int L, int LS>
-__device__ __forceinline__ void level_load_limbs(uint32_t* cur, const uint32_t* __restrict__ poly,
-                                                 const LevelArgs& A, long long c0) {
     constexpr int D = Dig<L>::D;
     const int nel = 1 << (A.log2C + A.log2r);
     for (int t = threadIdx.x; t < (nel << A.log2m); t += kThreads) {
         const int e = t >> A.log2m, k = t & ((1 << A.log2m) - 1);
         const int c = e & ((1 << A.log2C) - 1), j = e >> A.log2C;
-        const uint32_t* src = poly + ((size_t)level_pos(A, c0, c, j) << A.log2m) * D + k * D;
-        uint32_t dv[D], x[L];
+        const uint32_t* src = poly + (((size_t)level_pos(A, c0, c, j) << A.log2m) + k) * L;
+        uint32_t x[L], dv[D];
 #pragma unroll
-        for (int w = 0; w < D; ++w) dv[w] = src[w];
-        digits_to_limbs<L>(dv, x);
-        uint32_t* dst = cur + ((((c << A.log2r) + bitrev(j, A.log2r)) << A.log2m) + k) * LS;
+        for (int w = 0; w < L; ++w) x[w] = src[w];
+        limbs_to_digits<L>(x, dv);
+        uint32_t* dst = cur + ((((c << A.log2r) + bitrev(j, A.log2r)) << A.log2m) + k) * D;
 #pragma unroll
-        for (int w = 0; w < L; ++w) dst[w] = x[w];
+        for (int w = 0; w < D; ++w) dst[w] = dv[w];
     }
 }
 
-// Coefficient k of element i as limbs: bits [u (i m/2 + k), u (i m/2 + k) + u) of a for k < m/2
-// and i < M; zero otherwise (encode_digits in limb form).
-template <int L>
-__device__ __forceinline__ void encode_limbs(const uint32_t* __restrict__ a, long long alen, int u, long long i,
-                                             int k, long long M, int log2m, uint32_t* out) {
-    const int hm = 1 << (log2m - 1);
+// HBM limbs into LDS limbs, LS words per residue (one coefficient per thread and step)
+template <int L, int LS>
+__device__ __forceinline__ void level_load_limbs(uint32_t* cur, const uint32_t* __restrict__ poly,
+                                                 const LevelArgs& A, long long c0) {
+    const int nel = 1 << (A.log2C + A.log2r);
+    for (int t = threadIdx.x; t < (nel << A.log2m); t += kThreads) {
+        const int e = t >> A.log2m, k = t & ((1 << A.log2m) - 1);
+        const int c = e & ((1 << A.log2C) - 1), j = e >> A.log2C;
+        const uint32_t* src = poly + (((size_t)level_pos(A, c0, c, j) << A.log2m) + k) * L;
+        uint32_t* dst = cur + ((((c << A.log2r) + bitrev(j, A.log2r)) << A.log2m) + k) * LS;
 #pragma unroll
-    for (int w = 0; w < L; ++w) out[w] = 0;
-    if (i < M && k < hm) {
-        const unsigned long long pos = ((unsigned long long)i * hm + k) * (unsigned)u;
-#pragma unroll
-        for (int w = 0; w < L; ++w) {
-            const int nb = u - 32 * w;
-            if (nb > 0) {
-                const unsigned long long bit = pos + 32ull * w;
-                const long long wi = (long long)(bit >> 5);
-                const int sh = (int)(bit & 31);
-                const uint64_t lo = wi < alen ? a[wi] : 0u;
-                const uint64_t hi = wi + 1 < alen ? a[wi + 1] : 0u;
-                uint32_t v = (uint32_t)(((hi << 32) | lo) >> sh);
-                if (nb < 32) v &= (1u << nb) - 1u;
-                out[w] = v;
-            }
-        }
+        for (int w = 0; w < L; ++w) dst[w] = src[w];
     }
 }
 
@@ -293,23 +248,18 @@ __device__ __forceinline__ void level_encode_in(uint32_t* cur, const uint32_t* _
     }
 }
 
-// LDS limbs (slot v) out to HBM digits (position v)
+// LDS limbs (slot v) out to HBM limbs (position v)
 template <int L, int LS>
 __device__ __forceinline__ void level_store_limbs(uint32_t* __restrict__ poly, const uint32_t* cur,
                                                   const LevelArgs& A, long long c0) {
-    constexpr int D = Dig<L>::D;
     const int nel = 1 << (A.log2C + A.log2r);
     for (int t = threadIdx.x; t < (nel << A.log2m); t += kThreads) {
         const int e = t >> A.log2m, k = t & ((1 << A.log2m) - 1);
         const int c = e & ((1 << A.log2C) - 1), v = e >> A.log2C;
         const uint32_t* src = cur + ((((c << A.log2r) + v) << A.log2m) + k) * LS;
-        uint32_t x[L], dv[D];
+        uint32_t* dst = poly + (((size_t)level_pos(A, c0, c, v) << A.log2m) + k) * L;
 #pragma unroll
-        for (int w = 0; w < L; ++w) x[w] = src[w];
-        limbs_to_digits<L>(x, dv);
-        uint32_t* dst = poly + ((size_t)level_pos(A, c0, c, v) << A.log2m) * D + k * D;
-#pragma unroll
-        for (int w = 0; w < D; ++w) dst[w] = dv[w];
+        for (int w = 0; w < L; ++w) dst[w] = src[w];
     }
 }
 
@@ -404,7 +354,7 @@ __device__ __forceinline__ void level_twiddle(Ahead<L>& f, uint32_t* cur, uint32
                                               long long c0, const QConst& Q) {
     constexpr int D = Dig<L>::D;
     const int m = 1 << A.log2m;
-    const int EW = D << A.log2m;
+    const int EW = D << A.log2m;                        // an element's digits in LDS
     const int per = kThreads >> A.log2m;
     const int g = threadIdx.x >> A.log2m, j = threadIdx.x & (m - 1);
     const int nel = 1 << (A.log2C + A.log2r);
@@ -437,9 +387,11 @@ __device__ __forceinline__ void level_twiddle(Ahead<L>& f, uint32_t* cur, uint32
                 for (int y = 0; y < D; ++y) out[y] = X[j * D + y];
             }
             if (A.mode == 1) {
-                uint32_t* dst = poly + (size_t)level_pos(A, c0, c, v) * EW + j * D;
+                uint32_t lo[L];
+                digits_to_limbs<L>(out, lo);
+                uint32_t* dst = poly + (((size_t)level_pos(A, c0, c, v) << A.log2m) + j) * L;
 #pragma unroll
-                for (int y = 0; y < D; ++y) dst[y] = out[y];
+                for (int y = 0; y < L; ++y) dst[y] = lo[y];
             }
         }
         wave_sync();
@@ -513,15 +465,16 @@ __device__ __forceinline__ void dft_passes(uint32_t*& cur, uint32_t*& nxt, const
 template <int L>
 __device__ __forceinline__ void pw_fetch(Ahead<L>& f, int r0, const uint32_t* __restrict__ bpoly,
                                          const LevelArgs& A, long long c0) {
-    constexpr int D = Dig<L>::D;
     const int g = threadIdx.x >> A.log2m, j = threadIdx.x & ((1 << A.log2m) - 1);
     const int el = r0 + g;
     f.nz = el < (1 << (A.log2C + A.log2r));
     if (!f.nz || !bpoly) return;
     const int c = el >> A.log2r, v = el & ((1 << A.log2r) - 1);
-    const uint32_t* src = bpoly + (size_t)level_pos(A, c0, c, v) * (D << A.log2m) + j * D;
+    const uint32_t* src = bpoly + (((size_t)level_pos(A, c0, c, v) << A.log2m) + j) * L;
+    uint32_t x[L];
 #pragma unroll
-    for (int y = 0; y < D; ++y) f.v[y] = src[y];
+    for (int y = 0; y < L; ++y) x[y] = src[y];
+    limbs_to_digits<L>(x, f.v);
 }
 
 // Componentwise products of the bottom level (Step 6 fused between the last forward and the
@@ -536,7 +489,7 @@ __device__ __forceinline__ void level_pointwise(Ahead<L>& f, uint32_t* cur, uint
                                                 long long c0, const QConst& Q) {
     constexpr int D = Dig<L>::D;
     const int m = 1 << A.log2m;
-    const int EW = D << A.log2m;
+    const int EW = D << A.log2m;                        // an element's digits in LDS
     const int per = kThreads >> A.log2m;
     const int g = threadIdx.x >> A.log2m, j = threadIdx.x & (m - 1);
     const int nel = 1 << (A.log2C + A.log2r);
@@ -661,14 +614,18 @@ __global__ __launch_bounds__(kThreads) void k_pointwise(uint32_t* A0, const uint
     const long long p = (long long)blockIdx.x * per + g;
     const bool active = p < count;
     if (active) {
-        uint32_t x[D], nx[D];
-        const uint32_t* sa = A + ((size_t)p * m + j) * D;
-        const uint32_t* sb = B + ((size_t)p * m + j) * D;
+        uint32_t la[L], lb[L], x[D], xb[D], nx[D];
+        const uint32_t* sa = A + ((size_t)p * m + j) * L;
+        const uint32_t* sb = B + ((size_t)p * m + j) * L;
 #pragma unroll
-        for (int w = 0; w < D; ++w) {
-            x[w] = sa[w];
-            X[j * D + w] = sb[w];
+        for (int w = 0; w < L; ++w) {
+            la[w] = sa[w];
+            lb[w] = sb[w];
         }
+        limbs_to_digits<L>(la, x);
+        limbs_to_digits<L>(lb, xb);
+#pragma unroll
+        for (int w = 0; w < D; ++w) X[j * D + w] = xb[w];
         dneg_q<L>(nx, x, Q);
 #pragma unroll
         for (int w = 0; w < D; ++w) {
@@ -678,12 +635,13 @@ __global__ __launch_bounds__(kThreads) void k_pointwise(uint32_t* A0, const uint
     }
     __syncthreads();
     if (active) {
-        uint32_t c[D], out[D];
+        uint32_t c[D], out[D], lo[L];
         rprod_coeff<L>(TP, X, log2m, j, 0, Q, c);     // (a*b)_j 2^-28K
         mont_scalar<L>(c, Q.kpw, Q, out);             // * (2M)^-1 2^28K
-        uint32_t* dst = A + ((size_t)p * m + j) * D;
+        digits_to_limbs<L>(out, lo);
+        uint32_t* dst = A + ((size_t)p * m + j) * L;
 #pragma unroll
-        for (int w = 0; w < D; ++w) dst[w] = out[w];
+        for (int w = 0; w < L; ++w) dst[w] = lo[w];
     }
 }
 
@@ -735,7 +693,7 @@ __global__ __launch_bounds__(kThreads) void k_table_mul(uint32_t* table, long lo
 // ---------------------------------------------------------------------------------------------
 
 // Sum of the 32-bit pieces that the coefficients c_(l,k) (value sum c_(l,k) 2^(u (k + l m/2)))
-// put into output word w.  Coefficients are exact integers below q, in D digits.
+// put into output word w.  Coefficients are exact integers below q < 2^(32L), in L limbs.
 // floor(x / u) for 0 <= x < 2^40 and 1 <= u < 2^20: a double-precision estimate, corrected by
 // one step either way (the estimate is within 1 of the quotient)
 __device__ __forceinline__ long long div_u(long long x, int u, double inv_u) {
@@ -749,11 +707,10 @@ __device__ __forceinline__ long long div_u(long long x, int u, double inv_u) {
 template <int L>
 __device__ __forceinline__ uint64_t word_sum(long long w, const uint32_t* __restrict__ poly, long long lbase,
                                              long long twoM, int log2m, int u) {
-    constexpr int D = Dig<L>::D;
     const int m = 1 << log2m;
     const int hm = m >> 1;
     const double inv_u = 1.0 / (double)u;
-    const long long lo_excl = 32 * w - 28 * D;            // piece iff u g > lo_excl
+    const long long lo_excl = 32 * w - 32 * L;            // piece iff u g > lo_excl
     const long long g_lo = lo_excl < 0 ? 0 : div_u(lo_excl, u, inv_u) + 1;
     const long long g_hi = div_u(32 * w + 31, u, inv_u);
     uint64_t V = 0;
@@ -766,18 +723,16 @@ __device__ __forceinline__ uint64_t word_sum(long long w, const uint32_t* __rest
             const long long l = lmax - t;
             if (l < 0 || l >= twoM) continue;
             const int k = (int)(g - l * hm);
-            const uint32_t* T = poly + ((size_t)(l - lbase) * m + k) * D;
+            const uint32_t* T = poly + ((size_t)(l - lbase) * m + k) * L;
             uint32_t piece;
             if (off >= 0) {
-                const int o = (int)off;                 // below 28 D
-                const int k0 = o / 28, sh = o - 28 * k0;
+                const int o = (int)off;                 // below 32 L
+                const int k0 = o >> 5, sh = o & 31;
                 uint64_t v = T[k0];
-                if (k0 + 1 < D) v |= (uint64_t)T[k0 + 1] << 28;
-                if (k0 + 2 < D) v |= (uint64_t)T[k0 + 2] << 56;
+                if (k0 + 1 < L) v |= (uint64_t)T[k0 + 1] << 32;
                 piece = (uint32_t)(v >> sh);
             } else {
-                const uint64_t v = (uint64_t)T[0] | ((uint64_t)T[1] << 28);
-                piece = (uint32_t)(v << (int)(-off));
+                piece = T[0] << (int)(-off);            // -32 < off < 0
             }
             V += piece;
         }
@@ -785,9 +740,9 @@ __device__ __forceinline__ uint64_t word_sum(long long w, const uint32_t* __rest
     return V;
 }
 
-// Words of a position's aligned value: V_g < 2^(28D + 1) shifted left by up to 31 bits.
+// Words of a position's aligned value: V_g < 2q < 2^(32L + 1) shifted left by up to 31 bits.
 template <int L>
-__host__ __device__ constexpr int pos_words() { return (28 * Dig<L>::D + 1 + 31 + 31) / 32; }
+__host__ __device__ constexpr int pos_words() { return L + 1; }
 
 // Position g = l m/2 + k (k < m/2) of the product's coefficient sequence: the value
 // V_g = c_(l,k) + c_(l-1,k+m/2) (the upper half of element l-1 overlaps the lower half of element l,
@@ -796,43 +751,27 @@ __host__ __device__ constexpr int pos_words() { return (28 * Dig<L>::D + 1 + 31 
 template <int L>
 __device__ __forceinline__ void position_value(const uint32_t* __restrict__ poly, long long g, long long twoM,
                                                int log2m, int u, uint32_t* out) {
-    constexpr int D = Dig<L>::D, NW = pos_words<L>();
+    constexpr int NW = pos_words<L>();
     const int m = 1 << log2m, hm = m >> 1;
     const long long l = g >> (log2m - 1);
     const int k = (int)(g & (hm - 1));
     const bool has1 = l < twoM, has2 = l >= 1 && l - 1 < twoM;
-    const size_t o1 = has1 ? ((size_t)l * m + k) * D : 0;
-    const size_t o2 = has2 ? ((size_t)(l - 1) * m + k + hm) * D : 0;
-    uint32_t v[D + 1];
-    uint32_t carry = 0;
+    const size_t o1 = has1 ? ((size_t)l * m + k) * L : 0;
+    const size_t o2 = has2 ? ((size_t)(l - 1) * m + k + hm) * L : 0;
+    uint32_t v[L + 1];
+    unsigned int carry = 0;
 #pragma unroll
-    for (int i = 0; i < D; ++i) {
+    for (int i = 0; i < L; ++i) {
         const uint32_t x = has1 ? poly[o1 + i] : 0u;
         const uint32_t y = has2 ? poly[o2 + i] : 0u;
-        const uint32_t t = x + y + carry;                 // < 2^29 + 1
-        v[i] = t & kMask28;
-        carry = t >> 28;
+        v[i] = __builtin_addc(x, y, carry, &carry);
     }
-    v[D] = carry;
-    // 32-bit limbs of V (28 (D + 1) bits), then the shift by sh = u g mod 32
-    constexpr int NL = (28 * (D + 1) + 31) / 32;
-    uint32_t lv[NL + 1];
-#pragma unroll
-    for (int w = 0; w < NL; ++w) {
-        const int bit = 32 * w;
-        const int d = bit / 28, s0 = bit % 28;
-        uint64_t x = v[d];
-        if (d + 1 <= D) x |= (uint64_t)v[d + 1] << 28;
-        if (d + 2 <= D) x |= (uint64_t)v[d + 2] << 56;
-        lv[w] = (uint32_t)(x >> s0);
-    }
-    lv[NL] = 0;
+    v[L] = carry;
     const int sh = (int)(((unsigned)u * (unsigned)g) & 31u);
 #pragma unroll
     for (int w = 0; w < NW; ++w) {
-        const uint32_t lo = w >= 1 && w - 1 <= NL ? lv[w - 1] : 0u;
-        const uint32_t hi = w <= NL ? lv[w] : 0u;
-        out[w] = (uint32_t)(((((uint64_t)hi << 32) | lo) << sh) >> 32);
+        const uint32_t lo = w >= 1 ? v[w - 1] : 0u;
+        out[w] = (uint32_t)(((((uint64_t)v[w] << 32) | lo) << sh) >> 32);
     }
 }
 
@@ -841,8 +780,8 @@ __device__ __forceinline__ void position_value(const uint32_t* __restrict__ poly
 template <int L>
 __device__ __forceinline__ uint64_t word_sum_tiled(long long w, const uint32_t* pv, long long g_min, long long g_max,
                                                    int u, double inv_u) {
-    constexpr int D = Dig<L>::D, NW = pos_words<L>();
-    const long long lo_excl = 32 * w - (28 * D + 1);      // V_g reaches word w iff u g > lo_excl
+    constexpr int NW = pos_words<L>();
+    const long long lo_excl = 32 * w - (32 * L + 1);      // V_g reaches word w iff u g > lo_excl
     long long g = lo_excl < 0 ? 0 : div_u(lo_excl, u, inv_u) + 1;
     long long g_hi = div_u(32 * w + 31, u, inv_u);
     if (g < g_min) g = g_min;
@@ -866,7 +805,7 @@ __global__ __launch_bounds__(kThreads) void k_decode(ProdArgs PA, const uint32_t
                                                      unsigned long long* __restrict__ gmask0,
                                                      unsigned long long* __restrict__ pmask0,
                                                      long long wstride) {
-    constexpr int D = Dig<L>::D, NW = pos_words<L>();
+    constexpr int NW = pos_words<L>();
     __shared__ uint32_t hiv[kThreads + 1];
     extern __shared__ uint4 dsmv[];
     const ProdDesc pd = PA.get();
@@ -887,7 +826,7 @@ __global__ __launch_bounds__(kThreads) void k_decode(ProdArgs PA, const uint32_t
         if (w0 < nw) {
             const long long wlo = w0 > 0 ? w0 - 1 : 0;
             const long long whi = (w0 + kThreads - 1 < nw ? w0 + kThreads : nw) - 1;
-            const long long lo_excl = 32 * wlo - (28 * D + 1);
+            const long long lo_excl = 32 * wlo - (32 * L + 1);
             g_min = lo_excl < 0 ? 0 : div_u(lo_excl, u, inv_u) + 1;
             g_max = div_u(32 * whi + 31, u, inv_u);
         }
@@ -1118,11 +1057,6 @@ __global__ __launch_bounds__(kThreads) void k_schoolbook(ProdArgs PA) {
     chunk_carry(col, w0, w1, cin, pd.c);
 }
 
-__global__ void k_fill(uint32_t* __restrict__ p, long long n, uint32_t v) {
-    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = v;
-}
-
 // c = 0 for products of the launch (alen + blen words each)
 __global__ void k_zero_products(ProdArgs PA) {
     const ProdDesc pd = PA.get();
@@ -1147,7 +1081,6 @@ struct LevelIdx {
 template <int L>
 __global__ void k_unscramble(uint32_t* __restrict__ dst, const uint32_t* __restrict__ src,
                              long long twoM, int log2m, LevelIdx LI) {
-    constexpr int D = Dig<L>::D;
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= (twoM << log2m)) return;
     const long long pos = t >> log2m;
@@ -1157,13 +1090,9 @@ __global__ void k_unscramble(uint32_t* __restrict__ dst, const uint32_t* __restr
         const long long v = (pos >> LI.log2mu[i]) & ((1LL << LI.log2r[i]) - 1);
         f |= v << LI.shift[i];
     }
-    uint32_t d[D], x[L];
-#pragma unroll
-    for (int w = 0; w < D; ++w) d[w] = src[(size_t)t * D + w];
-    digits_to_limbs<L>(d, x);
     uint32_t* o = dst + (((size_t)f << log2m) + k) * L;
 #pragma unroll
-    for (int w = 0; w < L; ++w) o[w] = x[w];
+    for (int w = 0; w < L; ++w) o[w] = src[(size_t)t * L + w];
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -1698,8 +1627,7 @@ struct Workspace {
 };
 
 // words of one polynomial in the workspace (digits) and in limb form (dkss_forward's output)
-size_t poly_words(const Plan& P) { return ((size_t)2 << P.log2_M) * P.m() * dig_D(P.L); }
-size_t poly_limb_words(const Plan& P) { return ((size_t)2 << P.log2_M) * P.m() * P.L; }
+size_t poly_words(const Plan& P) { return ((size_t)2 << P.log2_M) * P.m() * P.L; }
 
 Workspace layout(const Plan& P, size_t G, size_t nw_max, bool need_b, char* base) {
     Workspace w{};
@@ -1883,9 +1811,8 @@ struct Decode {
         {
             ProfScope ps(c.prof, DKSS_K_DECODE, s, S + 4.0 * out_words, 0.0);
             // positions per workgroup: the values reaching 257 words start within
-            // 32*257 + 28D + 1 bits, (32*257 + 28D + 1)/u + 2 positions of pos_words() words each
-            const int D = Dig<L>::D;
-            const long long gspan = (32LL * (kThreads + 1) + 28 * D + 1) / std::max(u_min, 1) + 2;
+            // 32*257 + 32L + 1 bits, (32*257 + 32L + 1)/u + 2 positions of pos_words() words each
+            const long long gspan = (32LL * (kThreads + 1) + 32 * L + 1) / std::max(u_min, 1) + 2;
             const long long tile_words = gspan * pos_words<L>();
             if (u_min >= 1 && tile_words * 4 <= 32768)
                 hipLaunchKernelGGL((k_decode<L, true>), dim3(blocks, G), dim3(kThreads), tile_words * 4, s, PA,
@@ -2343,7 +2270,7 @@ int dkss_plan_info(dkss_ctx* ctx, size_t alen, size_t blen, const dkss_params* p
     if (call.C) {
         out->L = (uint32_t)P.L;
         out->q_bits = (uint32_t)P.q_bits;
-        out->poly_bytes = poly_limb_words(P) * 4;
+        out->poly_bytes = poly_words(P) * 4;
         out->table_bytes = (uint64_t)std::max<long long>(call.C->table_count, 2) * 2 * P.m() * call.C->D * 4;
         for (int i = 0; i < P.L && i < 16; ++i) out->q[i] = P.q.limb32(i);
     }
