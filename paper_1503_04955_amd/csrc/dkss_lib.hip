@@ -162,8 +162,8 @@ __global__ __launch_bounds__(kThreads) void k_encode(ProdArgs PA, int which, uin
 // The DFT works on 32-bit limbs (additions with the hardware carry): inputs in bit-reversed LDS
 // slots, log2 r radix-2 decimation-in-time passes between the two halves of the workgroup's LDS;
 // the pass merging halves of h points multiplies the odd half by alpha^((m/h) k), k < h
-// (alpha^-((m/h) k) for the inverse).  Output v ends in slot v.  Products in R work on 28-bit
-// digits (HBM holds digits): the columns are converted in LDS between the two forms.  Twiddle
+// (alpha^-((m/h) k) for the inverse).  Output v ends in slot v.  HBM holds limbs; products in R
+// work on 28-bit digits, the columns converted in LDS between the two forms.  Twiddle
 // products run in rounds of 256/m elements, one output coefficient per thread: the element's
 // digits are read in place, the table entry rho^s (with its negation, Montgomery form) is staged
 // in the other half.
