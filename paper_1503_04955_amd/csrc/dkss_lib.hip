@@ -348,7 +348,7 @@ __device__ __forceinline__ void tw_fetch(Ahead<L>& f, int r0, const uint32_t* __
 // element with position v in column c sits in LDS slot v (after the DFT, mode 1) or bitrev(v)
 // (before it, mode 2).  Mode 1 writes results to HBM; mode 2 writes them back into the slot once
 // the round's products (which read the slot) are done.  f holds round 0's twiddle on entry.
-template <int L>
+template <int L, int MODE>
 __device__ __forceinline__ void level_twiddle(Ahead<L>& f, uint32_t* cur, uint32_t* RB, uint32_t* __restrict__ poly,
                                               const uint32_t* __restrict__ table, const LevelArgs& A,
                                               long long c0, const QConst& Q) {
@@ -365,7 +365,7 @@ __device__ __forceinline__ void level_twiddle(Ahead<L>& f, uint32_t* cur, uint32
         const int el = r0 + g;                          // (c, slot) with slot fastest
         const bool valid = el < nel;
         const int c = el >> A.log2r, slot = el & ((1 << A.log2r) - 1);
-        const int v = A.mode == 2 ? bitrev(slot, A.log2r) : slot;        // its position
+        const int v = MODE == 2 ? bitrev(slot, A.log2r) : slot;          // its position
         uint32_t* X = cur + ((c << A.log2r) + slot) * EW;
         const bool nz = f.nz;
         const int rot = f.rot;
@@ -378,29 +378,26 @@ __device__ __forceinline__ void level_twiddle(Ahead<L>& f, uint32_t* cur, uint32
         }
         if (r0 + per < nel) tw_fetch<L>(f, r0 + per, table, A, c0);     // next round's twiddle
         wave_sync();
-        uint32_t out[D];
+        uint32_t out[D];                                // mode 1: L limbs; mode 2: D digits
         if (valid) {
             if (nz) {
-                rprod_coeff<L>(TP, X, A.log2m, j, rot, Q, out);
-            } else {
-#pragma unroll
-                for (int y = 0; y < D; ++y) out[y] = X[j * D + y];
+                rprod_coeff<L, MODE == 1>(TP, X, A.log2m, j, rot, Q, out);
+            } else if (MODE == 1) {
+                digits_to_limbs<L>(X + j * D, out);
             }
-            if (A.mode == 1) {
-                uint32_t lo[L];
-                digits_to_limbs<L>(out, lo);
+            if (MODE == 1) {
                 uint32_t* dst = poly + (((size_t)level_pos(A, c0, c, v) << A.log2m) + j) * L;
 #pragma unroll
-                for (int y = 0; y < L; ++y) dst[y] = lo[y];
+                for (int y = 0; y < L; ++y) dst[y] = out[y];
             }
         }
         wave_sync();
-        if (valid && A.mode == 2 && nz) {
+        if (MODE == 2 && valid && nz) {
 #pragma unroll
             for (int y = 0; y < D; ++y) X[j * D + y] = out[y];
         }
     }
-    if (A.mode == 2) __syncthreads();
+    if (MODE == 2) __syncthreads();
 }
 
 // log2 r radix-2 decimation-in-time passes over the workgroup's columns (limbs, LS words per
@@ -553,7 +550,7 @@ __global__ __launch_bounds__(kThreads) void k_level(uint32_t* __restrict__ poly0
         tw_fetch<L>(f, 0, table, A, c0);
         level_load_digits<L>(H0, poly, A, c0);
         __syncthreads();
-        level_twiddle<L>(f, H0, H1, poly, table, A, c0, Q);
+        level_twiddle<L, 2>(f, H0, H1, poly, table, A, c0, Q);
         lds_to_limbs<L, LS>(H1, H0, A, false);
         uint32_t* cur = H1;
         uint32_t* nxt = H0;
@@ -582,7 +579,7 @@ __global__ __launch_bounds__(kThreads) void k_level(uint32_t* __restrict__ poly0
     uint32_t* dg = nxt;
     lds_to_digits<L, LS>(dg, cur, A);
     if (MODE == 1) {
-        level_twiddle<L>(f, dg, cur, poly, table, A, c0, Q);
+        level_twiddle<L, 1>(f, dg, cur, poly, table, A, c0, Q);
     } else {
         level_pointwise<L>(f, dg, cur, bpoly, A, c0, Q);
         lds_to_limbs<L, LS>(cur, dg, A, true);          // slot v -> bitrev(v): the inverse DFT's input

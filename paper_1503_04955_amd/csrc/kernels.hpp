@@ -210,9 +210,10 @@ __host__ __device__ __forceinline__ void redc_steps_sparse(uint64_t* col, const 
 }
 
 // col holds S = sum_k col[k] 2^(28k) with S < 64 q^2 (any split into 64-bit columns whose
-// running totals stay below 2^64).  Writes S 2^(-28K) mod q, canonical, in digits to x.
+// running totals stay below 2^64).  The K Montgomery steps leave S 2^(-28K) mod q, below 2q, in
+// columns K .. K+D-1; its D digits (carries resolved) go to d.
 template <int L>
-__host__ __device__ __forceinline__ void redc_cols(uint64_t* col, const QConst& Q, uint32_t* x) {
+__host__ __device__ __forceinline__ void redc_digits(uint64_t* col, const QConst& Q, uint32_t* d) {
     using G = Dig<L>;
     if (Q.se == (32 * L - 1) / 28) {
         redc_steps_sparse<L, (32 * L - 1) / 28>(col, Q);
@@ -226,15 +227,36 @@ __host__ __device__ __forceinline__ void redc_cols(uint64_t* col, const QConst& 
             col[i + 1] += col[i] >> 28;
         }
     }
-    // the result (< 2q < 2^(28D)) sits in columns K .. K+D-1
     uint64_t carry = 0;
 #pragma unroll
     for (int k = 0; k < G::D; ++k) {
         uint64_t v = col[G::K + k] + carry;
-        x[k] = (uint32_t)v & kMask28;
+        d[k] = (uint32_t)v & kMask28;
         carry = v >> 28;
     }
+}
+
+// S 2^(-28K) mod q, canonical, in digits
+template <int L>
+__host__ __device__ __forceinline__ void redc_cols(uint64_t* col, const QConst& Q, uint32_t* x) {
+    redc_digits<L>(col, Q, x);
     if (dgeq_q<L>(x, Q)) dsub_q<L>(x, Q);
+}
+
+// S 2^(-28K) mod q, canonical, in L limbs: the value (below 2q < 2^(32L+1)) as L limbs and its
+// bit 32L, then one subtraction of q on limbs with the hardware borrow
+template <int L>
+__host__ __device__ __forceinline__ void redc_cols_limbs(uint64_t* col, const QConst& Q, uint32_t* x) {
+    uint32_t d[Dig<L>::D], s[L];
+    redc_digits<L>(col, Q, d);
+    digits_to_limbs<L>(d, x);
+    const uint32_t top = (d[(32 * L) / 28] >> ((32 * L) % 28)) & 1u;
+    unsigned int b = 0;
+#pragma unroll
+    for (int k = 0; k < L; ++k) s[k] = __builtin_subc(x[k], Q.ql[k], b, &b);
+    const bool ge = top || !b;
+#pragma unroll
+    for (int k = 0; k < L; ++k) x[k] = ge ? s[k] : x[k];
 }
 
 template <int L>
@@ -247,14 +269,6 @@ __host__ __device__ __forceinline__ void normalize_cols(uint64_t* col) {
     }
 }
 
-// One output coefficient j of t * alpha^r * x in R, reduced by Montgomery.  With alpha^m = -1
-// (so alpha^(2m) = 1), the term t_i x_k lands on coefficient j with sign + when
-// i + k + r = j (mod 2m) and with sign - when i + k + r = j + m (mod 2m); for each k exactly one
-// i < m does one of the two, hence
-//   c_j = sum_{k<m} x_k T_((j - r - k) mod 2m),  T_w = t_w (w < m),  T_w = q - t_(w-m) (w >= m).
-// TP holds T_0..T_(2m-1) at a stride of DS words, X holds x_0..x_(m-1) at D words.  The lanes
-// of one element read the same x_k (one LDS address) and consecutive T entries (odd stride).
-// Returns c_j 2^(-28K) mod q in digits.
 // col[x + y] += t_x x_y over the D x D digit pairs of one term
 template <int L>
 __host__ __device__ __forceinline__ void rprod_term(uint64_t* col, const uint32_t* tp, const uint32_t* xp) {
@@ -271,7 +285,15 @@ __host__ __device__ __forceinline__ void rprod_term(uint64_t* col, const uint32_
         for (int y = 0; y < G::D; ++y) col[x + y] += (uint64_t)tv[x] * xv[y];
 }
 
-template <int L>
+// One output coefficient j of t * alpha^r * x in R, reduced by Montgomery.  With alpha^m = -1
+// (so alpha^(2m) = 1), the term t_i x_k lands on coefficient j with sign + when
+// i + k + r = j (mod 2m) and with sign - when i + k + r = j + m (mod 2m); for each k exactly one
+// i < m does one of the two, hence
+//   c_j = sum_{k<m} x_k T_((j - r - k) mod 2m),  T_w = t_w (w < m),  T_w = q - t_(w-m) (w >= m).
+// TP holds T_0..T_(2m-1) at a stride of DS words, X holds x_0..x_(m-1) at D words.  The lanes
+// of one element read the same x_k (one LDS address) and consecutive T entries (odd stride).
+// Returns c_j 2^(-28K) mod q, canonical, in digits (LIMBS: in L limbs).
+template <int L, bool LIMBS = false>
 __host__ __device__ __forceinline__ void rprod_coeff(const uint32_t* TP, const uint32_t* X, int log2m, int j,
                                             int r, const QConst& Q, uint32_t* out) {
     using G = Dig<L>;
@@ -287,7 +309,8 @@ __host__ __device__ __forceinline__ void rprod_coeff(const uint32_t* TP, const u
         rprod_term<L>(col, TP + w * G::DS, X + k * G::D);
         if ((k + 1) % G::NI == 0) normalize_cols<L>(col);
     }
-    redc_cols<L>(col, Q, out);
+    if (LIMBS) redc_cols_limbs<L>(col, Q, out);
+    else redc_cols<L>(col, Q, out);
 }
 
 // x * k 2^(-28K) mod q for a constant k given in digits (a scalar Montgomery product)

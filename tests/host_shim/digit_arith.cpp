@@ -40,6 +40,7 @@ void run(int op, const uint32_t* qd, uint32_t qinv, const uint32_t* a, const uin
         case 6: lmod_add<L>(out, a, b, Q.ql); break;   // a, b, out in limbs
         case 7: lmod_sub<L>(out, a, b, Q.ql); break;
         case 8: limbs_to_digits<L>(a, out); break;
+        case 9: rprod_coeff<L, true>(a, b, log2m, j, r, Q, out); break;   // out in limbs
         default: break;
     }
 }

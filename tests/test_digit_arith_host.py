@@ -121,6 +121,8 @@ def test_ring_product_coefficient(da, L, log2m):
                 want = sum(t[i] * ax[(j - i) % m] * (1 if j >= i else -1) for i in range(m)) % q
                 o, _ = call(da, L, 3, q, arr(TP), arr(X), D, log2m, j, r)
                 assert value(o) == want * Rinv % q, (q, j, r)
+                o, _ = call(da, L, 9, q, arr(TP), arr(X), D, log2m, j, r, n_out=L)
+                assert sum(int(o[w]) << (32 * w) for w in range(L)) == want * Rinv % q, (q, j, r)
 
 
 @pytest.mark.parametrize("L", [1, 2, 3, 4, 5, 6, 7, 8])
@@ -168,6 +170,8 @@ def test_ring_product_coefficient_extreme_digits(da, L, log2m):
     X = digits(v, D) * m
     o, _ = call(da, L, 3, q, arr(TP), arr(X), D, log2m, m - 1, 0)
     assert value(o) == m * v * v % q * Rinv % q
+    o, _ = call(da, L, 9, q, arr(TP), arr(X), D, log2m, m - 1, 0, n_out=L)
+    assert sum(int(o[w]) << (32 * w) for w in range(L)) == m * v * v % q * Rinv % q
     # and with every term wrapped (negated): r = m gives x_(j-i-m) = -x_(j-i)
     TPn = staged([1] * m + [v] * m, D, DS)
     o, _ = call(da, L, 3, q, arr(TPn), arr(X), D, log2m, m - 1, m)
