@@ -85,7 +85,11 @@ typedef struct {
 
 /* Create a context with the given policy.  cache_dir may be NULL; a TUNED context reads
  * cache_dir/dkss_tuning.txt and a LEARNED one cache_dir/dkss_mlp.txt (dkss_mlp_load) when they
- * exist.  Allocates nothing on the device until a parameter tuple is first prepared or selector
+ * exist.  The tuning table is text: lines "lo hi cand [radices] [dft_lds]" (a log2 N range, a
+ * candidate index of dkss_candidates or DKSS_CAND_SCHOOLBOOK, a level split such as 5.5.4, a
+ * DFT LDS budget in bytes), '#' comments, and "@batch B" lines: the entries after one hold for
+ * batches of at least B products (before the first, B = 1); a product takes the entry of the
+ * largest such B whose range holds its N.  Allocates nothing on the device until a parameter tuple is first prepared or selector
  * weights are installed.  Errors: DKSS_EINVAL. */
 int dkss_ctx_create(dkss_ctx** out, int policy, const char* cache_dir);
 
@@ -94,8 +98,8 @@ void dkss_ctx_destroy(dkss_ctx* ctx);
 
 /* Parameters the context's policy picks for operands of a_bits and b_bits bits in a batch of
  * `batch` products.  N = max(a_bits, b_bits) rounded up to whole limbs (the thesis assumes equal
- * lengths, Sec. 3.2).  A LEARNED choice of a candidate sets cutoff_bits 0; its choice of the
- * schoolbook sets cutoff_bits UINT64_MAX (with the thesis rule's tuple).  Errors: DKSS_EINVAL
+ * lengths, Sec. 3.2).  A LEARNED choice of a candidate sets cutoff_bits 0; a LEARNED or TUNED
+ * choice of the schoolbook sets cutoff_bits UINT64_MAX (with the thesis rule's tuple).  Errors: DKSS_EINVAL
  * (null), DKSS_ERANGE (N = 0 or beyond 2^36 bits), DKSS_EHIP (learned inference). */
 int dkss_select_params(dkss_ctx* ctx, uint64_t a_bits, uint64_t b_bits, uint32_t batch,
                        dkss_params* out);
@@ -133,7 +137,8 @@ int dkss_prepare(dkss_ctx* ctx, size_t alen, size_t blen, const dkss_params* p, 
  * dkss_workspace_bytes() bytes of device memory, 256-byte aligned (DKSS_ENOSPC / DKSS_EINVAL).
  * p = NULL uses the context's policy; under DKSS_POLICY_LEARNED the first product of a shape
  * waits for the selector's inference (dkss_mlp_choose, batch 1).  dkss_mul_batch asks the
- * selector once for all new shapes of the batch, with batch = count.
+ * selector once for all new shapes of the batch, with batch = count; a TUNED context looks its
+ * table up with batch = count there (batch 1 here).
  * Errors: DKSS_EINVAL, DKSS_ENOSPC, DKSS_ERANGE (p^z below
  * Mm 2^(2u), 2M not dividing p - 1, M < m, m < 2, capacity M*m/2*u below 32*max(alen, blen),
  * unsupported limb count, a transform length 2M above 2^31, a kernel grid of 2^32 work-items

@@ -1259,7 +1259,8 @@ int dig_K(int L) { return (32 * L + 6 + 27) / 28; }
 // Optionally with the FFT level split and the LDS budget of the DFT-only levels.
 struct TuneEntry {
     double lo, hi;
-    int cand;
+    int cand;                      // a candidate index or DKSS_CAND_SCHOOLBOOK
+    uint32_t batch = 1;            // the entry holds for batches of at least this many products
     std::vector<int> radices;      // empty: the library default
     long long dft_lds = 0;         // 0: the context's option
 };
@@ -1314,18 +1315,27 @@ namespace {
         if (e_ != hipSuccess) return note_hip(e_);     \
     } while (0)
 
-// the context's policy: the tuned table's candidate for N if it has one (its entry in *te),
-// else the thesis rule
-bool policy_tuple(const dkss_ctx* ctx, uint64_t N, int* lM, int* lm, int* u, int* pb,
-                  const TuneEntry** te = nullptr) {
+// the context's policy: the tuned table's entry for N (in *te) if it has one, else the thesis
+// rule.  Among the entries whose range holds N the one measured at the largest batch size not
+// above `batch` wins.  A schoolbook entry sets *school and leaves the thesis tuple in place
+// (the product falls back to it where the base case does not apply).
+bool policy_tuple(const dkss_ctx* ctx, uint64_t N, uint32_t batch, int* lM, int* lm, int* u, int* pb,
+                  const TuneEntry** te = nullptr, bool* school = nullptr) {
     if (te) *te = nullptr;
+    if (school) *school = false;
     if (ctx && ctx->policy == DKSS_POLICY_TUNED) {
         const double lg = std::log2((double)N);
+        const TuneEntry* hit = nullptr;
         for (const TuneEntry& t : ctx->tuning)
-            if (lg >= t.lo && lg < t.hi && candidate_params(N, t.cand, lM, lm, u, pb)) {
-                if (te) *te = &t;
-                return true;
-            }
+            if (t.batch <= batch && lg >= t.lo && lg < t.hi && (!hit || t.batch > hit->batch) &&
+                (t.cand == DKSS_CAND_SCHOOLBOOK || candidate_params(N, t.cand, lM, lm, u, pb)))
+                hit = &t;
+        if (hit && hit->cand == DKSS_CAND_SCHOOLBOOK) {
+            if (school) *school = true;
+        } else if (hit && candidate_params(N, hit->cand, lM, lm, u, pb)) {
+            if (te) *te = hit;
+            return true;
+        }
     }
     return thesis_params(N, lM, lm, u, pb);
 }
@@ -1411,7 +1421,8 @@ int learned_choices(dkss_ctx* ctx, size_t count, const size_t* alen, const size_
 
 // parameters for a product, from the policy or the caller.  choice: the learned selector's
 // output for the product (-1: none, use the policy's tuple).
-int resolve_params(dkss_ctx* ctx, size_t alen, size_t blen, const dkss_params* p, Call* out, int choice) {
+int resolve_params(dkss_ctx* ctx, size_t alen, size_t blen, const dkss_params* p, Call* out, int choice,
+                   uint32_t batch) {
     out->alen = alen;
     out->blen = blen;
     const uint64_t N = 32ull * std::max(alen, blen);
@@ -1425,8 +1436,9 @@ int resolve_params(dkss_ctx* ctx, size_t alen, size_t blen, const dkss_params* p
         if (choice >= 0 && choice < kNumCandidates && candidate_params(N, choice, &lM, &lm, &u, &pb)) {
             P.cutoff_bits = 0;
         } else {
-            if (!policy_tuple(ctx, N, &lM, &lm, &u, &pb, &te)) return DKSS_ERANGE;
-            if (choice == DKSS_CAND_SCHOOLBOOK) P.cutoff_bits = UINT64_MAX;
+            bool school = false;
+            if (!policy_tuple(ctx, N, batch, &lM, &lm, &u, &pb, &te, &school)) return DKSS_ERANGE;
+            if (school || choice == DKSS_CAND_SCHOOLBOOK) P.cutoff_bits = UINT64_MAX;
         }
         if (te) {                      // the tuned level split and LDS budget, where recorded
             int sum = 0;
@@ -1869,7 +1881,7 @@ int prepare_call(dkss_ctx* ctx, size_t alen, size_t blen, const dkss_params* p, 
         int rc = learned_choices(ctx, 1, &alen, &blen, batch, &choice);
         if (rc) return rc;
     }
-    int rc = resolve_params(ctx, alen, blen, p, call, choice);
+    int rc = resolve_params(ctx, alen, blen, p, call, choice, batch);
     if (rc) return rc;
     if (alen == 0 || blen == 0 || call->schoolbook) return DKSS_OK;
     return plan_constants(ctx, call);
@@ -2066,7 +2078,8 @@ int dkss_set_option(dkss_ctx* ctx, int option, long long value) {
     }
 }
 
-// The tuning table: text lines "lo hi cand" (log2 N range, candidate index); '#' comments.
+// The tuning table: text lines "lo hi cand" (log2 N range, candidate index or the schoolbook
+// output); '#' comments; a line "@batch B" starts the entries measured at B products per batch.
 static void load_tuning(dkss_ctx* c, const char* dir) {
     if (!dir) return;
     std::string path = std::string(dir) + "/dkss_tuning.txt";
@@ -2074,13 +2087,20 @@ static void load_tuning(dkss_ctx* c, const char* dir) {
     if (!f) return;
     // "lo hi cand [radices|-] [dft_lds]", radices as log2 values joined by '.', e.g. 5.5.5.5
     char line[256];
+    uint32_t batch = 1;
     while (fgets(line, sizeof line, f)) {
         if (line[0] == '#') continue;
+        unsigned long b = 0;
+        if (sscanf(line, "@batch %lu", &b) == 1) {
+            batch = (uint32_t)std::min<unsigned long>(std::max<unsigned long>(b, 1), UINT32_MAX);
+            continue;
+        }
         TuneEntry e{};
+        e.batch = batch;
         char rad[64] = "-";
         long long lds = 0;
         const int n = sscanf(line, "%lf %lf %d %63s %lld", &e.lo, &e.hi, &e.cand, rad, &lds);
-        if (n < 3 || e.cand < 0 || e.cand >= kNumCandidates) continue;
+        if (n < 3 || e.cand < 0 || (e.cand >= kNumCandidates && e.cand != DKSS_CAND_SCHOOLBOOK)) continue;
         if (n >= 4 && rad[0] != '-' && rad[0] != '#') {
             bool ok = true;
             for (char* t = rad; *t && ok;) {
@@ -2222,8 +2242,9 @@ int dkss_select_params(dkss_ctx* ctx, uint64_t a_bits, uint64_t b_bits, uint32_t
     if (choice >= 0 && choice < kNumCandidates && candidate_params(N, choice, &lM, &lm, &u, &pb)) {
         cutoff = 0;
     } else {
-        if (!policy_tuple(ctx, N, &lM, &lm, &u, &pb, &te)) return DKSS_ERANGE;
-        if (choice == DKSS_CAND_SCHOOLBOOK) cutoff = UINT64_MAX;
+        bool school = false;
+        if (!policy_tuple(ctx, N, batch ? batch : 1, &lM, &lm, &u, &pb, &te, &school)) return DKSS_ERANGE;
+        if (school || choice == DKSS_CAND_SCHOOLBOOK) cutoff = UINT64_MAX;
     }
     memset(out, 0, sizeof *out);
     out->log2_M = (uint32_t)lM;

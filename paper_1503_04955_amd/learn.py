@@ -114,9 +114,31 @@ def predict(weights, X, device="cuda"):
     return dk.mlp_forward(w, x).cpu().numpy()
 
 
+def tuned_choices(keys, tuning_dir=None):
+    """The TUNED policy's output at each point (x, ratio, batch), from the library's own table
+    lookup (dkss_select_params, host only): CAND_SCHOOLBOOK where the tuple comes with the base
+    case, else the index of the candidate with the same tuple, "thesis" where none has it.  The
+    candidates' timings at a point use the default level split, so the batch 1 entries' tuned
+    splits and LDS budgets do not enter the comparison."""
+    ctx = dk.Context(dk.POLICY_TUNED, tuning_dir=tuning_dir)
+    out = []
+    for x, ratio, batch in keys:
+        n, nb = _limbs(x, ratio)
+        q = ctx.select_params(32 * n, 32 * nb, batch)
+        if 32 * min(n, nb) <= q.cutoff_bits:
+            out.append(dk.CAND_SCHOOLBOOK)
+            continue
+        tup = (q.log2_M, q.log2_m, q.p_bits)
+        same = [c for c, p in ctx.candidates(32 * n, 32 * nb) if (p.log2_M, p.log2_m, p.p_bits) == tup]
+        out.append(same[0] if same else "thesis")
+    return out
+
+
 def regrets(points, pred, keys, tuned=None):
     """Per point: regret of the selector's choice (argmin of pred over measured outputs), of the
-    thesis rule and, if tuned (log2 N -> candidate) is given, of the tuned table."""
+    thesis rule and, if tuned (the TUNED policy's output per point) is given, of the tuned
+    table; an output not measured at the point (the base case beyond its limit) is the thesis
+    rule's, as in the library."""
     out = []
     for i, key in enumerate(keys):
         ms = points[key]
@@ -126,8 +148,8 @@ def regrets(points, pred, keys, tuned=None):
         r = {"point": list(key), "choice": choice, "best": min(meas, key=lambda c: ms[c]),
              "learned": ms[choice] / best - 1, "thesis": ms["thesis"] / best - 1}
         if tuned is not None:
-            c = tuned(key[0])
-            r["tuned"] = ms[c] / best - 1 if c in ms else None
+            r["tuned_choice"] = tuned[i]
+            r["tuned"] = ms.get(tuned[i], ms["thesis"]) / best - 1
         out.append(r)
     return out
 
@@ -152,10 +174,10 @@ def main():
         w = dk.mlp_load(args.weights or args.out)
         pts = load_points(args.eval)
         X, _, _, keys = dataset(pts)
-        regs = regrets(pts, predict(w, X), keys)
-        res = {"learned": summary(regs, "learned"), "thesis": summary(regs, "thesis"),
-               "points": regs}
-        print(json.dumps({k: res[k] for k in ("learned", "thesis")}), flush=True)
+        regs = regrets(pts, predict(w, X), keys, tuned_choices(keys))
+        res = {"learned": summary(regs, "learned"), "tuned": summary(regs, "tuned"),
+               "thesis": summary(regs, "thesis"), "points": regs}
+        print(json.dumps({k: res[k] for k in ("learned", "tuned", "thesis")}), flush=True)
         with open(os.path.splitext(args.eval)[0] + "_regret.json", "w") as f:
             json.dump(res, f, indent=1)
         return

@@ -21,8 +21,9 @@ Sets of points
             the FFT level split (library default, balanced, balanced with one more level) and
             the LDS budget of the DFT-only levels (16, 32, 64 KiB); needs DIR/timings.json
 
-Writes (train) DIR/dkss_tuning.txt, "lo hi cand" lines: the fastest candidate per size bucket at
-ratio 1 and batch 1 (what a DKSS_POLICY_TUNED context loads), and DIR/timings.json; (heldout)
+Writes (train) DIR/dkss_tuning.txt, "lo hi cand" lines: the fastest output per size bucket at
+ratio 1, for batch 1 and in an "@batch B" section per batch size of the grid (what a
+DKSS_POLICY_TUNED context loads), and DIR/timings.json; (heldout)
 DIR/timings_heldout.json; (kernels) DIR/timings_kernels.json and DIR/dkss_tuning.txt again, its
 lines extended to "lo hi cand radices dft_lds".  Choices never change result bits.
 """
@@ -180,11 +181,14 @@ def run(points, reps, out_json, verbose=True, tuned_txt=None, merge=False):
     return rows
 
 
-def best_candidates(rows):
-    """{x: (cand, ms)}: the fastest DKSS candidate per size at ratio 1 and batch 1."""
+def best_candidates(rows, batch=1, school=False):
+    """{x: (cand, ms)}: the fastest DKSS candidate (or, with school, also the schoolbook) per size
+    at ratio 1 and the given batch size."""
     best = {}
     for r in rows:
-        if r["ratio"] != 1 or r["batch"] != 1 or not isinstance(r["cand"], int) or r["cand"] == SCHOOLBOOK:
+        if r["ratio"] != 1 or r["batch"] != batch or not isinstance(r["cand"], int):
+            continue
+        if r["cand"] == SCHOOLBOOK and not school:
             continue
         x = r["log2_a"]
         if x not in best or r["ms"] < best[x][1]:
@@ -193,28 +197,42 @@ def best_candidates(rows):
 
 
 def write_tuned_table(rows, path, kernel_rows=None):
-    """Fastest DKSS candidate per size at ratio 1 and batch 1, as half-open log2 N buckets; with
-    kernel_rows, also the fastest level split and DFT LDS budget measured for it."""
-    best = best_candidates(rows)
-    thesis = {r["log2_a"]: r["ms"] for r in rows
-              if r["ratio"] == 1 and r["batch"] == 1 and r["cand"] == "thesis"}
+    """Fastest output (a DKSS candidate or the schoolbook) per size at ratio 1 as half-open
+    log2 N buckets, first for batch 1, then in one "@batch B" section per measured batch size;
+    with kernel_rows, batch 1 entries also carry the fastest level split and DFT LDS budget
+    measured for their candidate.  Sections other than batch 1 end at their largest measured
+    size: beyond it a product takes the entry of a smaller batch size."""
     kbest = {}
+    best1 = best_candidates(rows, 1, school=True)
     for r in kernel_rows or []:
         x = r["log2_a"]
-        if x in best and r["cand"] == best[x][0] and (x not in kbest or r["ms"] < kbest[x]["ms"]):
+        if x in best1 and r["cand"] == best1[x][0] and (x not in kbest or r["ms"] < kbest[x]["ms"]):
             kbest[x] = r
-    xs = sorted(best)
+    batches = sorted({r["batch"] for r in rows if r["ratio"] == 1})
     with open(path, "w") as f:
         f.write("# log2N_lo log2N_hi candidate [radices] [dft_lds]   (fastest measured; ms best / thesis)\n")
-        for i, x in enumerate(xs):
-            lo = (xs[i - 1] + x) / 2 if i else 0.0
-            hi = (x + xs[i + 1]) / 2 if i + 1 < len(xs) else 64.0
-            cfg, ms = "", best[x][1]
-            if x in kbest:
-                k = kbest[x]
-                cfg = " %s %d" % (".".join(str(v) for v in k["radices"]), k["dft_lds"])
-                ms = k["ms"]
-            f.write("%.3f %.3f %d%s   # %.4f / %.4f\n" % (lo, hi, best[x][0], cfg, ms, thesis.get(x, 0.0)))
+        f.write("# candidate %d: the schoolbook product\n" % SCHOOLBOOK)
+        for B in batches:
+            best = best_candidates(rows, B, school=True)
+            thesis = {r["log2_a"]: r["ms"] for r in rows
+                      if r["ratio"] == 1 and r["batch"] == B and r["cand"] == "thesis"}
+            xs = sorted(best)
+            if B != 1:
+                f.write("@batch %d\n" % B)
+            for i, x in enumerate(xs):
+                lo = (xs[i - 1] + x) / 2 if i else 0.0
+                if i + 1 < len(xs):
+                    hi = (x + xs[i + 1]) / 2
+                elif B == 1:
+                    hi = 64.0
+                else:
+                    hi = x + (x - xs[i - 1]) / 2 if i else x + 0.5
+                cfg, ms = "", best[x][1]
+                if B == 1 and x in kbest:
+                    k = kbest[x]
+                    cfg = " %s %d" % (".".join(str(v) for v in k["radices"]), k["dft_lds"])
+                    ms = k["ms"]
+                f.write("%.3f %.3f %d%s   # %.4f / %.4f\n" % (lo, hi, best[x][0], cfg, ms, thesis.get(x, 0.0)))
 
 
 def radix_splits(total, cap):

@@ -304,6 +304,26 @@ def test_tuned_policy_products(env):
         assert np.array_equal(dk.to_host(c), C.schoolbook(a, b))
 
 
+def test_tuned_policy_batch_sections(env):
+    """A batch of 300 mixed products under the TUNED policy takes the table's batch 256 section
+    (the schoolbook up to about 2^14.5 bits, other candidates above): it equals the thesis rule's
+    batch, and its small products the oracle's."""
+    dk, torch, ctx = env
+    tctx = dk.Context(dk.POLICY_TUNED)
+    assert tctx.select_params(2 ** 14, 2 ** 14, 300).cutoff_bits == 2 ** 64 - 1
+    lens = SI.batch_lengths(SI.SEED_BASE + 41, 300, hi_bits=19)
+    pairs = [SI.operand_pair(8000 + i, al, bl) for i, (al, bl) in enumerate(lens)]
+    as_ = [dk.to_device(a) for a, _ in pairs]
+    bs = [dk.to_device(b) for _, b in pairs]
+    out_t = tctx.mul_batch(as_, bs)
+    out_0 = ctx.mul_batch(as_, bs)
+    torch.cuda.synchronize()
+    assert all(torch.equal(x, y) for x, y in zip(out_t, out_0))
+    for (a, b), g in zip(pairs, out_t):
+        if len(a) * len(b) < 2e6:
+            assert np.array_equal(dk.to_host(g), C.schoolbook(a, b)), (len(a), len(b))
+
+
 def test_batch_graph_replays(env):
     """A batch captured into a HIP graph: every replay equals the eager batch, with eager work
     and synchronizations between replays, outputs cleared before each replay, and new operand

@@ -173,3 +173,41 @@ def test_tuned_table_with_level_split(dk, tmp_path):
     info = ctx.plan_info(N // 32, N // 32)
     assert [info.params.radix_log2[i] for i in range(info.params.n_levels)] == \
         [p.radix_log2[i] for i in range(p.n_levels)]
+
+
+def test_tuned_table_batch_sections_and_schoolbook(dk, tmp_path):
+    """"@batch B" sections: a product takes the entry of the largest B not above its batch size
+    whose range holds its N, falling back to smaller B; a schoolbook entry selects the base case
+    (cutoff UINT64_MAX, the thesis tuple) and falls back to DKSS where the base case does not
+    apply."""
+    ctx0 = dk.Context()
+    sizes = [2 ** 11, 2 ** 13, 2 ** 16, 2 ** 22]
+    common = set.intersection(*[{c for c, _ in ctx0.candidates(N, N)} for N in sizes])
+    c1, c2, c3 = sorted(common)[:3]
+    with open(tmp_path / "dkss_tuning.txt", "w") as f:
+        f.write("0 13 %d\n13 20 %d\n20 64 %d\n" % (dk.CAND_SCHOOLBOOK, c1, dk.CAND_SCHOOLBOOK))
+        f.write("@batch 16\n0 14 %d\n14 20 %d   # comment\n" % (dk.CAND_SCHOOLBOOK, c2))
+        f.write("@batch 256\n10 12 %d\n" % c3)
+    ctx = dk.Context(dk.POLICY_TUNED, tuning_dir=str(tmp_path))
+
+    def tup(p):
+        return (p.log2_M, p.log2_m, p.p_bits)
+
+    def cand(c, N):
+        return tup(dict(ctx0.candidates(N, N))[c])
+
+    thesis = {N: ctx0.select_params(N, N) for N in sizes}
+    school = 2 ** 64 - 1
+    for N, batch, want in [(2 ** 13, 1, c1), (2 ** 16, 1, c1), (2 ** 16, 16, c2), (2 ** 16, 300, c2),
+                           (2 ** 11, 300, c3), (2 ** 11, 255, None), (2 ** 13, 16, None),
+                           (2 ** 22, 16, None), (2 ** 22, 1, None), (2 ** 11, 1, None)]:
+        q = ctx.select_params(N, N, batch)
+        if want is None:                       # a schoolbook entry
+            assert tup(q) == tup(thesis[N]) and q.cutoff_bits == school, (N, batch)
+        else:
+            assert tup(q) == cand(want, N) and q.cutoff_bits == 2048, (N, batch)
+    # plan_info plans at batch 1: the schoolbook entry below 2^13 bits applies beyond the default
+    # cutoff; the one above 2^20 bits exceeds the base case and runs the thesis tuple
+    assert ctx.plan_info(200, 200).schoolbook == 1 and ctx0.plan_info(200, 200).schoolbook == 0
+    big = ctx.plan_info(2 ** 16, 2 ** 16)
+    assert big.schoolbook == 0 and tup(big.params) == tup(ctx0.plan_info(2 ** 16, 2 ** 16).params)
