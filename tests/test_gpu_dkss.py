@@ -202,6 +202,12 @@ def test_mul_2e24_vs_oracle_dkss(env):
     _residue_check(a, b, got, _primes61(1, 8))
 
 
+def _low_limbs_check(a, b, got, w=2048):
+    """The lowest w limbs of a product are the lowest w limbs of the product of the operands'
+    lowest w limbs: outputs the oracle's schoolbook computes exactly at any size."""
+    assert np.array_equal(got[:w], C.schoolbook(a[:w], b[:w])[:w])
+
+
 @pytest.mark.parametrize("kind", ["random", "ones", "square", "unbalanced"])
 def test_mul_2e28_residues(env, kind):
     n = 1 << 23
@@ -213,11 +219,13 @@ def test_mul_2e28_residues(env, kind):
         a = SI.limbs(SI.SEED_BASE + 3, n)
         got = _gpu_mul(env, a, a, square=True)
         _residue_check(a, a, got, _primes61(2, 8))
+        _low_limbs_check(a, a, got)
         return
     else:
         a, b = SI.operand_pair(SI.SEED_BASE + 4, n, n // 8)
     got = _gpu_mul(env, a, b)
     _residue_check(a, b, got, _primes61(3, 8))
+    _low_limbs_check(a, b, got)
     if kind == "ones":
         # (2^N - 1)^2 = 2^(2N) - 2^(N+1) + 1: low limb 1, limbs 1..n-1 zero, limb n = 0xFFFFFFFE
         assert got[0] == 1 and not got[1:n].any() and got[n] == 0xFFFFFFFE
