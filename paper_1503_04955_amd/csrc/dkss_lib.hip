@@ -67,10 +67,6 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Words of one element's twiddle staging: rho^s and its negation, 2m residues of D digits.  (At
-// radix 2m the staging of a round fills the free column buffer exactly, so it is not padded.)
-__host__ __device__ constexpr int tw_stage_words(int m, int DS) { return 2 * m * DS; }
-
 __device__ __forceinline__ int bitrev(int x, int bits) {
     return bits ? (int)(__brev((unsigned)x) >> (32 - bits)) : 0;
 }
@@ -173,6 +169,7 @@ struct LevelArgs {
     int log2nl, log2mu, log2r, log2m, log2C;
     int mode, inverse;
     int half;                     // words of each of the two LDS halves
+    int ew, sw;                   // LDS words per element in digits, per staged operand
 };
 
 // Position of element j of column c0 + c in the polynomial (positions stay below 2M < 2^32)
@@ -200,7 +197,7 @@ __device__ __forceinline__ void level_load_digits(uint32_t* cur, const uint32_t*
 #pragma unroll
         for (int w = 0; w < L; ++w) x[w] = src[w];
         limbs_to_digits<L>(x, dv);
-        uint32_t* dst = cur + ((((c << A.log2r) + bitrev(j, A.log2r)) << A.log2m) + k) * D;
+        uint32_t* dst = cur + ((c << A.log2r) + bitrev(j, A.log2r)) * A.ew + k * D;
 #pragma unroll
         for (int w = 0; w < D; ++w) dst[w] = dv[w];
     }
@@ -274,7 +271,7 @@ __device__ __forceinline__ void lds_to_digits(uint32_t* dg, const uint32_t* lb, 
         for (int w = 0; w < L; ++w) x[w] = lb[t * LS + w];
         limbs_to_digits<L>(x, dv);
 #pragma unroll
-        for (int w = 0; w < D; ++w) dg[t * D + w] = dv[w];
+        for (int w = 0; w < D; ++w) dg[(t >> A.log2m) * A.ew + (t & ((1 << A.log2m) - 1)) * D + w] = dv[w];
     }
     __syncthreads();
 }
@@ -288,7 +285,7 @@ __device__ __forceinline__ void lds_to_limbs(uint32_t* lb, const uint32_t* dg, c
     for (int t = threadIdx.x; t < n; t += kThreads) {
         uint32_t dv[D], x[L];
 #pragma unroll
-        for (int w = 0; w < D; ++w) dv[w] = dg[t * D + w];
+        for (int w = 0; w < D; ++w) dv[w] = dg[(t >> A.log2m) * A.ew + (t & ((1 << A.log2m) - 1)) * D + w];
         digits_to_limbs<L>(dv, x);
         int to = t;
         if (perm) {
@@ -354,11 +351,11 @@ __device__ __forceinline__ void level_twiddle(Ahead<L>& f, uint32_t* cur, uint32
                                               long long c0, const QConst& Q) {
     constexpr int D = Dig<L>::D;
     const int m = 1 << A.log2m;
-    const int EW = D << A.log2m;                        // an element's digits in LDS
+    const int EW = A.ew;                                // an element's digits in LDS
     const int per = kThreads >> A.log2m;
     const int g = threadIdx.x >> A.log2m, j = threadIdx.x & (m - 1);
     const int nel = 1 << (A.log2C + A.log2r);
-    uint32_t* TP = RB + g * tw_stage_words(m, Dig<L>::DS);
+    uint32_t* TP = RB + g * A.sw;
     // The m lanes of an element lie in one wavefront (m <= 64) and touch only that element's
     // column slot and staging area, so the rounds synchronize per wavefront.
     for (int r0 = 0; r0 < nel; r0 += per) {
@@ -368,12 +365,13 @@ __device__ __forceinline__ void level_twiddle(Ahead<L>& f, uint32_t* cur, uint32
         const int v = MODE == 2 ? bitrev(slot, A.log2r) : slot;          // its position
         uint32_t* X = cur + ((c << A.log2r) + slot) * EW;
         const bool nz = f.nz;
-        const int rot = f.rot;
         if (nz) {
+            uint32_t* t0 = TP + stage_pos(j, f.rot, A.log2m) * Dig<L>::DS;
+            uint32_t* t1 = TP + stage_pos(j + m, f.rot, A.log2m) * Dig<L>::DS;
 #pragma unroll
             for (int y = 0; y < D; ++y) {
-                TP[j * Dig<L>::DS + y] = f.v[y];
-                TP[(j + m) * Dig<L>::DS + y] = f.v[D + y];
+                t0[y] = f.v[y];
+                t1[y] = f.v[D + y];
             }
         }
         if (r0 + per < nel) tw_fetch<L>(f, r0 + per, table, A, c0);     // next round's twiddle
@@ -381,7 +379,7 @@ __device__ __forceinline__ void level_twiddle(Ahead<L>& f, uint32_t* cur, uint32
         uint32_t out[D];                                // mode 1: L limbs; mode 2: D digits
         if (valid) {
             if (nz) {
-                rprod_coeff<L, MODE == 1>(TP, X, A.log2m, j, rot, Q, out);
+                rprod_coeff<L, MODE == 1>(TP, X, A.log2m, j, Q, out);
             } else if (MODE == 1) {
                 digits_to_limbs<L>(X + j * D, out);
             }
@@ -486,11 +484,11 @@ __device__ __forceinline__ void level_pointwise(Ahead<L>& f, uint32_t* cur, uint
                                                 long long c0, const QConst& Q) {
     constexpr int D = Dig<L>::D;
     const int m = 1 << A.log2m;
-    const int EW = D << A.log2m;                        // an element's digits in LDS
+    const int EW = A.ew;                                // an element's digits in LDS
     const int per = kThreads >> A.log2m;
     const int g = threadIdx.x >> A.log2m, j = threadIdx.x & (m - 1);
     const int nel = 1 << (A.log2C + A.log2r);
-    uint32_t* TP = RB + g * tw_stage_words(m, Dig<L>::DS);
+    uint32_t* TP = RB + g * A.sw;
     for (int r0 = 0; r0 < nel; r0 += per) {
         const int el = r0 + g;
         const bool valid = el < nel;
@@ -501,10 +499,12 @@ __device__ __forceinline__ void level_pointwise(Ahead<L>& f, uint32_t* cur, uint
 #pragma unroll
             for (int y = 0; y < D; ++y) bv[y] = bpoly ? f.v[y] : X[j * D + y];
             dneg_q<L>(nb, bv, Q);
+            uint32_t* t0 = TP + stage_pos(j, 0, A.log2m) * Dig<L>::DS;
+            uint32_t* t1 = TP + stage_pos(j + m, 0, A.log2m) * Dig<L>::DS;
 #pragma unroll
             for (int y = 0; y < D; ++y) {
-                TP[j * Dig<L>::DS + y] = bv[y];
-                TP[(j + m) * Dig<L>::DS + y] = nb[y];
+                t0[y] = bv[y];
+                t1[y] = nb[y];
             }
         }
         if (r0 + per < nel) pw_fetch<L>(f, r0 + per, bpoly, A, c0);     // next round's b
@@ -512,7 +512,7 @@ __device__ __forceinline__ void level_pointwise(Ahead<L>& f, uint32_t* cur, uint
         uint32_t out[D];
         if (valid) {
             uint32_t cv[D];
-            rprod_coeff<L>(TP, X, A.log2m, j, 0, Q, cv);    // (a*b)_j 2^-28K
+            rprod_coeff<L>(TP, X, A.log2m, j, Q, cv);       // (a*b)_j 2^-28K
             mont_scalar<L>(cv, Q.kpw, Q, out);              // * (2M)^-1 2^28K
         }
         wave_sync();
@@ -626,14 +626,14 @@ __global__ __launch_bounds__(kThreads) void k_pointwise(uint32_t* A0, const uint
         dneg_q<L>(nx, x, Q);
 #pragma unroll
         for (int w = 0; w < D; ++w) {
-            TP[j * DS + w] = x[w];
-            TP[(j + m) * DS + w] = nx[w];
+            TP[stage_pos(j, 0, log2m) * DS + w] = x[w];
+            TP[stage_pos(j + m, 0, log2m) * DS + w] = nx[w];
         }
     }
     __syncthreads();
     if (active) {
         uint32_t c[D], out[D], lo[L];
-        rprod_coeff<L>(TP, X, log2m, j, 0, Q, c);     // (a*b)_j 2^-28K
+        rprod_coeff<L>(TP, X, log2m, j, Q, c);        // (a*b)_j 2^-28K
         mont_scalar<L>(c, Q.kpw, Q, out);             // * (2M)^-1 2^28K
         digits_to_limbs<L>(out, lo);
         uint32_t* dst = A + ((size_t)p * m + j) * L;
@@ -667,14 +667,14 @@ __global__ __launch_bounds__(kThreads) void k_table_mul(uint32_t* table, long lo
 #pragma unroll
         for (int y = 0; y < D; ++y) {
             X[j * D + y] = xs[j * D + y];
-            TP[j * DS + y] = ts[j * D + y];
-            TP[(j + m) * DS + y] = ts[(j + m) * D + y];
+            TP[stage_pos(j, 0, log2m) * DS + y] = ts[j * D + y];
+            TP[stage_pos(j + m, 0, log2m) * DS + y] = ts[(j + m) * D + y];
         }
     }
     __syncthreads();
     if (active) {
         uint32_t out[D], neg[D];
-        rprod_coeff<L>(TP, X, log2m, j, 0, Q, out);
+        rprod_coeff<L>(TP, X, log2m, j, Q, out);
         dneg_q<L>(neg, out, Q);
         uint32_t* dp = table + (size_t)(dst + jj) * 2 * m * D;
 #pragma unroll
@@ -1699,7 +1699,7 @@ struct Transform {
             const bool pw = fused && !inverse && k == nl - 1;     // fused componentwise products
             // columns per workgroup: two LDS halves of C columns (limbs; digits too where the
             // products run) within the budget, at most ncols; one column on twiddle levels
-            const size_t colbytes = (size_t)r * m * (pw ? Dig<L>::D : L) * 4;
+            const size_t colbytes = (size_t)r * (pw ? elem_words(m, D) : m * L) * 4;
             int log2C = 0;
             while (!tw && (2 * colbytes << (log2C + 1)) <= (size_t)c.dft_lds &&
                    (1LL << (log2C + 1)) <= ncols)
@@ -1718,9 +1718,11 @@ struct Transform {
             A.inverse = inverse;
             // two halves: each holds the columns in limbs (DFT) and, where products run, the
             // columns in digits and the staging of 256/m operands of 2m residues
+            A.ew = elem_words(m, D);
+            A.sw = stage_words(m, Dig<L>::DS);
             const size_t ncl = ((size_t)r << log2C) * m * (tw || pw ? Dig<L>::LS : L);
-            const size_t ncd = ((size_t)r << log2C) * m * D;
-            const size_t rb_words = (size_t)(kThreads / m) * tw_stage_words(m, Dig<L>::DS);
+            const size_t ncd = ((size_t)r << log2C) * A.ew;
+            const size_t rb_words = (size_t)(kThreads / m) * A.sw;
             size_t half = ncl;
             if (tw || pw) half = std::max(half, std::max(ncd, rb_words));
             half = (half + 3) & ~(size_t)3;                       // 16-byte aligned halves

@@ -290,27 +290,66 @@ __host__ __device__ __forceinline__ void rprod_term(uint64_t* col, const uint32_
 // i + k + r = j (mod 2m) and with sign - when i + k + r = j + m (mod 2m); for each k exactly one
 // i < m does one of the two, hence
 //   c_j = sum_{k<m} x_k T_((j - r - k) mod 2m),  T_w = t_w (w < m),  T_w = q - t_(w-m) (w >= m).
-// TP holds T_0..T_(2m-1) at a stride of DS words, X holds x_0..x_(m-1) at D words.  The lanes
-// of one element read the same x_k (one LDS address) and consecutive T entries (odd stride).
+// The operand is staged rotated (stage_pos): TP holds T_i at position (i + m + r) mod 2m, at a
+// stride of DS words, so that term k of coefficient j is the entry at position j + m - k for
+// every r; X holds x_0..x_(m-1) at D words.  The lanes of one element read the same x_k (one
+// LDS address) and m consecutive staged entries (odd stride), and the lanes of all elements of
+// a wavefront read the same positions, whatever their twiddles.
 // Returns c_j 2^(-28K) mod q, canonical, in digits (LIMBS: in L limbs).
 template <int L, bool LIMBS = false>
 __host__ __device__ __forceinline__ void rprod_coeff(const uint32_t* TP, const uint32_t* X, int log2m, int j,
-                                            int r, const QConst& Q, uint32_t* out) {
+                                            const QConst& Q, uint32_t* out) {
     using G = Dig<L>;
     const int m = 1 << log2m;
-    const int mask2 = 2 * m - 1;
     uint64_t col[G::NC];
 #pragma unroll
     for (int k = 0; k < G::NC; ++k) col[k] = 0;
-    int w = (j - r) & mask2;
+    int w = j + m;
     rprod_term<L>(col, TP + w * G::DS, X);      // k = 0 ahead of the loop: the columns start from it
     for (int k = 1; k < m; ++k) {
-        w = (w - 1) & mask2;
+        --w;
         rprod_term<L>(col, TP + w * G::DS, X + k * G::D);
         if ((k + 1) % G::NI == 0) normalize_cols<L>(col);
     }
     if (LIMBS) redc_cols_limbs<L>(col, Q, out);
     else redc_cols<L>(col, Q, out);
+}
+
+// Position in the staging area of entry i < 2m of the operand T of rprod_coeff for a product
+// by t alpha^r (r >= 0)
+__host__ __device__ __forceinline__ int stage_pos(int i, int r, int log2m) {
+    return (i + (1 << log2m) + r) & ((2 << log2m) - 1);
+}
+
+// LDS layout of the products in R, chosen so that the 64/m elements one wavefront serves read
+// distinct banks (64 banks of 4 bytes; also 32 banks within each half of the wavefront):
+//  - staging (stage_words): one element's operand, 2m residues at DS words, then m spare
+//    words.  Every lane reads position j + m - k of its element's area (rprod_coeff).  The area
+//    of element g starts at g (2m DS + m) = g m (2 DS + 1) words: modulo 64 these bases are the
+//    64/m multiples of m DS in some order (DS and 2 DS + 1 are odd), so the words read, DS
+//    (base / DS + position) + y, run over 64/m disjoint runs of m consecutive multiples of DS,
+//    one bank each.
+//  - digits (elem_words): an element's m residues at D words, then the fewest words (a
+//    multiple of the widest read of a residue, 1, 2 or 4 words) that put the broadcast reads of
+//    the wavefront's elements on disjoint banks.
+__host__ __device__ constexpr int stage_words(int m, int DS) { return 2 * m * DS + (m < 64 ? m : 0); }
+
+__host__ __device__ constexpr int elem_words(int m, int D) {
+    const int width = D % 4 == 0 ? 4 : D % 2 == 0 ? 2 : 1;
+    const int n = m < 64 ? 64 / m : 1;                 // elements per wavefront
+    for (int pad = 0; pad < 64; pad += width) {
+        const int ew = m * D + pad;
+        bool ok = true;
+        for (int g1 = 0; g1 < n && ok; ++g1)
+            for (int g2 = g1 + 1; g2 < n && ok; ++g2) {
+                const int d64 = ((g2 - g1) * ew) & 63, d32 = d64 & 31;
+                const bool same_half = (g1 < n / 2) == (g2 < n / 2);
+                ok = d64 >= width && 64 - d64 >= width &&
+                     (!same_half || (d32 >= width && 32 - d32 >= width));
+            }
+        if (ok) return ew;
+    }
+    return m * D;
 }
 
 // x * k 2^(-28K) mod q for a constant k given in digits (a scalar Montgomery product)

@@ -34,13 +34,22 @@ void run(int op, const uint32_t* qd, uint32_t qinv, const uint32_t* a, const uin
         case 0: dmod_add<L>(out, a, b, Q); break;
         case 1: dmod_sub<L>(out, a, b, Q); break;
         case 2: dneg_q<L>(out, a, Q); break;
-        case 3: rprod_coeff<L>(a, b, log2m, j, r, Q, out); break;
+        case 3: case 9: {
+            // a: T_0..T_(2m-1) at DS words; staged for t alpha^r as the kernels stage it
+            constexpr int DS = Dig<L>::DS;
+            const int m2 = 2 << log2m;
+            uint32_t tp[2 * 64 * DS];
+            for (int i = 0; i < m2; ++i)
+                memcpy(tp + stage_pos(i, r, log2m) * DS, a + i * DS, sizeof(uint32_t) * DS);
+            if (op == 3) rprod_coeff<L>(tp, b, log2m, j, Q, out);
+            else rprod_coeff<L, true>(tp, b, log2m, j, Q, out);      // out in limbs
+            break;
+        }
         case 4: mont_scalar<L>(a, b, Q, out); break;
         case 5: digits_to_limbs<L>(a, out); break;
         case 6: lmod_add<L>(out, a, b, Q.ql); break;   // a, b, out in limbs
         case 7: lmod_sub<L>(out, a, b, Q.ql); break;
         case 8: limbs_to_digits<L>(a, out); break;
-        case 9: rprod_coeff<L, true>(a, b, log2m, j, r, Q, out); break;   // out in limbs
         default: break;
     }
 }
@@ -64,6 +73,12 @@ int da_DS(int L) {
     }
     return -1;
 }
+
+// the LDS layout of the products in R (words per staged operand and per element in digits,
+// staging position of operand entry i for a product by t alpha^r)
+int da_stage_words(int m, int L) { return stage_words(m, (32 * L + 28) / 28 | 1); }
+int da_elem_words(int m, int L) { return elem_words(m, (32 * L + 28) / 28); }
+int da_stage_pos(int i, int r, int log2m) { return stage_pos(i, r, log2m); }
 
 // 1 when the Montgomery reduction for modulus digits qd takes its sparse steps
 int da_sparse(int L, const uint32_t* qd) {

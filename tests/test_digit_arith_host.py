@@ -179,6 +179,38 @@ def test_ring_product_coefficient_extreme_digits(da, L, log2m):
 
 
 
+@pytest.mark.parametrize("L", [1, 2, 3, 4, 5, 6, 7, 8])
+def test_product_lds_layout_is_bank_conflict_free(da, L):
+    """The LDS layout of the products in R.  Staging: for every rotation r the staged positions
+    of the 2m operand entries are a permutation; for every term k and digit y the 64 lanes of a
+    wavefront (64/m elements of m lanes) read 64 distinct banks of 4 bytes (and 32 distinct
+    banks modulo 32 in each half), whatever the elements' rotations.  Digits: the elements'
+    broadcast reads of x_k (1, 2 or 4 words) fall on disjoint banks wherever there are enough
+    banks for them."""
+    D, DS = da.da_D(L), da.da_DS(L)
+    width = 4 if D % 4 == 0 else 2 if D % 2 == 0 else 1
+    for log2m in range(1, 7):
+        m = 1 << log2m
+        sw, ew = da.da_stage_words(m, L), da.da_elem_words(m, L)
+        assert sw >= 2 * m * DS and ew >= m * D and ew % width == 0
+        for r in range(2 * m):
+            assert sorted(da.da_stage_pos(i, r, log2m) for i in range(2 * m)) == list(range(2 * m))
+        n = 64 // m
+        lanes = [(g, j) for g in range(n) for j in range(m)]
+        for k in range(m):
+            assert all(1 <= j + m - k < 2 * m for _, j in lanes)
+            for y in range(D):
+                words = [g * sw + (j + m - k) * DS + y for g, j in lanes]
+                assert len({w % 64 for w in words}) == 64, (m, k, y)
+                for h in (words[:32], words[32:]):
+                    assert len({w % 32 for w in h}) == 32, (m, k, y)
+            for banks, groups in ((64, range(n)), (32, range(n // 2)), (32, range(n // 2, n))):
+                if len(groups) * width > banks or len(groups) < 2:
+                    continue
+                used = [(g * ew + k * D + y) % banks for g in groups for y in range(width)]
+                assert len(set(used)) == len(used), (m, k, banks)
+
+
 def limbs(x, L):
     return [(x >> (32 * k)) & 0xFFFFFFFF for k in range(L)]
 
