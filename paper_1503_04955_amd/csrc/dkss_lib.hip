@@ -527,14 +527,19 @@ __device__ __forceinline__ void level_pointwise(Ahead<L>& f, uint32_t* cur, uint
 // MODE 0: DFT only; 1: forward DFT, then twiddles on the way out; 2: twiddles, then inverse DFT;
 // 3 (bottom level, no twiddles): forward DFT, componentwise products with bpoly, inverse DFT.
 // ENC (top forward level): the columns are encoded from operand `which` of PA's product instead
-// of being read from poly.  LDS: two halves of A.half words; a DFT runs between them on limbs,
+// of being read from poly.  M16: the launch has m = 16 and radix 32 (the commonest shape), given
+// to the compiler so that the index arithmetic of the passes and rounds folds.  LDS: two halves of A.half words; a DFT runs between them on limbs,
 // products run on digits in one half with their operands staged in the other.
-template <int L, int MODE, bool ENC>
+template <int L, int MODE, bool ENC, bool M16>
 __global__ __launch_bounds__(kThreads) void k_level(uint32_t* __restrict__ poly0, long long stride,
                                                     const uint32_t* __restrict__ table, LevelArgs A,
                                                     QConst Q, const uint32_t* __restrict__ bpoly0,
                                                     int squaring, ProdArgs PA, int which, long long M) {
     A.mode = MODE;
+    if (M16) {
+        A.log2m = 4;
+        A.log2r = 5;
+    }
     // words per limb-form residue in LDS: padded to an odd count where products follow (bank
     // conflicts cost more there than the LDS), dense on DFT-only levels (occupancy counts more)
     constexpr int LS = MODE == 0 ? L : Dig<L>::LS;
@@ -1740,8 +1745,14 @@ struct Transform {
             const uint32_t* bp = pw ? bpoly : nullptr;
             const int sq = pw ? squaring : 0;
 #define DKSS_LEVEL(MD, EC)                                                                          \
-    hipLaunchKernelGGL((k_level<L, MD, EC>), dim3(blocks, G), dim3(kThreads), lds, s, poly, (long long)stride, \
-                       tab, A, Q, bp, sq, PA, which, M)
+    do {                                                                                            \
+        if (A.log2m == 4 && A.log2r == 5)                                                           \
+            hipLaunchKernelGGL((k_level<L, MD, EC, true>), dim3(blocks, G), dim3(kThreads), lds, s, poly, \
+                               (long long)stride, tab, A, Q, bp, sq, PA, which, M);                 \
+        else                                                                                        \
+            hipLaunchKernelGGL((k_level<L, MD, EC, false>), dim3(blocks, G), dim3(kThreads), lds, s, poly, \
+                               (long long)stride, tab, A, Q, bp, sq, PA, which, M);                 \
+    } while (0)
             if (pw) {
                 // algorithmic work: a and b read, the product written; 2M products in R and
                 // 2M m scalar products for the (2M)^-1
