@@ -345,7 +345,7 @@ __device__ __forceinline__ void tw_fetch(Ahead<L>& f, int r0, const uint32_t* __
 // element with position v in column c sits in LDS slot v (after the DFT, mode 1) or bitrev(v)
 // (before it, mode 2).  Mode 1 writes results to HBM; mode 2 writes them back into the slot once
 // the round's products (which read the slot) are done.  f holds round 0's twiddle on entry.
-template <int L, int MODE>
+template <int L, int MODE, bool M16>
 __device__ __forceinline__ void level_twiddle(Ahead<L>& f, uint32_t* cur, uint32_t* RB, uint32_t* __restrict__ poly,
                                               const uint32_t* __restrict__ table, const LevelArgs& A,
                                               long long c0, const QConst& Q) {
@@ -379,7 +379,7 @@ __device__ __forceinline__ void level_twiddle(Ahead<L>& f, uint32_t* cur, uint32
         uint32_t out[D];                                // mode 1: L limbs; mode 2: D digits
         if (valid) {
             if (nz) {
-                rprod_coeff<L, MODE == 1>(TP, X, A.log2m, j, Q, out);
+                rprod_coeff<L, MODE == 1, M16 ? 4 : 0>(TP, X, A.log2m, j, Q, out);
             } else if (MODE == 1) {
                 digits_to_limbs<L>(X + j * D, out);
             }
@@ -478,7 +478,7 @@ __device__ __forceinline__ void pw_fetch(Ahead<L>& f, int r0, const uint32_t* __
 // polynomial position (bpoly; f holds round 0's on entry), or is a_v itself for a squaring
 // (bpoly NULL), and is staged with its negation, like a twiddle.  Rounds of 256/m elements,
 // synchronized per wavefront as in level_twiddle.
-template <int L>
+template <int L, bool M16>
 __device__ __forceinline__ void level_pointwise(Ahead<L>& f, uint32_t* cur, uint32_t* RB,
                                                 const uint32_t* __restrict__ bpoly, const LevelArgs& A,
                                                 long long c0, const QConst& Q) {
@@ -512,7 +512,7 @@ __device__ __forceinline__ void level_pointwise(Ahead<L>& f, uint32_t* cur, uint
         uint32_t out[D];
         if (valid) {
             uint32_t cv[D];
-            rprod_coeff<L>(TP, X, A.log2m, j, Q, cv);       // (a*b)_j 2^-28K
+            rprod_coeff<L, false, M16 ? 4 : 0>(TP, X, A.log2m, j, Q, cv);   // (a*b)_j 2^-28K
             mont_scalar<L>(cv, Q.kpw, Q, out);              // * (2M)^-1 2^28K
         }
         wave_sync();
@@ -555,7 +555,7 @@ __global__ __launch_bounds__(kThreads) void k_level(uint32_t* __restrict__ poly0
         tw_fetch<L>(f, 0, table, A, c0);
         level_load_digits<L>(H0, poly, A, c0);
         __syncthreads();
-        level_twiddle<L, 2>(f, H0, H1, poly, table, A, c0, Q);
+        level_twiddle<L, 2, M16>(f, H0, H1, poly, table, A, c0, Q);
         lds_to_limbs<L, LS>(H1, H0, A, false);
         uint32_t* cur = H1;
         uint32_t* nxt = H0;
@@ -584,9 +584,9 @@ __global__ __launch_bounds__(kThreads) void k_level(uint32_t* __restrict__ poly0
     uint32_t* dg = nxt;
     lds_to_digits<L, LS>(dg, cur, A);
     if (MODE == 1) {
-        level_twiddle<L, 1>(f, dg, cur, poly, table, A, c0, Q);
+        level_twiddle<L, 1, M16>(f, dg, cur, poly, table, A, c0, Q);
     } else {
-        level_pointwise<L>(f, dg, cur, bpoly, A, c0, Q);
+        level_pointwise<L, M16>(f, dg, cur, bpoly, A, c0, Q);
         lds_to_limbs<L, LS>(cur, dg, A, true);          // slot v -> bitrev(v): the inverse DFT's input
         nxt = dg;
         dft_passes<L, LS>(cur, nxt, A, 1, Q);

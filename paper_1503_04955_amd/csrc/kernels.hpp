@@ -295,21 +295,31 @@ __host__ __device__ __forceinline__ void rprod_term(uint64_t* col, const uint32_
 // every r; X holds x_0..x_(m-1) at D words.  The lanes of one element read the same x_k (one
 // LDS address) and m consecutive staged entries (odd stride), and the lanes of all elements of
 // a wavefront read the same positions, whatever their twiddles.
-// Returns c_j 2^(-28K) mod q, canonical, in digits (LIMBS: in L limbs).
-template <int L, bool LIMBS = false>
+// Returns c_j 2^(-28K) mod q, canonical, in digits (LIMBS: in L limbs).  FM > 0: log2m = FM is
+// known at compile time and the sum is unrolled (no address arithmetic per term).
+template <int L, bool LIMBS = false, int FM = 0>
 __host__ __device__ __forceinline__ void rprod_coeff(const uint32_t* TP, const uint32_t* X, int log2m, int j,
                                             const QConst& Q, uint32_t* out) {
     using G = Dig<L>;
-    const int m = 1 << log2m;
+    const int m = FM > 0 ? 1 << FM : 1 << log2m;
     uint64_t col[G::NC];
 #pragma unroll
     for (int k = 0; k < G::NC; ++k) col[k] = 0;
     int w = j + m;
     rprod_term<L>(col, TP + w * G::DS, X);      // k = 0 ahead of the loop: the columns start from it
-    for (int k = 1; k < m; ++k) {
-        --w;
-        rprod_term<L>(col, TP + w * G::DS, X + k * G::D);
-        if ((k + 1) % G::NI == 0) normalize_cols<L>(col);
+    if constexpr (FM > 0) {
+#pragma unroll
+        for (int k = 1; k < (1 << FM); ++k) {
+            --w;
+            rprod_term<L>(col, TP + w * G::DS, X + k * G::D);
+            if ((k + 1) % G::NI == 0) normalize_cols<L>(col);
+        }
+    } else {
+        for (int k = 1; k < m; ++k) {
+            --w;
+            rprod_term<L>(col, TP + w * G::DS, X + k * G::D);
+            if ((k + 1) % G::NI == 0) normalize_cols<L>(col);
+        }
     }
     if (LIMBS) redc_cols_limbs<L>(col, Q, out);
     else redc_cols<L>(col, Q, out);
