@@ -345,7 +345,7 @@ __device__ __forceinline__ void tw_fetch(Ahead<L>& f, int r0, const uint32_t* __
 // element with position v in column c sits in LDS slot v (after the DFT, mode 1) or bitrev(v)
 // (before it, mode 2).  Mode 1 writes results to HBM; mode 2 writes them back into the slot once
 // the round's products (which read the slot) are done.  f holds round 0's twiddle on entry.
-template <int L, int MODE, bool M16>
+template <int L, int MODE, int FM>
 __device__ __forceinline__ void level_twiddle(Ahead<L>& f, uint32_t* cur, uint32_t* RB, uint32_t* __restrict__ poly,
                                               const uint32_t* __restrict__ table, const LevelArgs& A,
                                               long long c0, const QConst& Q) {
@@ -379,7 +379,7 @@ __device__ __forceinline__ void level_twiddle(Ahead<L>& f, uint32_t* cur, uint32
         uint32_t out[D];                                // mode 1: L limbs; mode 2: D digits
         if (valid) {
             if (nz) {
-                rprod_coeff<L, MODE == 1, M16 ? 4 : 0>(TP, X, A.log2m, j, Q, out);
+                rprod_coeff<L, MODE == 1, FM>(TP, X, A.log2m, j, Q, out);
             } else if (MODE == 1) {
                 digits_to_limbs<L>(X + j * D, out);
             }
@@ -478,7 +478,7 @@ __device__ __forceinline__ void pw_fetch(Ahead<L>& f, int r0, const uint32_t* __
 // polynomial position (bpoly; f holds round 0's on entry), or is a_v itself for a squaring
 // (bpoly NULL), and is staged with its negation, like a twiddle.  Rounds of 256/m elements,
 // synchronized per wavefront as in level_twiddle.
-template <int L, bool M16>
+template <int L, int FM>
 __device__ __forceinline__ void level_pointwise(Ahead<L>& f, uint32_t* cur, uint32_t* RB,
                                                 const uint32_t* __restrict__ bpoly, const LevelArgs& A,
                                                 long long c0, const QConst& Q) {
@@ -512,7 +512,7 @@ __device__ __forceinline__ void level_pointwise(Ahead<L>& f, uint32_t* cur, uint
         uint32_t out[D];
         if (valid) {
             uint32_t cv[D];
-            rprod_coeff<L, false, M16 ? 4 : 0>(TP, X, A.log2m, j, Q, cv);   // (a*b)_j 2^-28K
+            rprod_coeff<L, false, FM>(TP, X, A.log2m, j, Q, cv);   // (a*b)_j 2^-28K
             mont_scalar<L>(cv, Q.kpw, Q, out);              // * (2M)^-1 2^28K
         }
         wave_sync();
@@ -527,18 +527,19 @@ __device__ __forceinline__ void level_pointwise(Ahead<L>& f, uint32_t* cur, uint
 // MODE 0: DFT only; 1: forward DFT, then twiddles on the way out; 2: twiddles, then inverse DFT;
 // 3 (bottom level, no twiddles): forward DFT, componentwise products with bpoly, inverse DFT.
 // ENC (top forward level): the columns are encoded from operand `which` of PA's product instead
-// of being read from poly.  M16: the launch has m = 16 and radix 32 (the commonest shape), given
-// to the compiler so that the index arithmetic of the passes and rounds folds.  LDS: two halves of A.half words; a DFT runs between them on limbs,
+// of being read from poly.  FM, FR > 0: the launch has log2 m = FM and radix 2^FR (the commonest
+// shapes), given to the compiler so that the index arithmetic of the passes and rounds folds and
+// the sum of the products in R unrolls; 0: both taken from A.  LDS: two halves of A.half words; a DFT runs between them on limbs,
 // products run on digits in one half with their operands staged in the other.
-template <int L, int MODE, bool ENC, bool M16>
+template <int L, int MODE, bool ENC, int FM, int FR>
 __global__ __launch_bounds__(kThreads) void k_level(uint32_t* __restrict__ poly0, long long stride,
                                                     const uint32_t* __restrict__ table, LevelArgs A,
                                                     QConst Q, const uint32_t* __restrict__ bpoly0,
                                                     int squaring, ProdArgs PA, int which, long long M) {
     A.mode = MODE;
-    if (M16) {
-        A.log2m = 4;
-        A.log2r = 5;
+    if (FM > 0) {
+        A.log2m = FM;
+        A.log2r = FR;
     }
     // words per limb-form residue in LDS: padded to an odd count where products follow (bank
     // conflicts cost more there than the LDS), dense on DFT-only levels (occupancy counts more)
@@ -555,7 +556,7 @@ __global__ __launch_bounds__(kThreads) void k_level(uint32_t* __restrict__ poly0
         tw_fetch<L>(f, 0, table, A, c0);
         level_load_digits<L>(H0, poly, A, c0);
         __syncthreads();
-        level_twiddle<L, 2, M16>(f, H0, H1, poly, table, A, c0, Q);
+        level_twiddle<L, 2, FM>(f, H0, H1, poly, table, A, c0, Q);
         lds_to_limbs<L, LS>(H1, H0, A, false);
         uint32_t* cur = H1;
         uint32_t* nxt = H0;
@@ -584,9 +585,9 @@ __global__ __launch_bounds__(kThreads) void k_level(uint32_t* __restrict__ poly0
     uint32_t* dg = nxt;
     lds_to_digits<L, LS>(dg, cur, A);
     if (MODE == 1) {
-        level_twiddle<L, 1, M16>(f, dg, cur, poly, table, A, c0, Q);
+        level_twiddle<L, 1, FM>(f, dg, cur, poly, table, A, c0, Q);
     } else {
-        level_pointwise<L, M16>(f, dg, cur, bpoly, A, c0, Q);
+        level_pointwise<L, FM>(f, dg, cur, bpoly, A, c0, Q);
         lds_to_limbs<L, LS>(cur, dg, A, true);          // slot v -> bitrev(v): the inverse DFT's input
         nxt = dg;
         dft_passes<L, LS>(cur, nxt, A, 1, Q);
@@ -1744,14 +1745,15 @@ struct Transform {
             const double in_b = ec ? Sb + 4.0 * in_words : 2.0 * Sb;   // bytes: read + write
             const uint32_t* bp = pw ? bpoly : nullptr;
             const int sq = pw ? squaring : 0;
+#define DKSS_LEVEL_AT(MD, EC, FM, FR)                                                                \
+    hipLaunchKernelGGL((k_level<L, MD, EC, FM, FR>), dim3(blocks, G), dim3(kThreads), lds, s, poly,     \
+                       (long long)stride, tab, A, Q, bp, sq, PA, which, M)
 #define DKSS_LEVEL(MD, EC)                                                                          \
     do {                                                                                            \
-        if (A.log2m == 4 && A.log2r == 5)                                                           \
-            hipLaunchKernelGGL((k_level<L, MD, EC, true>), dim3(blocks, G), dim3(kThreads), lds, s, poly, \
-                               (long long)stride, tab, A, Q, bp, sq, PA, which, M);                 \
-        else                                                                                        \
-            hipLaunchKernelGGL((k_level<L, MD, EC, false>), dim3(blocks, G), dim3(kThreads), lds, s, poly, \
-                               (long long)stride, tab, A, Q, bp, sq, PA, which, M);                 \
+        if (A.log2m == 4 && A.log2r == 5) DKSS_LEVEL_AT(MD, EC, 4, 5);                              \
+        else if (A.log2m == 5 && A.log2r == 5) DKSS_LEVEL_AT(MD, EC, 5, 5);                         \
+        else if (A.log2m == 5 && A.log2r == 6) DKSS_LEVEL_AT(MD, EC, 5, 6);                         \
+        else DKSS_LEVEL_AT(MD, EC, 0, 0);                                                           \
     } while (0)
             if (pw) {
                 // algorithmic work: a and b read, the product written; 2M products in R and
@@ -1774,6 +1776,7 @@ struct Transform {
                 DKSS_LEVEL(2, false);
             }
 #undef DKSS_LEVEL
+#undef DKSS_LEVEL_AT
             return launch_status();
         };
         int rc;
