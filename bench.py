@@ -21,6 +21,8 @@ profiles/<kernel>_traffic.txt records, when it was taken on the current kernel s
 null.  roofline_fft reports the FFT levels without twiddles (k_level<L, 0>) against HBM.
 
 "tuned" and "learned" time the same product under the tuned table and the learned selector;
+"cold" times a fresh context's first product of the same operands on the host clock: planning
+(prime, generator, rho on the host) and the rho-power table (GPU) as setup_ms, then the product;
 "sizes" times single products of 2^18 and 2^24 bits (thesis rule, learned selector, and the
 thesis-rule product replayed as a one-product HIP graph, which removes the host launch cost of
 the launch-bound small case).
@@ -351,7 +353,23 @@ def main():
     out["learned"] = {"ms_per_step": ms_l, "value": 2 * n * 32 / (ms_l / 1e3),
                       "choice": ctx_l.mlp_choose(32 * n, 32 * n),
                       "params": ctx_l.select_params(32 * n, 32 * n).as_dict()}
-    del ws_l, ws, c_t
+    # cold: a fresh context's planning (host), rho table (GPU) and first product, host clock
+    ws_c = torch.empty(dk.Context().workspace_bytes(n, n), dtype=torch.uint8, device=dev)
+    ctx_c = dk.Context()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx_c.prepare(n, n)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ctx_c.mul(a, b, out=c_t, ws=ws_c)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    if not torch.equal(c, c_t):
+        print("cold product differs", file=sys.stderr)
+        sys.exit(1)
+    out["cold"] = {"setup_ms": 1e3 * (t1 - t0), "first_product_ms": 1e3 * (t2 - t1),
+                   "ms": 1e3 * (t2 - t0)}
+    del ws_l, ws, ws_c, c_t, ctx_c
     torch.cuda.empty_cache()
     if args.batch:
         out["batch"] = batch_bench(args.batch, 3, dk, torch, SI)
