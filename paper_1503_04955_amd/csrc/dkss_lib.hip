@@ -541,9 +541,9 @@ __global__ __launch_bounds__(kThreads) void k_level(uint32_t* __restrict__ poly0
         A.log2m = FM;
         A.log2r = FR;
     }
-    // words per limb-form residue in LDS: padded to an odd count where products follow (bank
-    // conflicts cost more there than the LDS), dense on DFT-only levels (occupancy counts more)
-    constexpr int LS = MODE == 0 ? L : Dig<L>::LS;
+    // words per limb-form residue in LDS: padded to an odd count, so that the lanes of a
+    // butterfly pass or a conversion that read consecutive residues hit distinct banks
+    constexpr int LS = Dig<L>::LS;
     uint32_t* __restrict__ poly = poly0 + (size_t)blockIdx.y * stride;
     extern __shared__ uint4 smv[];
     uint32_t* const H0 = reinterpret_cast<uint32_t*>(smv);
@@ -1705,7 +1705,7 @@ struct Transform {
             const bool pw = fused && !inverse && k == nl - 1;     // fused componentwise products
             // columns per workgroup: two LDS halves of C columns (limbs; digits too where the
             // products run) within the budget, at most ncols; one column on twiddle levels
-            const size_t colbytes = (size_t)r * (pw ? elem_words(m, D) : m * L) * 4;
+            const size_t colbytes = (size_t)r * (pw ? elem_words(m, D) : m * Dig<L>::LS) * 4;
             int log2C = 0;
             while (!tw && (2 * colbytes << (log2C + 1)) <= (size_t)c.dft_lds &&
                    (1LL << (log2C + 1)) <= ncols)
@@ -1726,7 +1726,7 @@ struct Transform {
             // columns in digits and the staging of 256/m operands of 2m residues
             A.ew = elem_words(m, D);
             A.sw = stage_words(m, Dig<L>::DS);
-            const size_t ncl = ((size_t)r << log2C) * m * (tw || pw ? Dig<L>::LS : L);
+            const size_t ncl = ((size_t)r << log2C) * m * Dig<L>::LS;
             const size_t ncd = ((size_t)r << log2C) * A.ew;
             const size_t rb_words = (size_t)(kThreads / m) * A.sw;
             size_t half = ncl;
