@@ -780,20 +780,32 @@ __device__ __forceinline__ void position_value(const uint32_t* __restrict__ poly
 
 // Sum of word w's 32-bit pieces from the positions in LDS (positions g_min .. g_max of the
 // workgroup, pos_words() words each).
+// floor(y / u) for 0 <= y < 2^22 and 1 <= u < 2^16: a single-precision estimate, corrected by
+// one step either way (the estimate is within 1 of the quotient)
+__device__ __forceinline__ int div_small(int y, int u, float inv_u) {
+    int q = (int)((float)y * inv_u);
+    if (q * u > y) --q;
+    else if ((q + 1) * u <= y) ++q;
+    return q;
+}
+
+// V_w from the aligned position values pv of positions g_min..g_max (LDS).  The quotients by u
+// are taken relative to the workgroup's base bq (bq u is at most every numerator here, and the
+// numerators exceed it by less than 2^15), so that they are small divisions; the bit offset u g
+// of each position advances by u per step.
 template <int L>
 __device__ __forceinline__ uint64_t word_sum_tiled(long long w, const uint32_t* pv, long long g_min, long long g_max,
-                                                   int u, double inv_u) {
+                                                   int u, long long bq, float inv_u) {
     constexpr int NW = pos_words<L>();
+    const long long B = bq * u;
     const long long lo_excl = 32 * w - (32 * L + 1);      // V_g reaches word w iff u g > lo_excl
-    long long g = lo_excl < 0 ? 0 : div_u(lo_excl, u, inv_u) + 1;
-    long long g_hi = div_u(32 * w + 31, u, inv_u);
+    long long g = lo_excl < 0 ? 0 : bq + div_small((int)(lo_excl - B), u, inv_u) + 1;
+    long long g_hi = bq + div_small((int)(32 * w + 31 - B), u, inv_u);
     if (g < g_min) g = g_min;
     if (g_hi > g_max) g_hi = g_max;
     uint64_t V = 0;
-    for (; g <= g_hi; ++g) {
-        const long long W = ((long long)u * g) >> 5;
-        V += pv[(g - g_min) * NW + (w - W)];
-    }
+    long long ug = (long long)u * g;
+    for (; g <= g_hi; ++g, ug += u) V += pv[(g - g_min) * NW + (w - (ug >> 5))];
     return V;
 }
 
@@ -836,8 +848,10 @@ __global__ __launch_bounds__(kThreads) void k_decode(ProdArgs PA, const uint32_t
         for (long long g = g_min + threadIdx.x; g <= g_max; g += kThreads)
             position_value<L>(poly, g, twoM, log2m, u, pv + (g - g_min) * NW);
         __syncthreads();
-        if (w < nw) V = word_sum_tiled<L>(w, pv, g_min, g_max, u, inv_u);
-        if (threadIdx.x == 0 && w0 > 0 && w0 < nw) Vprev = word_sum_tiled<L>(w0 - 1, pv, g_min, g_max, u, inv_u);
+        const long long bq = g_min > 0 ? g_min - 1 : 0;    // floor(lo_excl(w0 - 1) / u)
+        const float inv_uf = 1.0f / (float)u;
+        if (w < nw) V = word_sum_tiled<L>(w, pv, g_min, g_max, u, bq, inv_uf);
+        if (threadIdx.x == 0 && w0 > 0 && w0 < nw) Vprev = word_sum_tiled<L>(w0 - 1, pv, g_min, g_max, u, bq, inv_uf);
     } else {
         if (w < nw) V = word_sum<L>(w, poly, 0, twoM, log2m, u);
         if (threadIdx.x == 0 && w0 > 0 && w0 < nw) Vprev = word_sum<L>(w0 - 1, poly, 0, twoM, log2m, u);
