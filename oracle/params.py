@@ -31,7 +31,9 @@ def modulus_bits_rule(N, word=64):
 
 def split_rule(N, log2_Mm):
     """M/m = 2^k with k of the parity of log2(Mm), nearest to log2(sqrt(2) * N / log^3 N)
-    (Sec. 4.1, last paragraph; the factor sqrt(2) is this repository's reading).
+    (Sec. 4.1, last paragraph).  The factor sqrt(2) is this repository's reading: read literally
+    (factor 1) the rule contradicts the m that the thesis's memory table implies at 5 of its 16
+    lengths, while any factor with log2 in (0.399, 0.516) fits all 16.
     Ties go to the smaller k; m >= 2 and M >= m (Sec. 3.2 Step 1)."""
     lg = math.log2(N)
     target = 0.5 + lg - 3.0 * math.log2(lg)
