@@ -302,6 +302,25 @@ def test_every_candidate_tuple_is_bit_exact(env, limbs):
         assert np.array_equal(_gpu_mul(env, a, b, p), want), ci
 
 
+@pytest.mark.parametrize("log2_m,radices_fixed,radices_general", [
+    (4, [5, 5, 5], [4, 4, 4, 3]),       # m = 16: radix-32 levels (compile-time shape) vs radix 16/8
+    (5, [6, 6, 3], [5, 5, 5]),          # m = 32: radix-64 levels vs radix-32 levels
+])
+def test_compile_time_shapes_match_general_kernels(env, log2_m, radices_fixed, radices_general):
+    """The level kernels compiled for fixed (m, radix) shapes and the general ones give the same
+    product for one tuple run with splits that take either; the product's lowest limbs equal the
+    oracle's and its residues the oracle's residues."""
+    dk, torch, ctx = env
+    log2_M = sum(radices_fixed) - 1
+    limbs = (1 << (log2_M + log2_m - 1)) * 24 // 32     # the tuple's full capacity (u = 24)
+    a, b = SI.operand_pair(SI.SEED_BASE + 60 + log2_m, limbs, limbs - 5)
+    got = [_gpu_mul(env, a, b, _params(dk, log2_M, log2_m, u=24, p_bits=128, radices=rad))
+           for rad in (radices_fixed, radices_general)]
+    assert np.array_equal(got[0], got[1])
+    _low_limbs_check(a, b, got[0])
+    _residue_check(a, b, got[0], _primes61(60 + log2_m, 4))
+
+
 def test_tuned_policy_products(env):
     dk, torch, ctx = env
     tctx = dk.Context(dk.POLICY_TUNED)
