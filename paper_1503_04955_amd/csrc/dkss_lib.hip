@@ -529,7 +529,7 @@ __device__ __forceinline__ void level_pointwise(Ahead<L>& f, uint32_t* cur, uint
 // ENC (top forward level): the columns are encoded from operand `which` of PA's product instead
 // of being read from poly.  FM, FR > 0: the launch has log2 m = FM and radix 2^FR (the commonest
 // shapes), given to the compiler so that the index arithmetic of the passes and rounds folds and
-// the sum of the products in R unrolls; 0: both taken from A.  LDS: two halves of A.half words; a DFT runs between them on limbs,
+// the sum of the products in R unrolls; 0: taken from A (FM > 0 with FR = 0: m fixed, any radix).  LDS: two halves of A.half words; a DFT runs between them on limbs,
 // products run on digits in one half with their operands staged in the other.
 template <int L, int MODE, bool ENC, int FM, int FR>
 __global__ __launch_bounds__(kThreads) void k_level(uint32_t* __restrict__ poly0, long long stride,
@@ -537,10 +537,8 @@ __global__ __launch_bounds__(kThreads) void k_level(uint32_t* __restrict__ poly0
                                                     QConst Q, const uint32_t* __restrict__ bpoly0,
                                                     int squaring, ProdArgs PA, int which, long long M) {
     A.mode = MODE;
-    if (FM > 0) {
-        A.log2m = FM;
-        A.log2r = FR;
-    }
+    if (FM > 0) A.log2m = FM;
+    if (FR > 0) A.log2r = FR;
     // words per limb-form residue in LDS: padded to an odd count, so that the lanes of a
     // butterfly pass or a conversion that read consecutive residues hit distinct banks
     constexpr int LS = Dig<L>::LS;
@@ -1767,6 +1765,8 @@ struct Transform {
         if (A.log2m == 4 && A.log2r == 5) DKSS_LEVEL_AT(MD, EC, 4, 5);                              \
         else if (A.log2m == 5 && A.log2r == 5) DKSS_LEVEL_AT(MD, EC, 5, 5);                         \
         else if (A.log2m == 5 && A.log2r == 6) DKSS_LEVEL_AT(MD, EC, 5, 6);                         \
+        else if (A.log2m == 4) DKSS_LEVEL_AT(MD, EC, 4, 0);                                         \
+        else if (A.log2m == 5) DKSS_LEVEL_AT(MD, EC, 5, 0);                                         \
         else DKSS_LEVEL_AT(MD, EC, 0, 0);                                                           \
     } while (0)
             if (pw) {

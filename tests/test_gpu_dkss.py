@@ -306,10 +306,11 @@ def test_every_candidate_tuple_is_bit_exact(env, limbs):
     (4, [5, 5, 5], [4, 4, 4, 3]),       # m = 16: radix-32 levels (compile-time shape) vs radix 16/8
     (5, [6, 6, 3], [5, 5, 5]),          # m = 32: radix-64 levels vs radix-32 levels
 ])
-def test_compile_time_shapes_match_general_kernels(env, log2_m, radices_fixed, radices_general):
-    """The level kernels compiled for fixed (m, radix) shapes and the general ones give the same
-    product for one tuple run with splits that take either; the product's lowest limbs equal the
-    oracle's and its residues the oracle's residues."""
+def test_compile_time_shapes_agree(env, log2_m, radices_fixed, radices_general):
+    """The level kernels compiled for fixed (m, radix) shapes and those with only m fixed (any
+    radix) give the same product for one tuple run with splits that take either; the product's
+    lowest limbs equal the oracle's and its residues the oracle's residues.  (Every other m runs
+    the fully general kernels, throughout the other tests.)"""
     dk, torch, ctx = env
     log2_M = sum(radices_fixed) - 1
     limbs = (1 << (log2_M + log2_m - 1)) * 24 // 32     # the tuple's full capacity (u = 24)
