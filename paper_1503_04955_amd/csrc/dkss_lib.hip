@@ -989,13 +989,24 @@ __global__ __launch_bounds__(kThreads) void k_carry_apply(ProdArgs PA,
     const unsigned long long* __restrict__ pmask = pmask0 + y * wstride;
     const unsigned char* __restrict__ cin01 = cin010 + y * wstride;
     const unsigned char* __restrict__ seg_cin = seg_cin0 + y * sstride;
-    const long long w = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    // four consecutive words per thread, all in the same 64-word wavefront group
+    const long long w = ((long long)blockIdx.x * blockDim.x + threadIdx.x) * 4;
     if (w >= nw) return;
     const long long wave = w >> 6;
     const int c = (cin01[wave] >> (seg_cin[wave >> 8] ? 1 : 0)) & 1;
     const unsigned long long G = gmask[wave], A = G | pmask[wave];
     const unsigned long long carries = (A + G + (unsigned long long)c) ^ A ^ G;
-    out[w] += (uint32_t)((carries >> (w & 63)) & 1);
+    const uint32_t bits = (uint32_t)(carries >> (w & 63)) & 0xFu;
+    if (w + 4 <= nw && ((uintptr_t)(out + w) & 15) == 0) {
+        uint4 v = *reinterpret_cast<const uint4*>(out + w);
+        v.x += bits & 1u;
+        v.y += (bits >> 1) & 1u;
+        v.z += (bits >> 2) & 1u;
+        v.w += (bits >> 3) & 1u;
+        *reinterpret_cast<uint4*>(out + w) = v;
+    } else {
+        for (int k = 0; k < 4 && w + k < nw; ++k) out[w + k] += (bits >> k) & 1u;
+    }
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -1873,7 +1884,8 @@ struct Decode {
         if (int rc_ = launch_status()) return rc_;
         {
             ProfScope ps(c.prof, DKSS_K_CARRY_APPLY, s, 8.0 * out_words, 0.0);
-            hipLaunchKernelGGL(k_carry_apply, dim3(blocks, G), dim3(kThreads), 0, s, PA, w.gmask, w.pmask,
+            const unsigned blocks4 = (unsigned)((nw_max + 4 * kThreads - 1) / (4 * kThreads));
+            hipLaunchKernelGGL(k_carry_apply, dim3(blocks4, G), dim3(kThreads), 0, s, PA, w.gmask, w.pmask,
                                w.cin01, w.seg_cin, (long long)w.wst, (long long)w.sst);
         }
         if (int rc_ = launch_status()) return rc_;
