@@ -211,3 +211,34 @@ def test_tuned_table_batch_sections_and_schoolbook(dk, tmp_path):
     assert ctx.plan_info(200, 200).schoolbook == 1 and ctx0.plan_info(200, 200).schoolbook == 0
     big = ctx.plan_info(2 ** 16, 2 ** 16)
     assert big.schoolbook == 0 and tup(big.params) == tup(ctx0.plan_info(2 ** 16, 2 ** 16).params)
+
+
+def test_tuned_table_writer_sections(dk, tmp_path):
+    """tune.write_tuned_table: half-open buckets around the measured sizes, the fastest output
+    per size (the schoolbook included), one "@batch B" section per measured batch size ending at
+    its largest size, and a table the library reads back with the same choices."""
+    from paper_1503_04955_amd import tune
+    S = dk.CAND_SCHOOLBOOK
+    ms = {  # (x, batch) -> {output: ms}
+        (12.0, 1): {S: 0.01, 3: 0.03, "thesis": 0.05}, (12.5, 1): {S: 0.05, 3: 0.03, "thesis": 0.06},
+        (13.0, 1): {2: 0.02, 3: 0.04, "thesis": 0.07},
+        (12.0, 16): {S: 0.001, 2: 0.004, "thesis": 0.005}, (13.0, 16): {S: 0.009, 8: 0.003, "thesis": 0.006},
+    }
+    rows = [{"log2_a": x, "ratio": 1, "batch": bt, "cand": c, "ms": v}
+            for (x, bt), d in ms.items() for c, v in d.items()]
+    rows.append({"log2_a": 12.0, "ratio": 2, "batch": 1, "cand": 9, "ms": 0.0001})   # other ratios ignored
+    path = tmp_path / "dkss_tuning.txt"
+    tune.write_tuned_table(rows, str(path))
+    lines = [l.split("#")[0].split() for l in open(path) if l.strip() and not l.startswith("#")]
+    assert lines == [["0.000", "12.250", str(S)], ["12.250", "12.750", "3"], ["12.750", "64.000", "2"],
+                     ["@batch", "16"], ["0.000", "12.500", str(S)], ["12.500", "13.500", "8"]]
+    ctx = dk.Context(dk.POLICY_TUNED, tuning_dir=str(tmp_path))
+    school = 2 ** 64 - 1
+    assert ctx.select_params(2 ** 12, 2 ** 12, 1).cutoff_bits == school
+    assert ctx.select_params(2 ** 12, 2 ** 12, 20).cutoff_bits == school
+    p16 = ctx.select_params(2 ** 13, 2 ** 13, 16)
+    c8 = dict(dk.Context().candidates(2 ** 13, 2 ** 13))[8]
+    assert (p16.log2_M, p16.log2_m, p16.p_bits) == (c8.log2_M, c8.log2_m, c8.p_bits)
+    p1 = ctx.select_params(2 ** 14, 2 ** 14, 16)          # beyond the batch-16 section: batch 1's entry
+    c2 = dict(dk.Context().candidates(2 ** 14, 2 ** 14))[2]
+    assert (p1.log2_M, p1.log2_m, p1.p_bits) == (c2.log2_M, c2.log2_m, c2.p_bits)
