@@ -89,8 +89,8 @@ typedef struct {
  * candidate index of dkss_candidates or DKSS_CAND_SCHOOLBOOK, a level split such as 5.5.4, a
  * DFT LDS budget in bytes), '#' comments, and "@batch B" lines: the entries after one hold for
  * batches of at least B products (before the first, B = 1); a product takes the entry of the
- * largest such B whose range holds its N.  Allocates nothing on the device until a parameter tuple is first prepared or selector
- * weights are installed.  Errors: DKSS_EINVAL. */
+ * largest such B whose range holds its N.  Allocates nothing on the device until a parameter tuple is first prepared or the
+ * selector's first inference.  Errors: DKSS_EINVAL. */
 int dkss_ctx_create(dkss_ctx** out, int policy, const char* cache_dir);
 
 /* Release the context and the device tables it owns.  Safe on NULL. */
@@ -120,14 +120,21 @@ int dkss_candidates(dkss_ctx* ctx, uint64_t a_bits, uint64_t b_bits, dkss_params
 /* Plan facts for a product of alen x blen limbs under params p (NULL = the policy). */
 int dkss_plan_info(dkss_ctx* ctx, size_t alen, size_t blen, const dkss_params* p, dkss_plan* out);
 
-/* Workspace bytes dkss_mul needs for alen x blen limbs under params p (NULL = the policy). */
+/* Workspace bytes dkss_mul needs for alen x blen limbs under params p (NULL = the policy),
+ * including room for the tuple's table of rho^s (used only while the context has not prepared
+ * that table, see dkss_prepare).  A planning call: under DKSS_POLICY_LEARNED it runs the
+ * selector's inference for a shape not seen before and waits for it (as dkss_mlp_choose), so
+ * that the products of that shape find the choice cached. */
 int dkss_workspace_bytes(dkss_ctx* ctx, size_t alen, size_t blen, const dkss_params* p,
                          size_t* out);
 
-/* Build (if not yet built) and cache in ctx the device constants of params p for operands of up
- * to alen x blen limbs: the table of rho^s (Sec. 4.2, powers below 2M/2m).  Allocates device
- * memory and synchronizes the stream.  dkss_mul calls it itself on the first use of a tuple;
- * calling it beforehand keeps dkss_mul free of allocations. */
+/* Build (if not yet built) and keep in ctx the device table of params p for operands of alen x
+ * blen limbs: rho^s for s below 2M/2m, Sec. 4.2 (and, under DKSS_POLICY_LEARNED, the selector's
+ * choice for the shape).  A planning call: allocates device memory, runs the build on s and
+ * waits for it; the table counts as built only once the build has finished, and a failed build
+ * leaves nothing behind.  Refused (DKSS_EINVAL) while s is capturing.  Without it, every product
+ * of the tuple rebuilds the table in its workspace (correct, slower).  Errors: DKSS_EINVAL,
+ * DKSS_ERANGE, DKSS_EHIP. */
 int dkss_prepare(dkss_ctx* ctx, size_t alen, size_t blen, const dkss_params* p, dkss_stream_t s);
 
 /*
@@ -135,10 +142,13 @@ int dkss_prepare(dkss_ctx* ctx, size_t alen, size_t blen, const dkss_params* p, 
  * included.  a == b with alen == blen is a squaring (one forward transform).  alen or blen of 0
  * gives c = 0.  c must not overlap a or b (DKSS_EINVAL).  ws must hold at least
  * dkss_workspace_bytes() bytes of device memory, 256-byte aligned (DKSS_ENOSPC / DKSS_EINVAL).
- * p = NULL uses the context's policy; under DKSS_POLICY_LEARNED the first product of a shape
- * waits for the selector's inference (dkss_mlp_choose, batch 1).  dkss_mul_batch asks the
- * selector once for all new shapes of the batch, with batch = count; a TUNED context looks its
- * table up with batch = count there (batch 1 here).
+ * p = NULL uses the context's policy; under DKSS_POLICY_LEARNED the product takes the choice a
+ * planning call (dkss_workspace_bytes, dkss_prepare, dkss_select_params, dkss_plan_info,
+ * dkss_mlp_choose) cached for the shape with batch 1, and the thesis rule when there is none; a
+ * TUNED context looks its table up with batch 1 (dkss_mul_batch: batch = count).
+ * The call allocates no memory and never waits on the host: all of its work, including the
+ * tuple's table when dkss_prepare has not built it (then in ws), is enqueued on s, so it may be
+ * recorded by a stream capture.
  * Errors: DKSS_EINVAL, DKSS_ENOSPC, DKSS_ERANGE (p^z below
  * Mm 2^(2u), 2M not dividing p - 1, M < m, m < 2, capacity M*m/2*u below 32*max(alen, blen),
  * unsupported limb count, a transform length 2M above 2^31, a kernel grid of 2^32 work-items
@@ -152,23 +162,33 @@ int dkss_mul(dkss_ctx* ctx, uint32_t* c, const uint32_t* a, size_t alen, const u
  * count independent products c[i] = a[i] * b[i] (each as in dkss_mul).  The arrays of
  * pointers and lengths are HOST arrays of device pointers.  p is NULL (policy per product) or
  * an array of count tuples.  Products that share a parameter tuple run together in the same
- * kernel launches.  The workspace must hold dkss_batch_workspace_bytes().
+ * kernel launches.  The workspace must hold dkss_batch_workspace_bytes().  Like dkss_mul it
+ * allocates nothing and does not wait: the product descriptors reach the start of ws through
+ * small kernel launches on s, and tables not built by a planning call are built in ws.
  */
 int dkss_mul_batch(dkss_ctx* ctx, size_t count, uint32_t* const* c, const uint32_t* const* a,
                    const size_t* alen, const uint32_t* const* b, const size_t* blen,
                    const dkss_params* p, void* ws, size_t ws_bytes, dkss_stream_t s);
 
-/* Workspace bytes for dkss_mul_batch with the same arguments. */
+/* Workspace bytes for dkss_mul_batch with the same arguments (descriptors, room for the table
+ * of every tuple the batch uses, the largest group's buffers).  A planning call like
+ * dkss_workspace_bytes: the selector's inference for the batch's new shapes runs here. */
 int dkss_batch_workspace_bytes(dkss_ctx* ctx, size_t count, const size_t* alen,
                                const size_t* blen, const dkss_params* p, size_t* out);
+
+/* dkss_prepare for every parameter tuple a batch with these lengths uses (a planning call:
+ * allocates, builds on s, waits).  Without it, dkss_mul_batch builds the tables it lacks in its
+ * workspace on every call.  Errors: as dkss_prepare. */
+int dkss_batch_prepare(dkss_ctx* ctx, size_t count, const size_t* alen, const size_t* blen,
+                       const dkss_params* p, dkss_stream_t s);
 
 /*
  * A batch (as in dkss_mul_batch) planned once and captured into a HIP graph; every
  * dkss_graph_launch recomputes all count products with one graph launch, reading the operands
  * and writing the results at the same device addresses.  At creation the library plans the
- * batch, builds the tables it needs, writes the product descriptors to the start of ws
- * (synchronously, on a stream of its own) and captures the kernels; nothing else enters the
- * graph.  The caller keeps ws, every operand and result buffer and the context alive and ws
+ * batch, builds the tables it needs in the context (as dkss_batch_prepare), writes the product
+ * descriptors to the start of ws (on a stream of its own, waiting for them) and captures the
+ * products' kernels; nothing else enters the graph.  The caller keeps ws, every operand and result buffer and the context alive and ws
  * otherwise unused until dkss_graph_destroy; launches of one graph must not overlap in time
  * (they share ws).  Profiling does not see graph launches.  count must be at least 1.
  * Errors: as dkss_mul_batch, DKSS_EHIP (capture or instantiation failed).
@@ -237,8 +257,9 @@ const char* dkss_kernel_name(int kind);
 /*
  * Context options (tuning knobs; none changes any result bit).
  *  DKSS_OPT_OVERLAP      1: the forward transform of b runs on a second, internal stream of
- *                        the context, forked from and joined back to the caller's stream with
- *                        events, so it overlaps the transform of a; 0 (default): one stream.
+ *                        the context (created when the option is first set to 1), forked from
+ *                        and joined back to the caller's stream with events, so it overlaps
+ *                        the transform of a; 0 (default): one stream.
  *  DKSS_OPT_DFT_LDS      LDS bytes an FFT-level workgroup may stage (default 32768; 16384 to
  *                        163840): more columns per workgroup versus more workgroups per CU.
  *  DKSS_OPT_FUSE_PW      1 (default): the componentwise products (Step 6) run inside the
@@ -312,7 +333,7 @@ int dkss_mlp_load(const char* path, float* params);
  * weights or no output is feasible (the thesis rule then applies).  Feasible: candidates that
  * dkss_candidates marks valid; the schoolbook when both operands together have at most 4096
  * limbs.  Inference runs dkss_mlp_forward on a stream private to the context and waits for it;
- * choices are cached per (limbs of a, limbs of b, batch).  Errors: DKSS_EINVAL, DKSS_ERANGE,
+ * choices are cached per (limbs of a, limbs of b, batch), where the products look them up.  Errors: DKSS_EINVAL, DKSS_ERANGE,
  * DKSS_EHIP.
  */
 int dkss_mlp_choose(dkss_ctx* ctx, uint64_t a_bits, uint64_t b_bits, uint32_t batch, int* cand);

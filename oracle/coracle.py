@@ -23,31 +23,49 @@ def build():
     subprocess.check_call(["gcc", "-O2", "-Wall", "-shared", "-fPIC", "-o", _LIB, _SRC])
 
 
+_native = {}
+
+
+def lib_native(dirpath):
+    """The same C source built with -O3 -march=native into dirpath (for timing the oracle on the
+    machine that runs it; the arithmetic is the source's, only the compiler flags differ)."""
+    path = os.path.join(dirpath, "libdkss_oracle_native.so")
+    if path not in _native:
+        os.makedirs(dirpath, exist_ok=True)
+        subprocess.check_call(["gcc", "-O3", "-march=native", "-Wall", "-shared", "-fPIC", "-o", path, _SRC])
+        _native[path] = _load(path)
+    return _native[path]
+
+
 def lib():
     global _lib
     if _lib is None:
         if not os.path.exists(_LIB):
             build()
-        L = ctypes.CDLL(_LIB)
-        u32p = ctypes.POINTER(ctypes.c_uint32)
-        u64p = ctypes.POINTER(ctypes.c_uint64)
-        sz, lg, i32 = ctypes.c_size_t, ctypes.c_long, ctypes.c_int
-        L.or_schoolbook.argtypes = [u32p, u32p, sz, u32p, sz]
-        L.or_residue.argtypes = [u32p, sz, ctypes.c_uint64]
-        L.or_residue.restype = ctypes.c_uint64
-        L.or_mod_reduce.argtypes = [u64p, u64p, i32, u64p, i32]
-        L.or_ring_mul.argtypes = [u32p, u32p, u32p, i32, i32, u32p]
-        L.or_ring_rotate.argtypes = [u32p, u32p, lg, i32, i32, u32p]
-        L.or_encode.argtypes = [u32p, u32p, sz, lg, i32, i32, i32]
-        L.or_fft.argtypes = [u32p, lg, i32, i32, u32p, u32p]
-        L.or_rho_powers.argtypes = [u32p, lg, i32, i32, u32p, u32p]
-        L.or_pointwise.argtypes = [u32p, u32p, u32p, lg, i32, i32, u32p]
-        L.or_decode.argtypes = [u32p, sz, u32p, lg, i32, i32, i32, u32p, u32p]
-        L.or_decode.restype = i32
-        L.or_dkss_mul.argtypes = [u32p, u32p, sz, u32p, sz, lg, i32, i32, i32, u32p, u32p, u32p]
-        L.or_dkss_mul.restype = i32
-        _lib = L
+        _lib = _load(_LIB)
     return _lib
+
+
+def _load(path):
+    L = ctypes.CDLL(path)
+    u32p = ctypes.POINTER(ctypes.c_uint32)
+    u64p = ctypes.POINTER(ctypes.c_uint64)
+    sz, lg, i32 = ctypes.c_size_t, ctypes.c_long, ctypes.c_int
+    L.or_schoolbook.argtypes = [u32p, u32p, sz, u32p, sz]
+    L.or_residue.argtypes = [u32p, sz, ctypes.c_uint64]
+    L.or_residue.restype = ctypes.c_uint64
+    L.or_mod_reduce.argtypes = [u64p, u64p, i32, u64p, i32]
+    L.or_ring_mul.argtypes = [u32p, u32p, u32p, i32, i32, u32p]
+    L.or_ring_rotate.argtypes = [u32p, u32p, lg, i32, i32, u32p]
+    L.or_encode.argtypes = [u32p, u32p, sz, lg, i32, i32, i32]
+    L.or_fft.argtypes = [u32p, lg, i32, i32, u32p, u32p]
+    L.or_rho_powers.argtypes = [u32p, lg, i32, i32, u32p, u32p]
+    L.or_pointwise.argtypes = [u32p, u32p, u32p, lg, i32, i32, u32p]
+    L.or_decode.argtypes = [u32p, sz, u32p, lg, i32, i32, i32, u32p, u32p]
+    L.or_decode.restype = i32
+    L.or_dkss_mul.argtypes = [u32p, u32p, sz, u32p, sz, lg, i32, i32, i32, u32p, u32p, u32p]
+    L.or_dkss_mul.restype = i32
+    return L
 
 
 def _p32(a):
@@ -165,9 +183,10 @@ def decode(cc, outlen, M2, m, L, u, q):
     return out
 
 
-def dkss_mul(a, b, setup=None):
+def dkss_mul(a, b, setup=None, library=None):
     """c = a*b through Steps 4-8 of Sec. 3.2 in the C oracle.  ``setup`` is an
-    ``oracle.params.Setup``; by default the thesis rule for N = 32*max(alen, blen)."""
+    ``oracle.params.Setup``; by default the thesis rule for N = 32*max(alen, blen).  ``library``:
+    a build of the oracle from lib_native (default: lib())."""
     a = np.ascontiguousarray(a, np.uint32)
     b = np.ascontiguousarray(b, np.uint32)
     n = len(a) + len(b)
@@ -179,7 +198,7 @@ def dkss_mul(a, b, setup=None):
     L = S.L
     M2 = 2 * S.params.M
     c = np.zeros(n, np.uint32)
-    rc = lib().or_dkss_mul(_p32(c), _p32(a), len(a), _p32(b), len(b), M2, S.params.m, L,
+    rc = (library or lib()).or_dkss_mul(_p32(c), _p32(a), len(a), _p32(b), len(b), M2, S.params.m, L,
                            S.params.u, _p32(to_limbs(S.q, L)), _p32(coeffs_to_limbs(S.rho, L)),
                            _p32(to_limbs(pow(M2, -1, S.q), L)))
     if rc:

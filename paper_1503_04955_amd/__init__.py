@@ -104,6 +104,7 @@ def lib():
                                      vp, sz, vp]
         L.dkss_batch_workspace_bytes.argtypes = [vp, sz, ctypes.POINTER(sz), ctypes.POINTER(sz), PP,
                                                  ctypes.POINTER(sz)]
+        L.dkss_batch_prepare.argtypes = [vp, sz, ctypes.POINTER(sz), ctypes.POINTER(sz), PP, vp]
         L.dkss_forward.argtypes = [vp, vp, vp, sz, sz, PP, vp, sz, vp]
         L.dkss_residues.argtypes = [vp, sz, ctypes.POINTER(u64), sz, vp, vp]
         L.dkss_profile_enable.argtypes = [vp, ctypes.c_int]
@@ -141,7 +142,7 @@ def lib():
 
 EXPORTED = ["dkss_ctx_create", "dkss_ctx_destroy", "dkss_select_params", "dkss_plan_info",
             "dkss_workspace_bytes", "dkss_prepare", "dkss_mul", "dkss_mul_batch",
-            "dkss_batch_workspace_bytes", "dkss_forward", "dkss_residues", "dkss_profile_enable",
+            "dkss_batch_workspace_bytes", "dkss_batch_prepare", "dkss_forward", "dkss_residues", "dkss_profile_enable",
             "dkss_profile_read", "dkss_profile_reset", "dkss_kernel_name", "dkss_set_option",
             "dkss_candidates", "dkss_mlp_features", "dkss_mlp_forward", "dkss_mlp_work_floats",
             "dkss_mlp_loss_grad", "dkss_mlp_adam", "dkss_set_mlp", "dkss_mlp_load",
@@ -175,6 +176,38 @@ def _stream_ptr(stream):
 
 def _ptr(t):
     return ctypes.c_void_p(t.data_ptr()) if t is not None and t.numel() else ctypes.c_void_p(0)
+
+
+def _check_limbs(name, t, device=None):
+    """An integer argument: a contiguous torch.int32 tensor on the device (a strided view or
+    another dtype would be read as the wrong limbs)."""
+    torch = _torch()
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("%s must be a torch tensor" % name)
+    if t.dtype != torch.int32:
+        raise TypeError("%s must be torch.int32 (uint32 limbs), not %s" % (name, t.dtype))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    if not t.is_cuda or (device is not None and t.device != device):
+        raise ValueError("%s must be on device %s" % (name, device if device is not None else "cuda"))
+
+
+def _capturing():
+    torch = _torch()
+    return torch.cuda.is_available() and torch.cuda.is_current_stream_capturing()
+
+
+def _keep_until_done(stream, *tensors):
+    """Tensors allocated on the current stream and used by work on another stream stay
+    allocated until that work is done."""
+    if stream is None:
+        return
+    torch = _torch()
+    if stream == torch.cuda.current_stream():
+        return
+    for t in tensors:
+        if t is not None and t.numel():
+            t.record_stream(stream)
 
 
 def _pp(params):
@@ -211,6 +244,7 @@ class Context:
         d = tuning_dir if tuning_dir is not None else TUNING_DIR
         _check(lib().dkss_ctx_create(ctypes.byref(h), policy, d.encode()), "dkss_ctx_create")
         self._h = h
+        self._prepared = set()
 
     def close(self):
         if self._h:
@@ -249,19 +283,32 @@ class Context:
         return n.value
 
     def prepare(self, alen, blen, params=None, stream=None):
+        """Build the tuple's table in the context (dkss_prepare: allocates, waits)."""
         _check(lib().dkss_prepare(self._h, alen, blen, _pp(params), _stream_ptr(stream)),
                "dkss_prepare")
+        self._prepared.add((alen, blen, bytes(params) if params is not None else None))
 
-    def mul(self, a, b, out=None, params=None, ws=None, stream=None):
-        """c = a * b for int32 (uint32-limb) device tensors; returns c (alen+blen limbs)."""
+    def mul(self, a, b, out=None, params=None, ws=None, stream=None, prepare=True):
+        """c = a * b for int32 (uint32-limb) device tensors; returns c (alen+blen limbs).
+        prepare: on the first product of a shape outside a stream capture, dkss_prepare builds
+        the tuple's table in the context (otherwise every call builds it in its workspace)."""
         torch = _torch()
+        _check_limbs("a", a)
+        _check_limbs("b", b, a.device)
         alen, blen = a.numel(), b.numel()
         if out is None:
             out = torch.empty(alen + blen, dtype=torch.int32, device=a.device)
+        _check_limbs("out", out, a.device)
+        if out.numel() < alen + blen:
+            raise ValueError("out holds %d limbs, the product %d" % (out.numel(), alen + blen))
+        key = (alen, blen, bytes(params) if params is not None else None)
+        if prepare and key not in self._prepared and not _capturing():
+            self.prepare(alen, blen, params, stream)
         if ws is None:
             ws = _alloc_ws(self.workspace_bytes(alen, blen, params), a.device)
         _check(lib().dkss_mul(self._h, _ptr(out), _ptr(a), alen, _ptr(b), blen, _pp(params),
                               _ptr(ws), ws.numel(), _stream_ptr(stream)), "dkss_mul")
+        _keep_until_done(stream, ws, out)
         return out
 
     def mul_batch(self, as_, bs, outs=None, params=None, ws=None, stream=None):
@@ -309,6 +356,7 @@ class Context:
     def forward(self, a, blen, params=None, stream=None):
         """encode + forward transform of a (operand pair a x blen limbs); natural order."""
         torch = _torch()
+        _check_limbs("a", a)
         plan = self.plan_info(a.numel(), blen, params)
         poly = torch.empty(plan.poly_bytes // 4, dtype=torch.int32, device=a.device)
         ws = _alloc_ws(self.workspace_bytes(a.numel(), blen, params), a.device)
@@ -321,12 +369,22 @@ class BatchCall:
     """A dkss_mul_batch call with its arguments marshalled once, for repeated launches over the
     same tensors (the products are recomputed by every call)."""
 
-    def __init__(self, ctx, as_, bs, outs=None, params=None, ws=None, alloc_ws=True):
+    def __init__(self, ctx, as_, bs, outs=None, params=None, ws=None, alloc_ws=True, prepare=True):
         torch = _torch()
         n = len(as_)
+        if len(bs) != n or (outs is not None and len(outs) != n):
+            raise ValueError("as_, bs and outs must have the same length")
+        dev = as_[0].device if n else None
+        for i in range(n):
+            _check_limbs("as_[%d]" % i, as_[i], dev)
+            _check_limbs("bs[%d]" % i, bs[i], dev)
         if outs is None:
             outs = [torch.empty(a.numel() + b.numel(), dtype=torch.int32, device=a.device)
                     for a, b in zip(as_, bs)]
+        for i, (o, a, b) in enumerate(zip(outs, as_, bs)):
+            _check_limbs("outs[%d]" % i, o, dev)
+            if o.numel() < a.numel() + b.numel():
+                raise ValueError("outs[%d] is too short" % i)
         self.ctx, self.as_, self.bs, self.outs, self.n = ctx, as_, bs, outs, n
         VP = ctypes.c_void_p * n
         SZ = ctypes.c_size_t * n
@@ -340,6 +398,9 @@ class BatchCall:
         _check(lib().dkss_batch_workspace_bytes(ctx._h, n, self.al, self.bl, self.pa,
                                                 ctypes.byref(nb)), "dkss_batch_workspace_bytes")
         self.ws_bytes = nb.value
+        if prepare and n and not _capturing():
+            _check(lib().dkss_batch_prepare(ctx._h, n, self.al, self.bl, self.pa, _stream_ptr(None)),
+                   "dkss_batch_prepare")
         if ws is None and alloc_ws:
             ws = _alloc_ws(nb.value, as_[0].device)
         self.ws = ws
@@ -348,6 +409,7 @@ class BatchCall:
         _check(lib().dkss_mul_batch(self.ctx._h, self.n, self.pc, self.pa_ptrs, self.al,
                                     self.pb_ptrs, self.bl, self.pa, _ptr(self.ws),
                                     self.ws.numel(), _stream_ptr(stream)), "dkss_mul_batch")
+        _keep_until_done(stream, self.ws, *self.outs)
         return self.outs
 
     def graph(self):

@@ -28,6 +28,7 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <tuple>
 #include <vector>
@@ -651,6 +652,20 @@ __global__ __launch_bounds__(kThreads) void k_pointwise(uint32_t* A0, const uint
 // their negations.  One launch computes table[dst + j] = table[src + j] * table[mul], j < cnt.
 // ---------------------------------------------------------------------------------------------
 
+// Words [first, first + count) of a table, count <= kPutWords, taken from the launch's arguments.
+// Entries 0 and 1 of a table reach the device this way, so that building a table is a sequence
+// of kernel launches on the caller's stream (no host buffer has to outlive the call, and a
+// stream capture records the whole build).
+constexpr int kPutWords = kThreads;
+struct PutChunk {
+    uint32_t w[kPutWords];
+};
+
+__global__ __launch_bounds__(kThreads) void k_table_put(uint32_t* __restrict__ table, PutChunk ch, long long first,
+                                                        int count) {
+    if ((int)threadIdx.x < count) table[first + threadIdx.x] = ch.w[threadIdx.x];
+}
+
 template <int L>
 __global__ __launch_bounds__(kThreads) void k_table_mul(uint32_t* table, long long src, long long mul,
                                                         long long dst, long long cnt, int log2m,
@@ -1083,6 +1098,18 @@ __global__ __launch_bounds__(kThreads) void k_schoolbook(ProdArgs PA) {
     chunk_carry(col, w0, w1, cin, pd.c);
 }
 
+// Batch descriptors [first, first + count) from the launch's arguments (count <= kDescPerPut):
+// a batch's descriptors reach the device as kernel launches on the caller's stream, without a
+// staging buffer or a wait on the host.
+constexpr int kDescPerPut = 40;
+struct DescChunk {
+    ProdDesc d[kDescPerPut];
+};
+
+__global__ void k_desc_put(ProdDesc* __restrict__ dst, DescChunk ch, long long first, int count) {
+    if ((int)threadIdx.x < count) dst[first + threadIdx.x] = ch.d[threadIdx.x];
+}
+
 // c = 0 for products of the launch (alen + blen words each)
 __global__ void k_zero_products(ProdArgs PA) {
     const ProdDesc pd = PA.get();
@@ -1260,9 +1287,14 @@ struct Cached {
     Plan plan;                 // constants (parameters as resolved for the key)
     QConst Q;
     std::vector<uint32_t> table_host01;   // entries 0 and 1 of the table (digits)
-    uint32_t* d_table = nullptr;
+    uint32_t* d_table = nullptr;          // the context's copy of the table, once built
+    bool table_ready = false;             // d_table holds the finished table
     long long table_count = 0;
     int D = 0;
+    // bytes of the table: max(table_count, 2) entries of 2m residues in D digits
+    size_t table_bytes() const {
+        return (size_t)std::max<long long>(table_count, 2) * 2 * plan.m() * D * sizeof(uint32_t);
+    }
 };
 
 // resolved per-call plan
@@ -1271,6 +1303,7 @@ struct Call {
     bool schoolbook = false;
     size_t alen = 0, blen = 0;
     Cached* C = nullptr;
+    const uint32_t* table = nullptr;  // the rho^s table the call's levels read
     Prof* prof = nullptr;
     long long dft_lds = 32768;
     bool overlap = false;
@@ -1286,9 +1319,11 @@ int dig_K(int L) { return (32 * L + 6 + 27) / 28; }
 
 // Tuned choices: for log2(N) in [lo, hi), candidate index cand (see candidate_params).
 // Optionally with the FFT level split and the LDS budget of the DFT-only levels.
+constexpr int kCandThesis = -1;  // a table entry that names the thesis rule ("T")
+
 struct TuneEntry {
     double lo, hi;
-    int cand;                      // a candidate index or DKSS_CAND_SCHOOLBOOK
+    int cand;                      // a candidate index, DKSS_CAND_SCHOOLBOOK or kCandThesis
     uint32_t batch = 1;            // the entry holds for batches of at least this many products
     std::vector<int> radices;      // empty: the library default
     long long dft_lds = 0;         // 0: the context's option
@@ -1311,18 +1346,9 @@ struct dkss_ctx {
     bool overlap = false;
     bool fuse_pw = true;
     long long dft_lds = 32768;
-    hipStream_t aux = nullptr;
+    hipStream_t aux = nullptr;          // made when DKSS_OPT_OVERLAP is first switched on
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
-    ProdDesc* hdesc = nullptr;          // pinned staging of batch descriptors
-    size_t hdesc_cap = 0;
-    hipEvent_t desc_ev = nullptr;       // recorded after the last descriptor copy
-    bool desc_pending = false;
     ~dkss_ctx() {
-        if (desc_ev) {
-            (void)hipEventSynchronize(desc_ev);
-            (void)hipEventDestroy(desc_ev);
-        }
-        if (hdesc) (void)hipHostFree(hdesc);
         if (ev_fork) (void)hipEventDestroy(ev_fork);
         if (ev_join) (void)hipEventDestroy(ev_join);
         if (aux) (void)hipStreamDestroy(aux);
@@ -1357,9 +1383,12 @@ bool policy_tuple(const dkss_ctx* ctx, uint64_t N, uint32_t batch, int* lM, int*
         const TuneEntry* hit = nullptr;
         for (const TuneEntry& t : ctx->tuning)
             if (t.batch <= batch && lg >= t.lo && lg < t.hi && (!hit || t.batch > hit->batch) &&
-                (t.cand == DKSS_CAND_SCHOOLBOOK || candidate_params(N, t.cand, lM, lm, u, pb)))
+                (t.cand == DKSS_CAND_SCHOOLBOOK || t.cand == kCandThesis ||
+                 candidate_params(N, t.cand, lM, lm, u, pb)))
                 hit = &t;
-        if (hit && hit->cand == DKSS_CAND_SCHOOLBOOK) {
+        if (hit && hit->cand == kCandThesis) {
+            // measured no faster than the rule: the rule, with its default level split
+        } else if (hit && hit->cand == DKSS_CAND_SCHOOLBOOK) {
             if (school) *school = true;
         } else if (hit && candidate_params(N, hit->cand, lM, lm, u, pb)) {
             if (te) *te = hit;
@@ -1446,6 +1475,13 @@ int learned_choices(dkss_ctx* ctx, size_t count, const size_t* alen, const size_
     for (size_t i = 0; i < count; ++i)
         if (alen[i] && blen[i]) out[i] = ctx->choices[Key{alen[i], blen[i], batch}];
     return DKSS_OK;
+}
+
+// The choice cached for a shape by an earlier planning call (-1: none).  Products take the
+// selector's choice from here only, so that they never wait for an inference.
+int learned_lookup(const dkss_ctx* ctx, size_t alen, size_t blen, uint32_t batch) {
+    const auto it = ctx->choices.find(std::make_tuple(alen, blen, batch));
+    return it == ctx->choices.end() ? -1 : it->second;
 }
 
 // parameters for a product, from the policy or the caller.  choice: the learned selector's
@@ -1609,43 +1645,60 @@ size_t rprod_lds(int L) { return (size_t)kThreads * (2 * (dig_D(L) | 1) + dig_D(
 
 template <int L>
 struct TableBuild {
-    // table[dst + j] = table[src + j] * table[mul], j < cnt
-    static int launch(Cached* C, Prof* prof, hipStream_t s, long long src, long long mul,
+    // tab[dst + j] = tab[src + j] * tab[mul], j < cnt
+    static int launch(const Cached* C, uint32_t* tab, Prof* prof, hipStream_t s, long long src, long long mul,
                       long long dst, long long cnt) {
         const int m = C->plan.m();
         const int per = kThreads / m;
         const unsigned blocks = (unsigned)((cnt + per - 1) / per);
         ProfScope ps(prof, DKSS_K_TABLE, s, 2.0 * cnt * m * dig_D(L) * 4, (double)cnt * m * m * L * L);
-        hipLaunchKernelGGL(k_table_mul<L>, dim3(blocks), dim3(kThreads), rprod_lds(L), s, C->d_table,
-                           src, mul, dst, cnt, C->plan.log2_m, C->Q);
+        hipLaunchKernelGGL(k_table_mul<L>, dim3(blocks), dim3(kThreads), rprod_lds(L), s, tab, src, mul, dst, cnt,
+                           C->plan.log2_m, C->Q);
         return launch_status();
     }
-    // entries 0 (one) and 1 (rho) are given; for n = 2, 4, ...: rho^n = rho^(n/2) rho^(n/2),
-    // then rho^(n+j) = rho^j rho^n for 0 < j < n
-    static int run(Cached* C, Prof* prof, hipStream_t s) {
-        int rc;
+    // The whole table into tab (C->table_bytes() bytes), on stream s: entries 0 (one) and 1
+    // (rho) from the host as launch arguments; then for n = 2, 4, ...: rho^n = rho^(n/2)
+    // rho^(n/2), and rho^(n+j) = rho^j rho^n for 0 < j < n.
+    static int run(const Cached* C, uint32_t* tab, Prof* prof, hipStream_t s) {
+        const size_t words01 = (size_t)std::min<long long>(C->table_count, 2) * 2 * C->plan.m() * C->D;
+        for (size_t off = 0; off < words01; off += kPutWords) {
+            PutChunk ch;
+            const int n = (int)std::min<size_t>(kPutWords, words01 - off);
+            memcpy(ch.w, C->table_host01.data() + off, (size_t)n * sizeof(uint32_t));
+            hipLaunchKernelGGL(k_table_put, dim3(1), dim3(kThreads), 0, s, tab, ch, (long long)off, n);
+        }
+        int rc = launch_status();
+        if (rc) return rc;
         for (long long n = 2; n < C->table_count; n *= 2) {
-            if ((rc = launch(C, prof, s, n / 2, n / 2, n, 1))) return rc;
+            if ((rc = launch(C, tab, prof, s, n / 2, n / 2, n, 1))) return rc;
             const long long cnt = std::min(n, C->table_count - n) - 1;
-            if (cnt > 0 && (rc = launch(C, prof, s, 1, n, n + 1, cnt))) return rc;
+            if (cnt > 0 && (rc = launch(C, tab, prof, s, 1, n, n + 1, cnt))) return rc;
         }
         return DKSS_OK;
     }
 };
 
+// The context's own copy of a tuple's table (planning calls only: dkss_prepare, the batch
+// preparation and graph creation).  Allocates it, builds it on s and waits for the build; only
+// a finished table is marked ready, and on any failure the memory is released and the entry
+// stays unbuilt.  Refused on a capturing stream: the build must really run before the table is
+// used by later calls.
 int ensure_table(Cached* C, Prof* prof, hipStream_t s) {
-    if (C->d_table) return DKSS_OK;
-    const int m = C->plan.m();
-    const size_t entries = (size_t)std::max<long long>(C->table_count, 2);
-    const size_t bytes = entries * 2 * m * C->D * sizeof(uint32_t);
+    if (C->table_ready) return DKSS_OK;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    HIP_OK(hipStreamIsCapturing(s, &cs));
+    if (cs != hipStreamCaptureStatusNone) return DKSS_EINVAL;
     uint32_t* d = nullptr;
-    HIP_OK(hipMalloc(&d, bytes));
+    HIP_OK(hipMalloc(&d, C->table_bytes()));
+    int rc = dispatch_L<TableBuild>(C->plan.L, C, d, prof, s);
+    if (!rc) rc = note_hip(hipStreamSynchronize(s));
+    if (rc) {
+        (void)hipStreamSynchronize(s);
+        (void)hipFree(d);
+        return rc;
+    }
     C->d_table = d;
-    const size_t first = (size_t)std::min<long long>(C->table_count, 2) * 2 * m * C->D * sizeof(uint32_t);
-    HIP_OK(hipMemcpyAsync(d, C->table_host01.data(), first, hipMemcpyHostToDevice, s));
-    int rc = dispatch_L<TableBuild>(C->plan.L, C, prof, s);
-    if (rc) return rc;
-    HIP_OK(hipStreamSynchronize(s));
+    C->table_ready = true;
     return DKSS_OK;
 }
 
@@ -1660,6 +1713,7 @@ struct Workspace {
     unsigned char* cin01;
     unsigned char* seg_gp;
     unsigned char* seg_cin;
+    uint32_t* tab;                     // room for the tuple's table (tab_bytes of layout), or NULL
     size_t wst, sst;
     size_t bytes;
 };
@@ -1667,7 +1721,8 @@ struct Workspace {
 // words of one polynomial in the workspace (digits) and in limb form (dkss_forward's output)
 size_t poly_words(const Plan& P) { return ((size_t)2 << P.log2_M) * P.m() * P.L; }
 
-Workspace layout(const Plan& P, size_t G, size_t nw_max, bool need_b, char* base) {
+// tab_bytes: room for a table after the group's buffers (0: none)
+Workspace layout(const Plan& P, size_t G, size_t nw_max, bool need_b, char* base, size_t tab_bytes = 0) {
     Workspace w{};
     w.S = poly_words(P);
     const size_t nwaves = (nw_max + 63) / 64;
@@ -1689,6 +1744,8 @@ Workspace layout(const Plan& P, size_t G, size_t nw_max, bool need_b, char* base
     off += align256(G * nseg);
     w.seg_cin = (unsigned char*)(base + off);
     off += align256(G * nseg);
+    w.tab = tab_bytes ? (uint32_t*)(base + off) : nullptr;
+    off += align256(tab_bytes);
     w.bytes = off;
     return w;
 }
@@ -1760,7 +1817,7 @@ struct Transform {
             if (!grid_ok((size_t)(ncols >> log2C))) return DKSS_ERANGE;
             const unsigned blocks = (unsigned)(ncols >> log2C);
             const double nprod = tw ? (double)(twoM / n_lvl[k]) * (r - 1) * (mu[k] - 1) : 0.0;
-            const uint32_t* tab = (const uint32_t*)c.C->d_table;
+            const uint32_t* tab = c.table;
             const bool ec = enc && !inverse && k == 0;         // encode fused into the top level
             const ProdArgs PA = ec ? *enc : ProdArgs{};
             const long long M = twoM / 2;
@@ -1911,17 +1968,23 @@ bool overlaps(const void* x, size_t xb, const void* y, size_t yb) {
     return a < b + yb && b < a + xb;
 }
 
-// batch: the product's batch size, the learned selector's third input
+// batch: the product's batch size, the learned selector's third input.  infer: a planning call
+// may run the selector's inference for a shape it has not seen (and cache the choice); products
+// (infer false) only look the choice up and otherwise take the policy's fallback, the thesis rule.
 int prepare_call(dkss_ctx* ctx, size_t alen, size_t blen, const dkss_params* p, Call* call,
-                 uint32_t batch = 1) {
+                 uint32_t batch, bool infer) {
     call->prof = &ctx->prof;
     call->dft_lds = ctx->dft_lds;          // a tuned entry may override it in resolve_params
     call->overlap = ctx->overlap;
     call->fuse_pw = ctx->fuse_pw;
     int choice = -1;
     if (!p && ctx->policy == DKSS_POLICY_LEARNED) {
-        int rc = learned_choices(ctx, 1, &alen, &blen, batch, &choice);
-        if (rc) return rc;
+        if (infer) {
+            int rc = learned_choices(ctx, 1, &alen, &blen, batch, &choice);
+            if (rc) return rc;
+        } else {
+            choice = learned_lookup(ctx, alen, blen, batch);
+        }
     }
     int rc = resolve_params(ctx, alen, blen, p, call, choice, batch);
     if (rc) return rc;
@@ -1977,8 +2040,20 @@ int launch_schoolbook(const Call& call, const ProdArgs& PA, unsigned G, size_t n
     return launch_status();
 }
 
-int run_mul(const Call& call, uint32_t* c, const uint32_t* a, size_t alen, const uint32_t* b,
-            size_t blen, void* ws, size_t ws_bytes, hipStream_t s) {
+// The table a product reads: the context's copy when a planning call has built it, else a copy
+// built on the stream into the workspace's table room (w.tab), part of this call's work.
+int use_table(Call* call, const Workspace& w, hipStream_t s) {
+    if (call->C->table_ready) {
+        call->table = call->C->d_table;
+        return DKSS_OK;
+    }
+    if (!w.tab) return DKSS_ENOSPC;
+    call->table = w.tab;
+    return dispatch_L<TableBuild>(call->P.L, call->C, w.tab, call->prof, s);
+}
+
+int run_mul(Call call, uint32_t* c, const uint32_t* a, size_t alen, const uint32_t* b, size_t blen,
+            void* ws, size_t ws_bytes, hipStream_t s) {
     const size_t nw = alen + blen;
     ProdArgs PA{};
     PA.one = ProdDesc{c, a, b, (long long)alen, (long long)blen, call.P.u, 0};
@@ -1987,8 +2062,10 @@ int run_mul(const Call& call, uint32_t* c, const uint32_t* a, size_t alen, const
     if (call.schoolbook) return launch_schoolbook(call, PA, 1, nw, (double)alen * (double)blen, s);
     const bool squaring = (a == b && alen == blen);
     if (ws == nullptr || ((uintptr_t)ws & 255)) return DKSS_EINVAL;
-    Workspace w = layout(call.P, 1, nw, !squaring, (char*)ws);
+    Workspace w = layout(call.P, 1, nw, !squaring, (char*)ws, call.C->table_ready ? 0 : call.C->table_bytes());
     if (ws_bytes < w.bytes) return DKSS_ENOSPC;
+    int rc = use_table(&call, w, s);
+    if (rc) return rc;
     return run_group(call, PA, 1, nw, (double)alen, (double)blen, (double)nw, squaring, w, s, call.P.u);
 }
 
@@ -2006,23 +2083,27 @@ struct BatchPlan {
     std::vector<Grp> groups;
     std::vector<size_t> order;
     std::vector<Call> calls;
-    size_t desc_bytes = 0, ws_bytes = 0;
+    // the distinct tuples of the DKSS groups, each with room for its table after the
+    // descriptors (used when the context has not built that table)
+    std::vector<std::pair<Cached*, size_t>> tabs;
+    size_t desc_bytes = 0, tab_bytes = 0, ws_bytes = 0;
 };
 
 constexpr size_t kMaxGroup = 65535;     // gridDim.y
 
+// infer: as in prepare_call (planning calls run one inference for every new shape)
 int plan_batch(dkss_ctx* ctx, size_t count, const size_t* alen, const size_t* blen,
-               const dkss_params* p, BatchPlan* B) {
+               const dkss_params* p, BatchPlan* B, bool infer) {
     B->calls.assign(count, Call());
     std::map<std::string, std::vector<size_t>> by_key;
     const uint32_t batch = (uint32_t)std::min<size_t>(count, UINT32_MAX);
-    if (!p && ctx->policy == DKSS_POLICY_LEARNED) {     // one inference for every new shape
+    if (infer && !p && ctx->policy == DKSS_POLICY_LEARNED) {
         std::vector<int> ch(count);
         int rc = learned_choices(ctx, count, alen, blen, batch, ch.data());
         if (rc) return rc;
     }
     for (size_t i = 0; i < count; ++i) {
-        int rc = prepare_call(ctx, alen[i], blen[i], p ? p + i : nullptr, &B->calls[i], batch);
+        int rc = prepare_call(ctx, alen[i], blen[i], p ? p + i : nullptr, &B->calls[i], batch, false);
         if (rc) return rc;
         const Call& c = B->calls[i];
         std::string key;
@@ -2057,13 +2138,35 @@ int plan_batch(dkss_ctx* ctx, size_t count, const size_t* alen, const size_t* bl
                 g.out_w += (double)(alen[i] + blen[i]);
                 g.ops += (double)alen[i] * (double)blen[i];
             }
-            if (g.kind == 2)
+            if (g.kind == 2) {
                 ws_max = std::max(ws_max, layout(g.call.P, g.count, g.nw_max, true, nullptr).bytes);
+                bool seen = false;
+                for (const auto& t : B->tabs) seen = seen || t.first == g.call.C;
+                if (!seen) {
+                    B->tabs.emplace_back(g.call.C, B->tab_bytes);
+                    B->tab_bytes += align256(g.call.C->table_bytes());
+                }
+            }
             B->groups.push_back(g);
         }
     }
-    B->ws_bytes = B->desc_bytes + ws_max;
+    B->ws_bytes = B->desc_bytes + B->tab_bytes + ws_max;
     return DKSS_OK;
+}
+
+// The batch's descriptors, in group order, to d_desc on stream s.
+int put_descs(const BatchPlan& B, size_t count, uint32_t* const* c, const uint32_t* const* a, const size_t* alen,
+              const uint32_t* const* b, const size_t* blen, ProdDesc* d_desc, hipStream_t s) {
+    for (size_t k0 = 0; k0 < count; k0 += kDescPerPut) {
+        DescChunk ch;
+        const int n = (int)std::min<size_t>(kDescPerPut, count - k0);
+        for (int j = 0; j < n; ++j) {
+            const size_t i = B.order[k0 + j];
+            ch.d[j] = ProdDesc{c[i], a[i], b[i], (long long)alen[i], (long long)blen[i], B.calls[i].P.u, 0};
+        }
+        hipLaunchKernelGGL(k_desc_put, dim3(1), dim3(64), 0, s, d_desc, ch, (long long)k0, n);
+    }
+    return launch_status();
 }
 
 
@@ -2074,24 +2177,6 @@ int plan_batch(dkss_ctx* ctx, size_t count, const size_t* alen, const size_t* bl
 // ---------------------------------------------------------------------------------------------
 
 extern "C" {
-
-// pinned staging for count descriptors; waits until the previous copy out of it has run
-static int ensure_desc(dkss_ctx* ctx, size_t count) {
-    if (!ctx->desc_ev) HIP_OK(hipEventCreateWithFlags(&ctx->desc_ev, hipEventDisableTiming));
-    if (ctx->desc_pending) {
-        HIP_OK(hipEventSynchronize(ctx->desc_ev));
-        ctx->desc_pending = false;
-    }
-    if (ctx->hdesc_cap < count) {
-        if (ctx->hdesc) HIP_OK(hipHostFree(ctx->hdesc));
-        ctx->hdesc = nullptr;
-        ctx->hdesc_cap = 0;
-        const size_t cap = std::max<size_t>(count, 1024);
-        HIP_OK(hipHostMalloc((void**)&ctx->hdesc, cap * sizeof(ProdDesc), hipHostMallocDefault));
-        ctx->hdesc_cap = cap;
-    }
-    return DKSS_OK;
-}
 
 static int ensure_aux(dkss_ctx* ctx) {
     if (ctx->aux) return DKSS_OK;
@@ -2106,6 +2191,10 @@ int dkss_set_option(dkss_ctx* ctx, int option, long long value) {
     if (!ctx) return DKSS_EINVAL;
     switch (option) {
         case DKSS_OPT_OVERLAP:
+            if (value) {
+                const int rc = ensure_aux(ctx);      // the second stream, made here and not in a product
+                if (rc) return rc;
+            }
             ctx->overlap = value != 0;
             return DKSS_OK;
         case DKSS_OPT_FUSE_PW:
@@ -2120,8 +2209,9 @@ int dkss_set_option(dkss_ctx* ctx, int option, long long value) {
     }
 }
 
-// The tuning table: text lines "lo hi cand" (log2 N range, candidate index or the schoolbook
-// output); '#' comments; a line "@batch B" starts the entries measured at B products per batch.
+// The tuning table: text lines "lo hi cand" (log2 N range, candidate index, the schoolbook
+// output, or T for the thesis rule); '#' comments; a line "@batch B" starts the entries measured
+// at B products per batch.
 static void load_tuning(dkss_ctx* c, const char* dir) {
     if (!dir) return;
     std::string path = std::string(dir) + "/dkss_tuning.txt";
@@ -2139,10 +2229,18 @@ static void load_tuning(dkss_ctx* c, const char* dir) {
         }
         TuneEntry e{};
         e.batch = batch;
-        char rad[64] = "-";
+        char rad[64] = "-", cs[16] = "";
         long long lds = 0;
-        const int n = sscanf(line, "%lf %lf %d %63s %lld", &e.lo, &e.hi, &e.cand, rad, &lds);
-        if (n < 3 || e.cand < 0 || (e.cand >= kNumCandidates && e.cand != DKSS_CAND_SCHOOLBOOK)) continue;
+        const int n = sscanf(line, "%lf %lf %15s %63s %lld", &e.lo, &e.hi, cs, rad, &lds);
+        if (n < 3) continue;
+        if (strcmp(cs, "T") == 0) {
+            e.cand = kCandThesis;
+        } else {
+            char* end = nullptr;
+            const long v = strtol(cs, &end, 10);
+            if (end == cs || *end || v < 0 || (v >= kNumCandidates && v != DKSS_CAND_SCHOOLBOOK)) continue;
+            e.cand = (int)v;
+        }
         if (n >= 4 && rad[0] != '-' && rad[0] != '#') {
             bool ok = true;
             for (char* t = rad; *t && ok;) {
@@ -2313,7 +2411,7 @@ int dkss_select_params(dkss_ctx* ctx, uint64_t a_bits, uint64_t b_bits, uint32_t
 int dkss_plan_info(dkss_ctx* ctx, size_t alen, size_t blen, const dkss_params* p, dkss_plan* out) {
     if (!ctx || !out) return DKSS_EINVAL;
     Call call;
-    int rc = prepare_call(ctx, alen, blen, p, &call);
+    int rc = prepare_call(ctx, alen, blen, p, &call, 1, true);
     if (rc) return rc;
     memset(out, 0, sizeof *out);
     const Plan& P = call.P;
@@ -2331,7 +2429,7 @@ int dkss_plan_info(dkss_ctx* ctx, size_t alen, size_t blen, const dkss_params* p
         out->L = (uint32_t)P.L;
         out->q_bits = (uint32_t)P.q_bits;
         out->poly_bytes = poly_words(P) * 4;
-        out->table_bytes = (uint64_t)std::max<long long>(call.C->table_count, 2) * 2 * P.m() * call.C->D * 4;
+        out->table_bytes = call.C->table_bytes();
         for (int i = 0; i < P.L && i < 16; ++i) out->q[i] = P.q.limb32(i);
     }
     return DKSS_OK;
@@ -2340,13 +2438,15 @@ int dkss_plan_info(dkss_ctx* ctx, size_t alen, size_t blen, const dkss_params* p
 int dkss_workspace_bytes(dkss_ctx* ctx, size_t alen, size_t blen, const dkss_params* p, size_t* out) {
     if (!ctx || !out) return DKSS_EINVAL;
     Call call;
-    int rc = prepare_call(ctx, alen, blen, p, &call);
+    int rc = prepare_call(ctx, alen, blen, p, &call, 1, true);
     if (rc) return rc;
     if (alen == 0 || blen == 0 || call.schoolbook) {
         *out = 0;
         return DKSS_OK;
     }
-    *out = layout(call.P, 1, alen + blen, true, nullptr).bytes;
+    // room for the table too: a product whose tuple the context has not prepared builds its
+    // table in the workspace
+    *out = layout(call.P, 1, alen + blen, true, nullptr, call.C->table_bytes()).bytes;
     return DKSS_OK;
 }
 
@@ -2354,39 +2454,55 @@ int dkss_prepare(dkss_ctx* ctx, size_t alen, size_t blen, const dkss_params* p, 
     clear_stale_hip_error();
     if (!ctx) return DKSS_EINVAL;
     Call call;
-    int rc = prepare_call(ctx, alen, blen, p, &call);
+    int rc = prepare_call(ctx, alen, blen, p, &call, 1, true);
     if (rc) return rc;
     if (!call.C) return DKSS_OK;
     return ensure_table(call.C, &ctx->prof, (hipStream_t)s);
 }
 
-int dkss_mul(dkss_ctx* ctx, uint32_t* c, const uint32_t* a, size_t alen, const uint32_t* b,
-             size_t blen, const dkss_params* p, void* ws, size_t ws_bytes, dkss_stream_t s) {
-    clear_stale_hip_error();
+// The product path of dkss_mul on a workspace (also the allocation-free entry point's).
+static int mul_on(dkss_ctx* ctx, uint32_t* c, const uint32_t* a, size_t alen, const uint32_t* b, size_t blen,
+                  const dkss_params* p, void* ws, size_t ws_bytes, hipStream_t s) {
     if (!ctx || !c || (alen && !a) || (blen && !b)) return DKSS_EINVAL;
     const size_t nw = alen + blen;
     if ((alen && overlaps(c, nw * 4, a, alen * 4)) || (blen && overlaps(c, nw * 4, b, blen * 4)))
         return DKSS_EINVAL;
     Call call;
-    int rc = prepare_call(ctx, alen, blen, p, &call);
+    int rc = prepare_call(ctx, alen, blen, p, &call, 1, false);
     if (rc) return rc;
-    if (call.C && (rc = ensure_table(call.C, &ctx->prof, (hipStream_t)s))) return rc;
-    if (call.C && ctx->overlap && (rc = ensure_aux(ctx))) return rc;
-    if (call.C && ctx->overlap) {
+    if (call.C && ctx->overlap && ctx->aux) {
         call.aux = ctx->aux;
         call.ev_fork = ctx->ev_fork;
         call.ev_join = ctx->ev_join;
     }
-    return run_mul(call, c, a, alen, b, blen, ws, ws_bytes, (hipStream_t)s);
+    return run_mul(call, c, a, alen, b, blen, ws, ws_bytes, s);
+}
+
+int dkss_mul(dkss_ctx* ctx, uint32_t* c, const uint32_t* a, size_t alen, const uint32_t* b,
+             size_t blen, const dkss_params* p, void* ws, size_t ws_bytes, dkss_stream_t s) {
+    clear_stale_hip_error();
+    return mul_on(ctx, c, a, alen, b, blen, p, ws, ws_bytes, (hipStream_t)s);
 }
 
 int dkss_batch_workspace_bytes(dkss_ctx* ctx, size_t count, const size_t* alen, const size_t* blen,
                                const dkss_params* p, size_t* out) {
     if (!ctx || !out || (count && (!alen || !blen))) return DKSS_EINVAL;
     BatchPlan B;
-    int rc = plan_batch(ctx, count, alen, blen, p, &B);
+    int rc = plan_batch(ctx, count, alen, blen, p, &B, true);
     if (rc) return rc;
     *out = count ? B.ws_bytes : 0;
+    return DKSS_OK;
+}
+
+int dkss_batch_prepare(dkss_ctx* ctx, size_t count, const size_t* alen, const size_t* blen,
+                       const dkss_params* p, dkss_stream_t s) {
+    clear_stale_hip_error();
+    if (!ctx || (count && (!alen || !blen))) return DKSS_EINVAL;
+    BatchPlan B;
+    int rc = plan_batch(ctx, count, alen, blen, p, &B, true);
+    if (rc) return rc;
+    for (const auto& t : B.tabs)
+        if ((rc = ensure_table(t.first, &ctx->prof, (hipStream_t)s))) return rc;
     return DKSS_OK;
 }
 
@@ -2403,11 +2519,24 @@ static int check_batch_args(size_t count, uint32_t* const* c, const uint32_t* co
     return DKSS_OK;
 }
 
-// The launches of a planned batch whose descriptors sit at the start of ws.  prof: NULL inside
-// a graph capture (no timing events there).
+// The launches of a planned batch whose descriptors sit at the start of ws.  Tuples whose table
+// the context has not built get one in the workspace's table room first.  prof: NULL inside a
+// graph capture (no timing events there).
 static int enqueue_batch(const BatchPlan& B, void* ws, Prof* prof, hipStream_t st) {
     ProdDesc* d_desc = (ProdDesc*)ws;
-    char* gws = (char*)ws + B.desc_bytes;
+    char* tws = (char*)ws + B.desc_bytes;
+    char* gws = tws + B.tab_bytes;
+    std::map<const Cached*, const uint32_t*> table;
+    for (const auto& t : B.tabs) {
+        if (t.first->table_ready) {
+            table[t.first] = t.first->d_table;
+            continue;
+        }
+        uint32_t* dst = (uint32_t*)(tws + t.second);
+        int rc = dispatch_L<TableBuild>(t.first->plan.L, t.first, dst, prof, st);
+        if (rc) return rc;
+        table[t.first] = dst;
+    }
     for (const BatchPlan::Grp& g : B.groups) {
         ProdArgs PA{};
         PA.many = d_desc + g.first;
@@ -2415,6 +2544,7 @@ static int enqueue_batch(const BatchPlan& B, void* ws, Prof* prof, hipStream_t s
         Call call = g.call;
         call.prof = prof;
         call.aux = nullptr;                // groups are wide enough to fill the GPU on one stream
+        if (g.kind == 2) call.table = table[g.call.C];
         int rc;
         if (g.kind == 0) {
             rc = launch_zero(PA, G, g.nw_max, st);
@@ -2438,21 +2568,11 @@ int dkss_mul_batch(dkss_ctx* ctx, size_t count, uint32_t* const* c, const uint32
     if (rc) return rc;
     if (count == 0) return DKSS_OK;
     BatchPlan B;
-    if ((rc = plan_batch(ctx, count, alen, blen, p, &B))) return rc;
+    if ((rc = plan_batch(ctx, count, alen, blen, p, &B, false))) return rc;
     if (ws == nullptr || ((uintptr_t)ws & 255)) return DKSS_EINVAL;
     if (ws_bytes < B.ws_bytes) return DKSS_ENOSPC;
     hipStream_t st = (hipStream_t)s;
-    for (const BatchPlan::Grp& g : B.groups)
-        if (g.kind == 2 && (rc = ensure_table(g.call.C, &ctx->prof, st))) return rc;
-    // descriptors, in group order, through the context's pinned staging buffer
-    if ((rc = ensure_desc(ctx, count))) return rc;
-    for (size_t k = 0; k < count; ++k) {
-        const size_t i = B.order[k];
-        ctx->hdesc[k] = ProdDesc{c[i], a[i], b[i], (long long)alen[i], (long long)blen[i], B.calls[i].P.u, 0};
-    }
-    HIP_OK(hipMemcpyAsync(ws, ctx->hdesc, count * sizeof(ProdDesc), hipMemcpyHostToDevice, st));
-    HIP_OK(hipEventRecord(ctx->desc_ev, st));
-    ctx->desc_pending = true;
+    if ((rc = put_descs(B, count, c, a, alen, b, blen, (ProdDesc*)ws, st))) return rc;
     return enqueue_batch(B, ws, &ctx->prof, st);
 }
 
@@ -2480,26 +2600,18 @@ int dkss_batch_graph_create(dkss_ctx* ctx, size_t count, uint32_t* const* c, con
     if (rc) return rc;
     if (count == 0) return DKSS_EINVAL;
     BatchPlan B;
-    if ((rc = plan_batch(ctx, count, alen, blen, p, &B))) return rc;
+    if ((rc = plan_batch(ctx, count, alen, blen, p, &B, true))) return rc;
     if (ws == nullptr || ((uintptr_t)ws & 255)) return DKSS_EINVAL;
     if (ws_bytes < B.ws_bytes) return DKSS_ENOSPC;
     hipStream_t cs = nullptr;
     HIP_OK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
     std::unique_ptr<dkss_graph> G(new (std::nothrow) dkss_graph());
     rc = G ? DKSS_OK : DKSS_EINVAL;
-    // tables and descriptors are written once, before the capture; the graph holds kernels only
-    for (size_t k = 0; !rc && k < B.groups.size(); ++k)
-        if (B.groups[k].kind == 2) rc = ensure_table(B.groups[k].call.C, nullptr, cs);
-    if (!rc) {
-        std::vector<ProdDesc> hd(count);
-        for (size_t k = 0; k < count; ++k) {
-            const size_t i = B.order[k];
-            hd[k] = ProdDesc{c[i], a[i], b[i], (long long)alen[i], (long long)blen[i], B.calls[i].P.u, 0};
-        }
-        if (hipMemcpyAsync(ws, hd.data(), count * sizeof(ProdDesc), hipMemcpyHostToDevice, cs) != hipSuccess ||
-            hipStreamSynchronize(cs) != hipSuccess)
-            rc = DKSS_EHIP;
-    }
+    // tables and descriptors are written once, before the capture; the graph holds the
+    // products' kernels only
+    for (size_t k = 0; !rc && k < B.tabs.size(); ++k) rc = ensure_table(B.tabs[k].first, nullptr, cs);
+    if (!rc) rc = put_descs(B, count, c, a, alen, b, blen, (ProdDesc*)ws, cs);
+    if (!rc) rc = note_hip(hipStreamSynchronize(cs));
     if (!rc) {
         if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
             rc = DKSS_EHIP;
@@ -2544,14 +2656,14 @@ int dkss_forward(dkss_ctx* ctx, uint32_t* poly, const uint32_t* a, size_t alen, 
     clear_stale_hip_error();
     if (!ctx || !poly || !a || alen == 0 || blen == 0) return DKSS_EINVAL;
     Call call;
-    int rc = prepare_call(ctx, alen, blen, p, &call);
+    int rc = prepare_call(ctx, alen, blen, p, &call, 1, false);
     if (rc) return rc;
     if (call.schoolbook) return DKSS_ERANGE;
-    if ((rc = ensure_table(call.C, &ctx->prof, (hipStream_t)s))) return rc;
     if (ws == nullptr || ((uintptr_t)ws & 255)) return DKSS_EINVAL;
-    Workspace w = layout(call.P, 1, alen + blen, true, (char*)ws);
+    Workspace w = layout(call.P, 1, alen + blen, true, (char*)ws, call.C->table_ready ? 0 : call.C->table_bytes());
     if (ws_bytes < w.bytes) return DKSS_ENOSPC;
     hipStream_t st = (hipStream_t)s;
+    if ((rc = use_table(&call, w, st))) return rc;
     ProdArgs PA{};
     PA.one = ProdDesc{nullptr, a, a, (long long)alen, (long long)blen, call.P.u, 0};
     if ((rc = dispatch_L<Encode>(call.P.L, call, PA, 1u, 0, w.A, w.S, (double)alen, st))) return rc;

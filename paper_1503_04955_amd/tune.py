@@ -232,7 +232,12 @@ def write_tuned_table(rows, path, kernel_rows=None):
                     k = kbest[x]
                     cfg = " %s %d" % (".".join(str(v) for v in k["radices"]), k["dft_lds"])
                     ms = k["ms"]
-                f.write("%.3f %.3f %d%s   # %.4f / %.4f\n" % (lo, hi, best[x][0], cfg, ms, thesis.get(x, 0.0)))
+                name = str(best[x][0])
+                if x in thesis and ms >= thesis[x]:
+                    # nothing measured beat the rule here: name the rule, so the lookup never
+                    # picks a slower tuple (nor an entry of a smaller batch size)
+                    name, cfg = "T", ""
+                f.write("%.3f %.3f %s%s   # %.4f / %.4f\n" % (lo, hi, name, cfg, ms, thesis.get(x, 0.0)))
 
 
 def radix_splits(total, cap):

@@ -62,3 +62,10 @@ def batch_lengths(seed, count, lo_bits=12, hi_bits=22, max_ratio=8.0):
         small = max(1, int(round(big / ratio)))
         out.append((big, small) if r[3 * i + 2] < 0.5 else (small, big))
     return out
+
+
+def mixed_batch(count=4096, seed=SEED_BASE + 2):
+    """The mixed-batch workload: `count` operand pairs with batch_lengths(seed, count) (operands
+    2^12..2^22 bits, length ratio U[1, 8]); pair i is operand_pair(SEED_BASE + 100000 + i, ...)."""
+    return [operand_pair(SEED_BASE + 100000 + i, al, bl)
+            for i, (al, bl) in enumerate(batch_lengths(seed, count))]

@@ -11,6 +11,7 @@ import numpy as np
 import pytest
 
 import seeded_inputs as SI
+from conftest import golden_rows, host_residues, primes61, residues_agree, sha256_limbs
 from oracle import coracle as C
 from oracle import params as OP
 
@@ -37,33 +38,7 @@ def _gpu_mul(env, a, b, params=None, square=False):
 
 
 def _primes61(seed, count):
-    rng = random.Random(seed)
-    out = []
-    while len(out) < count:
-        q = rng.getrandbits(61) | (1 << 60) | 1
-        if _isprime(q):
-            out.append(q)
-    return out
-
-
-def _isprime(n):
-    if n % 2 == 0:
-        return False
-    d, s = n - 1, 0
-    while d % 2 == 0:
-        d //= 2
-        s += 1
-    for a in (2, 3, 5, 7, 11, 13, 17, 19, 23, 29, 31, 37):
-        x = pow(a, d, n)
-        if x in (1, n - 1):
-            continue
-        for _ in range(s - 1):
-            x = x * x % n
-            if x == n - 1:
-                break
-        else:
-            return False
-    return True
+    return primes61(seed, count)
 
 
 def _residue_check(a, b, c, primes):
@@ -208,28 +183,76 @@ def _low_limbs_check(a, b, got, w=2048):
     assert np.array_equal(got[:w], C.schoolbook(a[:w], b[:w])[:w])
 
 
-@pytest.mark.parametrize("kind", ["random", "ones", "square", "unbalanced"])
-def test_mul_2e28_residues(env, kind):
-    n = 1 << 23
-    if kind == "random":
-        a, b = SI.operand_pair(SI.SEED_BASE + 2, n, n)
-    elif kind == "ones":
-        a = b = SI.all_ones(n)
-    elif kind == "square":
-        a = SI.limbs(SI.SEED_BASE + 3, n)
-        got = _gpu_mul(env, a, a, square=True)
-        _residue_check(a, a, got, _primes61(2, 8))
-        _low_limbs_check(a, a, got)
-        return
-    else:
-        a, b = SI.operand_pair(SI.SEED_BASE + 4, n, n // 8)
-    got = _gpu_mul(env, a, b)
+def _digest_case(name):
+    """Operands of a product whose oracle-DKSS digest is stored in tests/golden/dkss_digests.txt
+    (written by make_dkss_digests.py, which calls only the oracle)."""
+    rows = {r[0]: r for r in golden_rows("dkss_digests.txt")}
+    _, seed, alen, blen, square, want = rows[name]
+    seed, alen, blen = int(seed), int(alen), int(blen)
+    if int(square):
+        a = SI.limbs(seed, alen)
+        return a, a, True, want
+    a, b = SI.operand_pair(seed, alen, blen)
+    return a, b, False, want
+
+
+@pytest.mark.parametrize("name", ["2p28_random", "2p28_square", "2p28_unbalanced"])
+def test_mul_2e28_vs_oracle_dkss(env, name):
+    """2^28-bit products (random, squaring, 8:1) equal the CPU oracle's DKSS product, through its
+    stored SHA-256 (the oracle takes minutes per product), and pass residues mod 8 primes."""
+    a, b, square, want = _digest_case(name)
+    print("case", name, len(a), len(b), flush=True)
+    got = _gpu_mul(env, a, b, square=square)
+    assert sha256_limbs(got) == want
     _residue_check(a, b, got, _primes61(3, 8))
-    _low_limbs_check(a, b, got)
+
+
+@pytest.mark.parametrize("policy", ["thesis", "learned"])
+def test_mul_2e30_heldout_vs_oracle_dkss(env, policy):
+    """The held-out single product at 2^30 bits (outside the selector's training grid) under the
+    thesis rule and under the learned selector equals the CPU oracle's DKSS product (its stored
+    SHA-256), and passes residues mod 4 primes computed by the oracle on the host."""
+    dk, torch, _ = env
+    a, b, _, want = _digest_case("2p30_heldout")
+    ctx = dk.Context(dk.POLICY_THESIS if policy == "thesis" else dk.POLICY_LEARNED)
+    print("case 2^30", policy, ctx.select_params(32 * len(a), 32 * len(b)).as_dict(), flush=True)
+    c = ctx.mul(dk.to_device(a), dk.to_device(b))
+    torch.cuda.synchronize()
+    got = dk.to_host(c)
+    assert sha256_limbs(got) == want
+    qs = _primes61(30, 4)
+    ra, rb, rc = host_residues([a, b, got], qs)
+    assert residues_agree(ra, rb, rc, qs)
+
+
+def _ones_product(n, k):
+    """(2^(32n) - 1)(2^(32k) - 1) = 2^(32(n+k)) - 2^(32n) - 2^(32k) + 1 as n + k limbs (closed
+    form, linear time)."""
+    v = (1 << (32 * (n + k))) - (1 << (32 * n)) - (1 << (32 * k)) + 1
+    return np.frombuffer(v.to_bytes(4 * (n + k), "little"), dtype=np.uint32)
+
+
+@pytest.mark.parametrize("log2_bits", [24, 28])
+@pytest.mark.parametrize("kind", ["ones", "ones_unbalanced", "pow2", "pow2_top"])
+def test_mul_large_edge_operands(env, log2_bits, kind):
+    """Edge operands at 2^24 and 2^28 bits against closed forms: all-ones factors (every encoded
+    coefficient at its maximum, the largest coefficient sums), also 8:1 unbalanced, and powers of
+    two (a single bit in the product), one of them at the top bit of both operands."""
+    n = (1 << log2_bits) // 32
     if kind == "ones":
-        # (2^N - 1)^2 = 2^(2N) - 2^(N+1) + 1: low limb 1, limbs 1..n-1 zero, limb n = 0xFFFFFFFE
-        assert got[0] == 1 and not got[1:n].any() and got[n] == 0xFFFFFFFE
-        assert (got[n + 1:] == 0xFFFFFFFF).all()
+        a = b = SI.all_ones(n)
+        want = _ones_product(n, n)
+    elif kind == "ones_unbalanced":
+        a, b = SI.all_ones(n), SI.all_ones(n // 8)
+        want = _ones_product(n, n // 8)
+    else:
+        i, j = (32 * n - 1, 32 * n - 1) if kind == "pow2_top" else (12345, 32 * n - 777)
+        a, b = SI.power_of_two(i, n), SI.power_of_two(j, n)
+        want = np.zeros(2 * n, np.uint32)
+        want[(i + j) // 32] = np.uint32(1 << ((i + j) % 32))
+    print("case", kind, log2_bits, flush=True)
+    got = _gpu_mul(env, a, b)
+    assert np.array_equal(got, want)
 
 
 def test_gpu_residues_match_oracle(env):
@@ -414,20 +437,136 @@ def test_context_options_keep_the_bits(env, opts):
         assert torch.equal(x, y), opts
 
 
+def test_batch_4096_full_size(env):
+    """The mixed batch at its stated size (4096 products, 2^12..2^22 bits, ratio 1..8) under the
+    learned selector, replayed as a graph: every product passes c = a*b modulo 8 seeded 61-bit
+    primes with all residues computed by the oracle on the host, and 64 products spread over the
+    batch equal the oracle's DKSS product (thesis rule) limb for limb."""
+    dk, torch, _ = env
+    from concurrent.futures import ThreadPoolExecutor
+    pairs = SI.mixed_batch(4096)
+    as_ = [dk.to_device(a) for a, _ in pairs]
+    bs = [dk.to_device(b) for _, b in pairs]
+    call = dk.BatchCall(dk.Context(dk.POLICY_LEARNED), as_, bs)
+    graph = call.graph()
+    graph()
+    torch.cuda.synchronize()
+    got = [dk.to_host(o) for o in call.outs]
+    graph.close()
+    qs = _primes61(4096, 8)
+    flat = [x for (a, b), c in zip(pairs, got) for x in (a, b, c)]
+    res = host_residues(flat, qs)
+    bad = [i for i in range(len(pairs)) if not residues_agree(res[3 * i], res[3 * i + 1], res[3 * i + 2], qs)]
+    assert not bad, bad[:10]
+    sample = list(range(0, 4096, 64))
+    C.lib()
+    with ThreadPoolExecutor(max_workers=16) as ex:
+        want = list(ex.map(lambda i: C.dkss_mul(*pairs[i]), sample))
+    for i, w in zip(sample, want):
+        assert np.array_equal(got[i], w), (i, len(pairs[i][0]), len(pairs[i][1]))
+
+
+def test_mul_captured_on_a_fresh_context(env):
+    """dkss_mul allocates nothing and does not wait: on a context that has built no table, a
+    product recorded into a graph by torch's stream capture (global mode, where an allocation or
+    a synchronization would fail the capture) replays correctly, several times, with eager work
+    and other products of the same context between the replays."""
+    dk, torch, _ = env
+    a, b = SI.operand_pair(SI.SEED_BASE + 70, 30000, 20000)
+    want = C.schoolbook(a, b)
+    da, db = dk.to_device(a), dk.to_device(b)
+    ctx = dk.Context()
+    ws = torch.empty(ctx.workspace_bytes(30000, 20000), dtype=torch.uint8, device="cuda")
+    out = torch.zeros(50000, dtype=torch.int32, device="cuda")
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        ctx.mul(da, db, out=out, ws=ws)
+    torch.cuda.synchronize()
+    other = dk.to_device(SI.limbs(71, 8192))
+    for rep in range(3):
+        out.zero_()
+        sq = ctx.mul(other, other)                   # eager work of the same context in between
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(dk.to_host(out), want), rep
+        assert np.array_equal(dk.to_host(sq), C.schoolbook(dk.to_host(other), dk.to_host(other)))
+
+
+def test_prepare_refused_under_capture_leaves_context_usable(env):
+    """dkss_prepare on a capturing stream is refused before any work, and the context stays
+    unprepared: the product captured next builds its table in the workspace, and an eager product
+    afterwards (which prepares the context) is right too."""
+    dk, torch, _ = env
+    a, b = SI.operand_pair(SI.SEED_BASE + 72, 9000, 9000)
+    want = C.schoolbook(a, b)
+    da, db = dk.to_device(a), dk.to_device(b)
+    ctx = dk.Context()
+    ws = torch.empty(ctx.workspace_bytes(9000, 9000), dtype=torch.uint8, device="cuda")
+    out = torch.zeros(18000, dtype=torch.int32, device="cuda")
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        with pytest.raises(dk.DkssError) as e:
+            ctx.prepare(9000, 9000)
+        ctx.mul(da, db, out=out, ws=ws)
+    assert e.value.code == dk.EINVAL
+    torch.cuda.synchronize()
+    eager = ctx.mul(da, db)
+    torch.cuda.synchronize()
+    assert np.array_equal(dk.to_host(eager), want)
+    g.replay()
+    torch.cuda.synchronize()
+    assert np.array_equal(dk.to_host(out), want)
+
+
+@pytest.mark.parametrize("policy", ["thesis", "learned"])
+def test_products_without_prepare(env, policy):
+    """Without a planning call that builds the tables, single products and a batch build them in
+    their workspace on every call; the results equal the oracle's (schoolbook) and those of a
+    prepared context."""
+    dk, torch, _ = env
+    pol = dk.POLICY_THESIS if policy == "thesis" else dk.POLICY_LEARNED
+    ctx = dk.Context(pol)
+    for alen, blen in [(8192, 8192), (30000, 4000), (100000, 100000)]:
+        a, b = SI.operand_pair(alen + blen + 11, alen, blen)
+        da, db = dk.to_device(a), dk.to_device(b)
+        for _ in range(2):
+            got = ctx.mul(da, db, prepare=False)
+            torch.cuda.synchronize()
+            if alen * blen < 1e9:
+                assert np.array_equal(dk.to_host(got), C.schoolbook(a, b)), (alen, blen)
+        assert torch.equal(got, dk.Context(pol).mul(da, db)), (alen, blen)
+    lens = SI.batch_lengths(SI.SEED_BASE + 73, 80, hi_bits=18)
+    pairs = [SI.operand_pair(400 + i, al, bl) for i, (al, bl) in enumerate(lens)]
+    as_ = [dk.to_device(x) for x, _ in pairs]
+    bs = [dk.to_device(y) for _, y in pairs]
+    bc = dk.BatchCall(dk.Context(pol), as_, bs, prepare=False)
+    for _ in range(2):
+        outs = bc()
+        torch.cuda.synchronize()
+        for (x, y), o in zip(pairs, outs):
+            assert np.array_equal(dk.to_host(o), C.schoolbook(x, y)), (len(x), len(y))
+
+
 def test_mul_2e34_thesis_learned_and_square(env):
-    """The largest single product: two 2^34-bit operands (2 GiB each, seeded uniform limbs made
-    on the device) under the thesis rule and under the learned selector, and the squaring of a:
-    residues mod 16 seeded 61-bit primes (a, b and c reduced on the GPU, compared in Python
-    integers); both policies give identical limbs."""
+    """The largest single product: two 2^34-bit operands (2 GiB each, seeded uniform limbs from
+    the host generator) under the thesis rule and under the learned selector, and the squaring
+    of a.  Checked by residues mod 16 seeded 61-bit primes: the residues of a, b and the products
+    modulo 2 of them are the oracle's, computed on the host; all 16 from the GPU's residue kernel
+    (itself pinned to the oracle) agree with c = a*b.  Both policies give identical limbs."""
     dk, torch, _ = env
     import time
     n = (1 << 34) // 32
-    g = torch.Generator(device="cuda")
-    g.manual_seed(SI.SEED_BASE + 34)
-    a = torch.randint(-2 ** 31, 2 ** 31, (n,), dtype=torch.int32, device="cuda", generator=g)
-    b = torch.randint(-2 ** 31, 2 ** 31, (n,), dtype=torch.int32, device="cuda", generator=g)
+    ha, hb = SI.operand_pair(SI.SEED_BASE + 34, n, n)
+    a, b = dk.to_device(ha), dk.to_device(hb)
     qs = _primes61(34, 16)
+    host_q = qs[:2]
+    hra, hrb = host_residues([ha, hb], host_q)
     ra, rb = dk.residues(a, qs), dk.residues(b, qs)
+    assert ra[:2] == hra and rb[:2] == hrb
+    del ha, hb
     outs = {}
     for name, policy in (("thesis", dk.POLICY_THESIS), ("learned", dk.POLICY_LEARNED)):
         ctx = dk.Context(policy)
@@ -441,13 +580,17 @@ def test_mul_2e34_thesis_learned_and_square(env):
         print("2^34 x 2^34 %s: %.1f ms, params %s" % (name, 1e3 * (time.perf_counter() - t0),
                                                       ctx.select_params(1 << 34, 1 << 34).as_dict()), flush=True)
         rc = dk.residues(c, qs)
-        assert all(z == x * y % q for x, y, z, q in zip(ra, rb, rc, qs)), name
-        outs[name] = c
+        assert residues_agree(ra, rb, rc, qs), name
         if name == "thesis":
+            (hrc,) = host_residues([dk.to_host(c)], host_q)
+            assert residues_agree(hra, hrb, hrc, host_q)
             sq = ctx.mul(a, a, ws=ws)
             rs = dk.residues(sq, qs)
-            assert all(z == x * x % q for x, z, q in zip(ra, rs, qs))
+            assert residues_agree(ra, ra, rs, qs)
+            (hrs,) = host_residues([dk.to_host(sq)], host_q)
+            assert residues_agree(hra, hra, hrs, host_q)
             del sq
+        outs[name] = c
         del ws
         torch.cuda.empty_cache()
     assert torch.equal(outs["thesis"], outs["learned"])

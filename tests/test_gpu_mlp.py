@@ -8,6 +8,7 @@ import pytest
 
 import oracle.mlp as om
 import seeded_inputs as SI
+from conftest import host_residues, primes61, residues_agree
 
 pytestmark = pytest.mark.gpu
 
@@ -202,7 +203,8 @@ def _time(fn, torch, reps=3):
 
 def test_learned_beats_thesis_on_heldout_sizes(env):
     """Live timing on sizes outside the training grid, the largest 2^30 bits: the products under
-    the LEARNED policy take less time in total than under the thesis rule, and are identical."""
+    the LEARNED policy take less time in total than under the thesis rule, are identical, and pass
+    residue checks against the oracle's residues of a, b and c."""
     dk, torch = env
     _weights(dk)
     ctx_t = dk.Context()
@@ -222,6 +224,10 @@ def test_learned_beats_thesis_on_heldout_sizes(env):
         mt = _time(lambda: ctx_t.mul(a, b, out=ct, ws=wt), torch)
         ml = _time(lambda: ctx_l.mul(a, b, out=cl, ws=wl), torch)
         assert torch.equal(ct, cl)
+        # c = a*b modulo 4 seeded primes, every residue computed by the oracle on the host
+        qs = primes61(int(x * 100), 4)
+        ra, rb, rc = host_residues([dk.to_host(a), dk.to_host(b), dk.to_host(cl)], qs)
+        assert residues_agree(ra, rb, rc, qs), x
         tot_t += mt
         tot_l += ml
         lines.append("2^%.2f: thesis %.3f ms, learned %.3f ms (choice %d)"

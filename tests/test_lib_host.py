@@ -242,3 +242,34 @@ def test_tuned_table_writer_sections(dk, tmp_path):
     p1 = ctx.select_params(2 ** 14, 2 ** 14, 16)          # beyond the batch-16 section: batch 1's entry
     c2 = dict(dk.Context().candidates(2 ** 14, 2 ** 14))[2]
     assert (p1.log2_M, p1.log2_m, p1.p_bits) == (c2.log2_M, c2.log2_m, c2.p_bits)
+
+
+def test_tuned_table_names_the_rule_where_nothing_beats_it(dk, tmp_path):
+    """Where no measured candidate beats the thesis rule's own timing, the writer names the rule
+    ("T"); the library then plans that size with the rule, also inside a batch section (not with
+    the entry of a smaller batch size)."""
+    from paper_1503_04955_amd import tune
+    ms = {(16.0, 1): {3: 0.03, 8: 0.06, "thesis": 0.04}, (17.0, 1): {3: 0.05, "thesis": 0.09},
+          (18.0, 1): {3: 0.05, "thesis": 0.04},
+          (16.0, 16): {2: 0.02, "thesis": 0.01}, (17.0, 16): {2: 0.02, "thesis": 0.03}}
+    rows = [{"log2_a": x, "ratio": 1, "batch": bt, "cand": c, "ms": v}
+            for (x, bt), d in ms.items() for c, v in d.items()]
+    path = tmp_path / "dkss_tuning.txt"
+    tune.write_tuned_table(rows, str(path))
+    lines = [l.split("#")[0].split() for l in open(path) if l.strip() and not l.startswith("#")]
+    assert lines == [["0.000", "16.500", "3"], ["16.500", "17.500", "3"], ["17.500", "64.000", "T"],
+                     ["@batch", "16"], ["0.000", "16.500", "T"], ["16.500", "17.500", "2"]]
+    ctx = dk.Context(dk.POLICY_TUNED, tuning_dir=str(tmp_path))
+    ctx0 = dk.Context()
+
+    def tup(p):
+        return (p.log2_M, p.log2_m, p.u, p.p_bits)
+
+    rule = {N: tup(ctx0.select_params(N, N)) for N in (2 ** 16, 2 ** 18)}
+    c3 = {N: tup(dict(ctx0.candidates(N, N))[3]) for N in (2 ** 16, 2 ** 17)}
+    assert c3[2 ** 16] != rule[2 ** 16]          # the rule entry of batch 16 decides, not batch 1's
+    assert tup(ctx.select_params(2 ** 16, 2 ** 16, 1)) == c3[2 ** 16]
+    for batch in (16, 100):
+        assert tup(ctx.select_params(2 ** 16, 2 ** 16, batch)) == rule[2 ** 16], batch
+    assert tup(ctx.select_params(2 ** 17, 2 ** 17)) == c3[2 ** 17]
+    assert tup(ctx.select_params(2 ** 18, 2 ** 18)) == rule[2 ** 18]
