@@ -40,7 +40,8 @@ enum {
     DKSS_ENOSPC = -2,     /* workspace smaller than dkss_workspace_bytes() */
     DKSS_ERANGE = -3,     /* size or parameter tuple unsupported or infeasible */
     DKSS_EHIP = -4,       /* a HIP runtime call failed */
-    DKSS_ENOTIMPL = -5
+    DKSS_ENOTIMPL = -5,
+    DKSS_ETOOBIG = -6     /* dkss_mul_noalloc: the product needs more than its fixed scratch */
 };
 
 /* Parameter policy of a context. */
@@ -157,6 +158,28 @@ int dkss_prepare(dkss_ctx* ctx, size_t alen, size_t blen, const dkss_params* p, 
  */
 int dkss_mul(dkss_ctx* ctx, uint32_t* c, const uint32_t* a, size_t alen, const uint32_t* b,
              size_t blen, const dkss_params* p, void* ws, size_t ws_bytes, dkss_stream_t s);
+
+/* Bytes of the fixed device scratch of dkss_mul_noalloc (one copy per device). */
+#define DKSS_NOALLOC_SCRATCH_BYTES ((size_t)128 << 20)
+
+/*
+ * dkss_mul without a workspace argument, for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * kernels and result as dkss_mul, with the workspace placed in a scratch array of
+ * DKSS_NOALLOC_SCRATCH_BYTES bytes that the library holds in device memory on every device it
+ * runs on, until the process ends.  The call allocates nothing (no hipMalloc, no library
+ * allocation) and does not wait; the scratch's device address for the current device is looked
+ * up by dkss_ctx_create or by the first call on that device.  Products whose workspace
+ * (dkss_workspace_bytes, which includes room for the tuple's table unless dkss_prepare has built
+ * it) exceeds the scratch are refused with DKSS_ETOOBIG: about 2^24 bits per operand under the
+ * thesis rule, 2^25 under the tuned table.  Nothing in the scratch needs to start at zero, and a
+ * call keeps no state there for the next one.  Every call on one device shares that device's
+ * scratch: calls that overlap in time on one device (several streams, several host threads,
+ * several contexts) race and give wrong products; serialize them.
+ * Errors: as dkss_mul (except DKSS_ENOSPC), DKSS_ETOOBIG.
+ */
+int dkss_mul_noalloc(dkss_ctx* ctx, uint32_t* c, const uint32_t* a, size_t alen, const uint32_t* b,
+                     size_t blen, const dkss_params* p, dkss_stream_t s);
 
 /*
  * count independent products c[i] = a[i] * b[i] (each as in dkss_mul).  The arrays of

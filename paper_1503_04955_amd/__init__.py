@@ -18,7 +18,8 @@ POLICY_THESIS = 0
 POLICY_TUNED = 1
 POLICY_LEARNED = 2
 
-OK, EINVAL, ENOSPC, ERANGE, EHIP, ENOTIMPL = 0, -1, -2, -3, -4, -5
+OK, EINVAL, ENOSPC, ERANGE, EHIP, ENOTIMPL, ETOOBIG = 0, -1, -2, -3, -4, -5, -6
+NOALLOC_SCRATCH_BYTES = 128 << 20
 
 
 class DkssError(RuntimeError):
@@ -99,6 +100,7 @@ def lib():
         L.dkss_workspace_bytes.argtypes = [vp, sz, sz, PP, ctypes.POINTER(sz)]
         L.dkss_prepare.argtypes = [vp, sz, sz, PP, vp]
         L.dkss_mul.argtypes = [vp, vp, vp, sz, vp, sz, PP, vp, sz, vp]
+        L.dkss_mul_noalloc.argtypes = [vp, vp, vp, sz, vp, sz, PP, vp]
         L.dkss_mul_batch.argtypes = [vp, sz, ctypes.POINTER(vp), ctypes.POINTER(vp),
                                      ctypes.POINTER(sz), ctypes.POINTER(vp), ctypes.POINTER(sz), PP,
                                      vp, sz, vp]
@@ -141,7 +143,7 @@ def lib():
 
 
 EXPORTED = ["dkss_ctx_create", "dkss_ctx_destroy", "dkss_select_params", "dkss_plan_info",
-            "dkss_workspace_bytes", "dkss_prepare", "dkss_mul", "dkss_mul_batch",
+            "dkss_workspace_bytes", "dkss_prepare", "dkss_mul", "dkss_mul_noalloc", "dkss_mul_batch",
             "dkss_batch_workspace_bytes", "dkss_batch_prepare", "dkss_forward", "dkss_residues", "dkss_profile_enable",
             "dkss_profile_read", "dkss_profile_reset", "dkss_kernel_name", "dkss_set_option",
             "dkss_candidates", "dkss_mlp_features", "dkss_mlp_forward", "dkss_mlp_work_floats",
@@ -309,6 +311,19 @@ class Context:
         _check(lib().dkss_mul(self._h, _ptr(out), _ptr(a), alen, _ptr(b), blen, _pp(params),
                               _ptr(ws), ws.numel(), _stream_ptr(stream)), "dkss_mul")
         _keep_until_done(stream, ws, out)
+        return out
+
+    def mul_noalloc(self, a, b, out, params=None, stream=None):
+        """out = a * b through dkss_mul_noalloc: no workspace, no preparation, no allocation
+        (the library's fixed scratch on the current device; out is the caller's tensor)."""
+        _check_limbs("a", a)
+        _check_limbs("b", b, a.device)
+        _check_limbs("out", out, a.device)
+        alen, blen = a.numel(), b.numel()
+        if out.numel() < alen + blen:
+            raise ValueError("out holds %d limbs, the product %d" % (out.numel(), alen + blen))
+        _check(lib().dkss_mul_noalloc(self._h, _ptr(out), _ptr(a), alen, _ptr(b), blen, _pp(params),
+                                      _stream_ptr(stream)), "dkss_mul_noalloc")
         return out
 
     def mul_batch(self, as_, bs, outs=None, params=None, ws=None, stream=None):

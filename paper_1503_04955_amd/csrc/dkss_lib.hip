@@ -2176,6 +2176,8 @@ int put_descs(const BatchPlan& B, size_t count, uint32_t* const* c, const uint32
 // C ABI
 // ---------------------------------------------------------------------------------------------
 
+static int scratch_address(void** out);
+
 extern "C" {
 
 static int ensure_aux(dkss_ctx* ctx) {
@@ -2266,6 +2268,14 @@ int dkss_ctx_create(dkss_ctx** out, int policy, const char* cache_dir) {
     if (!c) return DKSS_EINVAL;
     c->policy = policy;
     load_tuning(c, cache_dir);
+    {
+        // set-up of the allocation-free entry point for the current device; without a device
+        // (or on failure) its first call does it
+        int ndev = 0;
+        void* ptr = nullptr;
+        if (hipGetDeviceCount(&ndev) == hipSuccess && ndev > 0) (void)scratch_address(&ptr);
+        clear_stale_hip_error();
+    }
     if (cache_dir && policy == DKSS_POLICY_LEARNED) {
         std::vector<float> w(DKSS_MLP_NPARAM);
         if (dkss_mlp_load((std::string(cache_dir) + "/dkss_mlp.txt").c_str(), w.data()) == DKSS_OK)
@@ -2482,6 +2492,50 @@ int dkss_mul(dkss_ctx* ctx, uint32_t* c, const uint32_t* a, size_t alen, const u
              size_t blen, const dkss_params* p, void* ws, size_t ws_bytes, dkss_stream_t s) {
     clear_stale_hip_error();
     return mul_on(ctx, c, a, alen, b, blen, p, ws, ws_bytes, (hipStream_t)s);
+}
+
+}  // extern "C"
+
+// ----- allocation-free products: one fixed scratch per device ----------------------------------
+// dkss_mul_noalloc places the workspace of dkss_mul's kernels in this array instead of a caller
+// buffer.  Every device the library runs on holds its own copy, at its own address, until the
+// process ends.  In host code the name `scratch` is only a host-side stand-in: kernels receive
+// the device address that hipGetSymbolAddress returns for the current device.
+__device__ __align__(256) unsigned char scratch[DKSS_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_addr[kMaxDevices];     // device address of `scratch` per device, or null
+}  // namespace
+
+// The current device's scratch address, looked up once per device with that device current.
+static int scratch_address(void** out) {
+    int dev = -1;
+    HIP_OK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return DKSS_ERANGE;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_addr[dev]) {
+        void* ptr = nullptr;
+        HIP_OK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr || ((uintptr_t)ptr & 255)) return DKSS_EHIP;
+        g_scratch_addr[dev] = ptr;
+    }
+    *out = g_scratch_addr[dev];
+    return DKSS_OK;
+}
+
+extern "C" {
+
+int dkss_mul_noalloc(dkss_ctx* ctx, uint32_t* c, const uint32_t* a, size_t alen, const uint32_t* b,
+                     size_t blen, const dkss_params* p, dkss_stream_t s) {
+    clear_stale_hip_error();
+    if (!ctx) return DKSS_EINVAL;
+    void* ws = nullptr;
+    int rc = scratch_address(&ws);
+    if (rc) return rc;
+    rc = mul_on(ctx, c, a, alen, b, blen, p, ws, DKSS_NOALLOC_SCRATCH_BYTES, (hipStream_t)s);
+    return rc == DKSS_ENOSPC ? DKSS_ETOOBIG : rc;
 }
 
 int dkss_batch_workspace_bytes(dkss_ctx* ctx, size_t count, const size_t* alen, const size_t* blen,
@@ -2770,6 +2824,7 @@ const char* dkss_strerror(int code) {
         case DKSS_ERANGE: return "size or parameters unsupported or infeasible";
         case DKSS_EHIP: return "HIP runtime error";
         case DKSS_ENOTIMPL: return "not implemented";
+        case DKSS_ETOOBIG: return "product needs more than the allocation-free entry point's fixed scratch";
         default: return "unknown error";
     }
 }
