@@ -162,8 +162,8 @@ __global__ __launch_bounds__(kThreads) void k_encode(ProdArgs PA, int which, uin
 // (alpha^-((m/h) k) for the inverse).  Output v ends in slot v.  HBM holds limbs; products in R
 // work on 28-bit digits, the columns converted in LDS between the two forms.  Twiddle
 // products run in rounds of 256/m elements, one output coefficient per thread: the element's
-// digits are read in place, the table entry rho^s (with its negation, Montgomery form) is staged
-// in the other half.
+// digits are read in place, the table entry rho^s (Montgomery form) is staged in the other half
+// together with its negation, formed while staging.
 struct LevelArgs {
     long long twoM, base, mu_top;
     int log2mut;                  // log2 mu_top
@@ -303,10 +303,10 @@ __device__ __forceinline__ void lds_to_limbs(uint32_t* lb, const uint32_t* dg, c
 
 // A thread's operand for one round of products, fetched from HBM a round ahead (the load is
 // issued before the preceding work and waited for at first use): coefficient j of the table
-// entry rho^s and of its negation (twiddles), or coefficient j of b (componentwise products).
+// entry rho^s (twiddles), or coefficient j of b (componentwise products).
 template <int L>
 struct Ahead {
-    uint32_t v[2 * Dig<L>::D];
+    uint32_t v[Dig<L>::D];
     int rot;                      // the twiddle's power of alpha
     bool nz;                      // the element gets a product
 };
@@ -334,12 +334,9 @@ __device__ __forceinline__ void tw_fetch(Ahead<L>& f, int r0, const uint32_t* __
     f.nz = true;
     f.rot = (int)(e >> A.log2mut);
     const uint32_t s = e & ((1u << A.log2mut) - 1u);
-    const uint32_t* ts = table + (size_t)s * 2 * m * D;
+    const uint32_t* ts = table + (size_t)s * m * D;
 #pragma unroll
-    for (int y = 0; y < D; ++y) {
-        f.v[y] = ts[j * D + y];
-        f.v[D + y] = ts[(j + m) * D + y];
-    }
+    for (int y = 0; y < D; ++y) f.v[y] = ts[j * D + y];
 }
 
 // Twiddle products of all C r elements of the workgroup, in rounds of 256/m elements.  The
@@ -367,12 +364,15 @@ __device__ __forceinline__ void level_twiddle(Ahead<L>& f, uint32_t* cur, uint32
         uint32_t* X = cur + ((c << A.log2r) + slot) * EW;
         const bool nz = f.nz;
         if (nz) {
+            // the twiddle's extension to 2m entries: t_j and, m further on, q - t_j
+            uint32_t nt[D];
+            dneg_q<L>(nt, f.v, Q);
             uint32_t* t0 = TP + stage_pos(j, f.rot, A.log2m) * Dig<L>::DS;
             uint32_t* t1 = TP + stage_pos(j + m, f.rot, A.log2m) * Dig<L>::DS;
 #pragma unroll
             for (int y = 0; y < D; ++y) {
                 t0[y] = f.v[y];
-                t1[y] = f.v[D + y];
+                t1[y] = nt[y];
             }
         }
         if (r0 + per < nel) tw_fetch<L>(f, r0 + per, table, A, c0);     // next round's twiddle
@@ -648,8 +648,8 @@ __global__ __launch_bounds__(kThreads) void k_pointwise(uint32_t* A0, const uint
 }
 
 // ---------------------------------------------------------------------------------------------
-// Table of rho^s, s < mu_top, Montgomery form: entry s = m digits-residues of rho^s followed by
-// their negations.  One launch computes table[dst + j] = table[src + j] * table[mul], j < cnt.
+// Table of rho^s, s < mu_top, Montgomery form: entry s = the m coefficients of rho^s as digit
+// residues.  One launch computes table[dst + j] = table[src + j] * table[mul], j < cnt.
 // ---------------------------------------------------------------------------------------------
 
 // Words [first, first + count) of a table, count <= kPutWords, taken from the launch's arguments.
@@ -681,26 +681,26 @@ __global__ __launch_bounds__(kThreads) void k_table_mul(uint32_t* table, long lo
     const long long jj = (long long)blockIdx.x * per + g;
     const bool active = jj < cnt;
     if (active) {
-        const uint32_t* xs = table + (size_t)(src + jj) * 2 * m * D;
-        const uint32_t* ts = table + (size_t)mul * 2 * m * D;
+        const uint32_t* xs = table + (size_t)(src + jj) * m * D;
+        const uint32_t* ts = table + (size_t)mul * m * D;
+        uint32_t tv[D], nt[D];
+#pragma unroll
+        for (int y = 0; y < D; ++y) tv[y] = ts[j * D + y];
+        dneg_q<L>(nt, tv, Q);
 #pragma unroll
         for (int y = 0; y < D; ++y) {
             X[j * D + y] = xs[j * D + y];
-            TP[stage_pos(j, 0, log2m) * DS + y] = ts[j * D + y];
-            TP[stage_pos(j + m, 0, log2m) * DS + y] = ts[(j + m) * D + y];
+            TP[stage_pos(j, 0, log2m) * DS + y] = tv[y];
+            TP[stage_pos(j + m, 0, log2m) * DS + y] = nt[y];
         }
     }
     __syncthreads();
     if (active) {
-        uint32_t out[D], neg[D];
+        uint32_t out[D];
         rprod_coeff<L>(TP, X, log2m, j, Q, out);
-        dneg_q<L>(neg, out, Q);
-        uint32_t* dp = table + (size_t)(dst + jj) * 2 * m * D;
+        uint32_t* dp = table + (size_t)(dst + jj) * m * D;
 #pragma unroll
-        for (int y = 0; y < D; ++y) {
-            dp[j * D + y] = out[y];
-            dp[(j + m) * D + y] = neg[y];
-        }
+        for (int y = 0; y < D; ++y) dp[j * D + y] = out[y];
     }
 }
 
@@ -1291,9 +1291,9 @@ struct Cached {
     bool table_ready = false;             // d_table holds the finished table
     long long table_count = 0;
     int D = 0;
-    // bytes of the table: max(table_count, 2) entries of 2m residues in D digits
+    // bytes of the table: max(table_count, 2) entries of m residues in D digits
     size_t table_bytes() const {
-        return (size_t)std::max<long long>(table_count, 2) * 2 * plan.m() * D * sizeof(uint32_t);
+        return (size_t)std::max<long long>(table_count, 2) * plan.m() * D * sizeof(uint32_t);
     }
 };
 
@@ -1590,11 +1590,10 @@ int plan_constants(dkss_ctx* ctx, Call* call) {
         digits(mq.mul(inv2M, R2), Q.kpw);
         // table entries 0 (one) and 1 (rho), Montgomery form
         const int m = CP.m();
-        // entry = m residues followed by their negations (q - x; q itself for x = 0)
-        c->table_host01.assign((size_t)2 * 2 * m * D, 0u);
+        // entry = m residues (the kernels form the negations q - x when they stage an entry)
+        c->table_host01.assign((size_t)2 * m * D, 0u);
         auto put = [&](int entry, int k, const Big& x) {
-            digits(x, &c->table_host01[((size_t)entry * 2 * m + k) * D]);
-            digits(CP.q.sub(x), &c->table_host01[((size_t)entry * 2 * m + m + k) * D]);
+            digits(x, &c->table_host01[((size_t)entry * m + k) * D]);
         };
         for (int k = 0; k < m; ++k) {
             put(0, k, k == 0 ? Rm : Big());
@@ -1660,7 +1659,7 @@ struct TableBuild {
     // (rho) from the host as launch arguments; then for n = 2, 4, ...: rho^n = rho^(n/2)
     // rho^(n/2), and rho^(n+j) = rho^j rho^n for 0 < j < n.
     static int run(const Cached* C, uint32_t* tab, Prof* prof, hipStream_t s) {
-        const size_t words01 = (size_t)std::min<long long>(C->table_count, 2) * 2 * C->plan.m() * C->D;
+        const size_t words01 = (size_t)std::min<long long>(C->table_count, 2) * C->plan.m() * C->D;
         for (size_t off = 0; off < words01; off += kPutWords) {
             PutChunk ch;
             const int n = (int)std::min<size_t>(kPutWords, words01 - off);
