@@ -12,4 +12,7 @@ Modules
   brute    tiny brute-force references (naive DFT over R, Kronecker-Schoenhage, Python-int products)
   coracle  ctypes binding of dkss_oracle.c: schoolbook, ring arithmetic, FFT over R,
            encode / pointwise / decode, residues, and the whole DKSS pipeline
+  smul     Schoenhage-Strassen multiplication modulo 2^N + 1 (Sec. 2.9) in Python integers: the
+           transform over Z/(2^K + 1)Z, the weighted (negacyclic) procedure and the outermost
+           full-product form
 """
