@@ -159,6 +159,45 @@ int dkss_prepare(dkss_ctx* ctx, size_t alen, size_t blen, const dkss_params* p, 
 int dkss_mul(dkss_ctx* ctx, uint32_t* c, const uint32_t* a, size_t alen, const uint32_t* b,
              size_t blen, const dkss_params* p, void* ws, size_t ws_bytes, dkss_stream_t s);
 
+/*
+ * Schoenhage-Strassen multiplication, the thesis's SMUL (Sec. 2.9), in its outermost form for the
+ * full product (Sec. 2.9.3 with its optimizations): both operands cut into n = 2^log2_n
+ * coefficients of s bits, a cyclic FFT of length n over Z/(2^K + 1)Z with root omega = 2^(2K/n)
+ * (n | 2K; every multiplication by a root is a cyclic shift), componentwise products in that ring,
+ * the inverse FFT and the coefficients added up with carries.  K = 2048 lw bits (lw = 1, 2, 4,
+ * ..., 32).  The thesis's comparison method for DKSS; it needs no context.
+ */
+typedef struct {
+    uint32_t log2_n;      /* FFT length n = 2^log2_n (0 = chosen by the library) */
+    uint32_t lw;          /* K = 2048 lw bits per ring element (0 = chosen) */
+    uint32_t s;           /* output: bits per input coefficient, ceil(32 (alen + blen) / n) */
+    uint32_t K;           /* output: ring exponent */
+    uint32_t n_levels;    /* output: LDS-staged FFT levels per transform */
+} dkss_smul_params;
+
+/* The library's choice of (log2_n, lw) for alen x blen limbs (a modelled cost over the feasible
+ * pairs: na + nb - 1 <= n coefficients, min(na, nb) (2^s - 1)^2 < 2^K, n | 2K).  All zero when
+ * alen or blen is 0.  Errors: DKSS_EINVAL (null), DKSS_ERANGE (no feasible pair). */
+int dkss_smul_select(size_t alen, size_t blen, dkss_smul_params* out);
+
+/* Workspace bytes of dkss_smul under p (NULL or zero fields = the library's choice). */
+int dkss_smul_workspace_bytes(size_t alen, size_t blen, const dkss_smul_params* p, size_t* out);
+
+/* c[0 .. alen+blen) = a * b by SMUL (Sec. 2.9.3, Steps 1, 3-7, 9-10 of the outermost form), all
+ * enqueued on s; conventions as dkss_mul (device pointers, c not overlapping a or b, a == b with
+ * alen == blen a squaring with one forward transform, ws of dkss_smul_workspace_bytes() bytes,
+ * 256-byte aligned).  Allocates nothing and does not wait.  Errors: DKSS_EINVAL, DKSS_ENOSPC,
+ * DKSS_ERANGE (the given (log2_n, lw) infeasible, or none), DKSS_EHIP. */
+int dkss_smul(uint32_t* c, const uint32_t* a, size_t alen, const uint32_t* b, size_t blen,
+              const dkss_smul_params* p, void* ws, size_t ws_bytes, dkss_stream_t s);
+
+/* The forward transform of SMUL for the operand a of an alen x blen product under p: Step 1
+ * (n coefficients of s bits) and Steps 3-4 (evaluation at omega^i), in bit-reversed order: poly
+ * (n x 64 lw limbs, device) element bitrev(i) holds a(omega^i) mod 2^K + 1 below 2^K and
+ * tops[bitrev(i)] (n words, device) is 1 exactly when that value is 2^K.  Errors: as dkss_smul. */
+int dkss_smul_forward(uint32_t* poly, uint32_t* tops, const uint32_t* a, size_t alen, size_t blen,
+                      const dkss_smul_params* p, dkss_stream_t s);
+
 /* Bytes of the fixed device scratch of dkss_mul_noalloc (one copy per device). */
 #define DKSS_NOALLOC_SCRATCH_BYTES ((size_t)128 << 20)
 

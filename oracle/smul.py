@@ -23,7 +23,7 @@ def fermat_shift(x, t, K):
     """x * 2^t mod 2^K + 1 for any integer t (Sec. 2.9: 2 has order 2K in R, so a multiplication
     by a root of unity is a shift followed by a reduction).  By the definition of the residue."""
     F = (1 << K) + 1
-    return (x * pow(2, t % (2 * K), F)) % F
+    return (x << (t % (2 * K))) % F
 
 
 def omega_shift(n, K):

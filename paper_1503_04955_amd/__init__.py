@@ -55,6 +55,23 @@ class Params(ctypes.Structure):
                 "cutoff_bits": self.cutoff_bits}
 
 
+class SmulParams(ctypes.Structure):
+    """dkss_smul_params: FFT length 2^log2_n and K = 2048 lw (0: the library's choice); s, K and
+    n_levels are filled in by smul_select."""
+    _fields_ = [("log2_n", ctypes.c_uint32), ("lw", ctypes.c_uint32), ("s", ctypes.c_uint32),
+                ("K", ctypes.c_uint32), ("n_levels", ctypes.c_uint32)]
+
+    @classmethod
+    def make(cls, log2_n=0, lw=0):
+        p = cls()
+        p.log2_n, p.lw = log2_n, lw
+        return p
+
+    def as_dict(self):
+        return {"log2_n": self.log2_n, "lw": self.lw, "s": self.s, "K": self.K,
+                "n_levels": self.n_levels}
+
+
 class Plan(ctypes.Structure):
     _fields_ = [("params", Params), ("L", ctypes.c_uint32), ("q_bits", ctypes.c_uint32),
                 ("schoolbook", ctypes.c_uint32), ("squaring", ctypes.c_uint32),
@@ -101,6 +118,11 @@ def lib():
         L.dkss_prepare.argtypes = [vp, sz, sz, PP, vp]
         L.dkss_mul.argtypes = [vp, vp, vp, sz, vp, sz, PP, vp, sz, vp]
         L.dkss_mul_noalloc.argtypes = [vp, vp, vp, sz, vp, sz, PP, vp]
+        SP = ctypes.POINTER(SmulParams)
+        L.dkss_smul_select.argtypes = [sz, sz, SP]
+        L.dkss_smul_workspace_bytes.argtypes = [sz, sz, SP, ctypes.POINTER(sz)]
+        L.dkss_smul.argtypes = [vp, vp, sz, vp, sz, SP, vp, sz, vp]
+        L.dkss_smul_forward.argtypes = [vp, vp, vp, sz, sz, SP, vp]
         L.dkss_mul_batch.argtypes = [vp, sz, ctypes.POINTER(vp), ctypes.POINTER(vp),
                                      ctypes.POINTER(sz), ctypes.POINTER(vp), ctypes.POINTER(sz), PP,
                                      vp, sz, vp]
@@ -144,6 +166,7 @@ def lib():
 
 EXPORTED = ["dkss_ctx_create", "dkss_ctx_destroy", "dkss_select_params", "dkss_plan_info",
             "dkss_workspace_bytes", "dkss_prepare", "dkss_mul", "dkss_mul_noalloc", "dkss_mul_batch",
+            "dkss_smul_select", "dkss_smul_workspace_bytes", "dkss_smul", "dkss_smul_forward",
             "dkss_batch_workspace_bytes", "dkss_batch_prepare", "dkss_forward", "dkss_residues", "dkss_profile_enable",
             "dkss_profile_read", "dkss_profile_reset", "dkss_kernel_name", "dkss_set_option",
             "dkss_candidates", "dkss_mlp_features", "dkss_mlp_forward", "dkss_mlp_work_floats",
@@ -214,6 +237,57 @@ def _keep_until_done(stream, *tensors):
 
 def _pp(params):
     return ctypes.byref(params) if params is not None else None
+
+
+def smul_select(alen, blen):
+    """The library's SMUL parameters for alen x blen limbs (dkss_smul_select)."""
+    p = SmulParams()
+    _check(lib().dkss_smul_select(alen, blen, ctypes.byref(p)), "dkss_smul_select")
+    return p
+
+
+def smul_workspace_bytes(alen, blen, params=None):
+    n = ctypes.c_size_t()
+    _check(lib().dkss_smul_workspace_bytes(alen, blen, _pp(params), ctypes.byref(n)),
+           "dkss_smul_workspace_bytes")
+    return n.value
+
+
+def smul(a, b, out=None, params=None, ws=None, stream=None):
+    """c = a * b by Schoenhage-Strassen multiplication (dkss_smul) for int32 (uint32-limb)
+    device tensors; returns c (alen + blen limbs)."""
+    torch = _torch()
+    _check_limbs("a", a)
+    _check_limbs("b", b, a.device)
+    alen, blen = a.numel(), b.numel()
+    if out is None:
+        out = torch.empty(alen + blen, dtype=torch.int32, device=a.device)
+    _check_limbs("out", out, a.device)
+    if out.numel() < alen + blen:
+        raise ValueError("out holds %d limbs, the product %d" % (out.numel(), alen + blen))
+    if ws is None:
+        ws = _alloc_ws(smul_workspace_bytes(alen, blen, params), a.device)
+    _check(lib().dkss_smul(_ptr(out), _ptr(a), alen, _ptr(b), blen, _pp(params), _ptr(ws), ws.numel(),
+                           _stream_ptr(stream)), "dkss_smul")
+    _keep_until_done(stream, ws, out)
+    return out
+
+
+def smul_forward(a, alen, blen, params=None, stream=None):
+    """SMUL's forward transform of a for an alen x blen product (dkss_smul_forward): returns
+    (poly, tops) in bit-reversed order, poly as (n, 64 lw) int32 limbs, tops (n,) int32."""
+    torch = _torch()
+    _check_limbs("a", a)
+    p = SmulParams()
+    if params is not None:
+        p.log2_n, p.lw = params.log2_n, params.lw
+    _check(lib().dkss_smul_select(alen, blen, ctypes.byref(p)) if params is None else OK, "dkss_smul_select")
+    n, W = 1 << p.log2_n, 64 * p.lw
+    poly = torch.empty((n, W), dtype=torch.int32, device=a.device)
+    tops = torch.empty(n, dtype=torch.int32, device=a.device)
+    _check(lib().dkss_smul_forward(_ptr(poly), _ptr(tops), _ptr(a), alen, blen, ctypes.byref(p),
+                                   _stream_ptr(stream)), "dkss_smul_forward")
+    return poly, tops
 
 
 def to_device(limbs, device="cuda"):

@@ -1949,6 +1949,30 @@ struct Decode {
     }
 };
 
+}  // namespace
+
+// Carry resolution of a product whose words and per-wavefront generate/propagate masks were
+// written under k_decode's contract (word w = low 32 bits of its sum plus the high part of the
+// previous word's, a 1-bit carry left); used by the SMUL decode too.
+int dkss::carry_resolve(uint32_t* c, long long nw, unsigned long long* gmask, unsigned long long* pmask,
+                        unsigned char* cin01, unsigned char* seg_gp, unsigned char* seg_cin, hipStream_t s) {
+    if (nw <= 0) return DKSS_OK;
+    const long long nwaves = (nw + 63) / 64;
+    const long long nseg = (nwaves + kThreads - 1) / kThreads;
+    if (nseg > (1LL << 31)) return DKSS_ERANGE;
+    ProdArgs PA{};
+    PA.one = ProdDesc{c, nullptr, nullptr, nw, 0, 0, 0};
+    hipLaunchKernelGGL(k_carry_block, dim3((unsigned)nseg, 1), dim3(kThreads), 0, s, PA, gmask, pmask, cin01,
+                       seg_gp, nwaves, nseg);
+    hipLaunchKernelGGL(k_carry_top, dim3(1, 1), dim3(1024), 0, s, PA, seg_gp, seg_cin, nseg);
+    const unsigned blocks4 = (unsigned)((nw + 4 * kThreads - 1) / (4 * kThreads));
+    hipLaunchKernelGGL(k_carry_apply, dim3(blocks4, 1), dim3(kThreads), 0, s, PA, gmask, pmask, cin01, seg_cin,
+                       nwaves, nseg);
+    return launch_status();
+}
+
+namespace {
+
 template <int L>
 struct Unscramble {
     static int run(const Call& c, uint32_t* poly, const uint32_t* src, const LevelIdx& LI, hipStream_t s) {
