@@ -357,6 +357,43 @@ def sizes_leg(bits_list, reps, dk, torch, SI):
     return out
 
 
+def smul_leg(bits_list, reps, dk, torch, SI):
+    """The thesis's comparison method on the same GPU: one 2^bits x 2^bits-bit product by SMUL
+    (Schoenhage-Strassen, the library's FFT length and ring) beside DKSS under the thesis rule and
+    the learned selector; the DKSS/SMUL time ratio (the thesis measures 26-36 on one CPU core)."""
+    out = {}
+    for bits in bits_list:
+        n = (1 << bits) // 32
+        a_h, b_h = SI.operand_pair(SI.SEED_BASE + 2, n, n)
+        a, b = dk.to_device(a_h), dk.to_device(b_h)
+        del a_h, b_h
+        res = {"limbs": n}
+        c_s = torch.empty(2 * n, dtype=torch.int32, device="cuda")
+        p = dk.smul_select(n, n)
+        ws = torch.empty(dk.smul_workspace_bytes(n, n), dtype=torch.uint8, device="cuda")
+        ms = _timed(lambda: dk.smul(a, b, out=c_s, ws=ws), reps, torch, warmup=2)
+        res["smul"] = {"ms": ms, "value": 2 * n * 32 / (ms / 1e3), "params": p.as_dict()}
+        del ws
+        for name, policy in (("dkss_thesis", dk.POLICY_THESIS), ("dkss_learned", dk.POLICY_LEARNED)):
+            ctx = dk.Context(policy)
+            c = torch.empty(2 * n, dtype=torch.int32, device="cuda")
+            ws = torch.empty(ctx.workspace_bytes(n, n), dtype=torch.uint8, device="cuda")
+            ctx.prepare(n, n)
+            ms = _timed(lambda: ctx.mul(a, b, out=c, ws=ws), reps, torch, warmup=2)
+            if not torch.equal(c, c_s):
+                raise RuntimeError("2^%d SMUL and DKSS products differ" % bits)
+            res[name] = {"ms": ms, "value": 2 * n * 32 / (ms / 1e3)}
+            del ws, c
+        res["dkss_over_smul"] = {"thesis": res["dkss_thesis"]["ms"] / res["smul"]["ms"],
+                                 "learned": res["dkss_learned"]["ms"] / res["smul"]["ms"]}
+        res["verified"] = "SMUL product equal to both DKSS products"
+        out["2^%d" % bits] = res
+        log("2^%d: smul %.3f ms, dkss thesis %.3f ms, learned %.3f ms" %
+            (bits, res["smul"]["ms"], res["dkss_thesis"]["ms"], res["dkss_learned"]["ms"]))
+        torch.cuda.empty_cache()
+    return out
+
+
 def c5_leg(dk, torch, SI):
     """One 2^34 x 2^34-bit product under the thesis rule and under the learned selector, and the
     squaring a*a (thesis rule): one timed call each after a warm-up call (tables prepared)."""
@@ -402,7 +439,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--batch", type=int, default=4096, help="products in the headline batch")
-    ap.add_argument("--legs", default="batch,2p28,sizes,c5",
+    ap.add_argument("--legs", default="batch,2p28,sizes,smul,c5",
                     help="comma-separated legs to run (the headline batch is always run)")
     ap.add_argument("--no-c5", action="store_true", help="skip the 2^34 leg")
     ap.add_argument("--no-cpu", action="store_true")
@@ -443,6 +480,8 @@ def main():
         out["single_2p28"] = single_leg(28, args.steps, dk, torch, SI)
     if "sizes" in legs:
         out["sizes"] = sizes_leg([18, 24], 20, dk, torch, SI)
+    if "smul" in legs:
+        out["smul"] = smul_leg([24, 28], 10, dk, torch, SI)
     if "c5" in legs and not args.no_c5:
         out["c5"] = c5_leg(dk, torch, SI)
     if args.copy_calib:

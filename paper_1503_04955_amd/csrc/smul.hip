@@ -33,6 +33,7 @@ using namespace dkss;
 namespace {
 
 constexpr int kT = 256;                   // threads per workgroup: four wavefronts
+constexpr int kTL = 512;                  // threads per workgroup of a transform level: eight wavefronts
 constexpr int kMaxLw = 32;                // limbs per lane: W <= 2048, K <= 65536
 constexpr size_t kColumnBytes = 65536;    // LDS for the elements of one level column
 
@@ -238,7 +239,7 @@ struct SmulLevel {
 // DIT = 1: decimation in time with omega^-1, spans 1 .. r/2: x, y -> x + omega^(-i n / 2h) y,
 // x - omega^(-i n / 2h) y.  omega^e = 2^(e 2K / n): the exponent i n / 2h is the shift i K / h.
 template <int LW, int DIT>
-__global__ __launch_bounds__(kT) void k_smul_level(uint32_t* __restrict__ poly, uint32_t* __restrict__ tops,
+__global__ __launch_bounds__(kTL) void k_smul_level(uint32_t* __restrict__ poly, uint32_t* __restrict__ tops,
                                                    SmulLevel A) {
     constexpr int W = 64 * LW;
     constexpr int K = 32 * W;
@@ -250,7 +251,7 @@ __global__ __launch_bounds__(kT) void k_smul_level(uint32_t* __restrict__ poly, 
     const long long col = blockIdx.x;
     const long long c = col & (H - 1);
     const long long base = ((col >> A.log2H) << (A.log2H + A.log2r)) + c;
-    for (int idx = threadIdx.x; idx < r * W; idx += kT) {
+    for (int idx = threadIdx.x; idx < r * W; idx += kTL) {
         const int j = idx / W, w = idx - j * W;
         E[idx] = poly[(size_t)(base + j * H) * W + w];
     }
@@ -260,7 +261,7 @@ __global__ __launch_bounds__(kT) void k_smul_level(uint32_t* __restrict__ poly, 
     for (int st = 0; st < A.log2r; ++st) {
         const int lh = DIT ? st : A.log2r - 1 - st;   // log2 of the local span hl
         const int hl = 1 << lh;
-        for (int b = wave; b < r / 2; b += kT / 64) {
+        for (int b = wave; b < r / 2; b += kTL / 64) {
             const int j = ((b >> lh) << (lh + 1)) + (b & (hl - 1));
             // twiddle shift i K / h, i = c + (j mod hl) H < h = hl H (so the shift is below K)
             const long long i = c + (long long)(b & (hl - 1)) * H;
@@ -300,7 +301,7 @@ __global__ __launch_bounds__(kT) void k_smul_level(uint32_t* __restrict__ poly, 
         }
         __syncthreads();
     }
-    for (int idx = threadIdx.x; idx < r * W; idx += kT) {
+    for (int idx = threadIdx.x; idx < r * W; idx += kTL) {
         const int j = idx / W, w = idx - j * W;
         poly[(size_t)(base + j * H) * W + w] = E[idx];
     }
@@ -311,11 +312,11 @@ __global__ __launch_bounds__(kT) void k_smul_level(uint32_t* __restrict__ poly, 
 // bits (zero beyond x's limbs); tops 0.  One thread per limb.
 __global__ __launch_bounds__(kT) void k_smul_encode(uint32_t* __restrict__ poly, uint32_t* __restrict__ tops,
                                                     const uint32_t* __restrict__ x, long long xlen, int s,
-                                                    long long n, int W) {
+                                                    long long n, int log2W) {
     const long long idx = (long long)blockIdx.x * kT + threadIdx.x;
-    if (idx >= n * W) return;
-    const long long e = idx / W;
-    const int j = (int)(idx - e * W);
+    if (idx >= (n << log2W)) return;
+    const long long e = idx >> log2W;
+    const int j = (int)(idx & ((1 << log2W) - 1));
     if (j == 0) tops[e] = 0;
     const int nb = s - 32 * j;                 // the coefficient's bits left at limb j
     uint32_t v = 0;
@@ -335,9 +336,11 @@ __global__ __launch_bounds__(kT) void k_smul_encode(uint32_t* __restrict__ poly,
 // their 28-bit digits, the column sums (28-bit low part and a 64-bit high part), the words'
 // 64-bit sums and the product's 2W words.
 __host__ __device__ constexpr int pw_digits(int W) { return (32 * W + 27) / 28; }
+// columns per block of the column sums: 2 Dg columns in 512 blocks (two per thread), odd so that
+// the lanes' strided digit reads fall on distinct banks
+__host__ __device__ constexpr int pw_cb(int W) { return ((2 * pw_digits(W) + 2 * kT - 1) / (2 * kT)) | 1; }
 __host__ __device__ constexpr size_t pw_lds_words(int W) {
-    return 2 * (size_t)W + 2 * (size_t)pw_digits(W) + 3 * 2 * (size_t)pw_digits(W) + 2 * 2 * (size_t)W +
-           2 * (size_t)W;
+    return 2 * (size_t)W + 2 * (size_t)pw_digits(W) + 4 * (size_t)pw_cb(W) + 3 * 2 * (size_t)pw_digits(W);
 }
 
 // Step 5 with the scaling of Step 9: element k of A becomes A_k B_k 2^(-log2 n) mod 2^K + 1.
@@ -354,15 +357,20 @@ __global__ __launch_bounds__(kT) void k_smul_pointwise(uint32_t* Ap, uint32_t* A
     constexpr int K = 32 * W;
     constexpr int Dg = pw_digits(W);
     constexpr int NC = 2 * Dg;                    // columns 0 .. 2 Dg - 2, and one more for the carry
+    constexpr int CB = pw_cb(W);
+    constexpr int PADL = 2 * CB;
     extern __shared__ uint32_t sm[];
     uint32_t* XA = sm;
     uint32_t* XB = XA + W;
-    uint32_t* AD = XB + W;
-    uint32_t* BD = AD + Dg;
-    uint32_t* C0 = BD + Dg;                       // NC low parts
+    uint32_t* AD = XB + W;                        // Dg digits, then CB zeros
+    uint32_t* BP = AD + Dg + CB;                  // 2 CB zeros, Dg digits, CB zeros
+    uint32_t* BD = BP + PADL;
+    uint32_t* C0 = BP + PADL + Dg + CB;           // NC low parts
     uint64_t* C1 = reinterpret_cast<uint64_t*>(C0 + NC + (NC & 1));   // NC high parts
-    uint64_t* V = C1 + NC;                        // 2W word sums
-    uint32_t* PW = reinterpret_cast<uint32_t*>(V + 2 * W);            // 2W product words
+    // once the columns are summed: the 2W word sums over the factors and digits (4W <= 2W +
+    // 2 Dg words), then the 2W product words over the columns
+    uint64_t* V = reinterpret_cast<uint64_t*>(sm);
+    uint32_t* PW = C0;
     const size_t k = blockIdx.x;
     uint32_t* a = Ap + k * W;
     const uint32_t* b = Bp + k * W;
@@ -396,21 +404,62 @@ __global__ __launch_bounds__(kT) void k_smul_pointwise(uint32_t* Ap, uint32_t* A
             AD[d] = (uint32_t)(va >> sh) & 0x0FFFFFFFu;
             BD[d] = (uint32_t)(vb >> sh) & 0x0FFFFFFFu;
         }
+        if ((int)threadIdx.x < CB) {
+            AD[Dg + threadIdx.x] = 0;
+            BD[Dg + threadIdx.x] = 0;
+        }
+        if ((int)threadIdx.x < PADL) BP[threadIdx.x] = 0;
         __syncthreads();
-        for (int cc = threadIdx.x; cc < NC; cc += kT) {
-            uint64_t acc = 0, hi = 0;
-            if (cc < 2 * Dg - 1) {
-                const int i0 = cc - Dg + 1 > 0 ? cc - Dg + 1 : 0;
-                const int i1 = cc < Dg - 1 ? cc : Dg - 1;
-                for (int blk = i0; blk <= i1; blk += 128) {
-                    const int e = blk + 128 <= i1 + 1 ? blk + 128 : i1 + 1;
-                    for (int i = blk; i < e; ++i) acc += (uint64_t)AD[i] * BD[cc - i];
-                    hi += acc >> 28;
-                    acc &= 0x0FFFFFFFull;
+        // columns c0 .. c0 + CB - 1 of a block: sum over i of A_i B_(c - i).  The B digits of the
+        // block's CB columns at step i, B_(c0 + k - i) (k < CB), sit in registers, position k in
+        // slot (k - i) mod CB, so one new digit per step enters; out-of-range digits are the
+        // zero padding.  512 blocks of CB columns are centred on the 2 Dg - 1 columns, so that
+        // blocks t and 511 - t, thread t's two, are mirror images with equal work.
+        static_assert(2 * kT * CB >= 2 * Dg, "the blocks cover every column");
+        constexpr int OFF = (2 * kT * CB - (2 * Dg - 1)) / 2;
+        for (int hb = 0; hb < 2; ++hb) {
+            const int c0 = (hb ? 2 * kT - 1 - (int)threadIdx.x : (int)threadIdx.x) * CB - OFF;
+            uint64_t acc[CB], hi[CB];
+#pragma unroll
+            for (int k = 0; k < CB; ++k) acc[k] = hi[k] = 0;
+            const int ilo = c0 - (Dg - 1) > 0 ? c0 - (Dg - 1) : 0;
+            const int ihi = c0 + CB - 1 < Dg - 1 ? c0 + CB - 1 : Dg - 1;
+            if (ihi >= ilo) {
+                const int ngroups = (ihi - ilo + CB) / CB;
+                uint32_t buf[CB];
+#pragma unroll
+                for (int k = 0; k < CB; ++k) buf[k] = BD[c0 + k - ilo];
+                for (int g = 0; g < ngroups; ++g) {
+                    const int ib = ilo + g * CB;
+                    uint32_t av[CB], bv[CB];              // the group's digits, loaded together
+#pragma unroll
+                    for (int r = 0; r < CB; ++r) {
+                        av[r] = AD[ib + r];
+                        bv[r] = BD[c0 - (ib + r) - 1];
+                    }
+#pragma unroll
+                    for (int r = 0; r < CB; ++r) {
+                        const uint64_t a_i = av[r];
+#pragma unroll
+                        for (int k = 0; k < CB; ++k) acc[k] += a_i * buf[(k - r + CB) % CB];
+                        buf[CB - 1 - r] = bv[r];
+                    }
+                    if ((g & 15) == 15) {          // at most 16 CB products of 2^56 per term
+#pragma unroll
+                        for (int k = 0; k < CB; ++k) {
+                            hi[k] += acc[k] >> 28;
+                            acc[k] &= 0x0FFFFFFFull;
+                        }
+                    }
                 }
             }
-            C0[cc] = (uint32_t)acc;
-            C1[cc] = hi;
+#pragma unroll
+            for (int k = 0; k < CB; ++k) {
+                if (c0 + k >= 0 && c0 + k < NC) {
+                    C0[c0 + k] = (uint32_t)(acc[k] & 0x0FFFFFFFull);
+                    C1[c0 + k] = hi[k] + (acc[k] >> 28);
+                }
+            }
         }
         __syncthreads();
         // the product is sum_c e_c 2^(28 c), e_c = C0[c] + C1[c - 1] < 2^42; word w sums the
@@ -665,9 +714,9 @@ int launch_transform(const SmulPlan& P, uint32_t* poly, uint32_t* tops, bool inv
         const size_t lds = ((size_t)P.W << A.log2r) * 4 + ((size_t)4 << A.log2r);
         const unsigned cols = (unsigned)(P.n >> A.log2r);
         if (inverse)
-            hipLaunchKernelGGL((k_smul_level<LW, 1>), dim3(cols), dim3(kT), lds, s, poly, tops, A);
+            hipLaunchKernelGGL((k_smul_level<LW, 1>), dim3(cols), dim3(kTL), lds, s, poly, tops, A);
         else
-            hipLaunchKernelGGL((k_smul_level<LW, 0>), dim3(cols), dim3(kT), lds, s, poly, tops, A);
+            hipLaunchKernelGGL((k_smul_level<LW, 0>), dim3(cols), dim3(kTL), lds, s, poly, tops, A);
     }
     return launch_status();
 }
@@ -710,8 +759,10 @@ struct Pointwise {
 
 int encode(const SmulPlan& P, uint32_t* poly, uint32_t* tops, const uint32_t* x, size_t xlen, hipStream_t s) {
     const long long total = P.n * P.W;
+    int log2W = 0;
+    while ((1 << log2W) < P.W) ++log2W;
     hipLaunchKernelGGL(k_smul_encode, dim3((unsigned)((total + kT - 1) / kT)), dim3(kT), 0, s, poly, tops, x,
-                       (long long)xlen, P.s, P.n, P.W);
+                       (long long)xlen, P.s, P.n, log2W);
     return launch_status();
 }
 
