@@ -256,7 +256,9 @@ def batch_leg(args, dk, torch, SI):
     res = {"workload": "4096 products, operands 2^12..2^22 bits log-uniform, length ratio U[1,8]",
            "operand_bits": bits, "graph_learned": head,
            "plain_sequential": {"ms": ms_plain, "value": bits / (ms_plain / 1e3)}}
-    # the profiled pass of the headline's kernels: the eager learned batch, K steps
+    # the profiled pass of the headline's kernels: the eager learned batch, K steps, its groups
+    # on one stream (concurrent groups would stretch each other's kernel times)
+    call.ctx.set_option(dk.OPT_BATCH_LANES, 1)
     call.ctx.profile_reset()
     call.ctx.profile(True)
     for _ in range(args.steps):
@@ -264,6 +266,7 @@ def batch_leg(args, dk, torch, SI):
     torch.cuda.synchronize()
     call.ctx.profile(False)
     stats = call.ctx.profile_read()
+    call.ctx.set_option(dk.OPT_BATCH_LANES, 4)
     same = all(torch.equal(x, y) for x, y in zip(outs_p, call.outs))
     graph.close()
     for name, policy in (("thesis", dk.POLICY_THESIS), ("tuned", dk.POLICY_TUNED),

@@ -328,8 +328,18 @@ const char* dkss_kernel_name(int kind);
  *                        bottom FFT level, which then also runs the bottom level of the inverse
  *                        transform (one launch instead of three); 0: separate launches.  Not
  *                        fused while DKSS_OPT_OVERLAP transforms b on the second stream.
+ *  DKSS_OPT_BATCH_LANES  1..8 (default 4): a batch's launch groups (one per parameter tuple)
+ *                        are spread over this many streams, the largest modelled work first,
+ *                        each group to the least loaded one, every stream with its own
+ *                        workspace slice (dkss_batch_workspace_bytes grows accordingly), so that
+ *                        independent groups overlap; the extra streams of the context are made
+ *                        by this option or by a planning call (dkss_batch_workspace_bytes,
+ *                        dkss_batch_prepare, dkss_batch_graph_create), forked from and joined
+ *                        back to the caller's stream with events, and a captured batch graph
+ *                        holds them as parallel branches.  Without them (no planning call yet)
+ *                        the groups run on the caller's stream.
  */
-enum { DKSS_OPT_OVERLAP = 0, DKSS_OPT_DFT_LDS = 1, DKSS_OPT_FUSE_PW = 2 };
+enum { DKSS_OPT_OVERLAP = 0, DKSS_OPT_DFT_LDS = 1, DKSS_OPT_FUSE_PW = 2, DKSS_OPT_BATCH_LANES = 3 };
 int dkss_set_option(dkss_ctx* ctx, int option, long long value);
 
 /*

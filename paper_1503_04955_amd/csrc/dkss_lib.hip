@@ -1320,6 +1320,7 @@ int dig_K(int L) { return (32 * L + 6 + 27) / 28; }
 // Tuned choices: for log2(N) in [lo, hi), candidate index cand (see candidate_params).
 // Optionally with the FFT level split and the LDS budget of the DFT-only levels.
 constexpr int kCandThesis = -1;  // a table entry that names the thesis rule ("T")
+constexpr int kMaxLanes = 8;     // concurrent streams of a batch's groups
 
 struct TuneEntry {
     double lo, hi;
@@ -1348,7 +1349,17 @@ struct dkss_ctx {
     long long dft_lds = 32768;
     hipStream_t aux = nullptr;          // made when DKSS_OPT_OVERLAP is first switched on
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    // batches: groups spread over batch_lanes streams (the caller's and lane_s[0 .. lanes-2],
+    // made by planning calls or the option), forked and joined with lane_ev
+    int batch_lanes = 4;
+    int lanes_made = 1;                 // streams available: 1 + the internal ones made so far
+    hipStream_t lane_s[kMaxLanes - 1] = {};
+    hipEvent_t lane_ev[kMaxLanes] = {};
     ~dkss_ctx() {
+        for (int i = 0; i < kMaxLanes; ++i)
+            if (lane_ev[i]) (void)hipEventDestroy(lane_ev[i]);
+        for (int i = 0; i < kMaxLanes - 1; ++i)
+            if (lane_s[i]) (void)hipStreamDestroy(lane_s[i]);
         if (ev_fork) (void)hipEventDestroy(ev_fork);
         if (ev_join) (void)hipEventDestroy(ev_join);
         if (aux) (void)hipStreamDestroy(aux);
@@ -2110,6 +2121,10 @@ struct BatchPlan {
     // descriptors (used when the context has not built that table)
     std::vector<std::pair<Cached*, size_t>> tabs;
     size_t desc_bytes = 0, tab_bytes = 0, ws_bytes = 0;
+    // groups spread over lanes (streams), each lane with its own workspace slice
+    int lanes = 1;
+    std::vector<int> lane_of;          // per group
+    std::vector<size_t> lane_off;      // per lane: its slice's offset after descriptors and tables
 };
 
 constexpr size_t kMaxGroup = 65535;     // gridDim.y
@@ -2117,6 +2132,7 @@ constexpr size_t kMaxGroup = 65535;     // gridDim.y
 // infer: as in prepare_call (planning calls run one inference for every new shape)
 int plan_batch(dkss_ctx* ctx, size_t count, const size_t* alen, const size_t* blen,
                const dkss_params* p, BatchPlan* B, bool infer) {
+    const int lanes = std::max(1, std::min(ctx->batch_lanes, kMaxLanes));
     B->calls.assign(count, Call());
     std::map<std::string, std::vector<size_t>> by_key;
     const uint32_t batch = (uint32_t)std::min<size_t>(count, UINT32_MAX);
@@ -2141,7 +2157,7 @@ int plan_batch(dkss_ctx* ctx, size_t count, const size_t* alen, const size_t* bl
         by_key[key].push_back(i);
     }
     B->desc_bytes = align256(count * sizeof(ProdDesc));
-    size_t ws_max = 0;
+    std::vector<size_t> gws;           // workspace bytes of each group
     for (auto& kv : by_key) {
         const std::vector<size_t>& idx = kv.second;
         for (size_t off = 0; off < idx.size(); off += kMaxGroup) {
@@ -2161,8 +2177,9 @@ int plan_batch(dkss_ctx* ctx, size_t count, const size_t* alen, const size_t* bl
                 g.out_w += (double)(alen[i] + blen[i]);
                 g.ops += (double)alen[i] * (double)blen[i];
             }
+            gws.push_back(0);
             if (g.kind == 2) {
-                ws_max = std::max(ws_max, layout(g.call.P, g.count, g.nw_max, true, nullptr).bytes);
+                gws.back() = layout(g.call.P, g.count, g.nw_max, true, nullptr).bytes;
                 bool seen = false;
                 for (const auto& t : B->tabs) seen = seen || t.first == g.call.C;
                 if (!seen) {
@@ -2173,7 +2190,35 @@ int plan_batch(dkss_ctx* ctx, size_t count, const size_t* alen, const size_t* bl
             B->groups.push_back(g);
         }
     }
-    B->ws_bytes = B->desc_bytes + B->tab_bytes + ws_max;
+    // groups to lanes, largest modelled work first, each to the lane with the least so far
+    // (work ~ the group's operand words times its transform length's log, schoolbook ~ words^2)
+    const size_t ng = B->groups.size();
+    B->lanes = (int)std::min<size_t>((size_t)lanes, std::max<size_t>(ng, 1));
+    std::vector<double> work(ng);
+    for (size_t i = 0; i < ng; ++i) {
+        const BatchPlan::Grp& g = B->groups[i];
+        work[i] = g.kind == 2 ? (double)gws[i] * (double)(g.call.P.log2_M + 1)
+                              : g.kind == 1 ? g.ops : g.out_w;
+    }
+    std::vector<size_t> by_work(ng);
+    for (size_t i = 0; i < ng; ++i) by_work[i] = i;
+    std::stable_sort(by_work.begin(), by_work.end(), [&](size_t x, size_t y) { return work[x] > work[y]; });
+    std::vector<double> load(B->lanes, 0.0);
+    std::vector<size_t> lane_ws(B->lanes, 0);
+    B->lane_of.assign(ng, 0);
+    for (size_t i : by_work) {
+        const int l = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        B->lane_of[i] = l;
+        load[l] += work[i];
+        lane_ws[l] = std::max(lane_ws[l], gws[i]);
+    }
+    B->lane_off.assign(B->lanes, 0);
+    size_t off = 0;
+    for (int l = 0; l < B->lanes; ++l) {
+        B->lane_off[l] = off;
+        off += align256(lane_ws[l]);
+    }
+    B->ws_bytes = B->desc_bytes + B->tab_bytes + off;
     return DKSS_OK;
 }
 
@@ -2212,6 +2257,20 @@ static int ensure_aux(dkss_ctx* ctx) {
     return DKSS_OK;
 }
 
+// The batch lanes' streams and events (planning calls and the option; never a product call).
+static int ensure_lanes(dkss_ctx* ctx) {
+    const int want = std::max(1, std::min(ctx->batch_lanes, kMaxLanes));
+    if (want > 1 && !ctx->lane_ev[0]) HIP_OK(hipEventCreateWithFlags(&ctx->lane_ev[0], hipEventDisableTiming));
+    while (ctx->lanes_made < want) {
+        const int l = ctx->lanes_made;
+        // default priority (same as any caller stream)
+        HIP_OK(hipStreamCreateWithFlags(&ctx->lane_s[l - 1], hipStreamNonBlocking));
+        HIP_OK(hipEventCreateWithFlags(&ctx->lane_ev[l], hipEventDisableTiming));
+        ctx->lanes_made = l + 1;
+    }
+    return DKSS_OK;
+}
+
 int dkss_set_option(dkss_ctx* ctx, int option, long long value) {
     if (!ctx) return DKSS_EINVAL;
     switch (option) {
@@ -2225,6 +2284,10 @@ int dkss_set_option(dkss_ctx* ctx, int option, long long value) {
         case DKSS_OPT_FUSE_PW:
             ctx->fuse_pw = value != 0;
             return DKSS_OK;
+        case DKSS_OPT_BATCH_LANES:
+            if (value < 1 || value > kMaxLanes) return DKSS_EINVAL;
+            ctx->batch_lanes = (int)value;
+            return ensure_lanes(ctx);
         case DKSS_OPT_DFT_LDS:
             if (value < 16384 || value > 163840) return DKSS_EINVAL;
             ctx->dft_lds = value;
@@ -2568,7 +2631,7 @@ int dkss_batch_workspace_bytes(dkss_ctx* ctx, size_t count, const size_t* alen, 
     int rc = plan_batch(ctx, count, alen, blen, p, &B, true);
     if (rc) return rc;
     *out = count ? B.ws_bytes : 0;
-    return DKSS_OK;
+    return ensure_lanes(ctx);
 }
 
 int dkss_batch_prepare(dkss_ctx* ctx, size_t count, const size_t* alen, const size_t* blen,
@@ -2578,6 +2641,7 @@ int dkss_batch_prepare(dkss_ctx* ctx, size_t count, const size_t* alen, const si
     BatchPlan B;
     int rc = plan_batch(ctx, count, alen, blen, p, &B, true);
     if (rc) return rc;
+    if ((rc = ensure_lanes(ctx))) return rc;
     for (const auto& t : B.tabs)
         if ((rc = ensure_table(t.first, &ctx->prof, (hipStream_t)s))) return rc;
     return DKSS_OK;
@@ -2599,7 +2663,7 @@ static int check_batch_args(size_t count, uint32_t* const* c, const uint32_t* co
 // The launches of a planned batch whose descriptors sit at the start of ws.  Tuples whose table
 // the context has not built get one in the workspace's table room first.  prof: NULL inside a
 // graph capture (no timing events there).
-static int enqueue_batch(const BatchPlan& B, void* ws, Prof* prof, hipStream_t st) {
+static int enqueue_batch(const dkss_ctx* ctx, const BatchPlan& B, void* ws, Prof* prof, hipStream_t st) {
     ProdDesc* d_desc = (ProdDesc*)ws;
     char* tws = (char*)ws + B.desc_bytes;
     char* gws = tws + B.tab_bytes;
@@ -2614,7 +2678,22 @@ static int enqueue_batch(const BatchPlan& B, void* ws, Prof* prof, hipStream_t s
         if (rc) return rc;
         table[t.first] = dst;
     }
-    for (const BatchPlan::Grp& g : B.groups) {
+    // lane 0 is the caller's stream; the others fork from it after the tables and join back at
+    // the end (without the context's lane streams every lane runs on the caller's stream)
+    const int nl = ctx->lanes_made >= B.lanes ? B.lanes : 1;
+    hipStream_t ls[kMaxLanes];
+    ls[0] = st;
+    for (int l = 1; l < B.lanes; ++l) ls[l] = nl > 1 ? ctx->lane_s[l - 1] : st;
+    if (nl > 1) {
+        HIP_OK(hipEventRecord(ctx->lane_ev[0], st));
+        for (int l = 1; l < nl; ++l) HIP_OK(hipStreamWaitEvent(ls[l], ctx->lane_ev[0], 0));
+    }
+    int rc_all = DKSS_OK;
+    for (size_t gi = 0; gi < B.groups.size() && !rc_all; ++gi) {
+        const BatchPlan::Grp& g = B.groups[gi];
+        const int lane = B.lane_of[gi];
+        hipStream_t gst = ls[lane];
+        char* lws = gws + B.lane_off[lane];
         ProdArgs PA{};
         PA.many = d_desc + g.first;
         const unsigned G = (unsigned)g.count;
@@ -2624,16 +2703,25 @@ static int enqueue_batch(const BatchPlan& B, void* ws, Prof* prof, hipStream_t s
         if (g.kind == 2) call.table = table[g.call.C];
         int rc;
         if (g.kind == 0) {
-            rc = launch_zero(PA, G, g.nw_max, st);
+            rc = launch_zero(PA, G, g.nw_max, gst);
         } else if (g.kind == 1) {
-            rc = launch_schoolbook(call, PA, G, g.nw_max, g.ops, st);
+            rc = launch_schoolbook(call, PA, G, g.nw_max, g.ops, gst);
         } else {
-            Workspace w = layout(call.P, G, g.nw_max, true, gws);
-            rc = run_group(call, PA, G, g.nw_max, g.in_a, g.in_b, g.out_w, false, w, st, g.u_min);
+            Workspace w = layout(call.P, G, g.nw_max, true, lws);
+            rc = run_group(call, PA, G, g.nw_max, g.in_a, g.in_b, g.out_w, false, w, gst, g.u_min);
         }
-        if (rc) return rc;
+        rc_all = rc;
     }
-    return DKSS_OK;
+    // the join is enqueued also after an error, so that no lane stream is left forked from a
+    // capture
+    if (nl > 1) {
+        for (int l = 1; l < nl; ++l) {
+            const int rc1 = note_hip(hipEventRecord(ctx->lane_ev[l], ls[l]));
+            const int rc2 = note_hip(hipStreamWaitEvent(st, ctx->lane_ev[l], 0));
+            if (!rc_all) rc_all = rc1 ? rc1 : rc2;
+        }
+    }
+    return rc_all;
 }
 
 int dkss_mul_batch(dkss_ctx* ctx, size_t count, uint32_t* const* c, const uint32_t* const* a,
@@ -2650,7 +2738,7 @@ int dkss_mul_batch(dkss_ctx* ctx, size_t count, uint32_t* const* c, const uint32
     if (ws_bytes < B.ws_bytes) return DKSS_ENOSPC;
     hipStream_t st = (hipStream_t)s;
     if ((rc = put_descs(B, count, c, a, alen, b, blen, (ProdDesc*)ws, st))) return rc;
-    return enqueue_batch(B, ws, &ctx->prof, st);
+    return enqueue_batch(ctx, B, ws, &ctx->prof, st);
 }
 
 }  // extern "C"
@@ -2680,6 +2768,7 @@ int dkss_batch_graph_create(dkss_ctx* ctx, size_t count, uint32_t* const* c, con
     if ((rc = plan_batch(ctx, count, alen, blen, p, &B, true))) return rc;
     if (ws == nullptr || ((uintptr_t)ws & 255)) return DKSS_EINVAL;
     if (ws_bytes < B.ws_bytes) return DKSS_ENOSPC;
+    if ((rc = ensure_lanes(ctx))) return rc;
     hipStream_t cs = nullptr;
     HIP_OK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
     std::unique_ptr<dkss_graph> G(new (std::nothrow) dkss_graph());
@@ -2693,7 +2782,7 @@ int dkss_batch_graph_create(dkss_ctx* ctx, size_t count, uint32_t* const* c, con
         if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
             rc = DKSS_EHIP;
         } else {
-            rc = enqueue_batch(B, ws, nullptr, cs);
+            rc = enqueue_batch(ctx, B, ws, nullptr, cs);
             hipGraph_t graph = nullptr;      // the capture is always ended, also after an error
             const hipError_t e = hipStreamEndCapture(cs, &graph);
             G->graph = graph;

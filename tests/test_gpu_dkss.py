@@ -410,13 +410,16 @@ def test_batch_graph_replays(env):
 
 
 @pytest.mark.parametrize("opts", [{"fuse": 0}, {"overlap": 1}, {"overlap": 1, "fuse": 0},
-                                  {"lds": 16384}, {"lds": 65536}, {"lds": 163840}])
+                                  {"lds": 16384}, {"lds": 65536}, {"lds": 163840},
+                                  {"lanes": 1}, {"lanes": 8}])
 def test_context_options_keep_the_bits(env, opts):
     """The unfused componentwise products (separate k_pointwise, k_encode), the second stream for
-    b and other LDS budgets give the same product, single and batched."""
+    b, other LDS budgets and other numbers of batch streams give the same product, single and
+    batched."""
     dk, torch, ctx0 = env
     ctx = dk.Context()
-    names = {"fuse": dk.OPT_FUSE_PW, "overlap": dk.OPT_OVERLAP, "lds": dk.OPT_DFT_LDS}
+    names = {"fuse": dk.OPT_FUSE_PW, "overlap": dk.OPT_OVERLAP, "lds": dk.OPT_DFT_LDS,
+             "lanes": dk.OPT_BATCH_LANES}
     for k, v in opts.items():
         ctx.set_option(names[k], v)
     for alen, blen in [(8192, 8192), (30000, 4000), (131072, 131072)]:
