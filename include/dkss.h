@@ -338,8 +338,19 @@ const char* dkss_kernel_name(int kind);
  *                        back to the caller's stream with events, and a captured batch graph
  *                        holds them as parallel branches.  Without them (no planning call yet)
  *                        the groups run on the caller's stream.
+ *  DKSS_OPT_STEP6_KS     1: the componentwise products in R (Step 6) as Sec. 3.2.6 writes them:
+ *                        each element packed into one integer by Kronecker-Schoenhage
+ *                        substitution (slots of 2 bits(q) + log2 m bits), the 2M integer
+ *                        products of a polynomial pair computed by the library itself under the
+ *                        context's policy (the schoolbook base case, or DKSS, whose own Step 6
+ *                        recurses the same way), the slots unpacked, alpha^m = -1 folded and
+ *                        reduced mod q.  Exact like the default (direct negacyclic products) and
+ *                        much slower; dkss_workspace_bytes and dkss_batch_workspace_bytes grow
+ *                        by the packed integers and the inner products' workspace, and the
+ *                        planning calls also build the inner products' tables.  0 (default).
  */
-enum { DKSS_OPT_OVERLAP = 0, DKSS_OPT_DFT_LDS = 1, DKSS_OPT_FUSE_PW = 2, DKSS_OPT_BATCH_LANES = 3 };
+enum { DKSS_OPT_OVERLAP = 0, DKSS_OPT_DFT_LDS = 1, DKSS_OPT_FUSE_PW = 2, DKSS_OPT_BATCH_LANES = 3,
+       DKSS_OPT_STEP6_KS = 4 };
 int dkss_set_option(dkss_ctx* ctx, int option, long long value);
 
 /*

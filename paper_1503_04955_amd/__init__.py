@@ -180,7 +180,7 @@ CAND_SCHOOLBOOK = NCAND
 MLP_NPARAM = MLP_HID * MLP_IN + MLP_HID + MLP_HID * MLP_HID + MLP_HID + MLP_OUT * MLP_HID + MLP_OUT
 TUNING_DIR = os.path.join(_HERE, "tuning")
 
-OPT_OVERLAP, OPT_DFT_LDS, OPT_FUSE_PW, OPT_BATCH_LANES = 0, 1, 2, 3
+OPT_OVERLAP, OPT_DFT_LDS, OPT_FUSE_PW, OPT_BATCH_LANES, OPT_STEP6_KS = 0, 1, 2, 3, 4
 
 
 def _check(rc, what):

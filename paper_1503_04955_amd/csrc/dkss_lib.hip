@@ -648,6 +648,107 @@ __global__ __launch_bounds__(kThreads) void k_pointwise(uint32_t* A0, const uint
 }
 
 // ---------------------------------------------------------------------------------------------
+// Step 6 as the thesis writes it (Sec. 3.2.6): a product in R by Kronecker-Schoenhage
+// substitution, the integer products by the library's own multiplication (recursively DKSS
+// above the base-case cutoff)
+// ---------------------------------------------------------------------------------------------
+
+// Element p of each of the group's polynomials (m coefficients of L limbs, canonical) becomes
+// the integer X_p = sum_j a_j 2^(slot j) of wks limbs; slot = 2 bits(q) + ceil(log2 m) holds any
+// coefficient of the product polynomial (a sum of m products below q^2).  Since slot exceeds
+// bits(q) + 32, a 32-bit window meets at most one coefficient.  One thread per limb.
+template <int L>
+__global__ __launch_bounds__(kThreads) void k_ks_pack(uint32_t* __restrict__ X, const uint32_t* __restrict__ A0,
+                                                      long long stride, long long count, int log2m, int slot,
+                                                      int wks) {
+    const long long t = (long long)blockIdx.x * kThreads + threadIdx.x;
+    if (t >= count * wks) return;
+    const size_t y = blockIdx.y;
+    const long long p = t / wks;
+    const int w = (int)(t - p * wks);
+    const int m = 1 << log2m;
+    const uint32_t* A = A0 + y * stride + ((size_t)p << log2m) * L;
+    const long long bit0 = 32LL * w;
+    const int j = (int)(bit0 / slot);
+    uint32_t v = 0;
+    for (int jj = j; jj <= j + 1 && jj < m; ++jj) {
+        const long long off = bit0 - (long long)slot * jj;     // bit of a_jj at the window's bit 0
+        if (off >= 32 * L || off <= -32) continue;
+        const uint32_t* cf = A + (size_t)jj * L;
+        if (off >= 0) {
+            const int q = (int)(off >> 5), b = (int)(off & 31);
+            const uint32_t lo = cf[q];
+            const uint32_t hi = q + 1 < L ? cf[q + 1] : 0u;
+            v |= b ? (lo >> b) | (hi << (32 - b)) : lo;
+        } else {
+            v |= cf[0] << (int)(-off);
+        }
+    }
+    X[y * (size_t)count * wks + t] = v;
+}
+
+// Coefficient j of element p: slots j and j + m of Z_p (the product X_p Y_p, 2 wks limbs) are
+// the sums of the product polynomial's coefficients j and j + m, below m q^2 <= 64 q^2; each is
+// reduced by Montgomery's method from its 28-bit digits, then c_j = (s_j - s_(j+m)) (2M)^-1
+// (alpha^m = -1), written as limbs.  One thread per coefficient.
+template <int L>
+__global__ __launch_bounds__(kThreads) void k_ks_unpack(uint32_t* A0, long long stride,
+                                                        const uint32_t* __restrict__ Z0, long long count,
+                                                        int log2m, int slot, int wks, QConst Q) {
+    using G = Dig<L>;
+    constexpr int D = G::D;
+    const long long t = (long long)blockIdx.x * kThreads + threadIdx.x;
+    const int m = 1 << log2m;
+    if (t >= (count << log2m)) return;
+    const size_t y = blockIdx.y;
+    const long long p = t >> log2m;
+    const int j = (int)(t & (m - 1));
+    const uint32_t* Z = Z0 + (y * (size_t)count + p) * 2 * wks;
+    const int zw = 2 * wks;
+    auto reduce_slot = [&](int i, uint32_t* r) {
+        uint64_t col[G::NC];
+#pragma unroll
+        for (int k = 0; k < G::NC; ++k) {
+            const long long bit = (long long)slot * i + 28LL * k;
+            uint32_t d = 0;
+            if (28 * k < slot) {
+                const long long q = bit >> 5;
+                const int b = (int)(bit & 31);
+                const uint32_t lo = q < zw ? Z[q] : 0u;
+                const uint32_t hi = q + 1 < zw ? Z[q + 1] : 0u;
+                d = (uint32_t)((((uint64_t)hi << 32) | lo) >> b) & kMask28;
+                const int nb = slot - 28 * k;           // the slot's bits left
+                if (nb < 28) d &= (1u << nb) - 1u;
+            }
+            col[k] = d;
+        }
+        redc_cols<L>(col, Q, r);
+    };
+    uint32_t r1[D], r2[D], c[D], out[D], lo[L];
+    reduce_slot(j, r1);
+    if (j + m < 2 * m - 1) {
+        reduce_slot(j + m, r2);
+    } else {
+#pragma unroll
+        for (int k = 0; k < D; ++k) r2[k] = 0;
+    }
+    dmod_sub<L>(c, r1, r2, Q);                     // (a*b)_j 2^-28K
+    mont_scalar<L>(c, Q.kpw, Q, out);              // * (2M)^-1 2^28K
+    digits_to_limbs<L>(out, lo);
+    uint32_t* dst = A0 + y * stride + (((size_t)p << log2m) + j) * L;
+#pragma unroll
+    for (int k = 0; k < L; ++k) dst[k] = lo[k];
+}
+
+// descriptors of the integer products Z_i = X_i Y_i (Y = X for a squaring)
+__global__ void k_ks_descs(ProdDesc* __restrict__ d, uint32_t* Z, const uint32_t* X, const uint32_t* Y,
+                           long long n, int wks, int u) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    d[i] = ProdDesc{Z + (size_t)i * 2 * wks, X + (size_t)i * wks, Y + (size_t)i * wks, wks, wks, u, 0};
+}
+
+// ---------------------------------------------------------------------------------------------
 // Table of rho^s, s < mu_top, Montgomery form: entry s = the m coefficients of rho^s as digit
 // residues.  One launch computes table[dst + j] = table[src + j] * table[mul], j < cnt.
 // ---------------------------------------------------------------------------------------------
@@ -1310,6 +1411,10 @@ struct Call {
     bool fuse_pw = true;              // componentwise products fused into the bottom level
     hipStream_t aux = nullptr;        // second stream for the transform of b
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    // Step 6 by Kronecker-Schoenhage (DKSS_OPT_STEP6_KS): slot bits, limbs per packed integer
+    // and the plan of the integer products (recursively with its own Step 6)
+    int ks_slot = 0, ks_wks = 0;
+    std::shared_ptr<Call> ks_inner;
 };
 
 int dig_D(int L) { return (32 * L + 28) / 28; }
@@ -1351,6 +1456,7 @@ struct dkss_ctx {
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     // batches: groups spread over batch_lanes streams (the caller's and lane_s[0 .. lanes-2],
     // made by planning calls or the option), forked and joined with lane_ev
+    bool step6_ks = false;              // Step 6 by Kronecker-Schoenhage substitution
     int batch_lanes = 4;
     int lanes_made = 1;                 // streams available: 1 + the internal ones made so far
     hipStream_t lane_s[kMaxLanes - 1] = {};
@@ -1724,6 +1830,7 @@ struct Workspace {
     unsigned char* seg_gp;
     unsigned char* seg_cin;
     uint32_t* tab;                     // room for the tuple's table (tab_bytes of layout), or NULL
+    char* ks;                          // Step 6 by Kronecker-Schoenhage: its region, or NULL
     size_t wst, sst;
     size_t bytes;
 };
@@ -1756,8 +1863,38 @@ Workspace layout(const Plan& P, size_t G, size_t nw_max, bool need_b, char* base
     off += align256(G * nseg);
     w.tab = tab_bytes ? (uint32_t*)(base + off) : nullptr;
     off += align256(tab_bytes);
+    w.ks = nullptr;
     w.bytes = off;
     return w;
+}
+
+// Bytes of the Kronecker-Schoenhage region of G products of call's plan: the packed factors
+// (2M G integers of wks limbs each, twice), their products (2 wks limbs), the descriptors, and
+// the integer products' own workspace (groups of at most 65535, one after another), with room
+// for their table and, recursively, their own Step 6.
+size_t ks_bytes(const Call& c, size_t G);
+
+// layout() for a product run under call, with the Kronecker-Schoenhage region appended
+Workspace layout_call(const Call& call, size_t G, size_t nw_max, bool need_b, char* base, size_t tab_bytes = 0) {
+    Workspace w = layout(call.P, G, nw_max, need_b, base, tab_bytes);
+    if (call.ks_inner) {
+        w.ks = base ? base + w.bytes : nullptr;
+        w.bytes += ks_bytes(call, G);
+    }
+    return w;
+}
+
+size_t ks_bytes(const Call& c, size_t G) {
+    if (!c.ks_inner) return 0;
+    const Call& in = *c.ks_inner;
+    const size_t cnt = ((size_t)2 << c.P.log2_M) * G;
+    const size_t wks = (size_t)c.ks_wks;
+    size_t b = 2 * align256(cnt * wks * 4) + align256(cnt * 2 * wks * 4) + align256(cnt * sizeof(ProdDesc));
+    if (!in.schoolbook) {
+        const size_t Gi = std::min<size_t>(cnt, 65535);
+        b += layout_call(in, Gi, 2 * wks, true, nullptr, in.C->table_bytes()).bytes;
+    }
+    return b;
 }
 
 template <int L>
@@ -2023,7 +2160,95 @@ int prepare_call(dkss_ctx* ctx, size_t alen, size_t blen, const dkss_params* p, 
     int rc = resolve_params(ctx, alen, blen, p, call, choice, batch);
     if (rc) return rc;
     if (alen == 0 || blen == 0 || call->schoolbook) return DKSS_OK;
-    return plan_constants(ctx, call);
+    if ((rc = plan_constants(ctx, call))) return rc;
+    if (ctx->step6_ks) {
+        // the packed integers and their products' plan (the policy's, without a tuple of the
+        // caller's: that belongs to the outer product)
+        const int m = call->P.m();
+        call->ks_slot = 2 * call->P.q_bits + call->P.log2_m;
+        call->ks_wks = (int)(((long long)m * call->ks_slot + 31) / 32);
+        call->ks_inner = std::make_shared<Call>();
+        const size_t cnt = (size_t)2 << call->P.log2_M;
+        rc = prepare_call(ctx, (size_t)call->ks_wks, (size_t)call->ks_wks, nullptr, call->ks_inner.get(),
+                          (uint32_t)std::min<size_t>(cnt, UINT32_MAX), infer);
+        if (rc) return rc;
+    }
+    return DKSS_OK;
+}
+
+int run_group(const Call& call, const ProdArgs& PA, unsigned G, size_t nw_max, double in_a, double in_b,
+              double out_w, bool squaring, const Workspace& w, hipStream_t s, int u_min);
+int launch_schoolbook(const Call& call, const ProdArgs& PA, unsigned G, size_t nw_max, double ops,
+                      hipStream_t s);
+
+template <int L>
+struct KsPack {
+    static int run(const Call& c, uint32_t* X, const uint32_t* A, size_t stride, unsigned G, hipStream_t s) {
+        const long long count = 2LL << c.P.log2_M;
+        const long long total = count * c.ks_wks;
+        if (!grid_ok((size_t)((total + kThreads - 1) / kThreads))) return DKSS_ERANGE;
+        hipLaunchKernelGGL(k_ks_pack<L>, dim3((unsigned)((total + kThreads - 1) / kThreads), G), dim3(kThreads), 0, s,
+                           X, A, (long long)stride, count, c.P.log2_m, c.ks_slot, c.ks_wks);
+        return launch_status();
+    }
+};
+
+template <int L>
+struct KsUnpack {
+    static int run(const Call& c, uint32_t* A, const uint32_t* Z, size_t stride, unsigned G, hipStream_t s) {
+        const long long count = 2LL << c.P.log2_M;
+        const long long total = count << c.P.log2_m;
+        if (!grid_ok((size_t)((total + kThreads - 1) / kThreads))) return DKSS_ERANGE;
+        hipLaunchKernelGGL(k_ks_unpack<L>, dim3((unsigned)((total + kThreads - 1) / kThreads), G), dim3(kThreads), 0,
+                           s, A, (long long)stride, Z, count, c.P.log2_m, c.ks_slot, c.ks_wks, c.C->Q);
+        return launch_status();
+    }
+};
+
+// Step 6 by Kronecker-Schoenhage substitution (Sec. 3.2.6) for G products: pack every element
+// of A and B into integers, multiply them pairwise with the library's own multiplication under
+// the inner plan (the schoolbook base case or DKSS, whose Step 6 recurses the same way), unpack,
+// fold alpha^m = -1 and reduce mod q, scaled by (2M)^-1, into A.  B == nullptr: a squaring.
+int ks_pointwise(const Call& c, uint32_t* A, const uint32_t* B, size_t stride, unsigned G, char* ks, hipStream_t s) {
+    const Call& in = *c.ks_inner;
+    const size_t cnt = ((size_t)2 << c.P.log2_M) * G;
+    const size_t wks = (size_t)c.ks_wks;
+    uint32_t* X = (uint32_t*)ks;
+    uint32_t* Y = (uint32_t*)(ks + align256(cnt * wks * 4));
+    uint32_t* Z = (uint32_t*)(ks + 2 * align256(cnt * wks * 4));
+    ProdDesc* d = (ProdDesc*)(ks + 2 * align256(cnt * wks * 4) + align256(cnt * 2 * wks * 4));
+    char* iws = (char*)d + align256(cnt * sizeof(ProdDesc));
+    int rc;
+    if ((rc = dispatch_L<KsPack>(c.P.L, c, X, A, stride, G, s))) return rc;
+    if (B && (rc = dispatch_L<KsPack>(c.P.L, c, Y, B, stride, G, s))) return rc;
+    hipLaunchKernelGGL(k_ks_descs, dim3((unsigned)((cnt + kThreads - 1) / kThreads)), dim3(kThreads), 0, s, d, Z, X,
+                       B ? (const uint32_t*)Y : (const uint32_t*)X, (long long)cnt, (int)wks, in.P.u);
+    if ((rc = launch_status())) return rc;
+    Call ic = in;
+    ic.prof = c.prof;
+    ic.aux = nullptr;
+    if (!ic.schoolbook) {
+        const size_t Gmax = std::min<size_t>(cnt, 65535);
+        Workspace iw = layout_call(ic, Gmax, 2 * wks, true, iws, ic.C->table_bytes());
+        ic.table = ic.C->table_ready ? ic.C->d_table : iw.tab;
+        if (!ic.C->table_ready && (rc = dispatch_L<TableBuild>(ic.P.L, ic.C, iw.tab, c.prof, s))) return rc;
+        for (size_t g0 = 0; g0 < cnt; g0 += 65535) {
+            const unsigned Gi = (unsigned)std::min<size_t>(65535, cnt - g0);
+            ProdArgs PA{};
+            PA.many = d + g0;
+            rc = run_group(ic, PA, Gi, 2 * wks, (double)Gi * wks, (double)Gi * wks, (double)Gi * 2 * wks, !B,
+                           iw, s, ic.P.u);
+            if (rc) return rc;
+        }
+    } else {
+        for (size_t g0 = 0; g0 < cnt; g0 += 65535) {
+            const unsigned Gi = (unsigned)std::min<size_t>(65535, cnt - g0);
+            ProdArgs PA{};
+            PA.many = d + g0;
+            if ((rc = launch_schoolbook(ic, PA, Gi, 2 * wks, (double)Gi * wks * wks, s))) return rc;
+        }
+    }
+    return dispatch_L<KsUnpack>(c.P.L, c, A, Z, stride, G, s);
 }
 
 // The DKSS pipeline (Steps 4-8) for G products sharing call's plan, described by PA; the
@@ -2045,7 +2270,7 @@ int run_group(const Call& call, const ProdArgs& PA, unsigned G, size_t nw_max, d
     // the componentwise products run inside the bottom level of a's transform (one launch for
     // the last forward level, the products and the first inverse level) unless b is still being
     // transformed on the other stream
-    const int fz = (call.fuse_pw && !fork) ? 1 : 0;
+    const int fz = (call.fuse_pw && !fork && !call.ks_inner) ? 1 : 0;
     const uint32_t* bp = squaring ? (const uint32_t*)w.A : w.B;
     if ((rc = dispatch_L<Transform>(L, call, w.A, w.S, G, 0, s, fz, squaring ? nullptr : bp,
                                     squaring ? 1 : 0, &PA, 0, in_a)))
@@ -2054,7 +2279,11 @@ int run_group(const Call& call, const ProdArgs& PA, unsigned G, size_t nw_max, d
         HIP_OK(hipEventRecord(call.ev_join, sb));
         HIP_OK(hipStreamWaitEvent(s, call.ev_join, 0));
     }
-    if (!fz && (rc = dispatch_L<Pointwise>(L, call, w.A, bp, w.S, G, s))) return rc;
+    if (call.ks_inner) {
+        if ((rc = ks_pointwise(call, w.A, squaring ? nullptr : bp, w.S, G, w.ks, s))) return rc;
+    } else if (!fz && (rc = dispatch_L<Pointwise>(L, call, w.A, bp, w.S, G, s))) {
+        return rc;
+    }
     if ((rc = dispatch_L<Transform>(L, call, w.A, w.S, G, 1, s, fz))) return rc;
     return dispatch_L<Decode>(L, call, PA, G, nw_max, out_w, w, s, u_min);
 }
@@ -2096,7 +2325,7 @@ int run_mul(Call call, uint32_t* c, const uint32_t* a, size_t alen, const uint32
     if (call.schoolbook) return launch_schoolbook(call, PA, 1, nw, (double)alen * (double)blen, s);
     const bool squaring = (a == b && alen == blen);
     if (ws == nullptr || ((uintptr_t)ws & 255)) return DKSS_EINVAL;
-    Workspace w = layout(call.P, 1, nw, !squaring, (char*)ws, call.C->table_ready ? 0 : call.C->table_bytes());
+    Workspace w = layout_call(call, 1, nw, !squaring, (char*)ws, call.C->table_ready ? 0 : call.C->table_bytes());
     if (ws_bytes < w.bytes) return DKSS_ENOSPC;
     int rc = use_table(&call, w, s);
     if (rc) return rc;
@@ -2179,7 +2408,7 @@ int plan_batch(dkss_ctx* ctx, size_t count, const size_t* alen, const size_t* bl
             }
             gws.push_back(0);
             if (g.kind == 2) {
-                gws.back() = layout(g.call.P, g.count, g.nw_max, true, nullptr).bytes;
+                gws.back() = layout_call(g.call, g.count, g.nw_max, true, nullptr).bytes;
                 bool seen = false;
                 for (const auto& t : B->tabs) seen = seen || t.first == g.call.C;
                 if (!seen) {
@@ -2283,6 +2512,9 @@ int dkss_set_option(dkss_ctx* ctx, int option, long long value) {
             return DKSS_OK;
         case DKSS_OPT_FUSE_PW:
             ctx->fuse_pw = value != 0;
+            return DKSS_OK;
+        case DKSS_OPT_STEP6_KS:
+            ctx->step6_ks = value != 0;
             return DKSS_OK;
         case DKSS_OPT_BATCH_LANES:
             if (value < 1 || value > kMaxLanes) return DKSS_EINVAL;
@@ -2542,7 +2774,16 @@ int dkss_workspace_bytes(dkss_ctx* ctx, size_t alen, size_t blen, const dkss_par
     }
     // room for the table too: a product whose tuple the context has not prepared builds its
     // table in the workspace
-    *out = layout(call.P, 1, alen + blen, true, nullptr, call.C->table_bytes()).bytes;
+    *out = layout_call(call, 1, alen + blen, true, nullptr, call.C->table_bytes()).bytes;
+    return DKSS_OK;
+}
+
+// the tables of the integer products of a Kronecker-Schoenhage Step 6, level by level
+static int ensure_inner_tables(const Call& c, Prof* prof, hipStream_t s) {
+    for (const Call* in = c.ks_inner.get(); in && !in->schoolbook && in->C; in = in->ks_inner.get()) {
+        const int rc = ensure_table(in->C, prof, s);
+        if (rc) return rc;
+    }
     return DKSS_OK;
 }
 
@@ -2553,7 +2794,8 @@ int dkss_prepare(dkss_ctx* ctx, size_t alen, size_t blen, const dkss_params* p, 
     int rc = prepare_call(ctx, alen, blen, p, &call, 1, true);
     if (rc) return rc;
     if (!call.C) return DKSS_OK;
-    return ensure_table(call.C, &ctx->prof, (hipStream_t)s);
+    if ((rc = ensure_table(call.C, &ctx->prof, (hipStream_t)s))) return rc;
+    return ensure_inner_tables(call, &ctx->prof, (hipStream_t)s);
 }
 
 // The product path of dkss_mul on a workspace (also the allocation-free entry point's).
@@ -2644,6 +2886,8 @@ int dkss_batch_prepare(dkss_ctx* ctx, size_t count, const size_t* alen, const si
     if ((rc = ensure_lanes(ctx))) return rc;
     for (const auto& t : B.tabs)
         if ((rc = ensure_table(t.first, &ctx->prof, (hipStream_t)s))) return rc;
+    for (const auto& g : B.groups)
+        if (g.kind == 2 && (rc = ensure_inner_tables(g.call, &ctx->prof, (hipStream_t)s))) return rc;
     return DKSS_OK;
 }
 
@@ -2707,7 +2951,7 @@ static int enqueue_batch(const dkss_ctx* ctx, const BatchPlan& B, void* ws, Prof
         } else if (g.kind == 1) {
             rc = launch_schoolbook(call, PA, G, g.nw_max, g.ops, gst);
         } else {
-            Workspace w = layout(call.P, G, g.nw_max, true, lws);
+            Workspace w = layout_call(call, G, g.nw_max, true, lws);
             rc = run_group(call, PA, G, g.nw_max, g.in_a, g.in_b, g.out_w, false, w, gst, g.u_min);
         }
         rc_all = rc;
@@ -2776,6 +3020,8 @@ int dkss_batch_graph_create(dkss_ctx* ctx, size_t count, uint32_t* const* c, con
     // tables and descriptors are written once, before the capture; the graph holds the
     // products' kernels only
     for (size_t k = 0; !rc && k < B.tabs.size(); ++k) rc = ensure_table(B.tabs[k].first, nullptr, cs);
+    for (size_t k = 0; !rc && k < B.groups.size(); ++k)
+        if (B.groups[k].kind == 2) rc = ensure_inner_tables(B.groups[k].call, nullptr, cs);
     if (!rc) rc = put_descs(B, count, c, a, alen, b, blen, (ProdDesc*)ws, cs);
     if (!rc) rc = note_hip(hipStreamSynchronize(cs));
     if (!rc) {

@@ -597,3 +597,30 @@ def test_mul_2e34_thesis_learned_and_square(env):
         del ws
         torch.cuda.empty_cache()
     assert torch.equal(outs["thesis"], outs["learned"])
+
+
+@pytest.mark.parametrize("policy", ["thesis", "learned"])
+def test_step6_by_kronecker_schoenhage(env, policy):
+    """Step 6 as Sec. 3.2.6 writes it (DKSS_OPT_STEP6_KS): products in R by Kronecker-Schoenhage
+    substitution, the integer products by the library itself (DKSS again above the base-case
+    cutoff): the same products as the direct path and the oracle's schoolbook, single, squared
+    and batched."""
+    dk, torch, ctx0 = env
+    ctx = dk.Context(dk.POLICY_THESIS if policy == "thesis" else dk.POLICY_LEARNED)
+    ctx.set_option(dk.OPT_STEP6_KS, 1)
+    for alen, blen in [(100, 70), (8192, 8192), (30000, 4000), (1 << 19, 1 << 19)]:
+        a, b = SI.operand_pair(SI.SEED_BASE + 600 + alen, alen, blen)
+        da, db = dk.to_device(a), dk.to_device(b)
+        print("ks case", policy, alen, blen, ctx.select_params(32 * alen, 32 * blen).as_dict(), flush=True)
+        got = ctx.mul(da, db)
+        want = ctx0.mul(da, db)
+        assert torch.equal(got, want), (alen, blen)
+        if alen * blen < 1e9:
+            assert np.array_equal(dk.to_host(got), C.schoolbook(a, b))
+        assert torch.equal(ctx.mul(da, da), ctx0.mul(da, da)), alen
+    lens = SI.batch_lengths(SI.SEED_BASE + 601, 48, hi_bits=18)
+    pairs = [SI.operand_pair(900 + i, al, bl) for i, (al, bl) in enumerate(lens)]
+    as_ = [dk.to_device(x) for x, _ in pairs]
+    bs = [dk.to_device(y) for _, y in pairs]
+    for (x, y), got in zip(pairs, ctx.mul_batch(as_, bs)):
+        assert np.array_equal(dk.to_host(got), C.schoolbook(x, y))
