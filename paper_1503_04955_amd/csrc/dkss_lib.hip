@@ -37,6 +37,7 @@
 #include "hip_status.hpp"
 #include "kernels.hpp"
 #include "planner.hpp"
+#include "wave_carry.hpp"
 
 using namespace dkss;
 
@@ -53,7 +54,21 @@ namespace {
 constexpr int kThreads = 256;
 
 constexpr uint64_t kDefaultCutoffBits = 2048;
-constexpr size_t kSchoolbookMaxWords = 4096;   // alen + blen of the base case
+constexpr size_t kSchoolbookMaxWords = 4096;   // alen + blen of a schoolbook product (one workgroup)
+constexpr int kMaxKaraDepth = 2;                // Karatsuba levels above the schoolbook leaves
+
+// Karatsuba levels the base case needs for alen x blen limbs so that every leaf fits the
+// schoolbook (0: none), or -1 beyond kMaxKaraDepth levels.  A level's largest sub-product is
+// (h + 1) x (h + 1), h = ceil(max / 2).
+inline int kara_depth(size_t alen, size_t blen) {
+    size_t na = alen, nb = blen;
+    for (int d = 0; d <= kMaxKaraDepth; ++d) {
+        if (na + nb <= kSchoolbookMaxWords) return d;
+        const size_t h = (std::max(na, nb) + 1) / 2;
+        na = nb = h + 1;
+    }
+    return -1;
+}
 
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -1163,18 +1178,37 @@ __global__ __launch_bounds__(kThreads) void k_schoolbook(ProdArgs PA) {
     for (long long i = threadIdx.x; i < blen; i += kThreads) B[i] = pd.b[i];
     __syncthreads();
     for (long long w = threadIdx.x; w < n; w += kThreads) {
-        uint64_t acc = 0;
-        uint32_t top = 0;
+        // four independent partial sums (terms i = i0 + 4 k + r), so that consecutive
+        // multiply-adds do not wait on each other's accumulator
+        uint64_t acc[4] = {0, 0, 0, 0};
+        uint32_t top[4] = {0, 0, 0, 0};
         const long long i0 = w - blen + 1 > 0 ? w - blen + 1 : 0;
         const long long i1 = w < alen - 1 ? w : alen - 1;
-        for (long long i = i0; i <= i1; ++i) {
-            const uint64_t s2 = (uint64_t)A[i] * B[w - i] + acc;
-            top += s2 < acc;
-            acc = s2;
+        long long i = i0;
+        for (; i + 3 <= i1; i += 4) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const uint64_t s2 = (uint64_t)A[i + r] * B[w - i - r] + acc[r];
+                top[r] += s2 < acc[r];
+                acc[r] = s2;
+            }
         }
-        col[3 * w] = (uint32_t)acc;
-        col[3 * w + 1] = (uint32_t)(acc >> 32);
-        col[3 * w + 2] = top;
+        for (int r = 0; i <= i1; ++i, ++r) {
+            const uint64_t s2 = (uint64_t)A[i] * B[w - i] + acc[r];
+            top[r] += s2 < acc[r];
+            acc[r] = s2;
+        }
+        uint64_t sum = acc[0];
+        uint32_t t = top[0];
+#pragma unroll
+        for (int r = 1; r < 4; ++r) {
+            const uint64_t s2 = sum + acc[r];
+            t += top[r] + (s2 < sum);
+            sum = s2;
+        }
+        col[3 * w] = (uint32_t)sum;
+        col[3 * w + 1] = (uint32_t)(sum >> 32);
+        col[3 * w + 2] = t;
     }
     __syncthreads();
     // carries: chunk t covers words [t K, min(n, (t+1) K))
@@ -1197,6 +1231,110 @@ __global__ __launch_bounds__(kThreads) void k_schoolbook(ProdArgs PA) {
     }
     const uint32_t cin = threadIdx.x ? fn[threadIdx.x - 1] & 3 : 0;
     chunk_carry(col, w0, w1, cin, pd.c);
+}
+
+// ---------------------------------------------------------------------------------------------
+// Base case above the schoolbook's size: Karatsuba levels (Sec. 2.4) over schoolbook leaves
+// ---------------------------------------------------------------------------------------------
+// A product of a (na limbs) and b (nb limbs), n = max(na, nb), h = ceil(n / 2), a = a0 + a1 B^h,
+// b = b0 + b1 B^h (B = 2^32; a0 = a's low min(h, na) limbs, a1 the rest, possibly empty):
+// a b = P0 + (P1 - P0 - P2) B^h + P2 B^2h with P0 = a0 b0, P2 = a1 b1 and
+// P1 = (a0 + a1)(b0 + b1).  One level's kernels: k_kara_eval writes a0 + a1 and b0 + b1 (h + 1
+// limbs) into the product's slot and the three sub-products' descriptors; the sub-products run as
+// a batch (the schoolbook, or another Karatsuba level); k_kara_combine assembles c.  One wavefront
+// per product; carries cross a row of 64 limbs by mask addition (wave_carry.hpp).
+
+// limbs of one level's slot for a product with half size h: a0 + a1, b0 + b1, P0, P2, P1
+__host__ __device__ inline long long kara_slot_words(long long h) { return 8 * h + 8; }
+
+__global__ __launch_bounds__(64) void k_kara_eval(ProdArgs PA, ProdDesc* __restrict__ child,
+                                                  uint32_t* __restrict__ scratch, long long stride) {
+    const ProdDesc pd = PA.get();
+    const size_t y = blockIdx.y;
+    const long long na = pd.alen, nb = pd.blen;
+    const long long n = na > nb ? na : nb;
+    const long long h = (n + 1) / 2;
+    uint32_t* SA = scratch + y * stride;
+    uint32_t* SB = SA + (h + 1);
+    uint32_t* P0 = SB + (h + 1);
+    uint32_t* P2 = P0 + 2 * h;
+    uint32_t* P1 = P2 + 2 * h;
+    const int l = wave_lane();
+    // x0 + x1 for both operands, h limbs each plus the carry out as limb h
+    for (int op = 0; op < 2; ++op) {
+        const uint32_t* x = op ? pd.b : pd.a;
+        const long long nx = op ? nb : na;
+        uint32_t* S = op ? SB : SA;
+        uint32_t c = 0;
+        for (long long w0 = 0; w0 < h; w0 += 64) {
+            const long long w = w0 + l;
+            const uint32_t u = w < h && w < nx ? x[w] : 0u;
+            const uint32_t v = w < h && h + w < nx ? x[h + w] : 0u;
+            uint32_t t = u + v;
+            const unsigned long long G = __ballot(t < u);
+            // lanes past the last limb pass a carry on, so that it leaves the row's top lane
+            const unsigned long long P = __ballot(w >= h || t == 0xFFFFFFFFu);
+            t += lane_bit(row_carries(G, P, c, &c));
+            if (w < h) S[w] = t;
+        }
+        if (l == 0) S[h] = c;
+    }
+    if (l == 0) {
+        const long long a0 = na < h ? na : h, b0 = nb < h ? nb : h;
+        const long long a1 = na > h ? na - h : 0, b1 = nb > h ? nb - h : 0;
+        child[3 * y + 0] = ProdDesc{P0, pd.a, pd.b, a0, b0, 0, 0};
+        child[3 * y + 1] = ProdDesc{P2, pd.a + h, pd.b + h, a1, b1, 0, 0};
+        child[3 * y + 2] = ProdDesc{P1, SA, SB, h + 1, h + 1, 0, 0};
+    }
+}
+
+__global__ __launch_bounds__(64) void k_kara_combine(ProdArgs PA, const ProdDesc* __restrict__ child) {
+    const ProdDesc pd = PA.get();
+    const size_t y = blockIdx.y;
+    const long long nc = pd.alen + pd.blen;
+    const long long na = pd.alen, nb = pd.blen;
+    const long long n = na > nb ? na : nb;
+    const long long h = (n + 1) / 2;
+    const ProdDesc d0 = child[3 * y], d2 = child[3 * y + 1], d1 = child[3 * y + 2];
+    const long long l0 = d0.alen + d0.blen, l2 = d2.alen + d2.blen, l1 = d1.alen + d1.blen;
+    uint32_t* P0 = d0.c;
+    uint32_t* P2 = d2.c;
+    uint32_t* P1 = d1.c;
+    uint32_t* c = pd.c;
+    const int l = wave_lane();
+    // T = P1 - P0 - P2 >= 0, in place of P1 (two subtractions with borrows)
+    for (int pass = 0; pass < 2; ++pass) {
+        const uint32_t* Q = pass ? P2 : P0;
+        const long long lq = pass ? l2 : l0;
+        uint32_t bo = 0;
+        for (long long w0 = 0; w0 < l1; w0 += 64) {
+            const long long w = w0 + l;
+            const uint32_t x = w < l1 ? P1[w] : 0u;
+            const uint32_t v = w < lq ? Q[w] : 0u;
+            uint32_t d = x - v;
+            const unsigned long long G = __ballot(x < v);
+            const unsigned long long P = __ballot(w < l1 && d == 0u);
+            d -= lane_bit(row_carries(G, P, bo, &bo));
+            if (w < l1) P1[w] = d;
+        }
+    }
+    // c = P0 + P2 B^2h (disjoint) + T B^h; the words above c's length are zero
+    uint32_t cy = 0;
+    for (long long w0 = 0; w0 < nc; w0 += 64) {
+        const long long w = w0 + l;
+        uint32_t base = 0;
+        if (w < 2 * h) {
+            base = w < l0 ? P0[w] : 0u;
+        } else if (w - 2 * h < l2) {
+            base = P2[w - 2 * h];
+        }
+        const uint32_t t = w >= h && w - h < l1 ? P1[w - h] : 0u;
+        uint32_t s = base + t;
+        const unsigned long long G = __ballot(w < nc && s < base);
+        const unsigned long long P = __ballot(w < nc && s == 0xFFFFFFFFu);
+        s += lane_bit(row_carries(G, P, cy, &cy));
+        if (w < nc) c[w] = s;
+    }
 }
 
 // Batch descriptors [first, first + count) from the launch's arguments (count <= kDescPerPut):
@@ -1402,6 +1540,7 @@ struct Cached {
 struct Call {
     Plan P;                    // parameters + radices
     bool schoolbook = false;
+    int kara = 0;                     // Karatsuba levels of a base-case product
     size_t alen = 0, blen = 0;
     Cached* C = nullptr;
     const uint32_t* table = nullptr;  // the rho^s table the call's levels read
@@ -1519,7 +1658,7 @@ bool policy_tuple(const dkss_ctx* ctx, uint64_t N, uint32_t batch, int* lM, int*
 
 // Can the selector's output c run a product of alen x blen limbs?
 bool learned_feasible(size_t alen, size_t blen, int c) {
-    if (c == DKSS_CAND_SCHOOLBOOK) return alen + blen <= kSchoolbookMaxWords;
+    if (c == DKSS_CAND_SCHOOLBOOK) return kara_depth(alen, blen) >= 0;
     int lM, lm, u, pb;
     const uint64_t N = 32ull * std::max(alen, blen);
     return candidate_params(N, c, &lM, &lm, &u, &pb) && default_radices(lM, lm, (pb + 31) / 32).size() <= 8;
@@ -1655,8 +1794,10 @@ int resolve_params(dkss_ctx* ctx, size_t alen, size_t blen, const dkss_params* p
     // every operand fits: M blocks of u m/2 bits
     const unsigned __int128 cap = (unsigned __int128)(1ull << P.log2_M) * ((1u << P.log2_m) / 2) * (unsigned)P.u;
     const uint64_t minlen = 32ull * std::min(alen, blen);
-    out->schoolbook = minlen <= P.cutoff_bits && alen + blen <= kSchoolbookMaxWords;
+    out->kara = kara_depth(alen, blen);
+    out->schoolbook = minlen <= P.cutoff_bits && out->kara >= 0;
     if (out->schoolbook) return DKSS_OK;
+    out->kara = 0;
     if (cap < N) return DKSS_ERANGE;
     return DKSS_OK;
 }
@@ -2241,6 +2382,7 @@ int ks_pointwise(const Call& c, uint32_t* A, const uint32_t* B, size_t stride, u
             if (rc) return rc;
         }
     } else {
+        if (ic.kara) return DKSS_ERANGE;           // packed integers stay within the schoolbook
         for (size_t g0 = 0; g0 < cnt; g0 += 65535) {
             const unsigned Gi = (unsigned)std::min<size_t>(65535, cnt - g0);
             ProdArgs PA{};
@@ -2303,6 +2445,59 @@ int launch_schoolbook(const Call& call, const ProdArgs& PA, unsigned G, size_t n
     return launch_status();
 }
 
+// Workspace of the base case's Karatsuba levels for G products whose longer operand has at most
+// n_max limbs: per level, a slot per parent and three sub-product descriptors per parent.
+size_t kara_bytes(int depth, size_t G, size_t n_max) {
+    size_t bytes = 0, parents = G, n = n_max;
+    for (int lv = 0; lv < depth; ++lv) {
+        const size_t h = (n + 1) / 2;
+        bytes += align256(parents * (size_t)kara_slot_words((long long)h) * 4) + align256(3 * parents * sizeof(ProdDesc));
+        parents *= 3;
+        n = h + 1;
+    }
+    return bytes;
+}
+
+// The base case of G products: the schoolbook (one workgroup per product), or depth Karatsuba
+// levels (k_kara_eval level by level, the schoolbook on the 3^depth G leaves, k_kara_combine back
+// up) in ws.
+int launch_base(const Call& call, const ProdArgs& PA, unsigned G, size_t nw_max, size_t n_max, double ops,
+                char* ws, hipStream_t s) {
+    const int depth = call.kara;
+    if (depth == 0) return launch_schoolbook(call, PA, G, nw_max, ops, s);
+    if (!ws) return DKSS_ENOSPC;
+    ProdArgs lvl[kMaxKaraDepth + 1];
+    long long stride[kMaxKaraDepth];
+    size_t parents = G, n = n_max, off = 0;
+    lvl[0] = PA;
+    {
+        ProfScope ps(call.prof, DKSS_K_SCHOOLBOOK, s, 0.0, 0.0);
+        for (int lv = 0; lv < depth; ++lv) {
+            const size_t h = (n + 1) / 2;
+            stride[lv] = kara_slot_words((long long)h);
+            uint32_t* scratch = (uint32_t*)(ws + off);
+            off += align256(parents * (size_t)stride[lv] * 4);
+            ProdDesc* child = (ProdDesc*)(ws + off);
+            off += align256(3 * parents * sizeof(ProdDesc));
+            hipLaunchKernelGGL(k_kara_eval, dim3(1, (unsigned)parents), dim3(64), 0, s, lvl[lv], child, scratch,
+                               stride[lv]);
+            lvl[lv + 1] = ProdArgs{};
+            lvl[lv + 1].many = child;
+            parents *= 3;
+            n = h + 1;
+        }
+        if (int rc_ = launch_status()) return rc_;
+    }
+    int rc = launch_schoolbook(call, lvl[depth], (unsigned)parents, 2 * n, ops, s);
+    if (rc) return rc;
+    ProfScope ps(call.prof, DKSS_K_SCHOOLBOOK, s, 0.0, 0.0);
+    for (int lv = depth - 1; lv >= 0; --lv) {
+        parents /= 3;
+        hipLaunchKernelGGL(k_kara_combine, dim3(1, (unsigned)parents), dim3(64), 0, s, lvl[lv], lvl[lv + 1].many);
+    }
+    return launch_status();
+}
+
 // The table a product reads: the context's copy when a planning call has built it, else a copy
 // built on the stream into the workspace's table room (w.tab), part of this call's work.
 int use_table(Call* call, const Workspace& w, hipStream_t s) {
@@ -2322,7 +2517,13 @@ int run_mul(Call call, uint32_t* c, const uint32_t* a, size_t alen, const uint32
     PA.one = ProdDesc{c, a, b, (long long)alen, (long long)blen, call.P.u, 0};
     PA.many = nullptr;
     if (alen == 0 || blen == 0) return launch_zero(PA, 1, nw, s);
-    if (call.schoolbook) return launch_schoolbook(call, PA, 1, nw, (double)alen * (double)blen, s);
+    if (call.schoolbook) {
+        if (call.kara) {
+            if (ws == nullptr || ((uintptr_t)ws & 255)) return DKSS_EINVAL;
+            if (ws_bytes < kara_bytes(call.kara, 1, std::max(alen, blen))) return DKSS_ENOSPC;
+        }
+        return launch_base(call, PA, 1, nw, std::max(alen, blen), (double)alen * (double)blen, (char*)ws, s);
+    }
     const bool squaring = (a == b && alen == blen);
     if (ws == nullptr || ((uintptr_t)ws & 255)) return DKSS_EINVAL;
     Workspace w = layout_call(call, 1, nw, !squaring, (char*)ws, call.C->table_ready ? 0 : call.C->table_bytes());
@@ -2336,9 +2537,10 @@ int run_mul(Call call, uint32_t* c, const uint32_t* a, size_t alen, const uint32
 // per DKSS parameter tuple and level split), in the order of `order`.
 struct BatchPlan {
     struct Grp {
-        int kind;                  // 0 zero, 1 schoolbook, 2 DKSS
+        int kind;                  // 0 zero, 1 base case (schoolbook, Karatsuba levels), 2 DKSS
         size_t first, count;       // range in order
         size_t nw_max;
+        size_t n_max = 0;          // the longest operand
         int u_min = 0;             // smallest u of the group's products
         double in_a, in_b, out_w, ops;
         Call call;
@@ -2378,7 +2580,7 @@ int plan_batch(dkss_ctx* ctx, size_t count, const size_t* alen, const size_t* bl
         if (alen[i] == 0 || blen[i] == 0) {
             key = "0";
         } else if (c.schoolbook) {
-            key = "1";
+            key = "1" + std::to_string(c.kara);
         } else {
             key = "2" + c.P.key() + "_r";
             for (int r : c.P.radix_log2) key += std::to_string(r) + ".";
@@ -2389,16 +2591,21 @@ int plan_batch(dkss_ctx* ctx, size_t count, const size_t* alen, const size_t* bl
     std::vector<size_t> gws;           // workspace bytes of each group
     for (auto& kv : by_key) {
         const std::vector<size_t>& idx = kv.second;
-        for (size_t off = 0; off < idx.size(); off += kMaxGroup) {
+        // a Karatsuba group's leaves (3^depth per product) share one launch's grid
+        size_t cap = kMaxGroup;
+        if (kv.first[0] == '1')
+            for (int d = 0; d < B->calls[idx[0]].kara; ++d) cap /= 3;
+        for (size_t off = 0; off < idx.size(); off += cap) {
             BatchPlan::Grp g{};
             g.kind = kv.first[0] - '0';
             g.first = B->order.size();
-            g.count = std::min(kMaxGroup, idx.size() - off);
+            g.count = std::min(cap, idx.size() - off);
             g.call = B->calls[idx[off]];
             for (size_t k = off; k < off + g.count; ++k) {
                 const size_t i = idx[k];
                 B->order.push_back(i);
                 g.nw_max = std::max(g.nw_max, alen[i] + blen[i]);
+                g.n_max = std::max(g.n_max, std::max(alen[i], blen[i]));
                 const int ui = B->calls[i].P.u;
                 g.u_min = g.u_min ? std::min(g.u_min, ui) : ui;
                 g.in_a += (double)alen[i];
@@ -2406,7 +2613,7 @@ int plan_batch(dkss_ctx* ctx, size_t count, const size_t* alen, const size_t* bl
                 g.out_w += (double)(alen[i] + blen[i]);
                 g.ops += (double)alen[i] * (double)blen[i];
             }
-            gws.push_back(0);
+            gws.push_back(g.kind == 1 ? kara_bytes(g.call.kara, g.count, g.n_max) : 0);
             if (g.kind == 2) {
                 gws.back() = layout_call(g.call, g.count, g.nw_max, true, nullptr).bytes;
                 bool seen = false;
@@ -2769,7 +2976,7 @@ int dkss_workspace_bytes(dkss_ctx* ctx, size_t alen, size_t blen, const dkss_par
     int rc = prepare_call(ctx, alen, blen, p, &call, 1, true);
     if (rc) return rc;
     if (alen == 0 || blen == 0 || call.schoolbook) {
-        *out = 0;
+        *out = call.schoolbook ? kara_bytes(call.kara, 1, std::max(alen, blen)) : 0;
         return DKSS_OK;
     }
     // room for the table too: a product whose tuple the context has not prepared builds its
@@ -2949,7 +3156,7 @@ static int enqueue_batch(const dkss_ctx* ctx, const BatchPlan& B, void* ws, Prof
         if (g.kind == 0) {
             rc = launch_zero(PA, G, g.nw_max, gst);
         } else if (g.kind == 1) {
-            rc = launch_schoolbook(call, PA, G, g.nw_max, g.ops, gst);
+            rc = launch_base(call, PA, G, g.nw_max, g.n_max, g.ops, lws, gst);
         } else {
             Workspace w = layout_call(call, G, g.nw_max, true, lws);
             rc = run_group(call, PA, G, g.nw_max, g.in_a, g.in_b, g.out_w, false, w, gst, g.u_min);

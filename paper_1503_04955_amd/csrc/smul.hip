@@ -27,6 +27,7 @@
 
 #include "../../include/dkss.h"
 #include "hip_status.hpp"
+#include "wave_carry.hpp"
 
 using namespace dkss;
 
@@ -47,19 +48,7 @@ __device__ __forceinline__ void wsync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Carries into the 64 lanes of a row: lane l generates (G) or propagates (P, disjoint from G) a
-// carry; c enters lane 0.  Bit l of the result is the carry into lane l; *cout gets the carry
-// out of lane 63.  (The carries of the 64-bit addition (G | P) + G + c are exactly these.)
-__device__ __forceinline__ unsigned long long row_carries(unsigned long long G, unsigned long long P,
-                                                          uint32_t c, uint32_t* cout) {
-    const unsigned long long A = G | P;
-    const unsigned long long t = A + G;
-    const unsigned long long S = t + c;
-    *cout = (uint32_t)((t < A) | (S < t));
-    return S ^ A ^ G;
-}
-
-__device__ __forceinline__ uint32_t bit_of(unsigned long long C) { return (uint32_t)(C >> lane_id()) & 1u; }
+__device__ __forceinline__ uint32_t bit_of(unsigned long long C) { return lane_bit(C); }
 
 // x += v (v < 2^32 added at limb 0) over W limbs; returns the carry out of the top limb.
 __device__ uint32_t fw_add_small(uint32_t* x, uint32_t v, int W) {

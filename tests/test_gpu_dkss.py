@@ -152,11 +152,15 @@ def test_mul_zero_length_and_schoolbook_path(env):
 
 
 @pytest.mark.parametrize("alen,blen,ones", [(2048, 2048, True), (2048, 2048, False), (4095, 1, True),
-                                             (2, 2, True), (31, 32, True), (1000, 3000, False)])
+                                             (2, 2, True), (31, 32, True), (1000, 3000, False),
+                                             (2049, 2048, True), (4000, 3999, False), (4093, 4093, True),
+                                             (6000, 5000, False), (8186, 8186, True), (8186, 8186, False),
+                                             (64, 8000, False), (8100, 3, True), (3000, 7000, False)])
 def test_schoolbook_base_case_up_to_its_limit(env, alen, blen, ones):
-    """The base case forced (cutoff above both operands) up to alen + blen = 4096 words, with
-    all-ones operands (every column at its largest sum, carries through whole chunks of the
-    carry scan) and random ones."""
+    """The base case forced (cutoff above both operands): the schoolbook up to alen + blen = 4096
+    words, Karatsuba levels above it (one level up to 4094 x 4094 words, two up to 8186 x
+    8186), balanced and unbalanced, with all-ones operands (every column at its largest sum,
+    the largest sums a0 + a1, carries through whole rows) and random ones."""
     dk, torch, ctx = env
     if ones:
         a, b = SI.all_ones(alen), SI.all_ones(blen)
@@ -165,7 +169,34 @@ def test_schoolbook_base_case_up_to_its_limit(env, alen, blen, ones):
     p = ctx.select_params(32 * alen, 32 * blen)
     p.cutoff_bits = 2 ** 64 - 1
     assert ctx.plan_info(alen, blen, p).schoolbook
-    assert np.array_equal(_gpu_mul(env, a, b, params=p), C.schoolbook(a, b)), (alen, blen)
+    want = C.schoolbook(a, b)
+    assert np.array_equal(_gpu_mul(env, a, b, params=p), want), (alen, blen)
+    if alen == blen:
+        assert np.array_equal(_gpu_mul(env, a, a, params=p, square=True), C.schoolbook(a, a))
+    # the allocation-free entry point takes the same path, in its scratch
+    dk_, torch_, _ = env
+    da, db = dk_.to_device(a), dk_.to_device(b)
+    out = torch_.empty(alen + blen, dtype=torch_.int32, device="cuda")
+    ctx.mul_noalloc(da, db, out, params=p)
+    torch_.cuda.synchronize()
+    assert np.array_equal(dk_.to_host(out), want)
+
+
+def test_karatsuba_base_case_in_batches(env):
+    """A batch of base-case products of one, two and no Karatsuba levels (the TUNED-style
+    schoolbook choice forced by parameters) equals the oracle's schoolbook products."""
+    dk, torch, ctx = env
+    lens = [(3000, 3000), (2100, 2000), (5000, 4000), (8000, 7000), (100, 100), (8184, 8184), (1, 8000)]
+    lens += SI.batch_lengths(SI.SEED_BASE + 41, 40, lo_bits=16, hi_bits=18)
+    pairs = [SI.operand_pair(4000 + i, al, bl) for i, (al, bl) in enumerate(lens)]
+    params = []
+    for al, bl in lens:
+        p = ctx.select_params(32 * al, 32 * bl)
+        p.cutoff_bits = 2 ** 64 - 1
+        params.append(p)
+    got = _batch_run(env, pairs, params=params)
+    for (a, b), g in zip(pairs, got):
+        assert np.array_equal(g, C.schoolbook(a, b)), (len(a), len(b))
 
 
 # ---- the large configurations: 2^24 and 2^28 bits --------------------------------------------

@@ -90,6 +90,20 @@ def test_errors_before_device_work(dk):
     assert L.dkss_strerror(dk.ENOSPC) == b"workspace too small"
 
 
+def test_karatsuba_base_case_routing(dk):
+    """The base case covers products whose leaves fit the schoolbook after at most two Karatsuba
+    levels (up to 8186 x 8186 words); such products need a workspace, plain schoolbook products
+    none, and beyond two levels the product goes to DKSS."""
+    ctx = dk.Context()
+    for alen, blen, base in [(2048, 2048, True), (4000, 4000, True), (8184, 8184, True), (64, 8000, True),
+                             (8186, 8186, True), (8187, 8187, False)]:
+        p = ctx.select_params(32 * alen, 32 * blen)
+        p.cutoff_bits = 2 ** 64 - 1
+        assert bool(ctx.plan_info(alen, blen, p).schoolbook) == base, (alen, blen)
+        ws = ctx.workspace_bytes(alen, blen, p)
+        assert (ws > 0) == (alen + blen > 4096), (alen, blen, ws)
+
+
 def test_workspace_and_schoolbook_routing(dk):
     ctx = dk.Context()
     assert ctx.workspace_bytes(0, 100) == 0
