@@ -181,8 +181,9 @@ def traffic_record(kernel, workload, source_files):
     return float(kv["hbm_bytes_per_launch"])
 
 
-def roofline_of(stats, workload):
-    """Roofline object of the kind with the most time in a profiled pass."""
+def roofline_of(stats, workload, mad_rate=None):
+    """Roofline object of the kind with the most time in a profiled pass (VALU-bound kinds also
+    against the measured multiply-add rate, when given)."""
     dom = max(stats, key=lambda k: stats[k].total_ms)
     st = stats[dom]
     avg_ms = st.total_ms / st.launches
@@ -191,6 +192,8 @@ def roofline_of(stats, workload):
         achieved = per / (avg_ms / 1e3) / 1e12
         r = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(PEAK_VALU_TOPS, 2),
              "unit": "TOP/s", "frac": round(achieved / PEAK_VALU_TOPS, 4), "ops_per_launch": per}
+        if mad_rate:
+            r["frac_of_measured_mad_rate"] = round(achieved / mad_rate, 4)
     else:
         per = st.alg_bytes / st.launches
         achieved = per / (avg_ms / 1e3) / 1e9
@@ -322,7 +325,7 @@ def single_leg(bits_log2, reps, dk, torch, SI):
         del ws
     torch.cuda.empty_cache()
     out["kernels"] = kernel_table(stats, reps)
-    out["roofline"] = roofline_of(stats, "dkss_mul_2p%d" % bits_log2)
+    out["roofline"] = roofline_of(stats, "dkss_mul_2p%d" % bits_log2, dk.probe_mad_rate() / 1e12)
     return out
 
 
@@ -461,6 +464,10 @@ def main():
     import seeded_inputs as SI
 
     props = torch.cuda.get_device_properties(0)
+    # the VALU peak is nominal (CUs x 64 lanes x clock); the measured rate of the products'
+    # multiply-add instruction is reported beside it
+    mad_rate = dk.probe_mad_rate() / 1e12
+    log("v_mad_u64_u32: %.2f T lane-ops/s measured (nominal %.2f)" % (mad_rate, PEAK_VALU_TOPS))
     ms_step, bits, batch, stats = batch_leg(args, dk, torch, SI)
     out = {
         "metric": METRIC, "value": bits / (ms_step / 1e3), "unit": "operand bits/s", "n_gpus": 1,
@@ -474,8 +481,8 @@ def main():
                                % (batch["plain_sequential"]["ms"], batch["plain_sequential"]["value"])},
         "verified": "every product equal to the plain calls' and c = a*b mod 8 random 61-bit primes",
         "device": {"name": props.name, "compute_units": props.multi_processor_count,
-                   "hbm_bytes": props.total_memory},
-        "roofline": roofline_of(stats, "batch4096"),
+                   "hbm_bytes": props.total_memory, "mad_u64_u32_tops_measured": round(mad_rate, 2)},
+        "roofline": roofline_of(stats, "batch4096", mad_rate),
         "kernels": kernel_table(stats, args.steps),
         "batch": batch,
     }

@@ -198,6 +198,12 @@ int dkss_smul(uint32_t* c, const uint32_t* a, size_t alen, const uint32_t* b, si
 int dkss_smul_forward(uint32_t* poly, uint32_t* tops, const uint32_t* a, size_t alen, size_t blen,
                       const dkss_smul_params* p, dkss_stream_t s);
 
+/* Measured rate of the 32 x 32 -> 64-bit multiply-add (v_mad_u64_u32, the instruction of the
+ * products in R) on the current device, in lane operations per second: 16 workgroups of 256
+ * threads per CU, eight independent chains per thread, timed with events on s after a warm-up
+ * launch.  A diagnostic: it waits for its launches.  Errors: DKSS_EINVAL, DKSS_EHIP. */
+int dkss_probe_mad_rate(double* mads_per_s, dkss_stream_t s);
+
 /* Bytes of the fixed device scratch of dkss_mul_noalloc (one copy per device). */
 #define DKSS_NOALLOC_SCRATCH_BYTES ((size_t)128 << 20)
 

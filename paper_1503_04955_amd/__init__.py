@@ -118,6 +118,7 @@ def lib():
         L.dkss_prepare.argtypes = [vp, sz, sz, PP, vp]
         L.dkss_mul.argtypes = [vp, vp, vp, sz, vp, sz, PP, vp, sz, vp]
         L.dkss_mul_noalloc.argtypes = [vp, vp, vp, sz, vp, sz, PP, vp]
+        L.dkss_probe_mad_rate.argtypes = [ctypes.POINTER(ctypes.c_double), vp]
         SP = ctypes.POINTER(SmulParams)
         L.dkss_smul_select.argtypes = [sz, sz, SP]
         L.dkss_smul_workspace_bytes.argtypes = [sz, sz, SP, ctypes.POINTER(sz)]
@@ -167,6 +168,7 @@ def lib():
 EXPORTED = ["dkss_ctx_create", "dkss_ctx_destroy", "dkss_select_params", "dkss_plan_info",
             "dkss_workspace_bytes", "dkss_prepare", "dkss_mul", "dkss_mul_noalloc", "dkss_mul_batch",
             "dkss_smul_select", "dkss_smul_workspace_bytes", "dkss_smul", "dkss_smul_forward",
+            "dkss_probe_mad_rate",
             "dkss_batch_workspace_bytes", "dkss_batch_prepare", "dkss_forward", "dkss_residues", "dkss_profile_enable",
             "dkss_profile_read", "dkss_profile_reset", "dkss_kernel_name", "dkss_set_option",
             "dkss_candidates", "dkss_mlp_features", "dkss_mlp_forward", "dkss_mlp_work_floats",
@@ -237,6 +239,13 @@ def _keep_until_done(stream, *tensors):
 
 def _pp(params):
     return ctypes.byref(params) if params is not None else None
+
+
+def probe_mad_rate(stream=None):
+    """Measured v_mad_u64_u32 lane operations per second on the current device."""
+    r = ctypes.c_double()
+    _check(lib().dkss_probe_mad_rate(ctypes.byref(r), _stream_ptr(stream)), "dkss_probe_mad_rate")
+    return r.value
 
 
 def smul_select(alen, blen):

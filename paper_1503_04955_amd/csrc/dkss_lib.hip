@@ -3377,6 +3377,58 @@ const char* dkss_kernel_name(int kind) {
     return names[kind];
 }
 
+}  // extern "C"
+
+// The VALU rate of the multiply-add the products in R are built from: every thread runs eight
+// independent chains of v_mad_u64_u32 (64-bit accumulators, as the column sums use them).
+constexpr int kProbeChains = 8;
+constexpr int kProbeSteps = 4096;
+__global__ __launch_bounds__(kThreads) void k_probe_mad(uint64_t* out, uint32_t seed) {
+    uint64_t acc[kProbeChains];
+    uint32_t x = seed ^ (uint32_t)(blockIdx.x * kThreads + threadIdx.x);
+#pragma unroll
+    for (int c = 0; c < kProbeChains; ++c) acc[c] = x + c;
+    for (int i = 0; i < kProbeSteps; ++i) {
+#pragma unroll
+        for (int c = 0; c < kProbeChains; ++c) acc[c] = (uint64_t)(uint32_t)acc[c] * (x + (uint32_t)c) + acc[c];
+    }
+    uint64_t r = 0;
+#pragma unroll
+    for (int c = 0; c < kProbeChains; ++c) r ^= acc[c];
+    if (r == 0x5EED5EED5EED5EEDull) out[0] = r;          // keeps the chains alive
+}
+
+extern "C" {
+
+int dkss_probe_mad_rate(double* mads_per_s, dkss_stream_t st) {
+    clear_stale_hip_error();
+    if (!mads_per_s) return DKSS_EINVAL;
+    hipStream_t s = (hipStream_t)st;
+    int dev = 0, cus = 0;
+    HIP_OK(hipGetDevice(&dev));
+    HIP_OK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    const unsigned blocks = (unsigned)std::max(cus, 1) * 16;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_OK(hipEventCreate(&e0));
+    int rc = note_hip(hipEventCreate(&e1));
+    float ms = 0.0f;
+    if (!rc) {
+        hipLaunchKernelGGL(k_probe_mad, dim3(blocks), dim3(kThreads), 0, s, (uint64_t*)nullptr, 1u);   // warm-up
+        rc = note_hip(hipEventRecord(e0, s));
+        if (!rc) hipLaunchKernelGGL(k_probe_mad, dim3(blocks), dim3(kThreads), 0, s, (uint64_t*)nullptr, 2u);
+        if (!rc) rc = launch_status();
+        if (!rc) rc = note_hip(hipEventRecord(e1, s));
+        if (!rc) rc = note_hip(hipEventSynchronize(e1));
+        if (!rc) rc = note_hip(hipEventElapsedTime(&ms, e0, e1));
+    }
+    (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    const double mads = (double)blocks * kThreads * kProbeSteps * kProbeChains;
+    *mads_per_s = ms > 0.0f ? mads / (ms * 1e-3) : 0.0;
+    return DKSS_OK;
+}
+
 int dkss_last_hip_error(void) { return g_last_hip; }
 
 const char* dkss_hip_error_string(int code) { return hipGetErrorString((hipError_t)code); }

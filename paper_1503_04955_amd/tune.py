@@ -5,8 +5,8 @@ training data of the learned selector.
 
 A point is (x, ratio, batch): `batch` independent products of 2^x-bit by 2^x/ratio-bit operands
 (whole limbs).  At each point every feasible candidate tuple (dkss_candidates: Mm offset x
-log2 m, the smallest modulus for it), the schoolbook base case where it applies (both operands
-together at most 4096 limbs) and the thesis's rule (the context's THESIS policy) are timed:
+log2 m, the smallest modulus for it), the base case where it applies (the schoolbook for operands
+of at most 4096 limbs together, Karatsuba levels over it up to 8186 x 8186 limbs) and the thesis's rule (the context's THESIS policy) are timed:
 `reps` back-to-back calls between two HIP events after one warm call, divided by reps and by
 batch, so each figure is milliseconds per product.  batch 1 runs dkss_mul, larger batches one
 dkss_mul_batch call.  Every timed product is checked by residues on the GPU (all of a single
@@ -108,9 +108,9 @@ def entries(ctx, n, nb):
     for ci, p in ctx.candidates(32 * n, 32 * nb):
         p.cutoff_bits = 0
         out.append((ci, p))
-    if n + nb <= 4096:
-        sb = ctx.select_params(32 * n, 32 * nb)
-        sb.cutoff_bits = (1 << 64) - 1
+    sb = ctx.select_params(32 * n, 32 * nb)
+    sb.cutoff_bits = (1 << 64) - 1
+    if ctx.plan_info(n, nb, sb).schoolbook:       # the base case applies (Karatsuba levels included)
         out.append((SCHOOLBOOK, sb))
     return out
 
