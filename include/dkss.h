@@ -86,12 +86,13 @@ typedef struct {
 
 /* Create a context with the given policy.  cache_dir may be NULL; a TUNED context reads
  * cache_dir/dkss_tuning.txt and a LEARNED one cache_dir/dkss_mlp.txt (dkss_mlp_load) when they
- * exist.  The tuning table is text: lines "lo hi cand [radices] [dft_lds]" (a log2 N range, a
- * candidate index of dkss_candidates or DKSS_CAND_SCHOOLBOOK, a level split such as 5.5.4, a
- * DFT LDS budget in bytes), '#' comments, and "@batch B" lines: the entries after one hold for
- * batches of at least B products (before the first, B = 1); a product takes the entry of the
- * largest such B whose range holds its N.  Allocates nothing on the device until a parameter tuple is first prepared or the
- * selector's first inference.  Errors: DKSS_EINVAL. */
+ * exist.  The tuning table is text: lines "lo hi cand [radices] [dft_lds]" (a log2 N range; a
+ * candidate index of dkss_candidates, S or DKSS_CAND_SCHOOLBOOK for the base case, or T for the
+ * thesis rule; a level split such as 5.5.4; a DFT LDS budget in bytes), '#' comments, and
+ * "@batch B" lines: the entries after one hold for batches of at least B products (before the
+ * first, B = 1); a product takes the entry of the largest such B whose range holds its N.
+ * Allocates nothing on the device until a parameter tuple is first prepared or the selector's
+ * first inference.  Errors: DKSS_EINVAL. */
 int dkss_ctx_create(dkss_ctx** out, int policy, const char* cache_dir);
 
 /* Release the context and the device tables it owns.  Safe on NULL. */
@@ -107,14 +108,16 @@ int dkss_select_params(dkss_ctx* ctx, uint64_t a_bits, uint64_t b_bits, uint32_t
 
 /*
  * Candidate parameter tuples for operands of a_bits x b_bits bits (N = the longer, in whole
- * limbs), the search space of the tuner and of the learned selector.  Candidate index
- * c = (t_off * 6 + (log2_m - 1)), t_off in 0..2, log2_m in 1..6: Mm = 2^(t_min + t_off), where
- * t_min is the smallest log2(Mm) whose u = ceil(2N/Mm) admits a modulus of at most 256 bits;
- * p has the fewest whole 32-bit limbs with p^z >= Mm 2^(2u) (z = 1, Sec. 3.2.2); M = Mm/m >= m.
+ * limbs), the search space of the tuner and of the learned selector.  t_min is the smallest
+ * log2(Mm) whose u = ceil(2N/Mm) admits a prime modulus of at most 256 bits; M = Mm/m >= m.
+ *   c = t_off * 6 + (log2_m - 1) < 18, t_off in 0..2, log2_m in 1..6: Mm = 2^(t_min + t_off),
+ *       z = 1, p of the fewest whole 32-bit limbs with p > Mm 2^(2u) (Sec. 3.2.2);
+ *   c = 18 + (log2_m - 1) < 24: Mm = 2^t_min, z = 2 (q = p^2, the lift of Sec. 3.2.3), p of the
+ *       fewest bits with p^2 > Mm 2^(2u) (Sec. 3.2 Step 2).
  * out[c] is filled for every c < DKSS_NCAND; valid[c] = 1 where the tuple is feasible.  The
  * radices are the library default, cutoff_bits 0.  Errors: DKSS_EINVAL, DKSS_ERANGE.
  */
-enum { DKSS_NCAND = 18 };
+enum { DKSS_NCAND = 24 };
 int dkss_candidates(dkss_ctx* ctx, uint64_t a_bits, uint64_t b_bits, dkss_params* out,
                     int* valid);
 

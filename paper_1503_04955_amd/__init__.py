@@ -176,7 +176,7 @@ EXPORTED = ["dkss_ctx_create", "dkss_ctx_destroy", "dkss_select_params", "dkss_p
             "dkss_mlp_choose", "dkss_batch_graph_create", "dkss_graph_launch", "dkss_graph_info",
             "dkss_graph_destroy", "dkss_last_hip_error", "dkss_hip_error_string", "dkss_strerror"]
 
-NCAND = 18
+NCAND = 24
 MLP_IN, MLP_HID, MLP_OUT = 3, 64, NCAND + 1
 CAND_SCHOOLBOOK = NCAND
 MLP_NPARAM = MLP_HID * MLP_IN + MLP_HID + MLP_HID * MLP_HID + MLP_HID + MLP_OUT * MLP_HID + MLP_OUT

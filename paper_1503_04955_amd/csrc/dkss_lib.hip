@@ -1558,6 +1558,8 @@ struct Call {
 
 int dig_D(int L) { return (32 * L + 28) / 28; }
 int dig_K(int L) { return (32 * L + 6 + 27) / 28; }
+// 32-bit limbs of q = p^z for a prime of pb bits (q < 2^(z pb)); exact for z = 1 and z = 2
+int tuple_limbs(int pb, int z) { return (z * pb + 31) / 32; }
 
 }  // namespace
 
@@ -1631,26 +1633,28 @@ namespace {
 // above `batch` wins.  A schoolbook entry sets *school and leaves the thesis tuple in place
 // (the product falls back to it where the base case does not apply).
 bool policy_tuple(const dkss_ctx* ctx, uint64_t N, uint32_t batch, int* lM, int* lm, int* u, int* pb,
-                  const TuneEntry** te = nullptr, bool* school = nullptr) {
+                  int* z, const TuneEntry** te = nullptr, bool* school = nullptr) {
     if (te) *te = nullptr;
     if (school) *school = false;
+    *z = 1;
     if (ctx && ctx->policy == DKSS_POLICY_TUNED) {
         const double lg = std::log2((double)N);
         const TuneEntry* hit = nullptr;
         for (const TuneEntry& t : ctx->tuning)
             if (t.batch <= batch && lg >= t.lo && lg < t.hi && (!hit || t.batch > hit->batch) &&
                 (t.cand == DKSS_CAND_SCHOOLBOOK || t.cand == kCandThesis ||
-                 candidate_params(N, t.cand, lM, lm, u, pb)))
+                 candidate_params(N, t.cand, lM, lm, u, pb, z)))
                 hit = &t;
         if (hit && hit->cand == kCandThesis) {
             // measured no faster than the rule: the rule, with its default level split
         } else if (hit && hit->cand == DKSS_CAND_SCHOOLBOOK) {
             if (school) *school = true;
-        } else if (hit && candidate_params(N, hit->cand, lM, lm, u, pb)) {
+        } else if (hit && candidate_params(N, hit->cand, lM, lm, u, pb, z)) {
             if (te) *te = hit;
             return true;
         }
     }
+    *z = 1;
     return thesis_params(N, lM, lm, u, pb);
 }
 
@@ -1659,9 +1663,10 @@ bool policy_tuple(const dkss_ctx* ctx, uint64_t N, uint32_t batch, int* lM, int*
 // Can the selector's output c run a product of alen x blen limbs?
 bool learned_feasible(size_t alen, size_t blen, int c) {
     if (c == DKSS_CAND_SCHOOLBOOK) return kara_depth(alen, blen) >= 0;
-    int lM, lm, u, pb;
+    int lM, lm, u, pb, z;
     const uint64_t N = 32ull * std::max(alen, blen);
-    return candidate_params(N, c, &lM, &lm, &u, &pb) && default_radices(lM, lm, (pb + 31) / 32).size() <= 8;
+    return candidate_params(N, c, &lM, &lm, &u, &pb, &z) &&
+           default_radices(lM, lm, tuple_limbs(pb, z)).size() <= 8;
 }
 
 int ensure_mlp_io(dkss_ctx* ctx, size_t n) {
@@ -1751,14 +1756,14 @@ int resolve_params(dkss_ctx* ctx, size_t alen, size_t blen, const dkss_params* p
     if (N == 0) return DKSS_OK;
     if (N > (1ull << 36)) return DKSS_ERANGE;
     if (p == nullptr) {
-        int lM, lm, u, pb;
+        int lM, lm, u, pb, z;
         P.cutoff_bits = kDefaultCutoffBits;
         const TuneEntry* te = nullptr;
-        if (choice >= 0 && choice < kNumCandidates && candidate_params(N, choice, &lM, &lm, &u, &pb)) {
+        if (choice >= 0 && choice < kNumCandidates && candidate_params(N, choice, &lM, &lm, &u, &pb, &z)) {
             P.cutoff_bits = 0;
         } else {
             bool school = false;
-            if (!policy_tuple(ctx, N, batch, &lM, &lm, &u, &pb, &te, &school)) return DKSS_ERANGE;
+            if (!policy_tuple(ctx, N, batch, &lM, &lm, &u, &pb, &z, &te, &school)) return DKSS_ERANGE;
             if (school || choice == DKSS_CAND_SCHOOLBOOK) P.cutoff_bits = UINT64_MAX;
         }
         if (te) {                      // the tuned level split and LDS budget, where recorded
@@ -1766,7 +1771,7 @@ int resolve_params(dkss_ctx* ctx, size_t alen, size_t blen, const dkss_params* p
             bool fits = true;
             for (int r : te->radices) {
                 sum += r;
-                fits = fits && r <= max_radix_log2(lm, (pb + 31) / 32);
+                fits = fits && r <= max_radix_log2(lm, tuple_limbs(pb, z));
             }
             if (fits && sum == lM + 1) P.radix_log2 = te->radices;
             if (te->dft_lds) out->dft_lds = te->dft_lds;
@@ -1775,7 +1780,7 @@ int resolve_params(dkss_ctx* ctx, size_t alen, size_t blen, const dkss_params* p
         P.log2_m = lm;
         P.u = u;
         P.p_bits = pb;
-        P.z = 1;
+        P.z = z;
     } else {
         P.log2_M = (int)p->log2_M;
         P.log2_m = (int)p->log2_m;
@@ -2736,9 +2741,9 @@ int dkss_set_option(dkss_ctx* ctx, int option, long long value) {
     }
 }
 
-// The tuning table: text lines "lo hi cand" (log2 N range, candidate index, the schoolbook
-// output, or T for the thesis rule); '#' comments; a line "@batch B" starts the entries measured
-// at B products per batch.
+// The tuning table: text lines "lo hi cand" (log2 N range, candidate index, S or
+// DKSS_CAND_SCHOOLBOOK for the base case, T for the thesis rule); '#' comments; a line "@batch B" starts the entries measured at B
+// products per batch.
 static void load_tuning(dkss_ctx* c, const char* dir) {
     if (!dir) return;
     std::string path = std::string(dir) + "/dkss_tuning.txt";
@@ -2765,8 +2770,12 @@ static void load_tuning(dkss_ctx* c, const char* dir) {
         } else {
             char* end = nullptr;
             const long v = strtol(cs, &end, 10);
-            if (end == cs || *end || v < 0 || (v >= kNumCandidates && v != DKSS_CAND_SCHOOLBOOK)) continue;
-            e.cand = (int)v;
+            if (strcmp(cs, "S") == 0) {
+                e.cand = DKSS_CAND_SCHOOLBOOK;
+            } else {
+                if (end == cs || *end || v < 0 || (v >= kNumCandidates && v != DKSS_CAND_SCHOOLBOOK)) continue;
+                e.cand = (int)v;
+            }
         }
         if (n >= 4 && rad[0] != '-' && rad[0] != '#') {
             bool ok = true;
@@ -2873,16 +2882,16 @@ int dkss_candidates(dkss_ctx* ctx, uint64_t a_bits, uint64_t b_bits, dkss_params
     const uint64_t N = 32 * ((std::max(a_bits, b_bits) + 31) / 32);
     if (N == 0 || N > (1ull << 36)) return DKSS_ERANGE;
     for (int c = 0; c < DKSS_NCAND; ++c) {
-        int lM = 0, lm = 0, u = 0, pb = 0;
+        int lM = 0, lm = 0, u = 0, pb = 0, z = 1;
         memset(&out[c], 0, sizeof out[c]);
-        valid[c] = candidate_params(N, c, &lM, &lm, &u, &pb) ? 1 : 0;
+        valid[c] = candidate_params(N, c, &lM, &lm, &u, &pb, &z) ? 1 : 0;
         if (!valid[c]) continue;
         out[c].log2_M = (uint32_t)lM;
         out[c].log2_m = (uint32_t)lm;
         out[c].u = (uint32_t)u;
         out[c].p_bits = (uint32_t)pb;
-        out[c].z = 1;
-        std::vector<int> r = default_radices(lM, lm, (pb + 31) / 32);
+        out[c].z = (uint32_t)z;
+        std::vector<int> r = default_radices(lM, lm, tuple_limbs(pb, z));
         if (r.size() > 8) {           // more FFT levels than a plan holds
             valid[c] = 0;
             continue;
@@ -2911,14 +2920,14 @@ int dkss_select_params(dkss_ctx* ctx, uint64_t a_bits, uint64_t b_bits, uint32_t
         int rc = learned_choices(ctx, 1, &alen, &blen, batch ? batch : 1, &choice);
         if (rc) return rc;
     }
-    int lM, lm, u, pb;
+    int lM, lm, u, pb, z;
     uint64_t cutoff = kDefaultCutoffBits;
     const TuneEntry* te = nullptr;
-    if (choice >= 0 && choice < kNumCandidates && candidate_params(N, choice, &lM, &lm, &u, &pb)) {
+    if (choice >= 0 && choice < kNumCandidates && candidate_params(N, choice, &lM, &lm, &u, &pb, &z)) {
         cutoff = 0;
     } else {
         bool school = false;
-        if (!policy_tuple(ctx, N, batch ? batch : 1, &lM, &lm, &u, &pb, &te, &school)) return DKSS_ERANGE;
+        if (!policy_tuple(ctx, N, batch ? batch : 1, &lM, &lm, &u, &pb, &z, &te, &school)) return DKSS_ERANGE;
         if (school || choice == DKSS_CAND_SCHOOLBOOK) cutoff = UINT64_MAX;
     }
     memset(out, 0, sizeof *out);
@@ -2926,15 +2935,15 @@ int dkss_select_params(dkss_ctx* ctx, uint64_t a_bits, uint64_t b_bits, uint32_t
     out->log2_m = (uint32_t)lm;
     out->u = (uint32_t)u;
     out->p_bits = (uint32_t)pb;
-    out->z = 1;
+    out->z = (uint32_t)z;
     out->cutoff_bits = cutoff;
-    std::vector<int> r = default_radices(lM, lm, (pb + 31) / 32);
+    std::vector<int> r = default_radices(lM, lm, tuple_limbs(pb, z));
     if (te && !te->radices.empty()) {
         int sum = 0;
         bool fits = true;
         for (int x : te->radices) {
             sum += x;
-            fits = fits && x <= max_radix_log2(lm, (pb + 31) / 32);
+            fits = fits && x <= max_radix_log2(lm, tuple_limbs(pb, z));
         }
         if (fits && sum == lM + 1) r = te->radices;
     }

@@ -178,7 +178,7 @@ bool thesis_params(uint64_t N, int* log2_M, int* log2_m, int* u, int* p_bits) {
     return true;
 }
 
-bool candidate_params(uint64_t N, int c, int* log2_M, int* log2_m, int* u, int* p_bits) {
+bool candidate_params(uint64_t N, int c, int* log2_M, int* log2_m, int* u, int* p_bits, int* z) {
     if (N == 0 || N > (1ULL << 40) || c < 0 || c >= kNumCandidates) return false;
     auto need_bits = [&](int t) -> uint64_t {       // bits of p: p - 1 >= Mm 2^(2u)
         const uint64_t uu = ((2 * N) + (1ULL << t) - 1) >> t;
@@ -187,16 +187,25 @@ bool candidate_params(uint64_t N, int c, int* log2_M, int* log2_m, int* u, int* 
     int t = 2;
     while (t <= 62 && need_bits(t) > 256) ++t;
     if (t > 62) return false;
-    t += c / 6;
-    const int lm = c % 6 + 1;
+    const bool squared = c >= kNumCandidatesZ1;
+    if (!squared) t += c / 6;
+    const int lm = (squared ? c - kNumCandidatesZ1 : c) % 6 + 1;
     if (lm > t - lm) return false;                   // M >= m
     const uint64_t uu = ((2 * N) + (1ULL << t) - 1) >> t;
-    const uint64_t pb = 32 * ((need_bits(t) + 31) / 32);
+    uint64_t pb;
+    if (!squared) {
+        pb = 32 * ((need_bits(t) + 31) / 32);
+    } else {
+        // q = p^2 with p of b bits: p^2 >= 2^(2b - 2), so 2b - 2 >= t + 2u gives q > Mm 2^(2u)
+        pb = ((uint64_t)t + 2 * uu + 3) / 2;
+        if (2 * pb > 256) return false;
+    }
     if (pb > 256) return false;
     *log2_m = lm;
     *log2_M = t - lm;
     *u = (int)uu;
     *p_bits = (int)pb;
+    *z = squared ? 2 : 1;
     return true;
 }
 

@@ -71,11 +71,15 @@ struct Plan {
 // tuple exists (N too large for the limits below).
 bool thesis_params(uint64_t N, int* log2_M, int* log2_m, int* u, int* p_bits);
 
-// Candidate tuple c (0 <= c < kNumCandidates) for N: Mm = 2^(t_min + c / 6), m = 2^(c % 6 + 1),
-// u = ceil(2N/Mm), p of the fewest whole 32-bit limbs with p >= 2 Mm 2^(2u).  t_min is the
-// smallest log2(Mm) for which that modulus has at most 256 bits.  False if M < m or no modulus.
-constexpr int kNumCandidates = 18;
-bool candidate_params(uint64_t N, int c, int* log2_M, int* log2_m, int* u, int* p_bits);
+// Candidate tuple c (0 <= c < kNumCandidates) for N.  t_min is the smallest log2(Mm) for which
+// a prime modulus p >= 2 Mm 2^(2u) (u = ceil(2N/Mm)) has at most 256 bits.
+//   c < 18:  z = 1, Mm = 2^(t_min + c / 6), m = 2^(c % 6 + 1), p of the fewest whole 32-bit limbs
+//   c >= 18: z = 2 (q = p^2, Sec. 3.2 Step 2 with the Hensel lift of Sec. 3.2.3), Mm = 2^t_min,
+//            m = 2^(c - 17), p of the fewest bits with p^2 > Mm 2^(2u)
+// False if M < m or no modulus.
+constexpr int kNumCandidatesZ1 = 18;
+constexpr int kNumCandidates = 24;
+bool candidate_params(uint64_t N, int c, int* log2_M, int* log2_m, int* u, int* p_bits, int* z);
 
 // Smallest odd h with p = h*2^n + 1 prime, n = bits - bitlen(h), n >= min_n (Sec. 4.6).
 bool proth_prime(int bits, int min_n, Big* p, uint64_t* h, int* n);

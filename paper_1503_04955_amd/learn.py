@@ -128,8 +128,9 @@ def tuned_choices(keys, tuning_dir=None):
         if 32 * min(n, nb) <= q.cutoff_bits:
             out.append(dk.CAND_SCHOOLBOOK)
             continue
-        tup = (q.log2_M, q.log2_m, q.p_bits)
-        same = [c for c, p in ctx.candidates(32 * n, 32 * nb) if (p.log2_M, p.log2_m, p.p_bits) == tup]
+        tup = (q.log2_M, q.log2_m, q.p_bits, q.z)
+        same = [c for c, p in ctx.candidates(32 * n, 32 * nb)
+                if (p.log2_M, p.log2_m, p.p_bits, p.z) == tup]
         out.append(same[0] if same else "thesis")
     return out
 

@@ -5,8 +5,10 @@ training data of the learned selector.
 
 A point is (x, ratio, batch): `batch` independent products of 2^x-bit by 2^x/ratio-bit operands
 (whole limbs).  At each point every feasible candidate tuple (dkss_candidates: Mm offset x
-log2 m, the smallest modulus for it), the base case where it applies (the schoolbook for operands
-of at most 4096 limbs together, Karatsuba levels over it up to 8186 x 8186 limbs) and the thesis's rule (the context's THESIS policy) are timed:
+log2 m with a prime modulus, and log2 m at the smallest Mm with the square of a prime, z = 2),
+the base case where it applies (the schoolbook for operands of at most 4096 limbs together,
+Karatsuba levels over it up to 8186 x 8186 limbs) and the thesis's rule (the context's THESIS
+policy) are timed:
 `reps` back-to-back calls between two HIP events after one warm call, divided by reps and by
 batch, so each figure is milliseconds per product.  batch 1 runs dkss_mul, larger batches one
 dkss_mul_batch call.  Every timed product is checked by residues on the GPU (all of a single
@@ -152,30 +154,49 @@ def measure_point(ctx, x, ratio, batch, reps, torch, seed):
     return res
 
 
-def run(points, reps, out_json, verbose=True, tuned_txt=None, merge=False):
-    """Measure the points; with merge, rows of out_json at other points are kept."""
+def _dump(rows, reps, out_json):
+    os.makedirs(os.path.dirname(out_json) or ".", exist_ok=True)
+    tmp = out_json + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump({"arch": "gfx950", "reps": reps, "unit": "ms per product", "rows": rows}, f)
+    os.replace(tmp, out_json)
+
+
+def run(points, reps, out_json, verbose=True, tuned_txt=None, merge=False, resume=False):
+    """Measure the points; with merge, rows of out_json at other points are kept; with resume,
+    also its rows at these points, which are then not measured again.  The file is rewritten
+    after every point, so that a run cut short keeps what it measured."""
     import torch
     ctx = dk.Context()
     rows = []
-    if merge and os.path.exists(out_json):
+    done = set()
+    if (merge or resume) and os.path.exists(out_json):
         keys = {(x, r, b) for x, r, b in points}
         with open(out_json) as f:
-            rows = [r for r in json.load(f)["rows"]
-                    if (r["log2_a"], r["ratio"], r["batch"]) not in keys]
+            old = json.load(f)["rows"]
+        for r in old:
+            key = (r["log2_a"], r["ratio"], r["batch"])
+            if key not in keys:
+                if merge:
+                    rows.append(r)
+            elif resume:
+                rows.append(r)
+                done.add(key)
     t0 = time.time()
     for k, (x, ratio, batch) in enumerate(points):
+        if (x, ratio, batch) in done:
+            continue
         res = measure_point(ctx, x, ratio, batch, reps, torch, seed=int(x * 1000) * 100 + ratio * 10 + k)
         for label, (ms, pd) in res.items():
             rows.append({"log2_a": x, "log2_b": x - math.log2(ratio), "ratio": ratio,
                          "batch": batch, "cand": label, "ms": ms, "params": pd})
+        _dump(rows, reps, out_json)
         if verbose:
             win = min((c for c in res if c != "thesis"), key=lambda c: res[c][0])
             print("[%4d/%d %6.0fs] 2^%.2f ratio %d batch %d: thesis %.5f ms, best %s %.5f ms"
                   % (k + 1, len(points), time.time() - t0, x, ratio, batch, res["thesis"][0], win,
                      res[win][0]), flush=True)
-    os.makedirs(os.path.dirname(out_json) or ".", exist_ok=True)
-    with open(out_json, "w") as f:
-        json.dump({"arch": "gfx950", "reps": reps, "unit": "ms per product", "rows": rows}, f)
+    _dump(rows, reps, out_json)
     if tuned_txt:
         write_tuned_table(rows, tuned_txt)
     return rows
@@ -211,7 +232,7 @@ def write_tuned_table(rows, path, kernel_rows=None):
     batches = sorted({r["batch"] for r in rows if r["ratio"] == 1})
     with open(path, "w") as f:
         f.write("# log2N_lo log2N_hi candidate [radices] [dft_lds]   (fastest measured; ms best / thesis)\n")
-        f.write("# candidate %d: the schoolbook product\n" % SCHOOLBOOK)
+        f.write("# candidate S: the base case (schoolbook, Karatsuba levels over it); T: the thesis rule\n")
         for B in batches:
             best = best_candidates(rows, B, school=True)
             thesis = {r["log2_a"]: r["ms"] for r in rows
@@ -232,7 +253,7 @@ def write_tuned_table(rows, path, kernel_rows=None):
                     k = kbest[x]
                     cfg = " %s %d" % (".".join(str(v) for v in k["radices"]), k["dft_lds"])
                     ms = k["ms"]
-                name = str(best[x][0])
+                name = "S" if best[x][0] == SCHOOLBOOK else str(best[x][0])
                 if x in thesis and ms >= thesis[x]:
                     # nothing measured beat the rule here: name the rule, so the lookup never
                     # picks a slower tuple (nor an entry of a smaller batch size)
@@ -287,7 +308,7 @@ def tune_kernels(train_json, reps, out_json, tuned_txt, lo=16.0, verbose=True):
         c = torch.empty(n + nb, dtype=torch.int32, device="cuda")
         res = []
         for split in radix_splits(total, cap):
-            p = dk.Params.make(p0.log2_M, p0.log2_m, p0.u, p0.p_bits, 1, split, 0)
+            p = dk.Params.make(p0.log2_M, p0.log2_m, p0.u, p0.p_bits, p0.z, split, 0)
             ws = torch.empty(max(ctx.workspace_bytes(n, nb, p), 1), dtype=torch.uint8, device="cuda")
             ctx.prepare(n, nb, p)
             for lds in KERNEL_LDS:
@@ -319,6 +340,8 @@ def main():
     ap.add_argument("--out", default=dk.TUNING_DIR)
     ap.add_argument("--batches", default="", help="measure only these batch sizes, e.g. 1 or 16,256")
     ap.add_argument("--merge", action="store_true", help="keep the file's rows at other points")
+    ap.add_argument("--resume", action="store_true",
+                    help="keep the file's rows at these points too and measure only the missing ones")
     args = ap.parse_args()
     if args.set == "kernels":
         t0 = time.time()
@@ -334,9 +357,10 @@ def main():
     t0 = time.time()
     if args.set == "train":
         run(pts, args.reps, os.path.join(args.out, "timings.json"),
-            tuned_txt=os.path.join(args.out, "dkss_tuning.txt"), merge=args.merge)
+            tuned_txt=os.path.join(args.out, "dkss_tuning.txt"), merge=args.merge, resume=args.resume)
     else:
-        run(pts, args.reps, os.path.join(args.out, "timings_heldout.json"), merge=args.merge)
+        run(pts, args.reps, os.path.join(args.out, "timings_heldout.json"), merge=args.merge,
+            resume=args.resume)
     print("tuning took %.1f s" % (time.time() - t0), flush=True)
 
 

@@ -64,6 +64,38 @@ def test_planner_prime_power(dk):
     assert info.modulus == (3 * 2 ** 30 + 1) ** 4
 
 
+@pytest.mark.parametrize("N", [2 ** 12, 5000 * 32, 2 ** 18, 2 ** 22, 2 ** 26, 2 ** 30, 2 ** 34])
+def test_candidate_set(dk, N):
+    """The candidates of dkss_candidates, restated from their definition: 18 tuples with a prime
+    modulus (Mm = 2^(t_min + c // 6), m = 2^(c % 6 + 1), the fewest whole limbs of p with
+    p > Mm 2^(2u)), and 6 with the square of a prime (z = 2, Mm = 2^t_min, the fewest bits of p
+    with p^2 > Mm 2^(2u) for every prime of that length); each feasible tuple plans on the host
+    with a modulus p^z of the oracle's Proth prime."""
+    ctx = dk.Context()
+    cands = dict(ctx.candidates(N, N))
+    assert cands and max(cands) < dk.NCAND == 24
+
+    def u_of(t):
+        return -(-2 * N // 2 ** t)
+
+    t_min = next(t for t in range(2, 63) if t + 2 * u_of(t) + 1 <= 256)
+    for c, p in cands.items():
+        t = t_min + (c // 6 if c < 18 else 0)
+        lm = c % 6 + 1 if c < 18 else c - 17
+        u = u_of(t)
+        assert (p.log2_M + p.log2_m, p.log2_m, p.u) == (t, lm, u), c
+        if c < 18:
+            assert p.z == 1 and p.p_bits % 32 == 0 and p.p_bits - 32 < t + 2 * u + 1 <= p.p_bits
+        else:
+            assert p.z == 2 and 2 * p.p_bits - 2 >= t + 2 * u > 2 * p.p_bits - 4, c
+        info = ctx.plan_info(N // 32, N // 32, p)
+        prime, _, _ = OP.proth_prime(p.p_bits, p.log2_M + 1)
+        assert info.modulus == prime ** p.z and info.q_bits > t + 2 * u
+    for c in range(18, 24):
+        if c - 18 in cands:
+            assert c in cands, c
+
+
 def test_errors_before_device_work(dk):
     ctx = dk.Context()
     # p^z below Mm 2^(2u)
@@ -244,8 +276,8 @@ def test_tuned_table_writer_sections(dk, tmp_path):
     path = tmp_path / "dkss_tuning.txt"
     tune.write_tuned_table(rows, str(path))
     lines = [l.split("#")[0].split() for l in open(path) if l.strip() and not l.startswith("#")]
-    assert lines == [["0.000", "12.250", str(S)], ["12.250", "12.750", "3"], ["12.750", "64.000", "2"],
-                     ["@batch", "16"], ["0.000", "12.500", str(S)], ["12.500", "13.500", "8"]]
+    assert lines == [["0.000", "12.250", "S"], ["12.250", "12.750", "3"], ["12.750", "64.000", "2"],
+                     ["@batch", "16"], ["0.000", "12.500", "S"], ["12.500", "13.500", "8"]]
     ctx = dk.Context(dk.POLICY_TUNED, tuning_dir=str(tmp_path))
     school = 2 ** 64 - 1
     assert ctx.select_params(2 ** 12, 2 ** 12, 1).cutoff_bits == school

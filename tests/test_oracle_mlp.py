@@ -5,7 +5,7 @@ import pytest
 
 import oracle.mlp as om
 
-OUT = 19
+OUT = 25
 
 
 def _rand(seed, n, n_out=OUT, scale=0.5):
@@ -18,8 +18,8 @@ def _rand(seed, n, n_out=OUT, scale=0.5):
 
 
 def test_param_count():
-    # 3*64 + 64 + 64*64 + 64 + 19*64 + 19
-    assert om.n_params(OUT) == 5651
+    # 3*64 + 64 + 64*64 + 64 + 25*64 + 25
+    assert om.n_params(OUT) == 6041
 
 
 @pytest.mark.parametrize("seed", [1, 2, 3])
