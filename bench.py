@@ -224,7 +224,9 @@ def batch_leg(args, dk, torch, SI):
     bs = [dk.to_device(b) for _, b in pairs]
     bits = 32.0 * sum(len(a) + len(b) for a, b in pairs)
     log("batch: %d products, %.4g operand bits" % (len(pairs), bits))
-    call = dk.BatchCall(dk.Context(dk.POLICY_LEARNED), as_, bs)     # plans, infers, prepares
+    ctx_l = dk.Context(dk.POLICY_LEARNED)
+    ctx_l.set_option(dk.OPT_BATCH_LANES, args.lanes)
+    call = dk.BatchCall(ctx_l, as_, bs)                              # plans, infers, prepares
     graph = call.graph()
     for _ in range(args.warmup):
         graph()
@@ -239,7 +241,22 @@ def batch_leg(args, dk, torch, SI):
     torch.cuda.synchronize()
     ms_step = e0.elapsed_time(e1) / args.steps
     log("batch: graph learned %.3f ms per step" % ms_step)
-    head = {"ms": ms_step, "value": bits / (ms_step / 1e3), "kernels": graph.kernels}
+    head = {"ms": ms_step, "value": bits / (ms_step / 1e3), "kernels": graph.kernels,
+            "lanes": args.lanes}
+    if args.headline_only:
+        # the profiling form: the headline's kernels alone (no plain calls, no other policies)
+        call.ctx.set_option(dk.OPT_BATCH_LANES, 1)
+        call.ctx.profile_reset()
+        call.ctx.profile(True)
+        for _ in range(args.steps):
+            call()
+        torch.cuda.synchronize()
+        call.ctx.profile(False)
+        stats = call.ctx.profile_read()
+        graph.close()
+        check_residues(dk, as_, bs, call.outs, primes61(SI.SEED_BASE, 8))
+        return ms_step, bits, {"workload": "4096 products (headline only)", "operand_bits": bits,
+                               "graph_learned": head}, stats
     # the plain calls: thesis rule, one dkss_mul per product (tables prepared)
     ctx = dk.Context()
     outs_p = [torch.empty(a.numel() + b.numel(), dtype=torch.int32, device="cuda") for a, b in zip(as_, bs)]
@@ -269,7 +286,7 @@ def batch_leg(args, dk, torch, SI):
     torch.cuda.synchronize()
     call.ctx.profile(False)
     stats = call.ctx.profile_read()
-    call.ctx.set_option(dk.OPT_BATCH_LANES, 4)
+    call.ctx.set_option(dk.OPT_BATCH_LANES, args.lanes)
     same = all(torch.equal(x, y) for x, y in zip(outs_p, call.outs))
     graph.close()
     for name, policy in (("thesis", dk.POLICY_THESIS), ("tuned", dk.POLICY_TUNED),
@@ -449,6 +466,11 @@ def main():
                     help="comma-separated legs to run (the headline batch is always run)")
     ap.add_argument("--no-c5", action="store_true", help="skip the 2^34 leg")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--lanes", type=int, default=4,
+                    help="stream lanes of the headline batch's groups (DKSS_OPT_BATCH_LANES)")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="run only the headline batch (graph and profiled pass): the form that "
+                         "kernel traces and counters are taken on")
     ap.add_argument("--copy-calib", type=int, default=0,
                     help="end with one device-to-device copy of this many bytes (a counter "
                          "calibration kernel of known traffic)")
@@ -476,9 +498,7 @@ def main():
         "data": "synthetic (seeded uniform uint32 limbs)",
         "config": {"workload": "batched DKSS, learned-tuned parameters, one replayed HIP graph: 4096 "
                                "products, operands 2^12..2^22 bits log-uniform, length ratio U[1,8]",
-                   "products": args.batch, "operand_bits": bits,
-                   "baseline": "plain sequential calls, thesis rule: %.3f ms (%.4g operand bits/s)"
-                               % (batch["plain_sequential"]["ms"], batch["plain_sequential"]["value"])},
+                   "products": args.batch, "operand_bits": bits},
         "verified": "every product equal to the plain calls' and c = a*b mod 8 random 61-bit primes",
         "device": {"name": props.name, "compute_units": props.multi_processor_count,
                    "hbm_bytes": props.total_memory, "mad_u64_u32_tops_measured": round(mad_rate, 2)},
@@ -486,6 +506,11 @@ def main():
         "kernels": kernel_table(stats, args.steps),
         "batch": batch,
     }
+    if "plain_sequential" in batch:
+        out["config"]["baseline"] = ("plain sequential calls, thesis rule: %.3f ms (%.4g operand bits/s)"
+                                     % (batch["plain_sequential"]["ms"], batch["plain_sequential"]["value"]))
+    else:
+        out["verified"] = "c = a*b mod 8 random 61-bit primes for every product"
     if "2p28" in legs:
         out["single_2p28"] = single_leg(28, args.steps, dk, torch, SI)
     if "sizes" in legs:

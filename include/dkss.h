@@ -82,6 +82,8 @@ typedef struct {
     uint64_t poly_bytes;      /* S = 2M * m * L * 4, one polynomial */
     uint64_t table_bytes;     /* device table of rho^s, s < 2M/2m */
     uint32_t q[16];           /* p^z, L limbs */
+    uint32_t digits;          /* 28-bit digits per residue in the products in R: ceil((32L+1)/28),
+                                 or one fewer when q < 2^(28 digits - 1) (L >= 2) */
 } dkss_plan;
 
 /* Create a context with the given policy.  cache_dir may be NULL; a TUNED context reads
@@ -111,7 +113,9 @@ int dkss_select_params(dkss_ctx* ctx, uint64_t a_bits, uint64_t b_bits, uint32_t
  * limbs), the search space of the tuner and of the learned selector.  t_min is the smallest
  * log2(Mm) whose u = ceil(2N/Mm) admits a prime modulus of at most 256 bits; M = Mm/m >= m.
  *   c = t_off * 6 + (log2_m - 1) < 18, t_off in 0..2, log2_m in 1..6: Mm = 2^(t_min + t_off),
- *       z = 1, p of the fewest whole 32-bit limbs with p > Mm 2^(2u) (Sec. 3.2.2);
+ *       z = 1, p of the fewest whole 32-bit limbs with p > Mm 2^(2u) (Sec. 3.2.2), or, where
+ *       a modulus of that size fits one 28-bit digit fewer than the limbs take, p of 28 D - 1
+ *       bits for the fewest such D (the products in R then run on D digits, dkss_plan.digits);
  *   c = 18 + (log2_m - 1) < 24: Mm = 2^t_min, z = 2 (q = p^2, the lift of Sec. 3.2.3), p of the
  *       fewest bits with p^2 > Mm 2^(2u) (Sec. 3.2 Step 2).
  * out[c] is filled for every c < DKSS_NCAND; valid[c] = 1 where the tuple is feasible.  The

@@ -76,7 +76,7 @@ class Plan(ctypes.Structure):
     _fields_ = [("params", Params), ("L", ctypes.c_uint32), ("q_bits", ctypes.c_uint32),
                 ("schoolbook", ctypes.c_uint32), ("squaring", ctypes.c_uint32),
                 ("poly_bytes", ctypes.c_uint64), ("table_bytes", ctypes.c_uint64),
-                ("q", ctypes.c_uint32 * 16)]
+                ("q", ctypes.c_uint32 * 16), ("digits", ctypes.c_uint32)]
 
     @property
     def modulus(self):

@@ -112,9 +112,10 @@ struct ProdArgs {
 
 // Coefficient k of element i as limbs: bits [u (i m/2 + k), u (i m/2 + k) + u) of a for k < m/2
 // and i < M; zero otherwise.
-template <int L>
+template <int C>
 __device__ __forceinline__ void encode_limbs(const uint32_t* __restrict__ a, long long alen, int u, long long i,
                                              int k, long long M, int log2m, uint32_t* out) {
+    constexpr int L = fmt_L(C);
     const int hm = 1 << (log2m - 1);
 #pragma unroll
     for (int w = 0; w < L; ++w) out[w] = 0;
@@ -138,9 +139,10 @@ __device__ __forceinline__ void encode_limbs(const uint32_t* __restrict__ a, lon
 }
 
 // poly: 2M elements x m coefficients x L limbs.
-template <int L>
+template <int C>
 __global__ __launch_bounds__(kThreads) void k_encode(ProdArgs PA, int which, uint32_t* __restrict__ poly0,
                                                      long long stride, long long M, int log2m) {
+    constexpr int L = fmt_L(C);
     const ProdDesc pd = PA.get();
     const uint32_t* __restrict__ a = which ? pd.b : pd.a;
     const long long alen = which ? pd.blen : pd.alen;
@@ -153,7 +155,7 @@ __global__ __launch_bounds__(kThreads) void k_encode(ProdArgs PA, int which, uin
     const long long i = t >> log2m;
     const int k = (int)(t & (m - 1));
     uint32_t out[L];
-    encode_limbs<L>(a, alen, u, i, k, M, log2m, out);
+    encode_limbs<C>(a, alen, u, i, k, M, log2m, out);
     uint32_t* dst = poly + (size_t)t * L;
 #pragma unroll
     for (int w = 0; w < L; ++w) dst[w] = out[w];
@@ -200,10 +202,11 @@ __device__ __forceinline__ long long level_pos(const LevelArgs& A, long long c0,
 // way out.
 
 // HBM limbs into LDS as digits, D words per residue (an inverse level's twiddles come first)
-template <int L>
+template <int C>
 __device__ __forceinline__ void level_load_digits(uint32_t* cur, const uint32_t* __restrict__ poly,
                                                   const LevelArgs& A, long long c0) {
-    constexpr int D = Dig<L>::D;
+    constexpr int L = fmt_L(C);
+    constexpr int D = Dig<C>::D;
     const int nel = 1 << (A.log2C + A.log2r);
     for (int t = threadIdx.x; t < (nel << A.log2m); t += kThreads) {
         const int e = t >> A.log2m, k = t & ((1 << A.log2m) - 1);
@@ -212,7 +215,7 @@ __device__ __forceinline__ void level_load_digits(uint32_t* cur, const uint32_t*
         uint32_t x[L], dv[D];
 #pragma unroll
         for (int w = 0; w < L; ++w) x[w] = src[w];
-        limbs_to_digits<L>(x, dv);
+        limbs_to_digits<C>(x, dv);
         uint32_t* dst = cur + ((c << A.log2r) + bitrev(j, A.log2r)) * A.ew + k * D;
 #pragma unroll
         for (int w = 0; w < D; ++w) dst[w] = dv[w];
@@ -220,9 +223,10 @@ __device__ __forceinline__ void level_load_digits(uint32_t* cur, const uint32_t*
 }
 
 // HBM limbs into LDS limbs, LS words per residue (one coefficient per thread and step)
-template <int L, int LS>
+template <int C, int LS>
 __device__ __forceinline__ void level_load_limbs(uint32_t* cur, const uint32_t* __restrict__ poly,
                                                  const LevelArgs& A, long long c0) {
+    constexpr int L = fmt_L(C);
     const int nel = 1 << (A.log2C + A.log2r);
     for (int t = threadIdx.x; t < (nel << A.log2m); t += kThreads) {
         const int e = t >> A.log2m, k = t & ((1 << A.log2m) - 1);
@@ -241,15 +245,16 @@ __device__ __forceinline__ void level_load_limbs(uint32_t* cur, const uint32_t* 
 // bitrev(2k) + r/2, without rotation, so it leaves the element of position bitrev(2k) in both.
 // Each element at j < r/2 is therefore written, as limbs, to slots bitrev(j) and bitrev(j) + 1,
 // and the DFT starts at its second pass.
-template <int L, int LS>
+template <int C, int LS>
 __device__ __forceinline__ void level_encode_in(uint32_t* cur, const uint32_t* __restrict__ a, long long alen,
                                                 int u, long long M, const LevelArgs& A, long long c0) {
+    constexpr int L = fmt_L(C);
     const int nel = 1 << (A.log2C + A.log2r - 1);        // the elements at j < r/2
     for (int t = threadIdx.x; t < (nel << A.log2m); t += kThreads) {
         const int e = t >> A.log2m, k = t & ((1 << A.log2m) - 1);
         const int c = e & ((1 << A.log2C) - 1), j = e >> A.log2C;
         uint32_t out[L];
-        encode_limbs<L>(a, alen, u, level_pos(A, c0, c, j), k, M, A.log2m, out);
+        encode_limbs<C>(a, alen, u, level_pos(A, c0, c, j), k, M, A.log2m, out);
         const int slot = (c << A.log2r) + bitrev(j, A.log2r);
         uint32_t* d0 = cur + ((slot << A.log2m) + k) * LS;
         uint32_t* d1 = cur + (((slot + 1) << A.log2m) + k) * LS;
@@ -262,9 +267,10 @@ __device__ __forceinline__ void level_encode_in(uint32_t* cur, const uint32_t* _
 }
 
 // LDS limbs (slot v) out to HBM limbs (position v)
-template <int L, int LS>
+template <int C, int LS>
 __device__ __forceinline__ void level_store_limbs(uint32_t* __restrict__ poly, const uint32_t* cur,
                                                   const LevelArgs& A, long long c0) {
+    constexpr int L = fmt_L(C);
     const int nel = 1 << (A.log2C + A.log2r);
     for (int t = threadIdx.x; t < (nel << A.log2m); t += kThreads) {
         const int e = t >> A.log2m, k = t & ((1 << A.log2m) - 1);
@@ -277,15 +283,16 @@ __device__ __forceinline__ void level_store_limbs(uint32_t* __restrict__ poly, c
 }
 
 // Within LDS: every coefficient from limbs to digits, same slot (then a barrier)
-template <int L, int LS>
+template <int C, int LS>
 __device__ __forceinline__ void lds_to_digits(uint32_t* dg, const uint32_t* lb, const LevelArgs& A) {
-    constexpr int D = Dig<L>::D;
+    constexpr int L = fmt_L(C);
+    constexpr int D = Dig<C>::D;
     const int n = 1 << (A.log2C + A.log2r + A.log2m);
     for (int t = threadIdx.x; t < n; t += kThreads) {
         uint32_t x[L], dv[D];
 #pragma unroll
         for (int w = 0; w < L; ++w) x[w] = lb[t * LS + w];
-        limbs_to_digits<L>(x, dv);
+        limbs_to_digits<C>(x, dv);
 #pragma unroll
         for (int w = 0; w < D; ++w) dg[(t >> A.log2m) * A.ew + (t & ((1 << A.log2m) - 1)) * D + w] = dv[w];
     }
@@ -294,15 +301,16 @@ __device__ __forceinline__ void lds_to_digits(uint32_t* dg, const uint32_t* lb, 
 
 // Within LDS: every coefficient from digits to limbs; the element in slot s of its column moves
 // to slot bitrev(s) if perm (then a barrier)
-template <int L, int LS>
+template <int C, int LS>
 __device__ __forceinline__ void lds_to_limbs(uint32_t* lb, const uint32_t* dg, const LevelArgs& A, bool perm) {
-    constexpr int D = Dig<L>::D;
+    constexpr int L = fmt_L(C);
+    constexpr int D = Dig<C>::D;
     const int n = 1 << (A.log2C + A.log2r + A.log2m);
     for (int t = threadIdx.x; t < n; t += kThreads) {
         uint32_t dv[D], x[L];
 #pragma unroll
         for (int w = 0; w < D; ++w) dv[w] = dg[(t >> A.log2m) * A.ew + (t & ((1 << A.log2m) - 1)) * D + w];
-        digits_to_limbs<L>(dv, x);
+        digits_to_limbs<C>(dv, x);
         int to = t;
         if (perm) {
             const int k = t & ((1 << A.log2m) - 1);
@@ -319,18 +327,20 @@ __device__ __forceinline__ void lds_to_limbs(uint32_t* lb, const uint32_t* dg, c
 // A thread's operand for one round of products, fetched from HBM a round ahead (the load is
 // issued before the preceding work and waited for at first use): coefficient j of the table
 // entry rho^s (twiddles), or coefficient j of b (componentwise products).
-template <int L>
+template <int C>
 struct Ahead {
-    uint32_t v[Dig<L>::D];
+    static constexpr int L = fmt_L(C);
+    uint32_t v[Dig<C>::D];
     int rot;                      // the twiddle's power of alpha
     bool nz;                      // the element gets a product
 };
 
 // Twiddle of the element that this thread serves in the round starting at element r0.
-template <int L>
-__device__ __forceinline__ void tw_fetch(Ahead<L>& f, int r0, const uint32_t* __restrict__ table,
+template <int C>
+__device__ __forceinline__ void tw_fetch(Ahead<C>& f, int r0, const uint32_t* __restrict__ table,
                                          const LevelArgs& A, long long c0) {
-    constexpr int D = Dig<L>::D;
+    constexpr int L = fmt_L(C);
+    constexpr int D = Dig<C>::D;
     const int m = 1 << A.log2m;
     const int g = threadIdx.x >> A.log2m, j = threadIdx.x & (m - 1);
     const int el = r0 + g;
@@ -358,11 +368,12 @@ __device__ __forceinline__ void tw_fetch(Ahead<L>& f, int r0, const uint32_t* __
 // element with position v in column c sits in LDS slot v (after the DFT, mode 1) or bitrev(v)
 // (before it, mode 2).  Mode 1 writes results to HBM; mode 2 writes them back into the slot once
 // the round's products (which read the slot) are done.  f holds round 0's twiddle on entry.
-template <int L, int MODE, int FM>
-__device__ __forceinline__ void level_twiddle(Ahead<L>& f, uint32_t* cur, uint32_t* RB, uint32_t* __restrict__ poly,
+template <int C, int MODE, int FM>
+__device__ __forceinline__ void level_twiddle(Ahead<C>& f, uint32_t* cur, uint32_t* RB, uint32_t* __restrict__ poly,
                                               const uint32_t* __restrict__ table, const LevelArgs& A,
                                               long long c0, const QConst& Q) {
-    constexpr int D = Dig<L>::D;
+    constexpr int L = fmt_L(C);
+    constexpr int D = Dig<C>::D;
     const int m = 1 << A.log2m;
     const int EW = A.ew;                                // an element's digits in LDS
     const int per = kThreads >> A.log2m;
@@ -381,23 +392,23 @@ __device__ __forceinline__ void level_twiddle(Ahead<L>& f, uint32_t* cur, uint32
         if (nz) {
             // the twiddle's extension to 2m entries: t_j and, m further on, q - t_j
             uint32_t nt[D];
-            dneg_q<L>(nt, f.v, Q);
-            uint32_t* t0 = TP + stage_pos(j, f.rot, A.log2m) * Dig<L>::DS;
-            uint32_t* t1 = TP + stage_pos(j + m, f.rot, A.log2m) * Dig<L>::DS;
+            dneg_q<C>(nt, f.v, Q);
+            uint32_t* t0 = TP + stage_pos(j, f.rot, A.log2m) * Dig<C>::DS;
+            uint32_t* t1 = TP + stage_pos(j + m, f.rot, A.log2m) * Dig<C>::DS;
 #pragma unroll
             for (int y = 0; y < D; ++y) {
                 t0[y] = f.v[y];
                 t1[y] = nt[y];
             }
         }
-        if (r0 + per < nel) tw_fetch<L>(f, r0 + per, table, A, c0);     // next round's twiddle
+        if (r0 + per < nel) tw_fetch<C>(f, r0 + per, table, A, c0);     // next round's twiddle
         wave_sync();
         uint32_t out[D];                                // mode 1: L limbs; mode 2: D digits
         if (valid) {
             if (nz) {
-                rprod_coeff<L, MODE == 1, FM>(TP, X, A.log2m, j, Q, out);
+                rprod_coeff<C, MODE == 1, FM>(TP, X, A.log2m, j, Q, out);
             } else if (MODE == 1) {
-                digits_to_limbs<L>(X + j * D, out);
+                digits_to_limbs<C>(X + j * D, out);
             }
             if (MODE == 1) {
                 uint32_t* dst = poly + (((size_t)level_pos(A, c0, c, v) << A.log2m) + j) * L;
@@ -419,9 +430,10 @@ __device__ __forceinline__ void level_twiddle(Ahead<L>& f, uint32_t* cur, uint32
 // cur holds the result).  Input: the element at position j of a column in slot bitrev(j);
 // output: position v in slot v.  The pass merging halves of h points multiplies the odd half by
 // alpha^((m/h) k) (alpha^-1 if inverse).  Passes before first_pass are taken as done.
-template <int L, int LS>
+template <int C, int LS>
 __device__ __forceinline__ void dft_passes(uint32_t*& cur, uint32_t*& nxt, const LevelArgs& A, int inverse,
                                            const QConst& Q, int first_pass = 0) {
+    constexpr int L = fmt_L(C);
     const int m = 1 << A.log2m, r = 1 << A.log2r;
     const int tasks = (1 << (A.log2C + A.log2r - 1)) << A.log2m;   // butterflies x coefficients
     // q's limbs in vector registers for all passes: an add or subtract with carry already reads
@@ -455,8 +467,8 @@ __device__ __forceinline__ void dft_passes(uint32_t*& cur, uint32_t*& nxt, const
                 xv[w] = X[w];
                 yv[w] = Y[w];
             }
-            lmod_add<L>(sv, xv, yv, qv);
-            lmod_sub<L>(dv, xv, yv, qv);
+            lmod_add<C>(sv, xv, yv, qv);
+            lmod_sub<C>(dv, xv, yv, qv);
             // a negated y swaps the two outputs: chosen by address, not per limb
             uint32_t* PS = nxt + ((neg ? ey : ex) + jj) * LS;
             uint32_t* PD = nxt + ((neg ? ex : ey) + jj) * LS;
@@ -473,9 +485,10 @@ __device__ __forceinline__ void dft_passes(uint32_t*& cur, uint32_t*& nxt, const
 }
 
 // Coefficient j of b for the element that this thread serves in the round starting at r0.
-template <int L>
-__device__ __forceinline__ void pw_fetch(Ahead<L>& f, int r0, const uint32_t* __restrict__ bpoly,
+template <int C>
+__device__ __forceinline__ void pw_fetch(Ahead<C>& f, int r0, const uint32_t* __restrict__ bpoly,
                                          const LevelArgs& A, long long c0) {
+    constexpr int L = fmt_L(C);
     const int g = threadIdx.x >> A.log2m, j = threadIdx.x & ((1 << A.log2m) - 1);
     const int el = r0 + g;
     f.nz = el < (1 << (A.log2C + A.log2r));
@@ -485,7 +498,7 @@ __device__ __forceinline__ void pw_fetch(Ahead<L>& f, int r0, const uint32_t* __
     uint32_t x[L];
 #pragma unroll
     for (int y = 0; y < L; ++y) x[y] = src[y];
-    limbs_to_digits<L>(x, f.v);
+    limbs_to_digits<C>(x, f.v);
 }
 
 // Componentwise products of the bottom level (Step 6 fused between the last forward and the
@@ -494,11 +507,12 @@ __device__ __forceinline__ void pw_fetch(Ahead<L>& f, int r0, const uint32_t* __
 // polynomial position (bpoly; f holds round 0's on entry), or is a_v itself for a squaring
 // (bpoly NULL), and is staged with its negation, like a twiddle.  Rounds of 256/m elements,
 // synchronized per wavefront as in level_twiddle.
-template <int L, int FM>
-__device__ __forceinline__ void level_pointwise(Ahead<L>& f, uint32_t* cur, uint32_t* RB,
+template <int C, int FM>
+__device__ __forceinline__ void level_pointwise(Ahead<C>& f, uint32_t* cur, uint32_t* RB,
                                                 const uint32_t* __restrict__ bpoly, const LevelArgs& A,
                                                 long long c0, const QConst& Q) {
-    constexpr int D = Dig<L>::D;
+    constexpr int L = fmt_L(C);
+    constexpr int D = Dig<C>::D;
     const int m = 1 << A.log2m;
     const int EW = A.ew;                                // an element's digits in LDS
     const int per = kThreads >> A.log2m;
@@ -514,22 +528,22 @@ __device__ __forceinline__ void level_pointwise(Ahead<L>& f, uint32_t* cur, uint
             uint32_t bv[D], nb[D];
 #pragma unroll
             for (int y = 0; y < D; ++y) bv[y] = bpoly ? f.v[y] : X[j * D + y];
-            dneg_q<L>(nb, bv, Q);
-            uint32_t* t0 = TP + stage_pos(j, 0, A.log2m) * Dig<L>::DS;
-            uint32_t* t1 = TP + stage_pos(j + m, 0, A.log2m) * Dig<L>::DS;
+            dneg_q<C>(nb, bv, Q);
+            uint32_t* t0 = TP + stage_pos(j, 0, A.log2m) * Dig<C>::DS;
+            uint32_t* t1 = TP + stage_pos(j + m, 0, A.log2m) * Dig<C>::DS;
 #pragma unroll
             for (int y = 0; y < D; ++y) {
                 t0[y] = bv[y];
                 t1[y] = nb[y];
             }
         }
-        if (r0 + per < nel) pw_fetch<L>(f, r0 + per, bpoly, A, c0);     // next round's b
+        if (r0 + per < nel) pw_fetch<C>(f, r0 + per, bpoly, A, c0);     // next round's b
         wave_sync();
         uint32_t out[D];
         if (valid) {
             uint32_t cv[D];
-            rprod_coeff<L, false, FM>(TP, X, A.log2m, j, Q, cv);   // (a*b)_j 2^-28K
-            mont_scalar<L>(cv, Q.kpw, Q, out);              // * (2M)^-1 2^28K
+            rprod_coeff<C, false, FM>(TP, X, A.log2m, j, Q, cv);   // (a*b)_j 2^-28K
+            mont_scalar<C>(cv, Q.kpw, Q, out);              // * (2M)^-1 2^28K
         }
         wave_sync();
         if (valid) {
@@ -547,65 +561,66 @@ __device__ __forceinline__ void level_pointwise(Ahead<L>& f, uint32_t* cur, uint
 // shapes), given to the compiler so that the index arithmetic of the passes and rounds folds and
 // the sum of the products in R unrolls; 0: taken from A (FM > 0 with FR = 0: m fixed, any radix).  LDS: two halves of A.half words; a DFT runs between them on limbs,
 // products run on digits in one half with their operands staged in the other.
-template <int L, int MODE, bool ENC, int FM, int FR>
+template <int C, int MODE, bool ENC, int FM, int FR>
 __global__ __launch_bounds__(kThreads) void k_level(uint32_t* __restrict__ poly0, long long stride,
                                                     const uint32_t* __restrict__ table, LevelArgs A,
                                                     QConst Q, const uint32_t* __restrict__ bpoly0,
                                                     int squaring, ProdArgs PA, int which, long long M) {
+    constexpr int L = fmt_L(C);
     A.mode = MODE;
     if (FM > 0) A.log2m = FM;
     if (FR > 0) A.log2r = FR;
     // words per limb-form residue in LDS: padded to an odd count, so that the lanes of a
     // butterfly pass or a conversion that read consecutive residues hit distinct banks
-    constexpr int LS = Dig<L>::LS;
+    constexpr int LS = Dig<C>::LS;
     uint32_t* __restrict__ poly = poly0 + (size_t)blockIdx.y * stride;
     extern __shared__ uint4 smv[];
     uint32_t* const H0 = reinterpret_cast<uint32_t*>(smv);
     uint32_t* const H1 = H0 + A.half;
     const long long c0 = (long long)blockIdx.x << A.log2C;
     const uint32_t* bpoly = (MODE == 3 && !squaring) ? bpoly0 + (size_t)blockIdx.y * stride : nullptr;
-    Ahead<L> f;
+    Ahead<C> f;
     if (MODE == 2) {
         // twiddles on digits in H0 (operands staged in H1), then limbs in H1 for the DFT
-        tw_fetch<L>(f, 0, table, A, c0);
-        level_load_digits<L>(H0, poly, A, c0);
+        tw_fetch<C>(f, 0, table, A, c0);
+        level_load_digits<C>(H0, poly, A, c0);
         __syncthreads();
-        level_twiddle<L, 2, FM>(f, H0, H1, poly, table, A, c0, Q);
-        lds_to_limbs<L, LS>(H1, H0, A, false);
+        level_twiddle<C, 2, FM>(f, H0, H1, poly, table, A, c0, Q);
+        lds_to_limbs<C, LS>(H1, H0, A, false);
         uint32_t* cur = H1;
         uint32_t* nxt = H0;
-        dft_passes<L, LS>(cur, nxt, A, 1, Q);
-        level_store_limbs<L, LS>(poly, cur, A, c0);
+        dft_passes<C, LS>(cur, nxt, A, 1, Q);
+        level_store_limbs<C, LS>(poly, cur, A, c0);
         return;
     }
     if (ENC) {
         const ProdDesc pd = PA.get();
-        level_encode_in<L, LS>(H0, which ? pd.b : pd.a, which ? pd.blen : pd.alen, pd.u, M, A, c0);
+        level_encode_in<C, LS>(H0, which ? pd.b : pd.a, which ? pd.blen : pd.alen, pd.u, M, A, c0);
     } else {
-        level_load_limbs<L, LS>(H0, poly, A, c0);
+        level_load_limbs<C, LS>(H0, poly, A, c0);
     }
     // round 0's operand after the column loads, so that its latency hides behind the DFT
-    if (MODE == 1) tw_fetch<L>(f, 0, table, A, c0);
-    if (MODE == 3) pw_fetch<L>(f, 0, bpoly, A, c0);
+    if (MODE == 1) tw_fetch<C>(f, 0, table, A, c0);
+    if (MODE == 3) pw_fetch<C>(f, 0, bpoly, A, c0);
     __syncthreads();
     uint32_t* cur = H0;
     uint32_t* nxt = H1;
-    dft_passes<L, LS>(cur, nxt, A, MODE == 3 ? 0 : A.inverse, Q, ENC ? 1 : 0);   // ENC: pass 0 done
+    dft_passes<C, LS>(cur, nxt, A, MODE == 3 ? 0 : A.inverse, Q, ENC ? 1 : 0);   // ENC: pass 0 done
     if (MODE == 0) {
-        level_store_limbs<L, LS>(poly, cur, A, c0);
+        level_store_limbs<C, LS>(poly, cur, A, c0);
         return;
     }
     // digits for the products in the other half; the staging takes the DFT's half
     uint32_t* dg = nxt;
-    lds_to_digits<L, LS>(dg, cur, A);
+    lds_to_digits<C, LS>(dg, cur, A);
     if (MODE == 1) {
-        level_twiddle<L, 1, FM>(f, dg, cur, poly, table, A, c0, Q);
+        level_twiddle<C, 1, FM>(f, dg, cur, poly, table, A, c0, Q);
     } else {
-        level_pointwise<L, FM>(f, dg, cur, bpoly, A, c0, Q);
-        lds_to_limbs<L, LS>(cur, dg, A, true);          // slot v -> bitrev(v): the inverse DFT's input
+        level_pointwise<C, FM>(f, dg, cur, bpoly, A, c0, Q);
+        lds_to_limbs<C, LS>(cur, dg, A, true);          // slot v -> bitrev(v): the inverse DFT's input
         nxt = dg;
-        dft_passes<L, LS>(cur, nxt, A, 1, Q);
-        level_store_limbs<L, LS>(poly, cur, A, c0);
+        dft_passes<C, LS>(cur, nxt, A, 1, Q);
+        level_store_limbs<C, LS>(poly, cur, A, c0);
     }
 }
 
@@ -615,17 +630,18 @@ __global__ __launch_bounds__(kThreads) void k_level(uint32_t* __restrict__ poly0
 
 // m threads per element, 256/m elements per workgroup; LDS per element: a and q - a (2m
 // residues) and b (m residues), digits.
-template <int L>
+template <int C>
 __global__ __launch_bounds__(kThreads) void k_pointwise(uint32_t* A0, const uint32_t* B0, long long stride,
                                                         long long count, int log2m, QConst Q) {
-    constexpr int D = Dig<L>::D;
+    constexpr int L = fmt_L(C);
+    constexpr int D = Dig<C>::D;
     uint32_t* A = A0 + (size_t)blockIdx.y * stride;
     const uint32_t* B = B0 + (size_t)blockIdx.y * stride;
     extern __shared__ uint32_t sm[];
     const int m = 1 << log2m;
     const int per = kThreads >> log2m;
     const int g = threadIdx.x >> log2m, j = threadIdx.x & (m - 1);
-    constexpr int DS = Dig<L>::DS;
+    constexpr int DS = Dig<C>::DS;
     uint32_t* TP = sm + g * m * (2 * DS + D);
     uint32_t* X = TP + 2 * m * DS;
     const long long p = (long long)blockIdx.x * per + g;
@@ -639,11 +655,11 @@ __global__ __launch_bounds__(kThreads) void k_pointwise(uint32_t* A0, const uint
             la[w] = sa[w];
             lb[w] = sb[w];
         }
-        limbs_to_digits<L>(la, x);
-        limbs_to_digits<L>(lb, xb);
+        limbs_to_digits<C>(la, x);
+        limbs_to_digits<C>(lb, xb);
 #pragma unroll
         for (int w = 0; w < D; ++w) X[j * D + w] = xb[w];
-        dneg_q<L>(nx, x, Q);
+        dneg_q<C>(nx, x, Q);
 #pragma unroll
         for (int w = 0; w < D; ++w) {
             TP[stage_pos(j, 0, log2m) * DS + w] = x[w];
@@ -653,9 +669,9 @@ __global__ __launch_bounds__(kThreads) void k_pointwise(uint32_t* A0, const uint
     __syncthreads();
     if (active) {
         uint32_t c[D], out[D], lo[L];
-        rprod_coeff<L>(TP, X, log2m, j, Q, c);        // (a*b)_j 2^-28K
-        mont_scalar<L>(c, Q.kpw, Q, out);             // * (2M)^-1 2^28K
-        digits_to_limbs<L>(out, lo);
+        rprod_coeff<C>(TP, X, log2m, j, Q, c);        // (a*b)_j 2^-28K
+        mont_scalar<C>(c, Q.kpw, Q, out);             // * (2M)^-1 2^28K
+        digits_to_limbs<C>(out, lo);
         uint32_t* dst = A + ((size_t)p * m + j) * L;
 #pragma unroll
         for (int w = 0; w < L; ++w) dst[w] = lo[w];
@@ -672,10 +688,11 @@ __global__ __launch_bounds__(kThreads) void k_pointwise(uint32_t* A0, const uint
 // the integer X_p = sum_j a_j 2^(slot j) of wks limbs; slot = 2 bits(q) + ceil(log2 m) holds any
 // coefficient of the product polynomial (a sum of m products below q^2).  Since slot exceeds
 // bits(q) + 32, a 32-bit window meets at most one coefficient.  One thread per limb.
-template <int L>
+template <int C>
 __global__ __launch_bounds__(kThreads) void k_ks_pack(uint32_t* __restrict__ X, const uint32_t* __restrict__ A0,
                                                       long long stride, long long count, int log2m, int slot,
                                                       int wks) {
+    constexpr int L = fmt_L(C);
     const long long t = (long long)blockIdx.x * kThreads + threadIdx.x;
     if (t >= count * wks) return;
     const size_t y = blockIdx.y;
@@ -706,11 +723,12 @@ __global__ __launch_bounds__(kThreads) void k_ks_pack(uint32_t* __restrict__ X, 
 // the sums of the product polynomial's coefficients j and j + m, below m q^2 <= 64 q^2; each is
 // reduced by Montgomery's method from its 28-bit digits, then c_j = (s_j - s_(j+m)) (2M)^-1
 // (alpha^m = -1), written as limbs.  One thread per coefficient.
-template <int L>
+template <int C>
 __global__ __launch_bounds__(kThreads) void k_ks_unpack(uint32_t* A0, long long stride,
                                                         const uint32_t* __restrict__ Z0, long long count,
                                                         int log2m, int slot, int wks, QConst Q) {
-    using G = Dig<L>;
+    constexpr int L = fmt_L(C);
+    using G = Dig<C>;
     constexpr int D = G::D;
     const long long t = (long long)blockIdx.x * kThreads + threadIdx.x;
     const int m = 1 << log2m;
@@ -737,7 +755,7 @@ __global__ __launch_bounds__(kThreads) void k_ks_unpack(uint32_t* A0, long long 
             }
             col[k] = d;
         }
-        redc_cols<L>(col, Q, r);
+        redc_cols<C>(col, Q, r);
     };
     uint32_t r1[D], r2[D], c[D], out[D], lo[L];
     reduce_slot(j, r1);
@@ -747,9 +765,9 @@ __global__ __launch_bounds__(kThreads) void k_ks_unpack(uint32_t* A0, long long 
 #pragma unroll
         for (int k = 0; k < D; ++k) r2[k] = 0;
     }
-    dmod_sub<L>(c, r1, r2, Q);                     // (a*b)_j 2^-28K
-    mont_scalar<L>(c, Q.kpw, Q, out);              // * (2M)^-1 2^28K
-    digits_to_limbs<L>(out, lo);
+    dmod_sub<C>(c, r1, r2, Q);                     // (a*b)_j 2^-28K
+    mont_scalar<C>(c, Q.kpw, Q, out);              // * (2M)^-1 2^28K
+    digits_to_limbs<C>(out, lo);
     uint32_t* dst = A0 + y * stride + (((size_t)p << log2m) + j) * L;
 #pragma unroll
     for (int k = 0; k < L; ++k) dst[k] = lo[k];
@@ -782,16 +800,17 @@ __global__ __launch_bounds__(kThreads) void k_table_put(uint32_t* __restrict__ t
     if ((int)threadIdx.x < count) table[first + threadIdx.x] = ch.w[threadIdx.x];
 }
 
-template <int L>
+template <int C>
 __global__ __launch_bounds__(kThreads) void k_table_mul(uint32_t* table, long long src, long long mul,
                                                         long long dst, long long cnt, int log2m,
                                                         QConst Q) {
-    constexpr int D = Dig<L>::D;
+    constexpr int L = fmt_L(C);
+    constexpr int D = Dig<C>::D;
     extern __shared__ uint32_t sm[];
     const int m = 1 << log2m;
     const int per = kThreads >> log2m;
     const int g = threadIdx.x >> log2m, j = threadIdx.x & (m - 1);
-    constexpr int DS = Dig<L>::DS;
+    constexpr int DS = Dig<C>::DS;
     uint32_t* TP = sm + g * m * (2 * DS + D);
     uint32_t* X = TP + 2 * m * DS;
     const long long jj = (long long)blockIdx.x * per + g;
@@ -802,7 +821,7 @@ __global__ __launch_bounds__(kThreads) void k_table_mul(uint32_t* table, long lo
         uint32_t tv[D], nt[D];
 #pragma unroll
         for (int y = 0; y < D; ++y) tv[y] = ts[j * D + y];
-        dneg_q<L>(nt, tv, Q);
+        dneg_q<C>(nt, tv, Q);
 #pragma unroll
         for (int y = 0; y < D; ++y) {
             X[j * D + y] = xs[j * D + y];
@@ -813,7 +832,7 @@ __global__ __launch_bounds__(kThreads) void k_table_mul(uint32_t* table, long lo
     __syncthreads();
     if (active) {
         uint32_t out[D];
-        rprod_coeff<L>(TP, X, log2m, j, Q, out);
+        rprod_coeff<C>(TP, X, log2m, j, Q, out);
         uint32_t* dp = table + (size_t)(dst + jj) * m * D;
 #pragma unroll
         for (int y = 0; y < D; ++y) dp[j * D + y] = out[y];
@@ -836,9 +855,10 @@ __device__ __forceinline__ long long div_u(long long x, int u, double inv_u) {
 }
 
 // poly holds the elements from lbase on (the whole polynomial: lbase 0).
-template <int L>
+template <int C>
 __device__ __forceinline__ uint64_t word_sum(long long w, const uint32_t* __restrict__ poly, long long lbase,
                                              long long twoM, int log2m, int u) {
+    constexpr int L = fmt_L(C);
     const int m = 1 << log2m;
     const int hm = m >> 1;
     const double inv_u = 1.0 / (double)u;
@@ -873,17 +893,20 @@ __device__ __forceinline__ uint64_t word_sum(long long w, const uint32_t* __rest
 }
 
 // Words of a position's aligned value: V_g < 2q < 2^(32L + 1) shifted left by up to 31 bits.
-template <int L>
-__host__ __device__ constexpr int pos_words() { return L + 1; }
+template <int C>
+__host__ __device__ constexpr int pos_words() {
+    return fmt_L(C) + 1;
+}
 
 // Position g = l m/2 + k (k < m/2) of the product's coefficient sequence: the value
 // V_g = c_(l,k) + c_(l-1,k+m/2) (the upper half of element l-1 overlaps the lower half of element l,
 // Sec. 3.2.8) starts at bit u g.  Writes V_g shifted left by (u g) mod 32 as pos_words() words,
 // so that word i of it is bits [32 (W_g + i), 32 (W_g + i + 1)) of its contribution, W_g = u g div 32.
-template <int L>
+template <int C>
 __device__ __forceinline__ void position_value(const uint32_t* __restrict__ poly, long long g, long long twoM,
                                                int log2m, int u, uint32_t* out) {
-    constexpr int NW = pos_words<L>();
+    constexpr int L = fmt_L(C);
+    constexpr int NW = pos_words<C>();
     const int m = 1 << log2m, hm = m >> 1;
     const long long l = g >> (log2m - 1);
     const int k = (int)(g & (hm - 1));
@@ -922,10 +945,11 @@ __device__ __forceinline__ int div_small(int y, int u, float inv_u) {
 // are taken relative to the workgroup's base bq (bq u is at most every numerator here, and the
 // numerators exceed it by less than 2^15), so that they are small divisions; the bit offset u g
 // of each position advances by u per step.
-template <int L>
+template <int C>
 __device__ __forceinline__ uint64_t word_sum_tiled(long long w, const uint32_t* pv, long long g_min, long long g_max,
                                                    int u, long long bq, float inv_u) {
-    constexpr int NW = pos_words<L>();
+    constexpr int L = fmt_L(C);
+    constexpr int NW = pos_words<C>();
     const long long B = bq * u;
     const long long lo_excl = 32 * w - (32 * L + 1);      // V_g reaches word w iff u g > lo_excl
     long long g = lo_excl < 0 ? 0 : bq + div_small((int)(lo_excl - B), u, inv_u) + 1;
@@ -943,13 +967,14 @@ __device__ __forceinline__ uint64_t word_sum_tiled(long long w, const uint32_t* 
 // and the per-wavefront generate / propagate masks.  TILED: the workgroup first writes the
 // aligned values of the positions its words draw on into LDS (one position per thread and step),
 // then sums each word from them; the host picks it when those positions fit.
-template <int L, bool TILED>
+template <int C, bool TILED>
 __global__ __launch_bounds__(kThreads) void k_decode(ProdArgs PA, const uint32_t* __restrict__ poly0,
                                                      long long stride, long long twoM, int log2m,
                                                      unsigned long long* __restrict__ gmask0,
                                                      unsigned long long* __restrict__ pmask0,
                                                      long long wstride) {
-    constexpr int NW = pos_words<L>();
+    constexpr int L = fmt_L(C);
+    constexpr int NW = pos_words<C>();
     __shared__ uint32_t hiv[kThreads + 1];
     extern __shared__ uint4 dsmv[];
     const ProdDesc pd = PA.get();
@@ -975,15 +1000,15 @@ __global__ __launch_bounds__(kThreads) void k_decode(ProdArgs PA, const uint32_t
             g_max = div_u(32 * whi + 31, u, inv_u);
         }
         for (long long g = g_min + threadIdx.x; g <= g_max; g += kThreads)
-            position_value<L>(poly, g, twoM, log2m, u, pv + (g - g_min) * NW);
+            position_value<C>(poly, g, twoM, log2m, u, pv + (g - g_min) * NW);
         __syncthreads();
         const long long bq = g_min > 0 ? g_min - 1 : 0;    // floor(lo_excl(w0 - 1) / u)
         const float inv_uf = 1.0f / (float)u;
-        if (w < nw) V = word_sum_tiled<L>(w, pv, g_min, g_max, u, bq, inv_uf);
-        if (threadIdx.x == 0 && w0 > 0 && w0 < nw) Vprev = word_sum_tiled<L>(w0 - 1, pv, g_min, g_max, u, bq, inv_uf);
+        if (w < nw) V = word_sum_tiled<C>(w, pv, g_min, g_max, u, bq, inv_uf);
+        if (threadIdx.x == 0 && w0 > 0 && w0 < nw) Vprev = word_sum_tiled<C>(w0 - 1, pv, g_min, g_max, u, bq, inv_uf);
     } else {
-        if (w < nw) V = word_sum<L>(w, poly, 0, twoM, log2m, u);
-        if (threadIdx.x == 0 && w0 > 0 && w0 < nw) Vprev = word_sum<L>(w0 - 1, poly, 0, twoM, log2m, u);
+        if (w < nw) V = word_sum<C>(w, poly, 0, twoM, log2m, u);
+        if (threadIdx.x == 0 && w0 > 0 && w0 < nw) Vprev = word_sum<C>(w0 - 1, poly, 0, twoM, log2m, u);
     }
     hiv[threadIdx.x + 1] = (uint32_t)(V >> 32);
     if (threadIdx.x == 0) hiv[0] = (uint32_t)(Vprev >> 32);
@@ -1370,9 +1395,10 @@ struct LevelIdx {
 };
 
 // one thread per coefficient: position pos holds a(rho^f), f from the digits of pos
-template <int L>
+template <int C>
 __global__ void k_unscramble(uint32_t* __restrict__ dst, const uint32_t* __restrict__ src,
                              long long twoM, int log2m, LevelIdx LI) {
+    constexpr int L = fmt_L(C);
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= (twoM << log2m)) return;
     const long long pos = t >> log2m;
@@ -1556,8 +1582,6 @@ struct Call {
     std::shared_ptr<Call> ks_inner;
 };
 
-int dig_D(int L) { return (32 * L + 28) / 28; }
-int dig_K(int L) { return (32 * L + 6 + 27) / 28; }
 // 32-bit limbs of q = p^z for a prime of pb bits (q < 2^(z pb)); exact for z = 1 and z = 2
 int tuple_limbs(int pb, int z) { return (z * pb + 31) / 32; }
 
@@ -1817,7 +1841,10 @@ int plan_constants(dkss_ctx* ctx, Call* call) {
         c->plan = P;
         if (!compute_constants(&c->plan)) return DKSS_ERANGE;
         if (c->plan.L > kMaxL) return DKSS_ERANGE;
-        const int L = c->plan.L, D = dig_D(L), K = dig_K(L);
+        // the tight format where q fits one digit fewer (not for one limb: no kernels for it)
+        const int tight = fmt_code(c->plan.L, true);
+        c->plan.fmt = fmt_code(c->plan.L, c->plan.L >= 2 && c->plan.q_bits <= fmt_qbits(tight));
+        const int L = c->plan.L, D = fmt_D(c->plan.fmt), K = fmt_K(c->plan.fmt);
         c->D = D;
         const Plan& CP = c->plan;
         ModQ mq(CP.q);
@@ -1886,10 +1913,10 @@ int plan_constants(dkss_ctx* ctx, Call* call) {
     return DKSS_OK;
 }
 
-// launch helpers, dispatched on L
+// launch helpers, dispatched on the residue format (limbs, tight digits)
 template <template <int> class F, typename... A>
-int dispatch_L(int L, const A&... args) {
-    switch (L) {
+int dispatch_fmt(int fmt, const A&... args) {
+    switch (fmt) {
         case 1: return F<1>::run(args...);
         case 2: return F<2>::run(args...);
         case 3: return F<3>::run(args...);
@@ -1898,43 +1925,51 @@ int dispatch_L(int L, const A&... args) {
         case 6: return F<6>::run(args...);
         case 7: return F<7>::run(args...);
         case 8: return F<8>::run(args...);
+        case 16 + 2: return F<16 + 2>::run(args...);
+        case 16 + 3: return F<16 + 3>::run(args...);
+        case 16 + 4: return F<16 + 4>::run(args...);
+        case 16 + 5: return F<16 + 5>::run(args...);
+        case 16 + 6: return F<16 + 6>::run(args...);
+        case 16 + 7: return F<16 + 7>::run(args...);
+        case 16 + 8: return F<16 + 8>::run(args...);
         default: return DKSS_ERANGE;
     }
 }
 
 // LDS of the R-product kernels: kThreads coefficient slots, 3 D digits each (T, x, q - x)
-size_t rprod_lds(int L) { return (size_t)kThreads * (2 * (dig_D(L) | 1) + dig_D(L)) * sizeof(uint32_t); }
+size_t rprod_lds(int fmt) { return (size_t)kThreads * (2 * (fmt_D(fmt) | 1) + fmt_D(fmt)) * sizeof(uint32_t); }
 
-template <int L>
+template <int C>
 struct TableBuild {
+    static constexpr int L = fmt_L(C);
     // tab[dst + j] = tab[src + j] * tab[mul], j < cnt
-    static int launch(const Cached* C, uint32_t* tab, Prof* prof, hipStream_t s, long long src, long long mul,
+    static int launch(const Cached* tc, uint32_t* tab, Prof* prof, hipStream_t s, long long src, long long mul,
                       long long dst, long long cnt) {
-        const int m = C->plan.m();
+        const int m = tc->plan.m();
         const int per = kThreads / m;
         const unsigned blocks = (unsigned)((cnt + per - 1) / per);
-        ProfScope ps(prof, DKSS_K_TABLE, s, 2.0 * cnt * m * dig_D(L) * 4, (double)cnt * m * m * L * L);
-        hipLaunchKernelGGL(k_table_mul<L>, dim3(blocks), dim3(kThreads), rprod_lds(L), s, tab, src, mul, dst, cnt,
-                           C->plan.log2_m, C->Q);
+        ProfScope ps(prof, DKSS_K_TABLE, s, 2.0 * cnt * m * Dig<C>::D * 4, (double)cnt * m * m * L * L);
+        hipLaunchKernelGGL(k_table_mul<C>, dim3(blocks), dim3(kThreads), rprod_lds(C), s, tab, src, mul, dst, cnt,
+                           tc->plan.log2_m, tc->Q);
         return launch_status();
     }
-    // The whole table into tab (C->table_bytes() bytes), on stream s: entries 0 (one) and 1
+    // The whole table into tab (tc->table_bytes() bytes), on stream s: entries 0 (one) and 1
     // (rho) from the host as launch arguments; then for n = 2, 4, ...: rho^n = rho^(n/2)
     // rho^(n/2), and rho^(n+j) = rho^j rho^n for 0 < j < n.
-    static int run(const Cached* C, uint32_t* tab, Prof* prof, hipStream_t s) {
-        const size_t words01 = (size_t)std::min<long long>(C->table_count, 2) * C->plan.m() * C->D;
+    static int run(const Cached* tc, uint32_t* tab, Prof* prof, hipStream_t s) {
+        const size_t words01 = (size_t)std::min<long long>(tc->table_count, 2) * tc->plan.m() * tc->D;
         for (size_t off = 0; off < words01; off += kPutWords) {
             PutChunk ch;
             const int n = (int)std::min<size_t>(kPutWords, words01 - off);
-            memcpy(ch.w, C->table_host01.data() + off, (size_t)n * sizeof(uint32_t));
+            memcpy(ch.w, tc->table_host01.data() + off, (size_t)n * sizeof(uint32_t));
             hipLaunchKernelGGL(k_table_put, dim3(1), dim3(kThreads), 0, s, tab, ch, (long long)off, n);
         }
         int rc = launch_status();
         if (rc) return rc;
-        for (long long n = 2; n < C->table_count; n *= 2) {
-            if ((rc = launch(C, tab, prof, s, n / 2, n / 2, n, 1))) return rc;
-            const long long cnt = std::min(n, C->table_count - n) - 1;
-            if (cnt > 0 && (rc = launch(C, tab, prof, s, 1, n, n + 1, cnt))) return rc;
+        for (long long n = 2; n < tc->table_count; n *= 2) {
+            if ((rc = launch(tc, tab, prof, s, n / 2, n / 2, n, 1))) return rc;
+            const long long cnt = std::min(n, tc->table_count - n) - 1;
+            if (cnt > 0 && (rc = launch(tc, tab, prof, s, 1, n, n + 1, cnt))) return rc;
         }
         return DKSS_OK;
     }
@@ -1952,7 +1987,7 @@ int ensure_table(Cached* C, Prof* prof, hipStream_t s) {
     if (cs != hipStreamCaptureStatusNone) return DKSS_EINVAL;
     uint32_t* d = nullptr;
     HIP_OK(hipMalloc(&d, C->table_bytes()));
-    int rc = dispatch_L<TableBuild>(C->plan.L, C, d, prof, s);
+    int rc = dispatch_fmt<TableBuild>(C->plan.fmt, C, d, prof, s);
     if (!rc) rc = note_hip(hipStreamSynchronize(s));
     if (rc) {
         (void)hipStreamSynchronize(s);
@@ -2043,8 +2078,9 @@ size_t ks_bytes(const Call& c, size_t G) {
     return b;
 }
 
-template <int L>
+template <int C>
 struct Transform {
+    static constexpr int L = fmt_L(C);
     // Forward (inverse = 0) or inverse (inverse = 1) transform of G polynomials in place.
     // fused (forward): the bottom level also multiplies componentwise by bpoly (poly itself if
     // squaring, (2M)^-1 included) and runs the bottom inverse level, so the inverse transform
@@ -2074,11 +2110,11 @@ struct Transform {
             const int log2r = P.radix_log2[k];
             const int r = 1 << log2r;
             const long long ncols = twoM >> log2r;
-            constexpr int D = Dig<L>::D;
+            constexpr int D = Dig<C>::D;
             const bool pw = fused && !inverse && k == nl - 1;     // fused componentwise products
             // columns per workgroup: two LDS halves of C columns (limbs; digits too where the
             // products run) within the budget, at most ncols; one column on twiddle levels
-            const size_t colbytes = (size_t)r * (pw ? elem_words(m, D) : m * Dig<L>::LS) * 4;
+            const size_t colbytes = (size_t)r * (pw ? elem_words(m, D) : m * Dig<C>::LS) * 4;
             int log2C = 0;
             while (!tw && (2 * colbytes << (log2C + 1)) <= (size_t)c.dft_lds &&
                    (1LL << (log2C + 1)) <= ncols)
@@ -2098,8 +2134,8 @@ struct Transform {
             // two halves: each holds the columns in limbs (DFT) and, where products run, the
             // columns in digits and the staging of 256/m operands of 2m residues
             A.ew = elem_words(m, D);
-            A.sw = stage_words(m, Dig<L>::DS);
-            const size_t ncl = ((size_t)r << log2C) * m * Dig<L>::LS;
+            A.sw = stage_words(m, Dig<C>::DS);
+            const size_t ncl = ((size_t)r << log2C) * m * Dig<C>::LS;
             const size_t ncd = ((size_t)r << log2C) * A.ew;
             const size_t rb_words = (size_t)(kThreads / m) * A.sw;
             size_t half = ncl;
@@ -2119,7 +2155,7 @@ struct Transform {
             const uint32_t* bp = pw ? bpoly : nullptr;
             const int sq = pw ? squaring : 0;
 #define DKSS_LEVEL_AT(MD, EC, FM, FR)                                                                \
-    hipLaunchKernelGGL((k_level<L, MD, EC, FM, FR>), dim3(blocks, G), dim3(kThreads), lds, s, poly,     \
+    hipLaunchKernelGGL((k_level<C, MD, EC, FM, FR>), dim3(blocks, G), dim3(kThreads), lds, s, poly,     \
                        (long long)stride, tab, A, Q, bp, sq, PA, which, M)
 #define DKSS_LEVEL(MD, EC)                                                                          \
     do {                                                                                            \
@@ -2166,8 +2202,9 @@ struct Transform {
     }
 };
 
-template <int L>
+template <int C>
 struct Encode {
+    static constexpr int L = fmt_L(C);
     // operand a (which = 0) or b (which = 1) of each product into poly + y * stride
     static int run(const Call& c, const ProdArgs& PA, unsigned G, int which, uint32_t* poly, size_t stride,
                    double in_words, hipStream_t s) {
@@ -2176,14 +2213,15 @@ struct Encode {
         if (!grid_ok((size_t)((total + kThreads - 1) / kThreads))) return DKSS_ERANGE;
         const unsigned blocks = (unsigned)((total + kThreads - 1) / kThreads);
         ProfScope ps(c.prof, DKSS_K_ENCODE, s, 4.0 * in_words + 4.0 * G * total * L, 0.0);
-        hipLaunchKernelGGL(k_encode<L>, dim3(blocks, G), dim3(kThreads), 0, s, PA, which, poly,
+        hipLaunchKernelGGL(k_encode<C>, dim3(blocks, G), dim3(kThreads), 0, s, PA, which, poly,
                            (long long)stride, M, c.P.log2_m);
         return launch_status();
     }
 };
 
-template <int L>
+template <int C>
 struct Pointwise {
+    static constexpr int L = fmt_L(C);
     static int run(const Call& c, uint32_t* A, const uint32_t* B, size_t stride, unsigned G, hipStream_t s) {
         const long long count = 2LL << c.P.log2_M;
         const int per = kThreads / c.P.m();
@@ -2192,14 +2230,15 @@ struct Pointwise {
         const int m = c.P.m();
         ProfScope ps(c.prof, DKSS_K_POINTWISE, s, 3.0 * G * count * m * L * 4,
                      (double)G * count * ((double)m * m * L * L + (double)m * L * L));
-        hipLaunchKernelGGL(k_pointwise<L>, dim3(blocks, G), dim3(kThreads), rprod_lds(L), s, A, B,
+        hipLaunchKernelGGL(k_pointwise<C>, dim3(blocks, G), dim3(kThreads), rprod_lds(C), s, A, B,
                            (long long)stride, count, c.P.log2_m, c.C->Q);
         return launch_status();
     }
 };
 
-template <int L>
+template <int C>
 struct Decode {
+    static constexpr int L = fmt_L(C);
     // u_min: the smallest u of the products (it bounds the elements one workgroup reads)
     static int run(const Call& c, const ProdArgs& PA, unsigned G, size_t nw_max, double out_words,
                    const Workspace& w, hipStream_t s, int u_min) {
@@ -2213,13 +2252,13 @@ struct Decode {
             // positions per workgroup: the values reaching 257 words start within
             // 32*257 + 32L + 1 bits, (32*257 + 32L + 1)/u + 2 positions of pos_words() words each
             const long long gspan = (32LL * (kThreads + 1) + 32 * L + 1) / std::max(u_min, 1) + 2;
-            const long long tile_words = gspan * pos_words<L>();
+            const long long tile_words = gspan * pos_words<C>();
             if (u_min >= 1 && tile_words * 4 <= 32768)
-                hipLaunchKernelGGL((k_decode<L, true>), dim3(blocks, G), dim3(kThreads), tile_words * 4, s, PA,
+                hipLaunchKernelGGL((k_decode<C, true>), dim3(blocks, G), dim3(kThreads), tile_words * 4, s, PA,
                                    (const uint32_t*)w.A, (long long)w.S, 2LL << c.P.log2_M, c.P.log2_m,
                                    w.gmask, w.pmask, (long long)w.wst);
             else
-                hipLaunchKernelGGL((k_decode<L, false>), dim3(blocks, G), dim3(kThreads), 0, s, PA,
+                hipLaunchKernelGGL((k_decode<C, false>), dim3(blocks, G), dim3(kThreads), 0, s, PA,
                                    (const uint32_t*)w.A, (long long)w.S, 2LL << c.P.log2_M, c.P.log2_m,
                                    w.gmask, w.pmask, (long long)w.wst);
         }
@@ -2267,13 +2306,14 @@ int dkss::carry_resolve(uint32_t* c, long long nw, unsigned long long* gmask, un
 
 namespace {
 
-template <int L>
+template <int C>
 struct Unscramble {
+    static constexpr int L = fmt_L(C);
     static int run(const Call& c, uint32_t* poly, const uint32_t* src, const LevelIdx& LI, hipStream_t s) {
         const long long twoM = 2LL << c.P.log2_M;
         const long long total = twoM << c.P.log2_m;
-        ProfScope ps(c.prof, DKSS_K_UNSCRAMBLE, s, (4.0 * L + 4.0 * Dig<L>::D) * total, 0.0);
-        hipLaunchKernelGGL(k_unscramble<L>, dim3((unsigned)((total + kThreads - 1) / kThreads)), dim3(kThreads),
+        ProfScope ps(c.prof, DKSS_K_UNSCRAMBLE, s, (4.0 * L + 4.0 * Dig<C>::D) * total, 0.0);
+        hipLaunchKernelGGL(k_unscramble<C>, dim3((unsigned)((total + kThreads - 1) / kThreads)), dim3(kThreads),
                            0, s, poly, src, twoM, c.P.log2_m, LI);
         return launch_status();
     }
@@ -2327,25 +2367,27 @@ int run_group(const Call& call, const ProdArgs& PA, unsigned G, size_t nw_max, d
 int launch_schoolbook(const Call& call, const ProdArgs& PA, unsigned G, size_t nw_max, double ops,
                       hipStream_t s);
 
-template <int L>
+template <int C>
 struct KsPack {
+    static constexpr int L = fmt_L(C);
     static int run(const Call& c, uint32_t* X, const uint32_t* A, size_t stride, unsigned G, hipStream_t s) {
         const long long count = 2LL << c.P.log2_M;
         const long long total = count * c.ks_wks;
         if (!grid_ok((size_t)((total + kThreads - 1) / kThreads))) return DKSS_ERANGE;
-        hipLaunchKernelGGL(k_ks_pack<L>, dim3((unsigned)((total + kThreads - 1) / kThreads), G), dim3(kThreads), 0, s,
+        hipLaunchKernelGGL(k_ks_pack<C>, dim3((unsigned)((total + kThreads - 1) / kThreads), G), dim3(kThreads), 0, s,
                            X, A, (long long)stride, count, c.P.log2_m, c.ks_slot, c.ks_wks);
         return launch_status();
     }
 };
 
-template <int L>
+template <int C>
 struct KsUnpack {
+    static constexpr int L = fmt_L(C);
     static int run(const Call& c, uint32_t* A, const uint32_t* Z, size_t stride, unsigned G, hipStream_t s) {
         const long long count = 2LL << c.P.log2_M;
         const long long total = count << c.P.log2_m;
         if (!grid_ok((size_t)((total + kThreads - 1) / kThreads))) return DKSS_ERANGE;
-        hipLaunchKernelGGL(k_ks_unpack<L>, dim3((unsigned)((total + kThreads - 1) / kThreads), G), dim3(kThreads), 0,
+        hipLaunchKernelGGL(k_ks_unpack<C>, dim3((unsigned)((total + kThreads - 1) / kThreads), G), dim3(kThreads), 0,
                            s, A, (long long)stride, Z, count, c.P.log2_m, c.ks_slot, c.ks_wks, c.C->Q);
         return launch_status();
     }
@@ -2365,8 +2407,8 @@ int ks_pointwise(const Call& c, uint32_t* A, const uint32_t* B, size_t stride, u
     ProdDesc* d = (ProdDesc*)(ks + 2 * align256(cnt * wks * 4) + align256(cnt * 2 * wks * 4));
     char* iws = (char*)d + align256(cnt * sizeof(ProdDesc));
     int rc;
-    if ((rc = dispatch_L<KsPack>(c.P.L, c, X, A, stride, G, s))) return rc;
-    if (B && (rc = dispatch_L<KsPack>(c.P.L, c, Y, B, stride, G, s))) return rc;
+    if ((rc = dispatch_fmt<KsPack>(c.P.fmt, c, X, A, stride, G, s))) return rc;
+    if (B && (rc = dispatch_fmt<KsPack>(c.P.fmt, c, Y, B, stride, G, s))) return rc;
     hipLaunchKernelGGL(k_ks_descs, dim3((unsigned)((cnt + kThreads - 1) / kThreads)), dim3(kThreads), 0, s, d, Z, X,
                        B ? (const uint32_t*)Y : (const uint32_t*)X, (long long)cnt, (int)wks, in.P.u);
     if ((rc = launch_status())) return rc;
@@ -2377,7 +2419,7 @@ int ks_pointwise(const Call& c, uint32_t* A, const uint32_t* B, size_t stride, u
         const size_t Gmax = std::min<size_t>(cnt, 65535);
         Workspace iw = layout_call(ic, Gmax, 2 * wks, true, iws, ic.C->table_bytes());
         ic.table = ic.C->table_ready ? ic.C->d_table : iw.tab;
-        if (!ic.C->table_ready && (rc = dispatch_L<TableBuild>(ic.P.L, ic.C, iw.tab, c.prof, s))) return rc;
+        if (!ic.C->table_ready && (rc = dispatch_fmt<TableBuild>(ic.P.fmt, ic.C, iw.tab, c.prof, s))) return rc;
         for (size_t g0 = 0; g0 < cnt; g0 += 65535) {
             const unsigned Gi = (unsigned)std::min<size_t>(65535, cnt - g0);
             ProdArgs PA{};
@@ -2395,14 +2437,14 @@ int ks_pointwise(const Call& c, uint32_t* A, const uint32_t* B, size_t stride, u
             if ((rc = launch_schoolbook(ic, PA, Gi, 2 * wks, (double)Gi * wks * wks, s))) return rc;
         }
     }
-    return dispatch_L<KsUnpack>(c.P.L, c, A, Z, stride, G, s);
+    return dispatch_fmt<KsUnpack>(c.P.fmt, c, A, Z, stride, G, s);
 }
 
 // The DKSS pipeline (Steps 4-8) for G products sharing call's plan, described by PA; the
 // workspace w holds their polynomials at stride w.S.  With squaring, b is not transformed.
 int run_group(const Call& call, const ProdArgs& PA, unsigned G, size_t nw_max, double in_a, double in_b,
               double out_w, bool squaring, const Workspace& w, hipStream_t s, int u_min) {
-    const int L = call.P.L;
+    const int fmt = call.P.fmt;
     int rc;
     // the transform of b on the auxiliary stream (forked from s, joined back before the products)
     const bool fork = !squaring && call.aux;
@@ -2412,14 +2454,14 @@ int run_group(const Call& call, const ProdArgs& PA, unsigned G, size_t nw_max, d
         HIP_OK(hipStreamWaitEvent(sb, call.ev_fork, 0));
     }
     // the encoding of each operand runs inside the top level of its transform
-    if (!squaring && (rc = dispatch_L<Transform>(L, call, w.B, w.S, G, 0, sb, 0, nullptr, 0, &PA, 1, in_b)))
+    if (!squaring && (rc = dispatch_fmt<Transform>(fmt, call, w.B, w.S, G, 0, sb, 0, nullptr, 0, &PA, 1, in_b)))
         return rc;
     // the componentwise products run inside the bottom level of a's transform (one launch for
     // the last forward level, the products and the first inverse level) unless b is still being
     // transformed on the other stream
     const int fz = (call.fuse_pw && !fork && !call.ks_inner) ? 1 : 0;
     const uint32_t* bp = squaring ? (const uint32_t*)w.A : w.B;
-    if ((rc = dispatch_L<Transform>(L, call, w.A, w.S, G, 0, s, fz, squaring ? nullptr : bp,
+    if ((rc = dispatch_fmt<Transform>(fmt, call, w.A, w.S, G, 0, s, fz, squaring ? nullptr : bp,
                                     squaring ? 1 : 0, &PA, 0, in_a)))
         return rc;
     if (fork) {
@@ -2428,11 +2470,11 @@ int run_group(const Call& call, const ProdArgs& PA, unsigned G, size_t nw_max, d
     }
     if (call.ks_inner) {
         if ((rc = ks_pointwise(call, w.A, squaring ? nullptr : bp, w.S, G, w.ks, s))) return rc;
-    } else if (!fz && (rc = dispatch_L<Pointwise>(L, call, w.A, bp, w.S, G, s))) {
+    } else if (!fz && (rc = dispatch_fmt<Pointwise>(fmt, call, w.A, bp, w.S, G, s))) {
         return rc;
     }
-    if ((rc = dispatch_L<Transform>(L, call, w.A, w.S, G, 1, s, fz))) return rc;
-    return dispatch_L<Decode>(L, call, PA, G, nw_max, out_w, w, s, u_min);
+    if ((rc = dispatch_fmt<Transform>(fmt, call, w.A, w.S, G, 1, s, fz))) return rc;
+    return dispatch_fmt<Decode>(fmt, call, PA, G, nw_max, out_w, w, s, u_min);
 }
 
 int launch_zero(const ProdArgs& PA, unsigned G, size_t nw_max, hipStream_t s) {
@@ -2512,7 +2554,7 @@ int use_table(Call* call, const Workspace& w, hipStream_t s) {
     }
     if (!w.tab) return DKSS_ENOSPC;
     call->table = w.tab;
-    return dispatch_L<TableBuild>(call->P.L, call->C, w.tab, call->prof, s);
+    return dispatch_fmt<TableBuild>(call->P.fmt, call->C, w.tab, call->prof, s);
 }
 
 int run_mul(Call call, uint32_t* c, const uint32_t* a, size_t alen, const uint32_t* b, size_t blen,
@@ -2975,6 +3017,7 @@ int dkss_plan_info(dkss_ctx* ctx, size_t alen, size_t blen, const dkss_params* p
         out->poly_bytes = poly_words(P) * 4;
         out->table_bytes = call.C->table_bytes();
         for (int i = 0; i < P.L && i < 16; ++i) out->q[i] = P.q.limb32(i);
+        out->digits = (uint32_t)fmt_D(P.fmt);
     }
     return DKSS_OK;
 }
@@ -3134,7 +3177,7 @@ static int enqueue_batch(const dkss_ctx* ctx, const BatchPlan& B, void* ws, Prof
             continue;
         }
         uint32_t* dst = (uint32_t*)(tws + t.second);
-        int rc = dispatch_L<TableBuild>(t.first->plan.L, t.first, dst, prof, st);
+        int rc = dispatch_fmt<TableBuild>(t.first->plan.fmt, t.first, dst, prof, st);
         if (rc) return rc;
         table[t.first] = dst;
     }
@@ -3294,8 +3337,8 @@ int dkss_forward(dkss_ctx* ctx, uint32_t* poly, const uint32_t* a, size_t alen, 
     if ((rc = use_table(&call, w, st))) return rc;
     ProdArgs PA{};
     PA.one = ProdDesc{nullptr, a, a, (long long)alen, (long long)blen, call.P.u, 0};
-    if ((rc = dispatch_L<Encode>(call.P.L, call, PA, 1u, 0, w.A, w.S, (double)alen, st))) return rc;
-    if ((rc = dispatch_L<Transform>(call.P.L, call, w.A, w.S, 1u, 0, st))) return rc;
+    if ((rc = dispatch_fmt<Encode>(call.P.fmt, call, PA, 1u, 0, w.A, w.S, (double)alen, st))) return rc;
+    if ((rc = dispatch_fmt<Transform>(call.P.fmt, call, w.A, w.S, 1u, 0, st))) return rc;
     LevelIdx LI{};
     LI.n = (int)call.P.radix_log2.size();
     int nlog = call.P.log2_M + 1, shift = 0;
@@ -3306,7 +3349,7 @@ int dkss_forward(dkss_ctx* ctx, uint32_t* poly, const uint32_t* a, size_t alen, 
         LI.shift[k] = shift;
         shift += call.P.radix_log2[k];
     }
-    return dispatch_L<Unscramble>(call.P.L, call, poly, (const uint32_t*)w.A, LI, st);
+    return dispatch_fmt<Unscramble>(call.P.fmt, call, poly, (const uint32_t*)w.A, LI, st);
 }
 
 int dkss_residues(const uint32_t* x, size_t n, const uint64_t* primes_host, size_t count,

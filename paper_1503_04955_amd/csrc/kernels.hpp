@@ -3,9 +3,10 @@
 //
 // Representation
 //  - A residue mod q is D = ceil((32L+1)/28) digits of 28 bits, least significant first, each
-//    digit in [0, 2^28), the value canonical in [0, q).  L = ceil(bits(q)/32) is the template
-//    parameter of every kernel.  Since 2q < 2^(32L+1) <= 2^(28D), sums of two residues never
-//    leave D digits.
+//    digit in [0, 2^28), the value canonical in [0, q), with L = ceil(bits(q)/32); or, in the
+//    tight format of a modulus below 2^(28D - 1), one digit fewer (fmt_D).  The format code C
+//    (L and the tight bit) is the template parameter of every kernel.  Since 2q < 2^(28D), sums
+//    of two residues never leave D digits.
 //  - A 28x28-bit digit product is below 2^56, so up to 255 of them add into one 64-bit column
 //    without carry handling: each digit product is a single v_mad_u64_u32 into its column.
 //  - Products are reduced by Montgomery's method in radix 2^28 with K digit steps,
@@ -29,10 +30,25 @@ struct QConst {
     int se;                  // e >= 1 when q = 1 + qd[e] 2^(28e) + qd[e+1] 2^(28(e+1)), else 0
 };
 
-template <int L>
+// A residue format C: L = C & 15 limbs of 32 bits; with bit 4 set ("tight") the modulus is below
+// 2^(28 D - 1) for one 28-bit digit fewer than 32L bits need, D = floor(32L / 28), so that the
+// digit products of a product in R shrink by that digit (q of 83 bits: 3 limbs, 3 digits instead
+// of 4).  A plan takes the tight format whenever its q fits it.
+__host__ __device__ constexpr int fmt_L(int C) { return C & 15; }
+__host__ __device__ constexpr bool fmt_tight(int C) { return (C & 16) != 0; }
+__host__ __device__ constexpr int fmt_D(int C) { return (32 * fmt_L(C) + 28) / 28 - (fmt_tight(C) ? 1 : 0); }
+// bits of the largest modulus the format holds
+__host__ __device__ constexpr int fmt_qbits(int C) { return fmt_tight(C) ? 28 * fmt_D(C) - 1 : 32 * fmt_L(C); }
+// Montgomery steps: 2^(28K) > 64 q
+__host__ __device__ constexpr int fmt_K(int C) { return (fmt_qbits(C) + 6 + 27) / 28; }
+__host__ __device__ constexpr int fmt_code(int L, bool tight) { return L | (tight ? 16 : 0); }
+
+template <int C>
 struct Dig {
-    static constexpr int D = (32 * L + 28) / 28;          // 28-bit digits per residue (2q fits)
-    static constexpr int K = (32 * L + 6 + 27) / 28;      // Montgomery steps: 2^(28K) > 64 q
+    static constexpr int L = fmt_L(C);
+    static constexpr int D = fmt_D(C);                    // 28-bit digits per residue (2q fits)
+    static constexpr int K = fmt_K(C);                    // Montgomery steps: 2^(28K) > 64 q
+    static constexpr int E = (fmt_qbits(C) - 1) / 28;     // digit of the top bit of the largest q
     static constexpr int NC = K + D + 1;                  // 64-bit columns of a product sum
     static constexpr int NI = (253 - K) / D;              // products per column between carries
     // LDS strides: a staged ring element's residues (and the limb-form residues of levels that
@@ -45,9 +61,10 @@ struct Dig {
 // ----- digit arithmetic mod q -----------------------------------------------------------------
 
 // x >= q ?  (the borrow out of the top digit of x - q)
-template <int L>
+template <int C>
 __host__ __device__ __forceinline__ bool dgeq_q(const uint32_t* x, const QConst& Q) {
-    constexpr int D = Dig<L>::D;
+    constexpr int L = fmt_L(C);
+    constexpr int D = Dig<C>::D;
     uint32_t b = 0;
 #pragma unroll
     for (int k = 0; k < D; ++k) {
@@ -58,9 +75,10 @@ __host__ __device__ __forceinline__ bool dgeq_q(const uint32_t* x, const QConst&
 }
 
 // x -= q (x >= q)
-template <int L>
+template <int C>
 __host__ __device__ __forceinline__ void dsub_q(uint32_t* x, const QConst& Q) {
-    constexpr int D = Dig<L>::D;
+    constexpr int L = fmt_L(C);
+    constexpr int D = Dig<C>::D;
     uint32_t b = 0;
 #pragma unroll
     for (int k = 0; k < D; ++k) {
@@ -71,10 +89,11 @@ __host__ __device__ __forceinline__ void dsub_q(uint32_t* x, const QConst& Q) {
 }
 
 // r = x + y mod q
-template <int L>
+template <int C>
 __host__ __device__ __forceinline__ void dmod_add(uint32_t* r, const uint32_t* x, const uint32_t* y,
                                          const QConst& Q) {
-    constexpr int D = Dig<L>::D;
+    constexpr int L = fmt_L(C);
+    constexpr int D = Dig<C>::D;
     uint32_t s[D], d[D];
     uint32_t c = 0;
 #pragma unroll
@@ -96,10 +115,11 @@ __host__ __device__ __forceinline__ void dmod_add(uint32_t* r, const uint32_t* x
 }
 
 // r = x - y mod q
-template <int L>
+template <int C>
 __host__ __device__ __forceinline__ void dmod_sub(uint32_t* r, const uint32_t* x, const uint32_t* y,
                                          const QConst& Q) {
-    constexpr int D = Dig<L>::D;
+    constexpr int L = fmt_L(C);
+    constexpr int D = Dig<C>::D;
     uint32_t d[D];
     uint32_t b = 0;
 #pragma unroll
@@ -119,9 +139,10 @@ __host__ __device__ __forceinline__ void dmod_sub(uint32_t* r, const uint32_t* x
 }
 
 // r = q - x (x in [0, q]; r = q for x = 0, which is harmless inside a product)
-template <int L>
+template <int C>
 __host__ __device__ __forceinline__ void dneg_q(uint32_t* r, const uint32_t* x, const QConst& Q) {
-    constexpr int D = Dig<L>::D;
+    constexpr int L = fmt_L(C);
+    constexpr int D = Dig<C>::D;
     uint32_t b = 0;
 #pragma unroll
     for (int k = 0; k < D; ++k) {
@@ -132,9 +153,10 @@ __host__ __device__ __forceinline__ void dneg_q(uint32_t* r, const uint32_t* x, 
 }
 
 // 32-bit limbs of a residue given in digits
-template <int L>
+template <int C>
 __host__ __device__ __forceinline__ void digits_to_limbs(const uint32_t* d, uint32_t* x) {
-    constexpr int D = Dig<L>::D;
+    constexpr int L = fmt_L(C);
+    constexpr int D = Dig<C>::D;
 #pragma unroll
     for (int w = 0; w < L; ++w) {
         const int bit = 32 * w;
@@ -147,9 +169,10 @@ __host__ __device__ __forceinline__ void digits_to_limbs(const uint32_t* d, uint
 }
 
 // 28-bit digits of a residue given in 32-bit limbs
-template <int L>
+template <int C>
 __host__ __device__ __forceinline__ void limbs_to_digits(const uint32_t* x, uint32_t* d) {
-    constexpr int D = Dig<L>::D;
+    constexpr int L = fmt_L(C);
+    constexpr int D = Dig<C>::D;
 #pragma unroll
     for (int k = 0; k < D; ++k) {
         const int bit = 28 * k;
@@ -165,9 +188,10 @@ __host__ __device__ __forceinline__ void limbs_to_digits(const uint32_t* x, uint
 // chains): 2q < 2^(32L + 1), the carry out of the top limb is the extra bit.
 
 // r = x + y mod q, q given by its limbs ql
-template <int L>
+template <int C>
 __host__ __device__ __forceinline__ void lmod_add(uint32_t* r, const uint32_t* x, const uint32_t* y,
                                                   const uint32_t* ql) {
+    constexpr int L = fmt_L(C);
     uint32_t s[L], d[L];
     unsigned int c = 0, b = 0;
 #pragma unroll
@@ -180,9 +204,10 @@ __host__ __device__ __forceinline__ void lmod_add(uint32_t* r, const uint32_t* x
 }
 
 // r = x - y mod q, q given by its limbs ql
-template <int L>
+template <int C>
 __host__ __device__ __forceinline__ void lmod_sub(uint32_t* r, const uint32_t* x, const uint32_t* y,
                                                   const uint32_t* ql) {
+    constexpr int L = fmt_L(C);
     uint32_t d[L];
     unsigned int b = 0, c = 0;
 #pragma unroll
@@ -197,9 +222,10 @@ __host__ __device__ __forceinline__ void lmod_sub(uint32_t* r, const uint32_t* x
 // The K Montgomery steps for a modulus q = 1 + qd[E] 2^(28E) + qd[E+1] 2^(28(E+1)), such as a
 // prime h 2^n + 1 with n >= 28 (the thesis's kind of prime, Sec. 3.2.2 and Sec. 4.6):
 // -q^-1 = -1 mod 2^28, and of the D digit products of a step only two are not zero.
-template <int L, int E>
+template <int C, int E>
 __host__ __device__ __forceinline__ void redc_steps_sparse(uint64_t* col, const QConst& Q) {
-    using G = Dig<L>;
+    constexpr int L = fmt_L(C);
+    using G = Dig<C>;
 #pragma unroll
     for (int i = 0; i < G::K; ++i) {
         const uint32_t u = (0u - (uint32_t)col[i]) & kMask28;
@@ -212,11 +238,12 @@ __host__ __device__ __forceinline__ void redc_steps_sparse(uint64_t* col, const 
 // col holds S = sum_k col[k] 2^(28k) with S < 64 q^2 (any split into 64-bit columns whose
 // running totals stay below 2^64).  The K Montgomery steps leave S 2^(-28K) mod q, below 2q, in
 // columns K .. K+D-1; its D digits (carries resolved) go to d.
-template <int L>
+template <int C>
 __host__ __device__ __forceinline__ void redc_digits(uint64_t* col, const QConst& Q, uint32_t* d) {
-    using G = Dig<L>;
-    if (Q.se == (32 * L - 1) / 28) {
-        redc_steps_sparse<L, (32 * L - 1) / 28>(col, Q);
+    constexpr int L = fmt_L(C);
+    using G = Dig<C>;
+    if (Q.se == G::E) {
+        redc_steps_sparse<C, G::E>(col, Q);
     } else {
 #pragma unroll
         for (int i = 0; i < G::K; ++i) {
@@ -237,20 +264,24 @@ __host__ __device__ __forceinline__ void redc_digits(uint64_t* col, const QConst
 }
 
 // S 2^(-28K) mod q, canonical, in digits
-template <int L>
+template <int C>
 __host__ __device__ __forceinline__ void redc_cols(uint64_t* col, const QConst& Q, uint32_t* x) {
-    redc_digits<L>(col, Q, x);
-    if (dgeq_q<L>(x, Q)) dsub_q<L>(x, Q);
+    constexpr int L = fmt_L(C);
+    redc_digits<C>(col, Q, x);
+    if (dgeq_q<C>(x, Q)) dsub_q<C>(x, Q);
 }
 
 // S 2^(-28K) mod q, canonical, in L limbs: the value (below 2q < 2^(32L+1)) as L limbs and its
-// bit 32L, then one subtraction of q on limbs with the hardware borrow
-template <int L>
+// bit 32L (zero in a tight format, where 2q < 2^(28D) <= 2^(32L)), then one subtraction of q on
+// limbs with the hardware borrow
+template <int C>
 __host__ __device__ __forceinline__ void redc_cols_limbs(uint64_t* col, const QConst& Q, uint32_t* x) {
-    uint32_t d[Dig<L>::D], s[L];
-    redc_digits<L>(col, Q, d);
-    digits_to_limbs<L>(d, x);
-    const uint32_t top = (d[(32 * L) / 28] >> ((32 * L) % 28)) & 1u;
+    constexpr int L = fmt_L(C);
+    uint32_t d[Dig<C>::D], s[L];
+    redc_digits<C>(col, Q, d);
+    digits_to_limbs<C>(d, x);
+    uint32_t top = 0;
+    if constexpr (!fmt_tight(C)) top = (d[(32 * L) / 28] >> ((32 * L) % 28)) & 1u;
     unsigned int b = 0;
 #pragma unroll
     for (int k = 0; k < L; ++k) s[k] = __builtin_subc(x[k], Q.ql[k], b, &b);
@@ -259,9 +290,10 @@ __host__ __device__ __forceinline__ void redc_cols_limbs(uint64_t* col, const QC
     for (int k = 0; k < L; ++k) x[k] = ge ? s[k] : x[k];
 }
 
-template <int L>
+template <int C>
 __host__ __device__ __forceinline__ void normalize_cols(uint64_t* col) {
-    using G = Dig<L>;
+    constexpr int L = fmt_L(C);
+    using G = Dig<C>;
 #pragma unroll
     for (int k = 0; k + 1 < G::NC; ++k) {
         col[k + 1] += col[k] >> 28;
@@ -270,9 +302,10 @@ __host__ __device__ __forceinline__ void normalize_cols(uint64_t* col) {
 }
 
 // col[x + y] += t_x x_y over the D x D digit pairs of one term
-template <int L>
+template <int C>
 __host__ __device__ __forceinline__ void rprod_term(uint64_t* col, const uint32_t* tp, const uint32_t* xp) {
-    using G = Dig<L>;
+    constexpr int L = fmt_L(C);
+    using G = Dig<C>;
     uint32_t tv[G::D], xv[G::D];
 #pragma unroll
     for (int x = 0; x < G::D; ++x) {
@@ -297,32 +330,33 @@ __host__ __device__ __forceinline__ void rprod_term(uint64_t* col, const uint32_
 // a wavefront read the same positions, whatever their twiddles.
 // Returns c_j 2^(-28K) mod q, canonical, in digits (LIMBS: in L limbs).  FM > 0: log2m = FM is
 // known at compile time and the sum is unrolled (no address arithmetic per term).
-template <int L, bool LIMBS = false, int FM = 0>
+template <int C, bool LIMBS = false, int FM = 0>
 __host__ __device__ __forceinline__ void rprod_coeff(const uint32_t* TP, const uint32_t* X, int log2m, int j,
                                             const QConst& Q, uint32_t* out) {
-    using G = Dig<L>;
+    constexpr int L = fmt_L(C);
+    using G = Dig<C>;
     const int m = FM > 0 ? 1 << FM : 1 << log2m;
     uint64_t col[G::NC];
 #pragma unroll
     for (int k = 0; k < G::NC; ++k) col[k] = 0;
     int w = j + m;
-    rprod_term<L>(col, TP + w * G::DS, X);      // k = 0 ahead of the loop: the columns start from it
+    rprod_term<C>(col, TP + w * G::DS, X);      // k = 0 ahead of the loop: the columns start from it
     if constexpr (FM > 0) {
 #pragma unroll
         for (int k = 1; k < (1 << FM); ++k) {
             --w;
-            rprod_term<L>(col, TP + w * G::DS, X + k * G::D);
-            if ((k + 1) % G::NI == 0) normalize_cols<L>(col);
+            rprod_term<C>(col, TP + w * G::DS, X + k * G::D);
+            if ((k + 1) % G::NI == 0) normalize_cols<C>(col);
         }
     } else {
         for (int k = 1; k < m; ++k) {
             --w;
-            rprod_term<L>(col, TP + w * G::DS, X + k * G::D);
-            if ((k + 1) % G::NI == 0) normalize_cols<L>(col);
+            rprod_term<C>(col, TP + w * G::DS, X + k * G::D);
+            if ((k + 1) % G::NI == 0) normalize_cols<C>(col);
         }
     }
-    if (LIMBS) redc_cols_limbs<L>(col, Q, out);
-    else redc_cols<L>(col, Q, out);
+    if (LIMBS) redc_cols_limbs<C>(col, Q, out);
+    else redc_cols<C>(col, Q, out);
 }
 
 // Position in the staging area of entry i < 2m of the operand T of rprod_coeff for a product
@@ -363,10 +397,11 @@ __host__ __device__ constexpr int elem_words(int m, int D) {
 }
 
 // x * k 2^(-28K) mod q for a constant k given in digits (a scalar Montgomery product)
-template <int L>
+template <int C>
 __host__ __device__ __forceinline__ void mont_scalar(const uint32_t* x, const uint32_t* kd, const QConst& Q,
                                             uint32_t* out) {
-    using G = Dig<L>;
+    constexpr int L = fmt_L(C);
+    using G = Dig<C>;
     uint64_t col[G::NC];
 #pragma unroll
     for (int k = 0; k < G::NC; ++k) col[k] = 0;
@@ -374,7 +409,7 @@ __host__ __device__ __forceinline__ void mont_scalar(const uint32_t* x, const ui
     for (int a = 0; a < G::D; ++a)
 #pragma unroll
         for (int b = 0; b < G::D; ++b) col[a + b] += (uint64_t)x[a] * kd[b];
-    redc_cols<L>(col, Q, out);
+    redc_cols<C>(col, Q, out);
 }
 
 }  // namespace dkss

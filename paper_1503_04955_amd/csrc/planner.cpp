@@ -194,7 +194,11 @@ bool candidate_params(uint64_t N, int c, int* log2_M, int* log2_m, int* u, int* 
     const uint64_t uu = ((2 * N) + (1ULL << t) - 1) >> t;
     uint64_t pb;
     if (!squared) {
-        pb = 32 * ((need_bits(t) + 31) / 32);
+        // the fewest whole limbs, or where the modulus can be one 28-bit digit shorter than those
+        // limbs need (2p < 2^(28 D)), the largest prime of that many digits
+        const uint64_t nb = need_bits(t), limbs = (nb + 31) / 32;
+        const uint64_t digits = (nb + 1 + 27) / 28;
+        pb = (limbs >= 2 && digits < (32 * limbs + 28) / 28) ? 28 * digits - 1 : 32 * limbs;
     } else {
         // q = p^2 with p of b bits: p^2 >= 2^(2b - 2), so 2b - 2 >= t + 2u gives q > Mm 2^(2u)
         pb = ((uint64_t)t + 2 * uu + 3) / 2;

@@ -60,6 +60,8 @@ struct Plan {
     std::vector<Big> rho;             // m coefficients of rho
     int q_bits = 0;
     int L = 0;                        // uint32 limbs per residue
+    int fmt = 0;                      // the kernels' residue format: L, and whether q fits one
+                                      // 28-bit digit fewer than 32L bits need (kernels.hpp)
     // key for caching device tables
     std::string key() const;
     long long M() const { return 1LL << log2_M; }
@@ -73,7 +75,9 @@ bool thesis_params(uint64_t N, int* log2_M, int* log2_m, int* u, int* p_bits);
 
 // Candidate tuple c (0 <= c < kNumCandidates) for N.  t_min is the smallest log2(Mm) for which
 // a prime modulus p >= 2 Mm 2^(2u) (u = ceil(2N/Mm)) has at most 256 bits.
-//   c < 18:  z = 1, Mm = 2^(t_min + c / 6), m = 2^(c % 6 + 1), p of the fewest whole 32-bit limbs
+//   c < 18:  z = 1, Mm = 2^(t_min + c / 6), m = 2^(c % 6 + 1), p of the fewest whole 32-bit limbs,
+//            or of 28 D - 1 bits where that many bits hold it in one 28-bit digit fewer than the
+//            limbs would take (D = ceil((bits + 1) / 28) < ceil((32 limbs + 1) / 28))
 //   c >= 18: z = 2 (q = p^2, Sec. 3.2 Step 2 with the Hensel lift of Sec. 3.2.3), Mm = 2^t_min,
 //            m = 2^(c - 17), p of the fewest bits with p^2 > Mm 2^(2u)
 // False if M < m or no modulus.

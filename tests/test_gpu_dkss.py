@@ -60,6 +60,15 @@ FWD = [  # (log2_M, log2_m, u, p_bits, z, radices, alen)
     (6, 2, 24, 64, 1, [1, 2, 3, 1], 24),     # forced split including radix 2
     (9, 4, 32, 128, 1, None, 256),           # C1-like ring, 2M = 1024 = 32 * 32
     (7, 3, 40, 192, 1, None, 64),            # L = 6
+    # tight formats: q < 2^(28 D - 1), one 28-bit digit fewer than the limbs take
+    (4, 2, 20, 55, 1, None, 8),              # L = 2, D = 2
+    (5, 3, 24, 83, 1, None, 16),             # L = 3, D = 3
+    (9, 4, 32, 111, 1, None, 256),           # L = 4, D = 4
+    (7, 3, 40, 139, 1, None, 64),            # L = 5, D = 5
+    (7, 3, 40, 167, 1, None, 64),            # L = 6, D = 6
+    (6, 2, 48, 223, 1, None, 32),            # L = 7, D = 8
+    (6, 3, 60, 251, 1, None, 48),            # L = 8, D = 9
+    (5, 2, 24, 40, 2, None, 16),             # q = p^2 of 79 bits: L = 3, D = 3, dense reduction
 ]
 
 
@@ -93,6 +102,15 @@ MUL = [  # (log2_M, log2_m, u, p_bits, z, radices)
     (10, 4, 60, 256, 1, None),              # L = 8
     (8, 2, 2, 64, 1, None),                 # u = 2: the decode's elements exceed an LDS tile
     (11, 1, 5, 64, 1, None),                # m = 2, u = 5
+    # tight formats (L, D): (2, 2), (3, 3), (4, 4), (5, 5), (6, 6), (7, 8), (8, 9); z = 2
+    (8, 3, 20, 55, 1, None),
+    (9, 4, 32, 83, 1, None),
+    (6, 6, 40, 111, 1, None),               # m = 64
+    (7, 5, 56, 139, 1, None),
+    (8, 4, 70, 167, 1, None),
+    (5, 2, 90, 223, 1, None),
+    (6, 3, 100, 251, 1, None),
+    (6, 3, 30, 36, 2, None),                # q = p^2 of 71 bits: L = 3, D = 3
 ]
 
 
@@ -106,6 +124,19 @@ def test_mul_parameter_tuples(env, case):
         a, b = SI.operand_pair(seed + 10 * log2_M, alen, blen)
         got = _gpu_mul(env, a, b, _params(dk, log2_M, log2_m, u, p_bits, z, radices))
         assert np.array_equal(got, C.schoolbook(a, b))
+
+
+def test_tight_format_plans(env):
+    """A modulus below 2^(28 D - 1) runs on D digits, one fewer than its limbs would take; the
+    tuples of the parameter tests above get the format their modulus fits."""
+    dk, torch, ctx = env
+    for log2_M, log2_m, u, p_bits, z, _ in MUL:
+        cap = (1 << log2_M) * (1 << log2_m) // 2 * u // 32
+        info = ctx.plan_info(cap, cap, _params(dk, log2_M, log2_m, u, p_bits, z))
+        L = info.L
+        full = (32 * L + 28) // 28
+        tight = L >= 2 and info.q_bits <= 28 * (full - 1) - 1
+        assert info.digits == (full - 1 if tight else full), (log2_M, log2_m, u, p_bits, z)
 
 
 # ---- the thesis rule at 2^18 bits (the small configuration) and edge operands --------------

@@ -68,9 +68,10 @@ def test_planner_prime_power(dk):
 def test_candidate_set(dk, N):
     """The candidates of dkss_candidates, restated from their definition: 18 tuples with a prime
     modulus (Mm = 2^(t_min + c // 6), m = 2^(c % 6 + 1), the fewest whole limbs of p with
-    p > Mm 2^(2u)), and 6 with the square of a prime (z = 2, Mm = 2^t_min, the fewest bits of p
-    with p^2 > Mm 2^(2u) for every prime of that length); each feasible tuple plans on the host
-    with a modulus p^z of the oracle's Proth prime."""
+    p > Mm 2^(2u), or 28 D - 1 bits where that saves a 28-bit digit), and 6 with the square of a
+    prime (z = 2, Mm = 2^t_min, the fewest bits of p with p^2 > Mm 2^(2u) for every prime of that
+    length); each feasible tuple plans on the host with a modulus p^z of the oracle's Proth
+    prime, and its products in R on the digits its modulus needs."""
     ctx = dk.Context()
     cands = dict(ctx.candidates(N, N))
     assert cands and max(cands) < dk.NCAND == 24
@@ -84,13 +85,20 @@ def test_candidate_set(dk, N):
         lm = c % 6 + 1 if c < 18 else c - 17
         u = u_of(t)
         assert (p.log2_M + p.log2_m, p.log2_m, p.u) == (t, lm, u), c
+        nb = t + 2 * u + 1                   # bits of the smallest prime above Mm 2^(2u)
+        limbs, digits = -(-nb // 32), -(-(nb + 1) // 28)
         if c < 18:
-            assert p.z == 1 and p.p_bits % 32 == 0 and p.p_bits - 32 < t + 2 * u + 1 <= p.p_bits
+            tight = limbs >= 2 and digits < (32 * limbs + 28) // 28
+            assert p.z == 1 and p.p_bits == (28 * digits - 1 if tight else 32 * limbs), c
         else:
             assert p.z == 2 and 2 * p.p_bits - 2 >= t + 2 * u > 2 * p.p_bits - 4, c
         info = ctx.plan_info(N // 32, N // 32, p)
         prime, _, _ = OP.proth_prime(p.p_bits, p.log2_M + 1)
         assert info.modulus == prime ** p.z and info.q_bits > t + 2 * u
+        # the products run on the fewest 28-bit digits that hold 2q, except one-limb moduli
+        full = (32 * info.L + 28) // 28
+        want = -(-(info.q_bits + 1) // 28) if info.L >= 2 else full
+        assert info.digits == max(want, full - 1), c
     for c in range(18, 24):
         if c - 18 in cands:
             assert c in cands, c
