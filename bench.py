@@ -191,7 +191,8 @@ def roofline_of(stats, workload, mad_rate=None):
         per = st.alg_ops / st.launches
         achieved = per / (avg_ms / 1e3) / 1e12
         r = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(PEAK_VALU_TOPS, 2),
-             "unit": "TOP/s", "frac": round(achieved / PEAK_VALU_TOPS, 4), "ops_per_launch": per}
+             "unit": "TOP/s", "frac": round(achieved / PEAK_VALU_TOPS, 4), "ops_per_launch": per,
+             "alg_bytes_per_launch": st.alg_bytes / st.launches}
         if mad_rate:
             r["frac_of_measured_mad_rate"] = round(achieved / mad_rate, 4)
     else:
@@ -254,7 +255,9 @@ def batch_leg(args, dk, torch, SI):
         call.ctx.profile(False)
         stats = call.ctx.profile_read()
         graph.close()
-        check_residues(dk, as_, bs, call.outs, primes61(SI.SEED_BASE, 8))
+        # every 64th product (the full check launches 24 residue kernels per product, which
+        # would crowd a trace of this form)
+        check_residues(dk, as_[::64], bs[::64], call.outs[::64], primes61(SI.SEED_BASE, 8))
         return ms_step, bits, {"workload": "4096 products (headline only)", "operand_bits": bits,
                                "graph_learned": head}, stats
     # the plain calls: thesis rule, one dkss_mul per product (tables prepared)
@@ -456,6 +459,17 @@ def c5_leg(dk, torch, SI):
     return out
 
 
+def copy_calibration(args, torch, out):
+    """One device-to-device copy of --copy-calib bytes: a kernel of known HBM traffic that the
+    counter runs scale their FETCH_SIZE and WRITE_SIZE by."""
+    if args.copy_calib:
+        src = torch.empty(args.copy_calib, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_calib_bytes"] = args.copy_calib
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -469,8 +483,8 @@ def main():
     ap.add_argument("--lanes", type=int, default=4,
                     help="stream lanes of the headline batch's groups (DKSS_OPT_BATCH_LANES)")
     ap.add_argument("--headline-only", action="store_true",
-                    help="run only the headline batch (graph and profiled pass): the form that "
-                         "kernel traces and counters are taken on")
+                    help="profiling form: the headline batch alone (graph and profiled pass), or, "
+                         "when --legs does not name batch, only the named legs among 2p28 and smul")
     ap.add_argument("--copy-calib", type=int, default=0,
                     help="end with one device-to-device copy of this many bytes (a counter "
                          "calibration kernel of known traffic)")
@@ -490,6 +504,16 @@ def main():
     # multiply-add instruction is reported beside it
     mad_rate = dk.probe_mad_rate() / 1e12
     log("v_mad_u64_u32: %.2f T lane-ops/s measured (nominal %.2f)" % (mad_rate, PEAK_VALU_TOPS))
+    if args.headline_only and "batch" not in legs:
+        # the profiling form of the other legs alone (no headline): one JSON line of them
+        sub = {}
+        if "2p28" in legs:
+            sub["single_2p28"] = single_leg(28, args.steps, dk, torch, SI)
+        if "smul" in legs:
+            sub["smul"] = smul_leg([28], args.steps, dk, torch, SI)
+        copy_calibration(args, torch, sub)
+        print(json.dumps(sub), flush=True)
+        return
     ms_step, bits, batch, stats = batch_leg(args, dk, torch, SI)
     out = {
         "metric": METRIC, "value": bits / (ms_step / 1e3), "unit": "operand bits/s", "n_gpus": 1,
@@ -510,7 +534,7 @@ def main():
         out["config"]["baseline"] = ("plain sequential calls, thesis rule: %.3f ms (%.4g operand bits/s)"
                                      % (batch["plain_sequential"]["ms"], batch["plain_sequential"]["value"]))
     else:
-        out["verified"] = "c = a*b mod 8 random 61-bit primes for every product"
+        out["verified"] = "c = a*b mod 8 random 61-bit primes for every 64th product"
     if "2p28" in legs:
         out["single_2p28"] = single_leg(28, args.steps, dk, torch, SI)
     if "sizes" in legs:
@@ -519,12 +543,7 @@ def main():
         out["smul"] = smul_leg([24, 28], 10, dk, torch, SI)
     if "c5" in legs and not args.no_c5:
         out["c5"] = c5_leg(dk, torch, SI)
-    if args.copy_calib:
-        src = torch.empty(args.copy_calib, dtype=torch.uint8, device="cuda")
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        out["copy_calib_bytes"] = args.copy_calib
+    copy_calibration(args, torch, out)
     if not args.no_cpu:
         log("cpu baseline ...")
         out["cpu_baseline"] = cpu_baseline(SI.mixed_batch(args.batch))

@@ -15,8 +15,9 @@ dkss_mul_batch call.  Every timed product is checked by residues on the GPU (all
 product, the first and the last of a batch).
 
 Sets of points
-  train     x in 12..29.5 step 0.5, ratios 1,2,4,8, batch 1; x in 12..22 step 0.5 for batch 16
-            and 256 and step 1 for batch 4096, ratios 1,2,4,8, while batch * 2^x <= 2^33
+  train     x in 12..29.5 step 0.5 and 30.5..32, ratios 1,2,4,8, batch 1; x in 12..22 step 0.5
+            for batch 16 and 256 and step 1 for batch 4096, ratios 1,2,4,8, while
+            batch * 2^x <= 2^33
   heldout   points the selector never sees in training: x = 30 and quarter points between the
             training sizes, ratio 1 and 3, batch 1; and batch 64 and 1024 at quarter points
   kernels   for each training size from 2^16 bits (ratio 1, batch 1) and its fastest candidate:
@@ -54,6 +55,11 @@ def train_points():
         for r in (1, 2, 4, 8):
             pts.append((x, r, 1))
         x += 0.5
+    # beyond the held-out 2^30: single products up to 2^32 bits, so that the selector's inputs
+    # at the largest sizes (2^34 bits) lie close to measured ones
+    for x in (30.5, 31.0, 31.5, 32.0):
+        for r in (1, 2, 4, 8):
+            pts.append((x, r, 1))
     # batches: every half-integer size for 16 and 256 products, whole sizes for 4096 (their
     # points are the costly ones)
     for B in (16, 256, 4096):

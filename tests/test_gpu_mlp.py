@@ -12,7 +12,7 @@ from conftest import host_residues, primes61, residues_agree
 
 pytestmark = pytest.mark.gpu
 
-OUT = 19
+OUT = 25                      # DKSS_MLP_OUT: 24 candidates and the base case
 
 
 @pytest.fixture(scope="module")
