@@ -399,6 +399,18 @@ def smul_leg(bits_list, reps, dk, torch, SI):
         ws = torch.empty(dk.smul_workspace_bytes(n, n), dtype=torch.uint8, device="cuda")
         ms = _timed(lambda: dk.smul(a, b, out=c_s, ws=ws), reps, torch, warmup=2)
         res["smul"] = {"ms": ms, "value": 2 * n * 32 / (ms / 1e3), "params": p.as_dict()}
+        if p.lw <= 16:
+            # the same ring with the componentwise products in the other form (A/B): 28-bit digits
+            # on the vector units (1) or exact 8-bit products on the matrix cores (2)
+            other = 3 - p.products
+            q = dk.SmulParams.make(p.log2_n, p.lw, other)
+            c_v = torch.empty(2 * n, dtype=torch.int32, device="cuda")
+            ms_v = _timed(lambda: dk.smul(a, b, out=c_v, params=q, ws=ws), reps, torch, warmup=2)
+            if not torch.equal(c_v, c_s):
+                raise RuntimeError("2^%d SMUL products differ between the two forms" % bits)
+            key = "smul_matrix_products" if other == 2 else "smul_vector_products"
+            res[key] = {"ms": ms_v, "value": 2 * n * 32 / (ms_v / 1e3)}
+            del c_v
         del ws
         for name, policy in (("dkss_thesis", dk.POLICY_THESIS), ("dkss_learned", dk.POLICY_LEARNED)):
             ctx = dk.Context(policy)
@@ -414,8 +426,12 @@ def smul_leg(bits_list, reps, dk, torch, SI):
                                  "learned": res["dkss_learned"]["ms"] / res["smul"]["ms"]}
         res["verified"] = "SMUL product equal to both DKSS products"
         out["2^%d" % bits] = res
-        log("2^%d: smul %.3f ms, dkss thesis %.3f ms, learned %.3f ms" %
-            (bits, res["smul"]["ms"], res["dkss_thesis"]["ms"], res["dkss_learned"]["ms"]))
+        log("2^%d: smul %.3f ms (%s), dkss thesis %.3f ms, learned %.3f ms" %
+            (bits, res["smul"]["ms"],
+             ", ".join(["%s products" % ("matrix-core" if p.products == 2 else "vector-unit")] +
+                       ["%s %.3f ms" % (k[5:].replace("_", " "), res[k]["ms"])
+                        for k in ("smul_matrix_products", "smul_vector_products") if k in res]),
+             res["dkss_thesis"]["ms"], res["dkss_learned"]["ms"]))
         torch.cuda.empty_cache()
     return out
 

@@ -180,6 +180,9 @@ typedef struct {
     uint32_t s;           /* output: bits per input coefficient, ceil(32 (alen + blen) / n) */
     uint32_t K;           /* output: ring exponent */
     uint32_t n_levels;    /* output: LDS-staged FFT levels per transform */
+    uint32_t products;    /* componentwise products (Step 5): 1 schoolbook of 28-bit digits on the
+                             vector units, 2 exact 8-bit products on the matrix cores (lw <= 16);
+                             0 = chosen by the modelled cost; output: the form used */
 } dkss_smul_params;
 
 /* The library's choice of (log2_n, lw) for alen x blen limbs (a modelled cost over the feasible

@@ -59,17 +59,17 @@ class SmulParams(ctypes.Structure):
     """dkss_smul_params: FFT length 2^log2_n and K = 2048 lw (0: the library's choice); s, K and
     n_levels are filled in by smul_select."""
     _fields_ = [("log2_n", ctypes.c_uint32), ("lw", ctypes.c_uint32), ("s", ctypes.c_uint32),
-                ("K", ctypes.c_uint32), ("n_levels", ctypes.c_uint32)]
+                ("K", ctypes.c_uint32), ("n_levels", ctypes.c_uint32), ("products", ctypes.c_uint32)]
 
     @classmethod
-    def make(cls, log2_n=0, lw=0):
+    def make(cls, log2_n=0, lw=0, products=0):
         p = cls()
-        p.log2_n, p.lw = log2_n, lw
+        p.log2_n, p.lw, p.products = log2_n, lw, products
         return p
 
     def as_dict(self):
         return {"log2_n": self.log2_n, "lw": self.lw, "s": self.s, "K": self.K,
-                "n_levels": self.n_levels}
+                "n_levels": self.n_levels, "products": self.products}
 
 
 class Plan(ctypes.Structure):

@@ -8,7 +8,9 @@
 //                     staged in LDS (natural order in, bit-reversed out); every multiplication by
 //                     a root of unity is a cyclic shift
 //   k_smul_pointwise  Step 5: products in R = Z/(2^K + 1)Z (schoolbook on 28-bit digits, the
-//                     2K-bit product folded with 2^K = -1), times 1/n = -2^(K - log2 n)
+//                     2K-bit product folded with 2^K = -1), times 1/n = -2^(K - log2 n); or
+//                     the same with the 2K-bit product as exact 8-bit products on the matrix
+//                     cores (k_smul_pointwise_mx, smul_mx.hip; K <= 32768)
 //   k_smul_level      Steps 6-7: radix-2 decimation in time with omega^-1 (bit-reversed in,
 //                     natural out)
 //   k_smul_decode     Step 10: the coefficients c_k added at bit s k, the carries resolved by
@@ -27,9 +29,17 @@
 
 #include "../../include/dkss.h"
 #include "hip_status.hpp"
+#include "smul_ring.hpp"
 #include "wave_carry.hpp"
 
 using namespace dkss;
+
+namespace dkss {
+// Step 5 on the matrix cores (smul_mx.hip): elements of 64 lw limbs, lw <= 16
+bool smul_mx_supported(int lw);
+int smul_pointwise_mx(int lw, long long n, uint32_t* A, uint32_t* At, const uint32_t* B, const uint32_t* Bt,
+                      int log2n, hipStream_t s);
+}  // namespace dkss
 
 namespace {
 
@@ -37,155 +47,6 @@ constexpr int kT = 256;                   // threads per workgroup: four wavefro
 constexpr int kTL = 512;                  // threads per workgroup of a transform level: eight wavefronts
 constexpr int kMaxLw = 32;                // limbs per lane: W <= 2048, K <= 65536
 constexpr size_t kColumnBytes = 65536;    // LDS for the elements of one level column
-
-__device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63); }
-
-// Orders the wavefront's LDS accesses (they are performed in issue order; this keeps the
-// compiler from moving them across the point).
-__device__ __forceinline__ void wsync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-__device__ __forceinline__ uint32_t bit_of(unsigned long long C) { return lane_bit(C); }
-
-// x += v (v < 2^32 added at limb 0) over W limbs; returns the carry out of the top limb.
-__device__ uint32_t fw_add_small(uint32_t* x, uint32_t v, int W) {
-    const int l = lane_id();
-    uint32_t c = 0;
-    for (int w0 = 0; w0 < W; w0 += 64) {
-        const uint32_t a = x[w0 + l];
-        const uint32_t b = (w0 == 0 && l == 0) ? v : 0u;
-        uint32_t s = a + b;
-        const unsigned long long G = __ballot(s < a);
-        const unsigned long long P = __ballot(s == 0xFFFFFFFFu);
-        s += bit_of(row_carries(G, P, c, &c));
-        x[w0 + l] = s;
-    }
-    wsync();
-    return c;
-}
-
-// x -= v (v < 2^32 subtracted at limb 0) over W limbs; returns the borrow out of the top limb.
-__device__ uint32_t fw_sub_small(uint32_t* x, uint32_t v, int W) {
-    const int l = lane_id();
-    uint32_t c = 0;
-    for (int w0 = 0; w0 < W; w0 += 64) {
-        const uint32_t a = x[w0 + l];
-        const uint32_t b = (w0 == 0 && l == 0) ? v : 0u;
-        uint32_t d = a - b;
-        const unsigned long long G = __ballot(a < b);
-        const unsigned long long P = __ballot(d == 0u);
-        d -= bit_of(row_carries(G, P, c, &c));
-        x[w0 + l] = d;
-    }
-    wsync();
-    return c;
-}
-
-// The value x + T 2^K (x below 2^K in W limbs, T in [-3, 3]) reduced mod 2^K + 1 into [0, 2^K]:
-// it is x - T (2^K = -1).  x is rewritten; returns the new top (1 only for 2^K, x then 0).
-// The common cases change limb 0 alone; the rest propagate a carry or borrow.
-__device__ uint32_t fw_norm(uint32_t* x, int T, int W) {
-    wsync();
-    if (T == 0) return 0;
-    const uint32_t x0 = x[0];
-    if (T > 0) {
-        if (x0 >= (uint32_t)T) {
-            if (lane_id() == 0) x[0] = x0 - (uint32_t)T;
-            wsync();
-            return 0;
-        }
-        if (!fw_sub_small(x, (uint32_t)T, W)) return 0;
-        // x - T < 0: the value is x - T + 2^K + 1, the wrapped difference plus 1; a carry out
-        // means the value 2^K
-        return fw_add_small(x, 1u, W);
-    }
-    const uint32_t v = (uint32_t)(-T);
-    if (x0 <= 0xFFFFFFFFu - v) {
-        if (lane_id() == 0) x[0] = x0 + v;
-        wsync();
-        return 0;
-    }
-    if (!fw_add_small(x, v, W)) return 0;
-    // x + v = 2^K + x' with x' < v (all limbs but limb 0 are zero): the value is x' - 1
-    const uint32_t xs = x[0];
-    if (xs == 0) return 1;                       // -1 = 2^K: x stays 0
-    if (lane_id() == 0) x[0] = xs - 1u;
-    wsync();
-    return 0;
-}
-
-// x (canonical, top xt) times 2^t mod 2^K + 1 for 0 < t < K, in place; returns the new top.
-// Below 2^K, x 2^t = Lo + H 2^K with Lo = (x << t) mod 2^K and H = x >> (K - t), so the result
-// is Lo - H (plus 2^K + 1 if negative).  For x = 2^K (= -1) it is 2^K + 1 - 2^t.
-template <int LW>
-__device__ uint32_t fw_shift(uint32_t* x, uint32_t xt, int t) {
-    constexpr int W = 64 * LW;
-    constexpr int K = 32 * W;
-    const int l = lane_id();
-    wsync();
-    if (xt) {
-#pragma unroll
-        for (int i = 0; i < LW; ++i) {
-            const int w = 64 * i + l;
-            const int lo = 32 * w;
-            uint32_t v = lo + 32 <= t ? 0u : lo >= t ? 0xFFFFFFFFu : (0xFFFFFFFFu << (t - lo));
-            if (w == 0) v |= 1u;
-            x[w] = v;
-        }
-        wsync();
-        return 0;
-    }
-    const int tq = t >> 5, tb = t & 31;
-    const int u = K - t, uq = u >> 5, ub = u & 31;
-    uint32_t lo[LW], hi[LW];
-#pragma unroll
-    for (int i = 0; i < LW; ++i) {
-        const int w = 64 * i + l;
-        const uint32_t a1 = w - tq >= 0 ? x[w - tq] : 0u;
-        const uint32_t a0 = w - tq - 1 >= 0 ? x[w - tq - 1] : 0u;
-        lo[i] = tb ? (a1 << tb) | (a0 >> (32 - tb)) : a1;
-        const uint32_t b0 = w + uq < W ? x[w + uq] : 0u;
-        const uint32_t b1 = w + uq + 1 < W ? x[w + uq + 1] : 0u;
-        hi[i] = ub ? (b0 >> ub) | (b1 << (32 - ub)) : b0;
-    }
-    wsync();
-    uint32_t c = 0;
-#pragma unroll
-    for (int i = 0; i < LW; ++i) {
-        uint32_t d = lo[i] - hi[i];
-        const unsigned long long G = __ballot(lo[i] < hi[i]);
-        const unsigned long long P = __ballot(d == 0u);
-        d -= bit_of(row_carries(G, P, c, &c));
-        x[64 * i + l] = d;
-    }
-    // Lo - H = d - c 2^K = d + c (mod 2^K + 1)
-    return fw_norm(x, -(int)c, W);
-}
-
-// x = -x mod 2^K + 1 (canonical x with top xt); returns the new top.  For 0 < x < 2^K,
-// 2^K + 1 - x = ~x + 2 (K-bit complement).
-template <int LW>
-__device__ uint32_t fw_neg(uint32_t* x, uint32_t xt) {
-    constexpr int W = 64 * LW;
-    const int l = lane_id();
-    wsync();
-    if (xt) {
-#pragma unroll
-        for (int i = 0; i < LW; ++i) x[64 * i + l] = (64 * i + l) == 0 ? 1u : 0u;
-        wsync();
-        return 0;
-    }
-    bool nz = false;
-#pragma unroll
-    for (int i = 0; i < LW; ++i) nz = nz || x[64 * i + l] != 0u;
-    if (__ballot(nz) == 0ull) return 0;
-#pragma unroll
-    for (int i = 0; i < LW; ++i) x[64 * i + l] = ~x[64 * i + l];
-    return fw_norm(x, -2, W);
-}
 
 // s = x + y into X and d = x - y into Y (canonical inputs with tops xt, yt, in LDS); returns
 // the tops of s and d in *st, *dt.
@@ -563,6 +424,7 @@ inline size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct SmulPlan {
     int log2n = 0, lw = 0, W = 0, K = 0, s = 0;
+    int products = 1;         // Step 5: 1 digit schoolbook on the vector units, 2 matrix cores
     long long n = 0;
     int nlev = 0;
     int lr[24] = {};          // radices (log2) of the forward levels, top level first
@@ -610,16 +472,28 @@ void smul_levels(SmulPlan* P) {
     for (int i = 0; i < nlev; ++i) P->lr[i] = P->log2n / nlev + (i < P->log2n % nlev ? 1 : 0);
 }
 
-// Modelled cost: componentwise products n (K / 28)^2 digit products, transforms 3 (levels) n W
-// limbs through HBM and the butterflies, in units of a digit product.
-double smul_cost(long long n, int W, int nlev) {
+// Modelled cost, in units of a digit product: the componentwise products (vector units:
+// n (K / 28)^2 digit products; matrix cores: about 2.2 n (K / 8)^2 byte products, the Toeplitz
+// zeros and the tiles' edges included, at kMxPerDigit byte products per digit product's time, and
+// the byte sums and carries, 60 per limb), and the transforms, 3 (levels) n W limbs through HBM
+// and the butterflies. kMxPerDigit is set from timed launches at lw = 16, n = 2^16, where the
+// matrix-core form took 1.05 times as long as the digit form (7.31 against 6.95 ms): the model
+// then prefers the digit form, and the matrix cores run when asked for.
+constexpr double kMxPerDigit = 26.0;
+double smul_products_cost(long long n, int W, int products) {
     const double K = 32.0 * W;
-    return (double)n * (K / 28.0) * (K / 28.0) + 3.0 * (double)nlev * (double)n * W * 120.0;
+    if (products == 2) return (double)n * (2.2 * (K / 8.0) * (K / 8.0) / kMxPerDigit + 60.0 * W);
+    return (double)n * (K / 28.0) * (K / 28.0);
+}
+double smul_cost(long long n, int W, int nlev, int products) {
+    return smul_products_cost(n, W, products) + 3.0 * (double)nlev * (double)n * W * 120.0;
 }
 
 int smul_plan(size_t alen, size_t blen, const dkss_smul_params* p, SmulPlan* P) {
     if (alen == 0 || blen == 0) return DKSS_OK;
-    int best_n = -1, best_lw = 0, best_s = 0;
+    const int want = p ? (int)p->products : 0;
+    if (want < 0 || want > 2) return DKSS_EINVAL;
+    int best_n = -1, best_lw = 0, best_s = 0, best_pr = 1;
     double best = 0;
     for (int lg = 1; lg <= 24; ++lg) {
         for (int lw = 1; lw <= kMaxLw; lw *= 2) {
@@ -631,16 +505,21 @@ int smul_plan(size_t alen, size_t blen, const dkss_smul_params* p, SmulPlan* P) 
             T.log2n = lg;
             T.W = 64 * lw;
             smul_levels(&T);
-            const double c = smul_cost(1LL << lg, 64 * lw, T.nlev);
-            if (best_n < 0 || c < best) {
-                best = c;
-                best_n = lg;
-                best_lw = lw;
-                best_s = s;
+            for (int pr = 1; pr <= 2; ++pr) {
+                if ((want && pr != want) || (pr == 2 && !smul_mx_supported(lw))) continue;
+                const double c = smul_cost(1LL << lg, 64 * lw, T.nlev, pr);
+                if (best_n < 0 || c < best) {
+                    best = c;
+                    best_n = lg;
+                    best_lw = lw;
+                    best_s = s;
+                    best_pr = pr;
+                }
             }
         }
     }
     if (best_n < 0) return DKSS_ERANGE;
+    P->products = best_pr;
     P->log2n = best_n;
     P->n = 1LL << best_n;
     P->lw = best_lw;
@@ -713,6 +592,7 @@ int launch_transform(const SmulPlan& P, uint32_t* poly, uint32_t* tops, bool inv
 template <int LW>
 int launch_pointwise(const SmulPlan& P, uint32_t* A, uint32_t* At, const uint32_t* B, const uint32_t* Bt,
                      hipStream_t s) {
+    if (P.products == 2) return smul_pointwise_mx(LW, P.n, A, At, B, Bt, P.log2n, s);
     const size_t lds = pw_lds_words(64 * LW) * 4;
     hipLaunchKernelGGL(k_smul_pointwise<LW>, dim3((unsigned)P.n), dim3(kT), lds, s, A, At, B, Bt, P.log2n);
     return launch_status();
@@ -762,6 +642,7 @@ void to_params(const SmulPlan& P, dkss_smul_params* out) {
     out->s = (uint32_t)P.s;
     out->K = (uint32_t)P.K;
     out->n_levels = (uint32_t)P.nlev;
+    out->products = (uint32_t)P.products;
 }
 
 bool overlap(const void* x, size_t xb, const void* y, size_t yb) {

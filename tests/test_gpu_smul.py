@@ -131,6 +131,42 @@ def test_smul_products_match_oracle(env, case):
     assert np.array_equal(got, C.schoolbook(a, b))
 
 
+PRODUCTS = [  # (alen, blen, log2_n, lw): rings where both forms of the componentwise products run
+    (64, 64, 4, 1), (300, 200, 9, 2), (500, 500, 6, 4), (3000, 3000, 9, 8), (3000, 3000, 8, 16),
+    (12000, 11000, 10, 16), (20000, 3000, 11, 8),
+]
+
+
+@pytest.mark.parametrize("products", [1, 2])
+@pytest.mark.parametrize("case", PRODUCTS, ids=lambda c: "%dx%d_n%d_lw%d" % c)
+def test_smul_componentwise_products_both_forms(env, case, products):
+    """The componentwise products by 28-bit digits on the vector units (1) and by exact 8-bit
+    products on the matrix cores (2) give the product bit for bit: random and all-ones factors
+    (every byte column at its largest sum) against the oracle's schoolbook."""
+    dk, torch = env
+    alen, blen, log2_n, lw = case
+    params = dk.SmulParams.make(log2_n, lw, products)
+    a, b = SI.operand_pair(SI.SEED_BASE + 740 + alen, alen, blen)
+    got = _smul(env, a, b, params)
+    assert np.array_equal(got, C.schoolbook(a, b))
+    ones_a = np.full(alen, 0xFFFFFFFF, dtype=np.uint32)
+    ones_b = np.full(blen, 0xFFFFFFFF, dtype=np.uint32)
+    assert _int(_smul(env, ones_a, ones_b, params)) == _int(ones_a) * _int(ones_b)
+    assert _int(_smul(env, ones_a, ones_a, params, square=True)) == _int(ones_a) ** 2
+
+
+def test_smul_products_form_reported(env):
+    """The parameters report the form of the products: the library's choice at 2^28 bits is the
+    digit form (the faster one there), and asking for the matrix cores beyond lw = 16 is refused."""
+    dk, torch = env
+    p = dk.smul_select(1 << 23, 1 << 23)
+    assert p.products == 1 and p.lw <= 16
+    a = dk.to_device(SI.limbs(SI.SEED_BASE + 750, 4096))
+    with pytest.raises(dk.DkssError) as e:
+        dk.smul(a, a, params=dk.SmulParams.make(0, 32, 2))
+    assert e.value.code == dk.ERANGE
+
+
 @pytest.mark.parametrize("n", [64, 3000, 32768])
 @pytest.mark.parametrize("kind", ["ones", "ones_unbalanced", "pow2", "square", "coeff_minus_one"])
 def test_smul_edge_operands(env, n, kind):
