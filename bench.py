@@ -1,7 +1,7 @@
 """Benchmark: DKSS multiplication on one MI355X, operand bits multiplied per second.
 
 python bench.py [--gpus 1] [--steps K] [--warmup W] [--batch 4096] [--no-cpu] [--no-c5]
-                [--legs batch,2p28,sizes,c5] [--copy-calib BYTES]
+                [--legs batch,2p28,sizes,smul,twforms,c5] [--copy-calib BYTES]
 
 Headline (`value`): the mixed batch, batched and learned-tuned.  One step is one pass of the whole
 hot path over the batch: 4096 independent products whose longer operand has 2^U(12,22) bits
@@ -30,7 +30,9 @@ else null.
 
 Other legs: "single_2p28" one 2^28 x 2^28-bit product (thesis rule, tuned table, learned
 selector; its own profiled pass gives `roofline` of its dominant kernel, the forward twiddle
-level); "sizes" single products of 2^18 and 2^24 bits; "c5" one 2^34 x 2^34-bit product (2 GiB
+level); "sizes" single products of 2^18 and 2^24 bits; "smul" SMUL beside DKSS at 2^24 and 2^28
+bits; "twforms" the bad multiplications of one 2^28-bit transform level on the vector units and
+on the matrix cores (dkss_probe_twiddle_products); "c5" one 2^34 x 2^34-bit product (2 GiB
 operands, seeded uniform limbs from the device generator) under the thesis rule and the learned
 selector, plus the squaring a*a, each checked by residues mod 16 primes; "cpu_baseline" the
 oracle's DKSS (C, gcc -O3 -march=native built on the machine that runs it) on a bounded sample
@@ -475,6 +477,57 @@ def c5_leg(dk, torch, SI):
     return out
 
 
+def twiddle_forms_leg(reps, dk, torch):
+    """The bad multiplications of one transform level of the 2^28-bit products (thesis rule and
+    learned selector: their m = 16 and modulus q) in the two forms of dkss_probe_twiddle_products:
+    2M elements in groups of 32 sharing one twiddle, seeded canonical residues, every output word
+    of the two forms compared.  A level that used the matrix cores would first have to gather
+    the elements of each table index together: that pass is priced here as one device copy of
+    the level's S bytes."""
+    out = {}
+    n = 1 << 23
+    gen = torch.Generator(device="cuda")
+    for name, policy in (("thesis", dk.POLICY_THESIS), ("learned", dk.POLICY_LEARNED)):
+        plan = dk.Context(policy).plan_info(n, n)
+        L, log2_M = plan.L, plan.params.log2_M
+        if plan.params.log2_m != 4 or not 3 <= L <= 6:
+            continue
+        q = sum(int(plan.q[k]) << (32 * k) for k in range(L))
+        groups = (2 << log2_M) // 32
+        top = q.bit_length() - 1 - 32 * (L - 1)
+        gen.manual_seed(0x44B55 + 900 + L)
+
+        def residues(count):
+            w = torch.randint(-2 ** 31, 2 ** 31, (count, L), dtype=torch.int32, device="cuda", generator=gen)
+            w[:, L - 1] &= (1 << top) - 1 if top < 31 else 0x7FFFFFFF
+            return w.reshape(-1)
+
+        t = residues(groups * 16)
+        x = residues(groups * 32 * 16)
+        r = torch.randint(0, 32, (groups * 32,), dtype=torch.int32, device="cuda", generator=gen)
+        y1, y2 = torch.empty_like(x), torch.empty_like(x)
+        # the two forms and the copy timed in turn, three times: the least time of each
+        ms1 = ms2 = ms_copy = float("inf")
+        for _ in range(3):
+            ms1 = min(ms1, _timed(lambda: dk.probe_twiddle_products(1, q, L, groups, t, x, r, y1), reps, torch))
+            ms2 = min(ms2, _timed(lambda: dk.probe_twiddle_products(2, q, L, groups, t, x, r, y2), reps, torch))
+            ms_copy = min(ms_copy, _timed(lambda: y1.copy_(x), reps, torch))
+        dk.probe_twiddle_products(1, q, L, groups, t, x, r, y1)
+        torch.cuda.synchronize()
+        if not torch.equal(y1, y2):
+            raise RuntimeError("the two forms of the twiddle products differ (%s)" % name)
+        S = x.numel() * 4
+        out[name] = {"L": L, "q_bits": q.bit_length(), "elements": groups * 32, "groups": groups,
+                     "poly_bytes": S, "vector_units_ms": ms1, "matrix_cores_ms": ms2,
+                     "matrix_over_vector": ms2 / ms1, "gather_pass_ms": ms_copy,
+                     "verified": "all %d output words of the two forms equal" % x.numel()}
+        log("twiddle products %s (L = %d, %d elements): vector units %.3f ms, matrix cores %.3f ms, "
+            "a gather pass %.3f ms" % (name, L, groups * 32, ms1, ms2, ms_copy))
+        del t, x, r, y1, y2
+        torch.cuda.empty_cache()
+    return out
+
+
 def copy_calibration(args, torch, out):
     """One device-to-device copy of --copy-calib bytes: a kernel of known HBM traffic that the
     counter runs scale their FETCH_SIZE and WRITE_SIZE by."""
@@ -492,7 +545,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--batch", type=int, default=4096, help="products in the headline batch")
-    ap.add_argument("--legs", default="batch,2p28,sizes,smul,c5",
+    ap.add_argument("--legs", default="batch,2p28,sizes,smul,twforms,c5",
                     help="comma-separated legs to run (the headline batch is always run)")
     ap.add_argument("--no-c5", action="store_true", help="skip the 2^34 leg")
     ap.add_argument("--no-cpu", action="store_true")
@@ -500,7 +553,8 @@ def main():
                     help="stream lanes of the headline batch's groups (DKSS_OPT_BATCH_LANES)")
     ap.add_argument("--headline-only", action="store_true",
                     help="profiling form: the headline batch alone (graph and profiled pass), or, "
-                         "when --legs does not name batch, only the named legs among 2p28 and smul")
+                         "when --legs does not name batch, only the named legs among 2p28, smul "
+                         "and twforms")
     ap.add_argument("--copy-calib", type=int, default=0,
                     help="end with one device-to-device copy of this many bytes (a counter "
                          "calibration kernel of known traffic)")
@@ -527,6 +581,8 @@ def main():
             sub["single_2p28"] = single_leg(28, args.steps, dk, torch, SI)
         if "smul" in legs:
             sub["smul"] = smul_leg([28], args.steps, dk, torch, SI)
+        if "twforms" in legs:
+            sub["twiddle_forms"] = twiddle_forms_leg(args.steps, dk, torch)
         copy_calibration(args, torch, sub)
         print(json.dumps(sub), flush=True)
         return
@@ -557,6 +613,8 @@ def main():
         out["sizes"] = sizes_leg([18, 24], 20, dk, torch, SI)
     if "smul" in legs:
         out["smul"] = smul_leg([24, 28], 10, dk, torch, SI)
+    if "twforms" in legs:
+        out["twiddle_forms"] = twiddle_forms_leg(10, dk, torch)
     if "c5" in legs and not args.no_c5:
         out["c5"] = c5_leg(dk, torch, SI)
     copy_calibration(args, torch, out)

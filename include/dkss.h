@@ -214,6 +214,26 @@ int dkss_smul_forward(uint32_t* poly, uint32_t* tops, const uint32_t* a, size_t 
  * launch.  A diagnostic: it waits for its launches.  Errors: DKSS_EINVAL, DKSS_EHIP. */
 int dkss_probe_mad_rate(double* mads_per_s, dkss_stream_t s);
 
+/* The bad multiplications of the FFT levels (Sec. 3.2.5 ii: the products by rho^s alpha^r) in
+ * two forms, for an A/B measurement of the vector units against the matrix cores.  For
+ * g < groups and n < 32, with m = 2^log2_m coefficients (log2_m must be 4):
+ *     y[g][n] = t[g] * alpha^(r[g][n] mod 2m) * x[g][n] * 2^(-28 K) mod q   in R,
+ * K the Montgomery digit steps of q's residue format (as dkss_plan.digits: K = ceil((qb + 6) / 28),
+ * qb = 28 digits - 1 for a tight format, else 32 L), every coefficient canonical in [0, q): the
+ * 32 elements of a group share one twiddle, as the elements of a transform whose twiddles have
+ * the same table index s do.  form 1: 28-bit digit products on the vector units, one lane per
+ * output coefficient (the level kernels' product); form 2: the group's 32 products as one
+ * contraction of 7-bit digits by v_mfma_i32_32x32x32_i8.  Both give the same words.
+ * q: HOST, L limbs (3 <= L <= 6, odd, top limb not zero).  t: DEVICE, groups x m residues of L
+ * limbs; x, y: DEVICE, groups x 32 x m residues of L limbs (residues canonical, x 16-byte
+ * aligned, y not overlapping t, x or r); r: DEVICE, groups x 32 words.  Enqueued on s; allocates
+ * nothing and does not wait.  Errors: DKSS_EINVAL (form not 1 or 2, null pointer, x not aligned,
+ * q even or not L limbs),
+ * DKSS_ERANGE (log2_m, L or groups >= 2^31 unsupported), DKSS_EHIP. */
+int dkss_probe_twiddle_products(int form, const uint32_t* q, uint32_t L, uint32_t log2_m, size_t groups,
+                                const uint32_t* t, const uint32_t* x, const uint32_t* r, uint32_t* y,
+                                dkss_stream_t s);
+
 /* Bytes of the fixed device scratch of dkss_mul_noalloc (one copy per device). */
 #define DKSS_NOALLOC_SCRATCH_BYTES ((size_t)128 << 20)
 

@@ -119,6 +119,8 @@ def lib():
         L.dkss_mul.argtypes = [vp, vp, vp, sz, vp, sz, PP, vp, sz, vp]
         L.dkss_mul_noalloc.argtypes = [vp, vp, vp, sz, vp, sz, PP, vp]
         L.dkss_probe_mad_rate.argtypes = [ctypes.POINTER(ctypes.c_double), vp]
+        L.dkss_probe_twiddle_products.argtypes = [ctypes.c_int, ctypes.POINTER(u32), u32, u32, sz, vp, vp,
+                                                  vp, vp, vp]
         SP = ctypes.POINTER(SmulParams)
         L.dkss_smul_select.argtypes = [sz, sz, SP]
         L.dkss_smul_workspace_bytes.argtypes = [sz, sz, SP, ctypes.POINTER(sz)]
@@ -168,7 +170,7 @@ def lib():
 EXPORTED = ["dkss_ctx_create", "dkss_ctx_destroy", "dkss_select_params", "dkss_plan_info",
             "dkss_workspace_bytes", "dkss_prepare", "dkss_mul", "dkss_mul_noalloc", "dkss_mul_batch",
             "dkss_smul_select", "dkss_smul_workspace_bytes", "dkss_smul", "dkss_smul_forward",
-            "dkss_probe_mad_rate",
+            "dkss_probe_mad_rate", "dkss_probe_twiddle_products",
             "dkss_batch_workspace_bytes", "dkss_batch_prepare", "dkss_forward", "dkss_residues", "dkss_profile_enable",
             "dkss_profile_read", "dkss_profile_reset", "dkss_kernel_name", "dkss_set_option",
             "dkss_candidates", "dkss_mlp_features", "dkss_mlp_forward", "dkss_mlp_work_floats",
@@ -246,6 +248,16 @@ def probe_mad_rate(stream=None):
     r = ctypes.c_double()
     _check(lib().dkss_probe_mad_rate(ctypes.byref(r), _stream_ptr(stream)), "dkss_probe_mad_rate")
     return r.value
+
+
+def probe_twiddle_products(form, q, L, groups, t, x, r, y, log2_m=4, stream=None):
+    """dkss_probe_twiddle_products: y[g][n] = t[g] alpha^r[g][n] x[g][n] 2^(-28K) mod q for groups of
+    32 elements sharing one twiddle; form 1 vector units, 2 matrix cores.  q: an int; t, x, r, y:
+    int32 device tensors (groups x m x L, groups x 32 x m x L, groups x 32, as x)."""
+    qa = (ctypes.c_uint32 * L)(*[(q >> (32 * k)) & 0xFFFFFFFF for k in range(L)])
+    _check(lib().dkss_probe_twiddle_products(form, qa, L, log2_m, groups, _ptr(t), _ptr(x), _ptr(r),
+                                             _ptr(y), _stream_ptr(stream)),
+           "dkss_probe_twiddle_products")
 
 
 def smul_select(alen, blen):

@@ -12,7 +12,7 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(CSRC, "libdkss.so")
-SOURCES = ["dkss_lib.hip", "mlp.hip", "smul.hip", "smul_mx.hip", "planner.cpp"]
+SOURCES = ["dkss_lib.hip", "mlp.hip", "smul.hip", "smul_mx.hip", "tw_mx.hip", "planner.cpp"]
 
 HIPCC_FLAGS = [
     "-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC",
