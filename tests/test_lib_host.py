@@ -153,6 +153,20 @@ def test_workspace_and_schoolbook_routing(dk):
     assert ctx.workspace_bytes(8192, 8192) >= 2 * info.poly_bytes
 
 
+def test_transform_memory_two_polynomials(dk):
+    """The transform needs no temporary polynomial (thesis Sec. 5.1 outlook; Sec. 4.5 counts three
+    polynomials): a 2^28-bit product's workspace under the thesis rule is the two polynomials and
+    the rho table plus less than 1 % for decode and carries, 24.6N bits against 36N for three
+    polynomials of the same coefficients."""
+    ctx = dk.Context(dk.POLICY_THESIS)
+    n = 1 << 23
+    info = ctx.plan_info(n, n)
+    ws = ctx.workspace_bytes(n, n)
+    base = 2 * info.poly_bytes + info.table_bytes
+    assert base <= ws < base + info.poly_bytes // 64
+    assert ws * 8 < 25 * (32 * n)
+
+
 @pytest.mark.parametrize("a,b,batch", [(1, 1, 1), (2 ** 18, 2 ** 15, 16), (2 ** 30, 2 ** 30, 4096),
                                        (100, 5000, 3), (2 ** 36, 7, 65535), (0, 40, 1)])
 def test_selector_features_match_oracle(dk, a, b, batch):
