@@ -580,7 +580,7 @@ def main():
         if "2p28" in legs:
             sub["single_2p28"] = single_leg(28, args.steps, dk, torch, SI)
         if "smul" in legs:
-            sub["smul"] = smul_leg([28], args.steps, dk, torch, SI)
+            sub["smul"] = smul_leg([24, 28], args.steps, dk, torch, SI)
         if "twforms" in legs:
             sub["twiddle_forms"] = twiddle_forms_leg(args.steps, dk, torch)
         copy_calibration(args, torch, sub)

@@ -472,18 +472,19 @@ void smul_levels(SmulPlan* P) {
     for (int i = 0; i < nlev; ++i) P->lr[i] = P->log2n / nlev + (i < P->log2n % nlev ? 1 : 0);
 }
 
-// Modelled cost, in units of a digit product: the componentwise products (vector units:
-// n (K / 28)^2 digit products; matrix cores: about 2.2 n (K / 8)^2 byte products, the Toeplitz
-// zeros and the tiles' edges included, at kMxPerDigit byte products per digit product's time, and
-// the byte sums and carries, 60 per limb), and the transforms, 3 (levels) n W limbs through HBM
-// and the butterflies. kMxPerDigit is set from timed launches at lw = 16, n = 2^16, where the
-// matrix-core form took 1.05 times as long as the digit form (7.31 against 6.95 ms): the model
-// then prefers the digit form, and the matrix cores run when asked for.
-constexpr double kMxPerDigit = 26.0;
+// Modelled cost, in units of a digit product: the componentwise products (digit form: n (K / 28)^2
+// digit products; matrix-core form: that cost times the ratio of the two forms' measured launch
+// times at the same ring, 0.48 at lw = 4 (n = 2^14) and 0.66 at lw = 16 (n = 2^16), 0.57 taken
+// between them at lw = 8 and 0.48 below lw = 4), and the transforms, 3 (levels) n W limbs through
+// HBM and the butterflies.
+double smul_mx_ratio(int W) {
+    const int lw = W / 64;
+    return lw >= 16 ? 0.66 : lw >= 8 ? 0.57 : 0.48;
+}
 double smul_products_cost(long long n, int W, int products) {
     const double K = 32.0 * W;
-    if (products == 2) return (double)n * (2.2 * (K / 8.0) * (K / 8.0) / kMxPerDigit + 60.0 * W);
-    return (double)n * (K / 28.0) * (K / 28.0);
+    const double digits = (double)n * (K / 28.0) * (K / 28.0);
+    return products == 2 ? smul_mx_ratio(W) * digits : digits;
 }
 double smul_cost(long long n, int W, int nlev, int products) {
     return smul_products_cost(n, W, products) + 3.0 * (double)nlev * (double)n * W * 120.0;

@@ -4,15 +4,17 @@
 // as k_smul_pointwise does on the vector units, with the 2K-bit product of the two factors (both
 // below 2^K) computed from exact 8-bit integer products:
 //
-// The product is a convolution of the factors' N = 4W bytes.  With 64-byte blocks
-// a = sum_i A_i z^i, b = sum_j B_j z^j (z = 2^512), the sums
-//     C[r][k] = sum_i sum_(u < 64) A_i[r - u] B_(k-i)[u],   r < 128, k < 2 NB - 1,
-// (A_i[x] = 0 outside 0 <= x < 64, B_j = 0 outside 0 <= j < NB) give column t = 64 k + r of the
-// product from C[t mod 64][t div 64] + C[t mod 64 + 64][t div 64 - 1].  For fixed i the u-sum is a
-// product of a 128 x 64 Toeplitz matrix of A_i's bytes with the 64 x (2 NB - 1) matrix of b's
-// blocks: a dense contraction, done by v_mfma_i32_32x32x32_i8 (32 x 32 tiles, 32 bytes of the
-// reduction per instruction).  The instruction takes signed bytes, so both factors enter as
-// byte - 128 and the column sums are corrected with the factors' byte sums over each column's range:
+// The product is a convolution of the factors' N = 4W bytes.  With column t = 32 T + r (r < 32) of
+// the product and b's 32-byte groups b_g (g < NG = N / 32), the sums
+//     C[r][T] = sum_d sum_(u < 32) a[32 d + r - u] b_(T - d)[u],   0 <= d <= NG,
+// (a zero outside 0 <= x < N, b_g = 0 outside 0 <= g < NG) are column 32 T + r.  For fixed d the
+// u-sum is the 32 x 32 Toeplitz matrix W_d[r][u] = a[32 d + r - u] of a 63-byte window of a times
+// the 32 x (2 NG) matrix of b's groups shifted by d: a dense contraction, done by
+// v_mfma_i32_32x32x32_i8 on 32 x 32 tiles of C (32 bytes of the reduction per instruction), each
+// W_d loaded once and applied to every tile it meets, about (NG + 1)(NG / 16 + 1) instructions per
+// element (640 at N = 4096, 1.25 N^2 byte products).  The instruction takes signed bytes, so both
+// factors enter as byte - 128 and the column sums are corrected with the factors' byte sums over
+// each column's range:
 //     sum a_x b_y = sum (a_x - 128)(b_y - 128) + 128 (sum a_x + sum b_y) - 16384 pairs,
 // over the pairs x + y = t; prefix sums of the bytes give the ranges' sums.  Every column sum is
 // below 4W 255^2 < 2^28, every partial sum of signed products below 2^26 in magnitude.
@@ -34,17 +36,16 @@ constexpr int kMxMaxLw = 16;              // the products' LDS fits up to W = 10
 typedef int mx_v4i __attribute__((ext_vector_type(4)));
 typedef int mx_v16i __attribute__((ext_vector_type(16)));
 
-__host__ __device__ constexpr int mx_nb(int W) { return W / 16; }                 // 64-byte blocks
-__host__ __device__ constexpr int mx_nct(int W) { return (2 * mx_nb(W) - 1 + 31) / 32; }   // 32-column tiles
-__host__ __device__ constexpr int mx_pitch(int W) { return 32 * mx_nct(W) + 1; }  // int32 per row of C (odd)
-// words of the padded, reversed first factor: per block 16 zero words, its 16 words byte-reversed
-// in reverse order, 16 zero words; 4 more words of zeros at the end
-__host__ __device__ constexpr int mx_apw(int W) { return 48 * mx_nb(W) + 4; }
+__host__ __device__ constexpr int mx_ng(int W) { return W / 8; }                 // 32-byte groups of b
+__host__ __device__ constexpr int mx_nt(int W) { return (2 * mx_ng(W) + 31) / 32; }   // 32-column tiles of C
+__host__ __device__ constexpr int mx_pitch(int W) { return 2 * mx_ng(W) + 1; }    // int32 per row of C (odd)
+// words of one copy of the padded, reversed first factor (N + 64 bytes)
+__host__ __device__ constexpr int mx_cw(int W) { return W + 16; }
 __host__ __device__ constexpr size_t mx_al16(size_t x) { return (x + 15) & ~(size_t)15; }
-// shared region: the padded first factor and the second factor's bytes while the products run,
-// then the 64 x pitch column sums C, then the 2W word sums
+// shared region: four copies of the padded first factor and the second factor's bytes while the
+// products run, then the 32 x pitch column sums C, then the 2W word sums
 __host__ __device__ constexpr size_t mx_region(int W) {
-    return mx_al16(std::max(std::max((size_t)4 * mx_apw(W) + 4 * (size_t)W, (size_t)64 * mx_pitch(W) * 4),
+    return mx_al16(std::max(std::max((size_t)16 * mx_cw(W) + 4 * (size_t)W, (size_t)32 * mx_pitch(W) * 4),
                             (size_t)16 * W));
 }
 __host__ __device__ constexpr size_t mx_pref(int W) { return mx_al16((size_t)4 * (W + 1)); }
@@ -123,20 +124,19 @@ __device__ __forceinline__ uint32_t mx_prefix(const uint32_t* X, const uint32_t*
 // One workgroup per element; B == A for a squaring; a factor equal to 2^K (= -1) makes the
 // product the other factor's negation.
 template <int LW>
-__global__ __launch_bounds__(kT) void k_smul_pointwise_mx(uint32_t* Ap, uint32_t* At, const uint32_t* Bp,
+__global__ __launch_bounds__(kT, 2) void k_smul_pointwise_mx(uint32_t* Ap, uint32_t* At, const uint32_t* Bp,
                                                           const uint32_t* Bt, int log2n) {
     constexpr int W = 64 * LW;
     constexpr int K = 32 * W;
     constexpr int N = 4 * W;                     // bytes per factor
-    constexpr int NB = mx_nb(W), KC = 2 * NB - 1, NCT = mx_nct(W), PITCH = mx_pitch(W);
-    constexpr int APW = mx_apw(W);
+    constexpr int NG = mx_ng(W), NT = mx_nt(W), PITCH = mx_pitch(W), CW = mx_cw(W);
     extern __shared__ uint4 smx[];
     unsigned char* const base = reinterpret_cast<unsigned char*>(smx);
     uint32_t* XA = reinterpret_cast<uint32_t*>(base);
     uint32_t* XB = XA + W;
     unsigned char* RG = base + 8 * W;
-    uint32_t* AP = reinterpret_cast<uint32_t*>(RG);                       // APW words
-    uint32_t* BS = reinterpret_cast<uint32_t*>(RG + 4 * APW);             // b's bytes, signed
+    uint32_t* AR = reinterpret_cast<uint32_t*>(RG);                       // 4 CW words
+    uint32_t* BS = reinterpret_cast<uint32_t*>(RG + 16 * CW);             // b's bytes, signed
     int* Cm = reinterpret_cast<int*>(RG);                                 // after the products
     uint64_t* V = reinterpret_cast<uint64_t*>(RG);                        // after the columns
     uint32_t* PA = reinterpret_cast<uint32_t*>(RG + mx_region(W));
@@ -169,14 +169,19 @@ __global__ __launch_bounds__(kT) void k_smul_pointwise_mx(uint32_t* Ap, uint32_t
             }
         }
     } else {
-        // the operands as byte - 128: the first factor padded and reversed per block (byte p of
-        // block i's 192 bytes is A_i[127 - p] for 64 <= p < 128, zero elsewhere), the second
-        // factor's bytes in order
-        for (int d = threadIdx.x; d < APW; d += kT) {
-            const int i = d / 48, m = d - 48 * i;
+        // the operands as byte - 128: the first factor padded with 32 zero bytes on each side and
+        // reversed, AR[i] = a[N + 31 - i] (zero outside a), in four copies shifted by c = 0..3
+        // bytes (copy c, byte i: AR[i + c]) so that every lane's 16-byte run starts on a word; the
+        // second factor's bytes in order
+        for (int q = threadIdx.x; q < 4 * CW; q += kT) {
+            const int c = q / CW, wi = q - c * CW;
             uint32_t v = 0;
-            if (i < NB && m >= 16 && m < 32) v = __builtin_bswap32(XA[16 * i + 31 - m]) ^ 0x80808080u;
-            AP[d] = v;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int x = N + 31 - 4 * wi - e - c;
+                if (x >= 0 && x < N) v |= (((XA[x >> 2] >> (8 * (x & 3))) & 0xFFu) ^ 0x80u) << (8 * e);
+            }
+            AR[q] = v;
         }
         for (int i = threadIdx.x; i < W; i += kT) BS[i] = XB[i] ^ 0x80808080u;
         // the factors' byte sums below each word: a scan over the workgroup, WT words per thread
@@ -209,70 +214,60 @@ __global__ __launch_bounds__(kT) void k_smul_pointwise_mx(uint32_t* Ap, uint32_t
             }
         }
         __syncthreads();
-        // the products: wavefront wv accumulates NCT tiles (row tile rtl, column tile ct) of C
+        // the products: wavefront wv takes d = wv, wv + 4, ... and all column tiles; lane (r, h)
+        // holds W_d[r][16h .. 16h + 15] (bytes a[32d + r - 16h - e], a run of AR from
+        // s = N + 31 - 32d - r + 16h, word-aligned in copy s mod 4) and, for tile ct, column
+        // T = 32 ct + r of the shifted groups (b_(T - d) bytes 16h .. 16h + 15)
         const int wv = (int)(threadIdx.x >> 6), l = lane_id();
-        mx_v16i acc[NCT];
+        const int r = l & 31, h = l >> 5;
+        mx_v16i acc[NT];
 #pragma unroll
-        for (int q = 0; q < NCT; ++q)
+        for (int q = 0; q < NT; ++q)
 #pragma unroll
             for (int e = 0; e < 16; ++e) acc[q][e] = 0;
-        for (int i = 0; i < NB; ++i) {
+        for (int d = wv; d <= NG; d += 4) {
+            const int sidx = N + 31 - 32 * d - r + 16 * h;
+            const int c = sidx & 3;
+            const uint32_t* src = AR + c * CW + ((sidx - c) >> 2);
+            mx_v4i av;
+            av[0] = (int)src[0];
+            av[1] = (int)src[1];
+            av[2] = (int)src[2];
+            av[3] = (int)src[3];
 #pragma unroll
-            for (int ch = 0; ch < 2; ++ch) {
-#pragma unroll
-                for (int q = 0; q < NCT; ++q) {
-                    const int t = wv + 4 * q;
-                    const int rtl = t / NCT, ct = (t % NCT + rtl) % NCT;
-                    // rows r < 32 meet bytes u <= r only, rows r >= 96 bytes u > r - 64 only
-                    if ((rtl == 0 && ch == 1) || (rtl == 3 && ch == 0)) continue;
-                    if (i < 32 * ct - NB + 1 || i > 32 * ct + 31) continue;
-                    const int r = 32 * rtl + (l & 31);
-                    const int u0 = 32 * ch + 16 * (l >> 5);
-                    const int p = 192 * i + 127 - r + u0;        // A_i[r - u0 - e] at byte p + e
-                    const uint32_t* src = AP + (p >> 2);
-                    const int sh = p & 3;
-                    const uint32_t w0 = src[0], w1 = src[1], w2 = src[2], w3 = src[3], w4 = src[4];
-                    mx_v4i av, bv;
-                    av[0] = (int)__builtin_amdgcn_alignbyte(w1, w0, sh);
-                    av[1] = (int)__builtin_amdgcn_alignbyte(w2, w1, sh);
-                    av[2] = (int)__builtin_amdgcn_alignbyte(w3, w2, sh);
-                    av[3] = (int)__builtin_amdgcn_alignbyte(w4, w3, sh);
-                    const int kk = 32 * ct + (l & 31), j = kk - i;
-                    if (kk < KC && j >= 0 && j < NB) {
-                        const uint4 q4 = *reinterpret_cast<const uint4*>(
-                            reinterpret_cast<const unsigned char*>(BS) + 64 * j + u0);
-                        bv[0] = (int)q4.x;
-                        bv[1] = (int)q4.y;
-                        bv[2] = (int)q4.z;
-                        bv[3] = (int)q4.w;
-                    } else {
-                        bv[0] = bv[1] = bv[2] = bv[3] = 0;
-                    }
-                    acc[q] = __builtin_amdgcn_mfma_i32_32x32x32_i8(av, bv, acc[q], 0, 0, 0);
+            for (int ct = 0; ct < NT; ++ct) {
+                if (32 * ct - d + 31 < 0 || 32 * ct - d >= NG) continue;     // no group of b meets it
+                const int g = 32 * ct + r - d;
+                mx_v4i bv;
+                if (g >= 0 && g < NG) {
+                    const uint4 q4 = *reinterpret_cast<const uint4*>(
+                        reinterpret_cast<const unsigned char*>(BS) + 32 * g + 16 * h);
+                    bv[0] = (int)q4.x;
+                    bv[1] = (int)q4.y;
+                    bv[2] = (int)q4.z;
+                    bv[3] = (int)q4.w;
+                } else {
+                    bv[0] = bv[1] = bv[2] = bv[3] = 0;
                 }
+                acc[ct] = __builtin_amdgcn_mfma_i32_32x32x32_i8(av, bv, acc[ct], 0, 0, 0);
             }
         }
         __syncthreads();                                  // the operands are read: C takes the region
-        // C'[r][k] = C[r][k] + C[r + 64][k - 1] (r < 64): the rows below 64 first, then the rows
-        // above added one column on
+        for (int i = threadIdx.x; i < 32 * PITCH; i += kT) Cm[i] = 0;
+        __syncthreads();
+        // C[row][T] summed over the four wavefronts (row-major at an odd pitch: the lanes of one
+        // add hit distinct banks)
 #pragma unroll
-        for (int ph = 0; ph < 2; ++ph) {
-            if (ph == 0 && (int)threadIdx.x < 64) Cm[threadIdx.x * PITCH + 32 * NCT] = 0;
+        for (int ct = 0; ct < NT; ++ct) {
+            const int T = 32 * ct + r;
+            if (T >= 2 * NG) continue;
 #pragma unroll
-            for (int q = 0; q < NCT; ++q) {
-                const int t = wv + 4 * q;
-                const int rtl = t / NCT, ct = (t % NCT + rtl) % NCT;
-                if ((rtl >= 2) != (ph == 1)) continue;
-#pragma unroll
-                for (int e = 0; e < 16; ++e) {
-                    const int row = 32 * rtl + 8 * (e >> 2) + 4 * (l >> 5) + (e & 3);
-                    const int col = 32 * ct + (l & 31);
-                    if (ph == 0) Cm[row * PITCH + col] = acc[q][e];
-                    else Cm[(row - 64) * PITCH + col + 1] += acc[q][e];
-                }
+            for (int e = 0; e < 16; ++e) {
+                const int row = 8 * (e >> 2) + 4 * h + (e & 3);
+                atomicAdd(&Cm[row * PITCH + T], acc[ct][e]);
             }
-            __syncthreads();
         }
+        __syncthreads();
         // word sums V_w = sum_(e < 4) c_(4w + e) 2^(8e), c_t the corrected column sums
         constexpr int WPT = (2 * W + kT - 1) / kT;       // words per thread
         uint64_t vw[WPT];
@@ -285,7 +280,7 @@ __global__ __launch_bounds__(kT) void k_smul_pointwise_mx(uint32_t* Ap, uint32_t
                 for (int e = 0; e < 4; ++e) {
                     const int t = 4 * w + e;
                     if (t > 2 * N - 2) continue;
-                    const long long m = Cm[(t & 63) * PITCH + (t >> 6)];
+                    const long long m = Cm[(t & 31) * PITCH + (t >> 5)];
                     const int lo = t - N + 1 > 0 ? t - N + 1 : 0;
                     const int hi = t < N - 1 ? t : N - 1;
                     const long long sa = (long long)mx_prefix(XA, PA, hi + 1, W) - mx_prefix(XA, PA, lo, W);

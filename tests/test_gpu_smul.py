@@ -156,11 +156,12 @@ def test_smul_componentwise_products_both_forms(env, case, products):
 
 
 def test_smul_products_form_reported(env):
-    """The parameters report the form of the products: the library's choice at 2^28 bits is the
-    digit form (the faster one there), and asking for the matrix cores beyond lw = 16 is refused."""
+    """The parameters report the form of the products: the library's choice at 2^24 and 2^28 bits
+    is the matrix cores (the faster form there), and asking for them beyond lw = 16 is refused."""
     dk, torch = env
-    p = dk.smul_select(1 << 23, 1 << 23)
-    assert p.products == 1 and p.lw <= 16
+    for n in (1 << 19, 1 << 23):
+        p = dk.smul_select(n, n)
+        assert p.products == 2 and p.lw <= 16, n
     a = dk.to_device(SI.limbs(SI.SEED_BASE + 750, 4096))
     with pytest.raises(dk.DkssError) as e:
         dk.smul(a, a, params=dk.SmulParams.make(0, 32, 2))
