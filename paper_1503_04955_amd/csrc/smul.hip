@@ -474,17 +474,13 @@ void smul_levels(SmulPlan* P) {
 
 // Modelled cost, in units of a digit product: the componentwise products (digit form: n (K / 28)^2
 // digit products; matrix-core form: that cost times the ratio of the two forms' measured launch
-// times at the same ring, 0.48 at lw = 4 (n = 2^14) and 0.66 at lw = 16 (n = 2^16), 0.57 taken
-// between them at lw = 8 and 0.48 below lw = 4), and the transforms, 3 (levels) n W limbs through
-// HBM and the butterflies.
-double smul_mx_ratio(int W) {
-    const int lw = W / 64;
-    return lw >= 16 ? 0.66 : lw >= 8 ? 0.57 : 0.48;
-}
+// times at the same ring, 0.50 both at lw = 4 (n = 2^14) and at lw = 16 (n = 2^16)), and the
+// transforms, 3 (levels) n W limbs through HBM and the butterflies.
+constexpr double kMxRatio = 0.50;
 double smul_products_cost(long long n, int W, int products) {
     const double K = 32.0 * W;
     const double digits = (double)n * (K / 28.0) * (K / 28.0);
-    return products == 2 ? smul_mx_ratio(W) * digits : digits;
+    return products == 2 ? kMxRatio * digits : digits;
 }
 double smul_cost(long long n, int W, int nlev, int products) {
     return smul_products_cost(n, W, products) + 3.0 * (double)nlev * (double)n * W * 120.0;

@@ -43,16 +43,17 @@ __host__ __device__ constexpr int mx_pitch(int W) { return 2 * mx_ng(W) + 1; }  
 __host__ __device__ constexpr int mx_cw(int W) { return W + 16; }
 __host__ __device__ constexpr size_t mx_al16(size_t x) { return (x + 15) & ~(size_t)15; }
 // shared region: four copies of the padded first factor and the second factor's bytes while the
-// products run, then the 32 x pitch column sums C, then the 2W word sums
+// products run, then the 32 x pitch column sums C, then the 2W word sums and the product's 2W
+// words
 __host__ __device__ constexpr size_t mx_region(int W) {
     return mx_al16(std::max(std::max((size_t)16 * mx_cw(W) + 4 * (size_t)W, (size_t)32 * mx_pitch(W) * 4),
-                            (size_t)16 * W));
+                            (size_t)24 * W));
 }
 __host__ __device__ constexpr size_t mx_pref(int W) { return mx_al16((size_t)4 * (W + 1)); }
 // LDS bytes: the factors (8W), the region, the word prefix sums of both factors' bytes, a 16-word
-// scan scratch, the product's 2W words
+// scan scratch (under 50 KB at W = 1024: three workgroups per CU)
 __host__ __device__ constexpr size_t mx_lds_bytes(int W) {
-    return (size_t)8 * W + mx_region(W) + 2 * mx_pref(W) + 64 + (size_t)8 * W;
+    return (size_t)8 * W + mx_region(W) + 2 * mx_pref(W) + 64;
 }
 
 // One wavefront: the 2W-word product P from its 64-bit word sums V (P = sum_w V_w 2^(32 w), each
@@ -124,7 +125,7 @@ __device__ __forceinline__ uint32_t mx_prefix(const uint32_t* X, const uint32_t*
 // One workgroup per element; B == A for a squaring; a factor equal to 2^K (= -1) makes the
 // product the other factor's negation.
 template <int LW>
-__global__ __launch_bounds__(kT, 2) void k_smul_pointwise_mx(uint32_t* Ap, uint32_t* At, const uint32_t* Bp,
+__global__ __launch_bounds__(kT, 3) void k_smul_pointwise_mx(uint32_t* Ap, uint32_t* At, const uint32_t* Bp,
                                                           const uint32_t* Bt, int log2n) {
     constexpr int W = 64 * LW;
     constexpr int K = 32 * W;
@@ -142,7 +143,7 @@ __global__ __launch_bounds__(kT, 2) void k_smul_pointwise_mx(uint32_t* Ap, uint3
     uint32_t* PA = reinterpret_cast<uint32_t*>(RG + mx_region(W));
     uint32_t* PB = reinterpret_cast<uint32_t*>(RG + mx_region(W) + mx_pref(W));
     uint32_t* TMP = reinterpret_cast<uint32_t*>(RG + mx_region(W) + 2 * mx_pref(W));
-    uint32_t* PW = TMP + 16;
+    uint32_t* PW = reinterpret_cast<uint32_t*>(RG + 16 * (size_t)W);            // after the word sums
     const size_t k = blockIdx.x;
     uint32_t* a = Ap + k * W;
     const uint32_t* b = Bp + k * W;
