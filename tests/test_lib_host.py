@@ -341,3 +341,23 @@ def test_tuned_table_names_the_rule_where_nothing_beats_it(dk, tmp_path):
         assert tup(ctx.select_params(2 ** 16, 2 ** 16, batch)) == rule[2 ** 16], batch
     assert tup(ctx.select_params(2 ** 17, 2 ** 17)) == c3[2 ** 17]
     assert tup(ctx.select_params(2 ** 18, 2 ** 18)) == rule[2 ** 18]
+
+
+def test_smul_parameters_and_product_form(dk):
+    """SMUL's plan (host only): the ring for 2^16..2^30-bit products satisfies the convolution
+    bound of the outermost form (min(na, nb) (2^s - 1)^2 < 2^K, n | 2K), and the componentwise
+    products run on the matrix cores where their kernel exists (lw <= 16), on the vector units
+    beyond; an explicit form is honoured and one the ring cannot take is refused."""
+    for bits in (16, 20, 24, 26, 28, 30):
+        n = (1 << bits) // 32
+        p = dk.smul_select(n, n)
+        N = 1 << p.log2_n
+        K = p.K
+        assert K == 2048 * p.lw and (2 * K) % N == 0
+        na = -(-32 * n // p.s)
+        assert 2 * na - 1 <= N and na * ((1 << p.s) - 1) ** 2 < (1 << K), bits
+        assert p.products == (2 if p.lw <= 16 else 1), (bits, p.as_dict())
+    with pytest.raises(dk.DkssError) as e:
+        dk.smul_workspace_bytes(1 << 20, 1 << 20, dk.SmulParams.make(0, 32, 2))
+    assert e.value.code == dk.ERANGE
+    assert dk.smul_workspace_bytes(1 << 18, 1 << 18, dk.SmulParams.make(0, 0, 1)) > 0
