@@ -1169,10 +1169,11 @@ __global__ __launch_bounds__(kThreads) void k_carry_apply(ProdArgs PA,
 // Base case: schoolbook product (Sec. 2.3), one workgroup per product, alen + blen <= 4096
 // ---------------------------------------------------------------------------------------------
 
-// LDS: a and b (alen + blen words, at least 64), then the three 32-bit parts of every output
-// column's sum; once the columns are summed, the first 256 bytes hold one carry function per
-// thread.  Thread t sums columns t, t + 256, ...; each column total sum_i a_i b_(w-i) < 2^76 is
-// kept as 64 + 32 bits (a carry count beside a 64-bit accumulator).
+// LDS: a, a zero word, b, a zero word (at least 64 words), then the three 32-bit parts of every
+// output column's sum; once the columns are summed, the first 256 bytes hold one carry function
+// per thread.  Thread t sums columns 2t and 2t + 1, then 2t + 512 and 2t + 513, ...; each column
+// total sum_i a_i b_(w-i) < 2^76 is kept as 64 + 32 bits (a carry count beside a 64-bit
+// accumulator).
 // The words x_w = col_w[0] + col_(w-1)[1] + col_(w-2)[2] < 3 2^32 then take carries of 0, 1 or 2:
 // thread t owns the chunk of K consecutive words starting at t K, its carry out as a function of
 // its carry in (three values of {0, 1, 2}) is composed across threads by a prefix scan, and each
@@ -1195,45 +1196,68 @@ __global__ __launch_bounds__(kThreads) void k_schoolbook(ProdArgs PA) {
     const ProdDesc pd = PA.get();
     const long long alen = pd.alen, blen = pd.blen;
     const long long n = alen + blen;
+    // a, then b between two zero words (B[-1] = B[blen] = 0), then the columns
     uint32_t* const A = sv;
-    uint32_t* const B = sv + alen;
-    uint32_t* const col = sv + (n > 64 ? n : 64);
+    uint32_t* const B = sv + alen + 1;
+    uint32_t* const col = sv + (n + 2 > 64 ? n + 2 : 64);
     unsigned char* const fn = reinterpret_cast<unsigned char*>(sv);     // after the columns
     for (long long i = threadIdx.x; i < alen; i += kThreads) A[i] = pd.a[i];
     for (long long i = threadIdx.x; i < blen; i += kThreads) B[i] = pd.b[i];
+    if (threadIdx.x == 0) {
+        B[-1] = 0;
+        B[blen] = 0;
+    }
     __syncthreads();
-    for (long long w = threadIdx.x; w < n; w += kThreads) {
-        // four independent partial sums (terms i = i0 + 4 k + r), so that consecutive
-        // multiply-adds do not wait on each other's accumulator
-        uint64_t acc[4] = {0, 0, 0, 0};
-        uint32_t top[4] = {0, 0, 0, 0};
+    // two neighbouring columns w, w + 1 per thread: each a_i read once for both, and b's
+    // words shared between them (b_(w+1-i) = b_(w-(i-1))); i runs over the union of the two
+    // ranges, the zero words standing in for the terms one column does not have
+    for (long long w = 2 * (long long)threadIdx.x; w < n; w += 2 * kThreads) {
+        // four independent partial sums per column (terms i = i0 + 4 k + r), so that
+        // consecutive multiply-adds do not wait on each other's accumulator
+        uint64_t acc0[4] = {0, 0, 0, 0}, acc1[4] = {0, 0, 0, 0};
+        uint32_t top0[4] = {0, 0, 0, 0}, top1[4] = {0, 0, 0, 0};
         const long long i0 = w - blen + 1 > 0 ? w - blen + 1 : 0;
-        const long long i1 = w < alen - 1 ? w : alen - 1;
+        const long long i1 = w + 1 < alen - 1 ? w + 1 : alen - 1;
         long long i = i0;
         for (; i + 3 <= i1; i += 4) {
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const uint64_t s2 = (uint64_t)A[i + r] * B[w - i - r] + acc[r];
-                top[r] += s2 < acc[r];
-                acc[r] = s2;
+                const uint64_t a = A[i + r];
+                const uint64_t s0 = a * B[w - i - r] + acc0[r];
+                const uint64_t s1 = a * B[w + 1 - i - r] + acc1[r];
+                top0[r] += s0 < acc0[r];
+                top1[r] += s1 < acc1[r];
+                acc0[r] = s0;
+                acc1[r] = s1;
             }
         }
         for (int r = 0; i <= i1; ++i, ++r) {
-            const uint64_t s2 = (uint64_t)A[i] * B[w - i] + acc[r];
-            top[r] += s2 < acc[r];
-            acc[r] = s2;
+            const uint64_t a = A[i];
+            const uint64_t s0 = a * B[w - i] + acc0[r];
+            const uint64_t s1 = a * B[w + 1 - i] + acc1[r];
+            top0[r] += s0 < acc0[r];
+            top1[r] += s1 < acc1[r];
+            acc0[r] = s0;
+            acc1[r] = s1;
         }
-        uint64_t sum = acc[0];
-        uint32_t t = top[0];
 #pragma unroll
-        for (int r = 1; r < 4; ++r) {
-            const uint64_t s2 = sum + acc[r];
-            t += top[r] + (s2 < sum);
-            sum = s2;
+        for (int h = 0; h < 2; ++h) {
+            const uint64_t* acc = h ? acc1 : acc0;
+            const uint32_t* top = h ? top1 : top0;
+            uint64_t sum = acc[0];
+            uint32_t t = top[0];
+#pragma unroll
+            for (int r = 1; r < 4; ++r) {
+                const uint64_t s2 = sum + acc[r];
+                t += top[r] + (s2 < sum);
+                sum = s2;
+            }
+            if (w + h < n) {
+                col[3 * (w + h)] = (uint32_t)sum;
+                col[3 * (w + h) + 1] = (uint32_t)(sum >> 32);
+                col[3 * (w + h) + 2] = t;
+            }
         }
-        col[3 * w] = (uint32_t)sum;
-        col[3 * w + 1] = (uint32_t)(sum >> 32);
-        col[3 * w + 2] = t;
     }
     __syncthreads();
     // carries: chunk t covers words [t K, min(n, (t+1) K))
@@ -2487,7 +2511,7 @@ int launch_zero(const ProdArgs& PA, unsigned G, size_t nw_max, hipStream_t s) {
 int launch_schoolbook(const Call& call, const ProdArgs& PA, unsigned G, size_t nw_max, double ops,
                       hipStream_t s) {
     ProfScope ps(call.prof, DKSS_K_SCHOOLBOOK, s, 8.0 * G * nw_max, ops);
-    const size_t lds = (std::max<size_t>(nw_max, 64) + 3 * nw_max) * sizeof(uint32_t);   // <= 64 KiB
+    const size_t lds = (std::max<size_t>(nw_max + 2, 64) + 3 * nw_max) * sizeof(uint32_t);   // 64 KiB + 8 B at most
     hipLaunchKernelGGL(k_schoolbook, dim3(1, G), dim3(kThreads), lds, s, PA);
     return launch_status();
 }
