@@ -185,8 +185,9 @@ typedef struct {
                              0 = chosen by the modelled cost; output: the form used */
 } dkss_smul_params;
 
-/* The library's choice of (log2_n, lw) for alen x blen limbs (a modelled cost over the feasible
- * pairs: na + nb - 1 <= n coefficients, min(na, nb) (2^s - 1)^2 < 2^K, n | 2K).  All zero when
+/* The library's choice of (log2_n, lw, products) for alen x blen limbs (a modelled cost over the
+ * feasible pairs: na + nb - 1 <= n coefficients, min(na, nb) (2^s - 1)^2 < 2^K, n | 2K; the
+ * matrix-core products wherever lw <= 16 allows them, at half the digit form's cost).  All zero when
  * alen or blen is 0.  Errors: DKSS_EINVAL (null), DKSS_ERANGE (no feasible pair). */
 int dkss_smul_select(size_t alen, size_t blen, dkss_smul_params* out);
 
